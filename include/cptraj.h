@@ -1,0 +1,153 @@
+/*
+ * cptraj.h — C ABI of libcptraj, an MI355X (gfx950) implementation of
+ * error-bounded lossy compression of 2D time-varying vector fields that
+ * preserves every critical-point trajectory, after "Time-Varying Vector
+ * Field Compression with Preserved Critical Point Trajectories"
+ * (arXiv 2510.25143).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Fields are float32 arrays of shape (2, T, H, W): the u plane then the v
+ *   plane, each [t][y][x] with x fastest.  The mesh is the regular grid split
+ *   along each quad's main diagonal, extruded in time and cut into three
+ *   tetrahedra per prism (Sec. III-C).
+ * - Pointers marked "device" are HIP device pointers; "host" are host
+ *   pointers.  The caller owns and allocates every buffer; the library never
+ *   frees caller memory.  The library keeps a grow-only scratch arena per
+ *   device for its intermediate arrays (allocated on first use, reused).
+ * - `stream` is a hipStream_t passed as void*.  Work is ordered on it.  Calls
+ *   that return a length or count to the host synchronise the stream before
+ *   returning that value; output data is complete once the stream is
+ *   synchronised.
+ * - Every entry point returns a cpt_status; on failure cpt_last_error()
+ *   gives a message (thread-local).  No C++ exception crosses the ABI.
+ * - Supported sizes: 2 <= H, W <= 32768, 1 <= T, H*W*T < 2^31.
+ */
+#ifndef CPTRAJ_H
+#define CPTRAJ_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CPT_OK = 0,
+  CPT_EINVAL = -1,       /* bad argument, non-finite input, unsupported size */
+  CPT_ENOMEM = -2,       /* device allocation failed */
+  CPT_ECORRUPT = -3,     /* stream fails a consistency check */
+  CPT_ECAPACITY = -4,    /* output buffer too small; needed size reported */
+  CPT_EHIP = -5,         /* HIP runtime error (message in cpt_last_error) */
+  CPT_EUNSUPPORTED = -6  /* valid request the library does not handle */
+} cpt_status;
+
+/* Predictor choice (Sec. VI).  CPT_PRED_MIX2 is the paper's mixture of
+ * predictors: per block and frame, Lorenzo or semi-Lagrangian (d_max = 2
+ * cells) chosen by the rate estimate of Sec. VI-B.  MIX4 adds the
+ * semi-Lagrangian backtrace step as a choice (d_max 1, 2 or 4 cells).
+ * LEARNED picks among the same four classes with the selector network. */
+typedef enum {
+  CPT_PRED_LORENZO = 0,
+  CPT_PRED_SL = 1,
+  CPT_PRED_MIX2 = 2,
+  CPT_PRED_MIX4 = 3,
+  CPT_PRED_LEARNED = 4
+} cpt_predictor;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(cpt_options) */
+  int32_t eb_mode;        /* 0: eb relative to max-min over both components
+                             (default), 1: eb absolute */
+  int32_t predictor;      /* cpt_predictor, default CPT_PRED_MIX2 */
+  int32_t mode_bt;        /* frames per predictor block (>= 1, default 1) */
+  double dt_dx, dt_dy;    /* time step over grid spacing for the
+                             semi-Lagrangian backtrace (default 1.0) */
+  const uint16_t* selector_w; /* device, bf16 selector weights (5124 values)
+                                 when predictor == CPT_PRED_LEARNED */
+} cpt_options;
+
+/* Parameters stored in a stream's header. */
+typedef struct {
+  int32_t H, W, T;
+  int32_t k;          /* fixed-point exponent: x_fp = rint(x * 2^k) */
+  double eb_abs;      /* absolute bound in field units */
+  int64_t eps;        /* bound eps' in fixed-point units */
+  int32_t predictor, mode_bt, K, R;
+  uint64_t total_len, n_q, n_raw;
+} cpt_info;
+
+/* Outcome of comparing two fields on the same fixed-point grid. */
+typedef struct {
+  uint64_t fc_t;      /* faces in time slices whose status or sign changed */
+  uint64_t fc_s;      /* space-time faces across slabs that changed */
+  double max_err;     /* max |a - b| over both components */
+  double psnr;        /* 20 log10(range(a)) - 10 log10(MSE) */
+} cpt_verify_result;
+
+/* Largest stream cpt_compress can produce for these dimensions. */
+cpt_status cpt_compress_bound(int H, int W, int T, size_t* max_bytes);
+
+/*
+ * Compress a field (Alg. 3 with Alg. 4 and the predictors of Sec. VI; the
+ * guarantees are those of Sec. IV-A: |x - x'| <= eb_abs pointwise, and every
+ * space-time face keeps its crossed status and sign).
+ *   field   device, (2,T,H,W) float32, all finite
+ *   eb      error bound (relative in (0, 0.5], or absolute > 0)
+ *   opt     host, may be NULL for defaults
+ *   out     device, capacity `cap` bytes, 4-byte aligned
+ *   out_len host, receives the stream length (also on CPT_ECAPACITY)
+ * Synchronises `stream`.  The stream is bit-identical to the reference CPU
+ * implementation's for the same input and options.
+ */
+cpt_status cpt_compress(const float* field, int H, int W, int T, double eb, const cpt_options* opt,
+                        uint8_t* out, size_t cap, size_t* out_len, void* stream);
+
+/* Same as cpt_compress, also writing per-vertex and per-block internals
+ * (device buffers; any may be NULL): xi [N] int32 bound before quantization
+ * (0 when lossless), xcode [N] bound code (24 = lossless), qcode [N] residual
+ * codes u | v << 16, modes [nblocks] predictor class per block, feats
+ * [nblocks][10] selector features; *nblocks receives the block count. */
+cpt_status cpt_compress_debug(const float* field, int H, int W, int T, double eb, const cpt_options* opt,
+                              uint8_t* out, size_t cap, size_t* out_len, int32_t* xi, uint8_t* xcode,
+                              uint32_t* qcode, uint8_t* modes, float* feats, size_t* nblocks, void* stream);
+
+/* Parse a stream header (host bytes, at least 256). */
+cpt_status cpt_stream_info(const uint8_t* bytes, size_t len, cpt_info* info);
+
+/*
+ * Decompress a stream (device, 4-byte aligned) into `field` (device,
+ * (2,T,H,W) float32 as given by cpt_stream_info).  Any inconsistency gives
+ * CPT_ECORRUPT without out-of-bounds access.  Synchronises `stream`.
+ */
+cpt_status cpt_decompress(const uint8_t* bytes, size_t len, float* field, void* stream);
+
+/*
+ * Critical-point trajectory pieces (Sec. III-E/F): the crossed space-time
+ * faces of the field on the fixed-point grid 2^k, under simulation of
+ * simplicity, as sorted codes ((g * 12 + type) << 1) | (sign > 0) where g =
+ * (t H + y) W + x is the face's owner vertex and type 0..11 its face type.
+ *   codes  device, capacity `cap` entries; count receives the number found
+ *          (also on CPT_ECAPACITY, when nothing is written)
+ * Requires max|x| 2^k < 2^24.  Synchronises `stream`.
+ */
+cpt_status cpt_extract_trajectories(const float* field, int H, int W, int T, int k, uint64_t* codes, size_t cap,
+                                    size_t* count, void* stream);
+
+/* Compare two fields (device) on the grid 2^k: false cases per slice and
+ * per slab, max error and PSNR.  Synchronises `stream`. */
+cpt_status cpt_verify(const float* a, const float* b, int H, int W, int T, int k, cpt_verify_result* res,
+                      void* stream);
+
+/* Fixed-point exponent k and bound eps' the compressor derives for a field
+ * (device) and bound; synchronises `stream`. */
+cpt_status cpt_field_params(const float* field, int H, int W, int T, int eb_mode, double eb, int* k,
+                            double* eb_abs, int64_t* eps, void* stream);
+
+/* Message of the last failure on this thread. */
+const char* cpt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,213 @@
+"""Python binding of libcptraj — MI355X-native trajectory-preserving
+compression of 2D time-varying vector fields (arXiv 2510.25143).
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libcptraj.so`` (built in-tree by ``paper_2510_25143_amd.build``).  Fields are
+float32 CUDA tensors of shape (2, T, H, W); streams are uint8 CUDA tensors.
+There is no CPU fallback: a missing library raises at first use.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcptraj.so")
+
+OK, EINVAL, ENOMEM, ECORRUPT, ECAPACITY, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+PRED_LORENZO, PRED_SL, PRED_MIX2, PRED_MIX4, PRED_LEARNED = 0, 1, 2, 3, 4
+SELECTOR_PARAMS = 5124
+
+
+class CptError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("libcptraj status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("eb_mode", ctypes.c_int32),
+                ("predictor", ctypes.c_int32), ("mode_bt", ctypes.c_int32),
+                ("dt_dx", ctypes.c_double), ("dt_dy", ctypes.c_double),
+                ("selector_w", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("T", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("eb_abs", ctypes.c_double), ("eps", ctypes.c_int64),
+                ("predictor", ctypes.c_int32), ("mode_bt", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("R", ctypes.c_int32), ("total_len", ctypes.c_uint64),
+                ("n_q", ctypes.c_uint64), ("n_raw", ctypes.c_uint64)]
+
+
+class VerifyResult(ctypes.Structure):
+    _fields_ = [("fc_t", ctypes.c_uint64), ("fc_s", ctypes.c_uint64),
+                ("max_err", ctypes.c_double), ("psnr", ctypes.c_double)]
+
+
+EXPORTS = ["cpt_compress_bound", "cpt_compress", "cpt_compress_debug", "cpt_stream_info",
+           "cpt_decompress", "cpt_extract_trajectories", "cpt_verify", "cpt_field_params",
+           "cpt_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libcptraj.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcptraj.so is not built: run paper_2510_25143_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, sz, i32, i64, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "cpt_compress_bound": [i32, i32, i32, P],
+        "cpt_compress": [P, i32, i32, i32, dbl, P, P, sz, P, P],
+        "cpt_compress_debug": [P, i32, i32, i32, dbl, P, P, sz, P, P, P, P, P, P, P, P],
+        "cpt_stream_info": [P, sz, P],
+        "cpt_decompress": [P, sz, P, P],
+        "cpt_extract_trajectories": [P, i32, i32, i32, i32, P, sz, P, P],
+        "cpt_verify": [P, P, i32, i32, i32, i32, P, P],
+        "cpt_field_params": [P, i32, i32, i32, i32, dbl, P, P, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.cpt_last_error.restype = ctypes.c_char_p
+    L.cpt_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != OK:
+        raise CptError(st, lib().cpt_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _field(f):
+    if not (isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float32):
+        raise TypeError("field must be a float32 CUDA tensor")
+    if f.dim() != 4 or f.shape[0] != 2:
+        raise ValueError("field must have shape (2, T, H, W)")
+    return f.contiguous()
+
+
+def _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w):
+    o = Options(ctypes.sizeof(Options), eb_mode, predictor, mode_bt, dt_dx, dt_dy, None)
+    if selector_w is not None:
+        if not (selector_w.is_cuda and selector_w.dtype in (torch.int16, torch.bfloat16, torch.uint16)):
+            raise TypeError("selector_w must be a CUDA bf16/int16 tensor of %d values" % SELECTOR_PARAMS)
+        if selector_w.numel() != SELECTOR_PARAMS:
+            raise ValueError("selector_w must hold %d values" % SELECTOR_PARAMS)
+        o.selector_w = selector_w.data_ptr()
+    return o
+
+
+def compress_bound(H, W, T):
+    n = ctypes.c_size_t()
+    _check(lib().cpt_compress_bound(H, W, T, ctypes.byref(n)))
+    return n.value
+
+
+def compress(field, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
+             selector_w=None, out=None):
+    """Compress ``field`` (2,T,H,W float32 CUDA) under bound ``eb``; returns the
+    stream as a uint8 CUDA tensor (a view of ``out`` when given)."""
+    f = _field(field)
+    _, T, H, W = f.shape
+    if out is None:
+        out = torch.empty(compress_bound(H, W, T), dtype=torch.uint8, device=f.device)
+    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w)
+    n = ctypes.c_size_t()
+    _check(lib().cpt_compress(_ptr(f), H, W, T, eb, ctypes.byref(o), _ptr(out), out.numel(),
+                              ctypes.byref(n), _stream()))
+    return out[:n.value]
+
+
+def compress_debug(field, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
+                   selector_w=None):
+    """Compress and also return per-vertex bounds, bound codes, residual codes,
+    per-block predictor classes and selector features."""
+    f = _field(field)
+    _, T, H, W = f.shape
+    N = T * H * W
+    dev = f.device
+    out = torch.empty(compress_bound(H, W, T), dtype=torch.uint8, device=dev)
+    nbmax = T * ((H + 15) // 16) * ((W + 15) // 16)
+    xi = torch.empty(N, dtype=torch.int32, device=dev)
+    xcode = torch.empty(N, dtype=torch.uint8, device=dev)
+    qcode = torch.empty(N, dtype=torch.int32, device=dev)
+    modes = torch.zeros(max(nbmax, 1), dtype=torch.uint8, device=dev)
+    feats = torch.zeros((max(nbmax, 1), 10), dtype=torch.float32, device=dev)
+    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w)
+    n, nb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().cpt_compress_debug(_ptr(f), H, W, T, eb, ctypes.byref(o), _ptr(out), out.numel(),
+                                    ctypes.byref(n), _ptr(xi), _ptr(xcode), _ptr(qcode), _ptr(modes),
+                                    _ptr(feats), ctypes.byref(nb), _stream()))
+    return out[:n.value], dict(xi=xi, xcode=xcode, qcode=qcode, modes=modes[:nb.value],
+                               feats=feats[:nb.value])
+
+
+def stream_info(stream_bytes):
+    """Header fields of a stream (CUDA or CPU uint8 tensor)."""
+    head = stream_bytes[:256].cpu().contiguous()
+    info = Info()
+    _check(lib().cpt_stream_info(ctypes.c_void_p(head.data_ptr()), stream_bytes.numel(),
+                                 ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in Info._fields_}
+
+
+def decompress(stream_bytes, out=None):
+    """Decompress a stream (uint8 CUDA tensor) into a (2,T,H,W) float32 tensor."""
+    if not (stream_bytes.is_cuda and stream_bytes.dtype == torch.uint8):
+        raise TypeError("stream must be a uint8 CUDA tensor")
+    b = stream_bytes.contiguous()
+    info = stream_info(b)
+    if out is None:
+        out = torch.empty((2, info["T"], info["H"], info["W"]), dtype=torch.float32, device=b.device)
+    _check(lib().cpt_decompress(_ptr(b), b.numel(), _ptr(out), _stream()))
+    return out
+
+
+def extract_trajectories(field, k):
+    """Crossed space-time faces (sorted int64 codes ((g*12+type)<<1)|sign) of
+    ``field`` on the fixed-point grid 2^k."""
+    f = _field(field)
+    _, T, H, W = f.shape
+    cnt = ctypes.c_size_t()
+    st = lib().cpt_extract_trajectories(_ptr(f), H, W, T, k, None, 0, ctypes.byref(cnt), _stream())
+    if st not in (OK, ECAPACITY):
+        _check(st)
+    codes = torch.empty(max(cnt.value, 1), dtype=torch.int64, device=f.device)
+    _check(lib().cpt_extract_trajectories(_ptr(f), H, W, T, k, _ptr(codes), codes.numel(),
+                                          ctypes.byref(cnt), _stream()))
+    return codes[:cnt.value]
+
+
+def verify(a, b, k):
+    """False-case counts per slice / slab, max error and PSNR of b against a."""
+    fa, fb = _field(a), _field(b)
+    _, T, H, W = fa.shape
+    r = VerifyResult()
+    _check(lib().cpt_verify(_ptr(fa), _ptr(fb), H, W, T, k, ctypes.byref(r), _stream()))
+    return dict(fc_t=r.fc_t, fc_s=r.fc_s, max_err=r.max_err, psnr=r.psnr)
+
+
+def field_params(field, eb, eb_mode=0):
+    """(k, eb_abs, eps') the compressor derives for ``field`` and ``eb``."""
+    f = _field(field)
+    _, T, H, W = f.shape
+    k, ea, eps = ctypes.c_int(), ctypes.c_double(), ctypes.c_int64()
+    _check(lib().cpt_field_params(_ptr(f), H, W, T, eb_mode, eb, ctypes.byref(k), ctypes.byref(ea),
+                                  ctypes.byref(eps), _stream()))
+    return k.value, ea.value, eps.value

@@ -1,0 +1,192 @@
+// cpt_device.hpp — device-side constants and exact integer helpers shared by
+// the HIP kernels of libcptraj.
+//
+// Method: "Time-Varying Vector Field Compression with Preserved Critical
+// Point Trajectories" (arXiv 2510.25143).  Every predicate below is exact:
+// values are 25-bit fixed-point integers, so every 2x2 determinant (< 2^50)
+// and every sum of three (< 2^52) is an exact fp64 value, and fp64 FMA runs
+// at full vector rate on CDNA4 where 64-bit integer multiply does not.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cpt {
+
+constexpr int TILE = 16;         // spatial block edge (blocking and mode choice)
+constexpr int QR = 512;          // residual quantization radius
+constexpr int QSYM = 2 * QR;     // residual code alphabet, code 0 = unpredictable
+constexpr int XSYM = 25;         // bound code alphabet, 24 = lossless
+constexpr int XLOSSLESS = 24;
+constexpr int MAXLEN = 12;       // longest Huffman codeword
+constexpr int CHUNK = 4096;      // symbols per independently decodable chunk
+constexpr int NMAX = 32;         // maximum semi-Lagrangian substeps
+constexpr int HALO = TILE + 2;   // block plus one-vertex halo
+
+// ---------------------------------------------------------------- integers
+__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {
+  int64_t q = a / b, r = a - q * b;
+  return (r != 0 && ((r < 0) != (b < 0))) ? q - 1 : q;
+}
+__device__ __forceinline__ int floor_div32(int a, int b) {  // b > 0
+  int q = a / b;
+  return (q * b > a) ? q - 1 : q;
+}
+__device__ __forceinline__ int iabs(int a) { return a < 0 ? -a : a; }
+
+// Exact round-half-even of x * 2^k computed from the float's bits, so that
+// the result never depends on the denormal or rounding mode of the ALU.
+// Callers guarantee |x| 2^k < 2^24.
+__device__ __forceinline__ int to_fixed(float x, int k) {
+  uint32_t b = __float_as_uint(x);
+  uint32_t e = (b >> 23) & 0xFFu;
+  uint32_t m = b & 0x7FFFFFu;
+  int ex;
+  if (e == 0) {
+    ex = -149 + k;
+  } else {
+    m |= 0x800000u;
+    ex = (int)e - 150 + k;
+  }
+  int r;
+  if (ex >= 0) {
+    r = ex > 7 ? 0x7FFFFFFF : (int)(m << ex);
+  } else {
+    int sh = -ex;
+    if (sh > 25) {
+      r = 0;
+    } else {
+      uint32_t q = m >> sh, rem = m & ((1u << sh) - 1u), half = 1u << (sh - 1);
+      if (rem > half || (rem == half && (q & 1u))) q++;
+      r = (int)q;
+    }
+  }
+  return (b >> 31) ? -r : r;
+}
+
+// Exact x 2^-k for |x| < 2^25 (all results normal or zero by choice of k).
+__device__ __forceinline__ float from_fixed(int x, int k) {
+  return ldexpf((float)x, -k);
+}
+
+// ------------------------------------------------- simulation of simplicity
+// Sign of det(p~, q~) for g_p < g_q with v perturbed by eps^(2^(2g)) and u by
+// eps^(2^(2g+1)): first nonzero of (u_p v_q - v_p u_q, -u_q, v_q, u_p, 1).
+__device__ __forceinline__ int sos_sign(int up, int vp, int uq, int vq) {
+  double d = fma((double)up, (double)vq, -((double)vp * (double)uq));
+  if (d != 0.0) return d > 0.0 ? 1 : -1;
+  if (uq != 0) return uq < 0 ? 1 : -1;
+  if (vq != 0) return vq > 0 ? 1 : -1;
+  if (up != 0) return up > 0 ? 1 : -1;
+  return 1;
+}
+
+// ------------------------------------------------ error bound of one face
+// floor((N-1)/D) capped at eps, for N >= 0 an exact integer in fp64, D > 0.
+__device__ __forceinline__ int cand_capped(double N, int D, int eps) {
+  if (N == 0.0) return 0;
+  if (D <= 0) return eps;
+  double Dd = (double)D, n1 = N - 1.0;
+  if (n1 >= (double)eps * Dd) return eps;
+  int q = (int)floor(n1 / Dd);
+  double r = n1 - (double)q * Dd;
+  if (r < 0.0) q--;
+  else if (r >= Dd) q++;
+  return q;
+}
+
+// Error bound for perturbing vertex 2 of a face, min(eps, bound): the three
+// determinants M0 = det(p2,p0), M1 = det(p1,p2), M2 = det(p0,p1) and their
+// sum keep their signs for any perturbation strictly below each quotient;
+// the same-sign relaxations use |u2|-1 and |v2|-1.
+__device__ __forceinline__ int face_bound(int u0, int v0, int u1, int v1, int u2, int v2, int eps) {
+  double M0 = fma((double)u2, (double)v0, -((double)u0 * (double)v2));
+  double M1 = fma((double)u1, (double)v2, -((double)u2 * (double)v1));
+  double M2 = fma((double)u0, (double)v1, -((double)u1 * (double)v0));
+  double M = (M0 + M1) + M2;
+  if (M == 0.0) return 0;
+  int eb = cand_capped(fabs(M), iabs(u1 - u0) + iabs(v0 - v1), eps);
+  int a1 = iabs(u1) + iabs(v1);
+  if (a1 == 0) return 0;
+  eb = min(eb, cand_capped(fabs(M1), a1, eps));
+  int a0 = iabs(u0) + iabs(v0);
+  if (a0 == 0) return 0;
+  eb = min(eb, cand_capped(fabs(M0), a0, eps));
+  if ((u0 > 0 && u1 > 0 && u2 > 0) || (u0 < 0 && u1 < 0 && u2 < 0)) eb = max(eb, min(iabs(u2) - 1, eps));
+  if ((v0 > 0 && v1 > 0 && v2 > 0) || (v0 < 0 && v1 < 0 && v2 < 0)) eb = max(eb, min(iabs(v2) - 1, eps));
+  return eb;
+}
+
+// Bound code: smallest q with (eps >> q) <= xi; 24 when xi == 0.
+__device__ __forceinline__ int xi_code(int eps, int xi) {
+  if (xi <= 0) return XLOSSLESS;
+  int q = (32 - __clz(eps)) - (32 - __clz(xi));
+  if (q < 0) q = 0;
+  if ((eps >> q) > xi) q++;
+  return q;
+}
+
+// Residual quantization with bin 2 xt + 1; returns the code (0 when the
+// component is unpredictable) and writes the reconstruction.
+__device__ __forceinline__ int quantize(int x, int pred, int xt, int* recon) {
+  int num = x - pred + xt;
+  int w = 2 * xt + 1;
+  int64_t hi = (int64_t)QR * w, lo = (int64_t)(1 - QR) * w;
+  if ((int64_t)num >= hi || (int64_t)num < lo) {
+    *recon = x;
+    return 0;
+  }
+  int q = floor_div32(num, w);
+  *recon = pred + q * w;
+  return q + QR;
+}
+
+// --------------------------------------------------------- incident faces
+// The 36 faces around a vertex as pairs of neighbour offsets (dx, dy, dt),
+// each packed as ((dx+1) | (dy+1) << 2 | (dt+1) << 4).  Built from the twelve
+// face types: the lower and upper slice triangles of the main-diagonal split,
+// the two inner faces of each prism, and two faces on each side quad.
+struct FaceTable {
+  uint8_t a[36], b[36];
+  int n;
+};
+
+constexpr int FTYPE[12][3][3] = {
+    {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}}, {{0, 0, 0}, {0, 1, 0}, {1, 1, 0}},
+    {{0, 0, 0}, {1, 0, 0}, {1, 1, 1}}, {{0, 0, 0}, {1, 0, 1}, {1, 1, 1}},
+    {{0, 0, 0}, {0, 1, 0}, {1, 1, 1}}, {{0, 0, 0}, {0, 1, 1}, {1, 1, 1}},
+    {{0, 0, 0}, {1, 0, 0}, {1, 0, 1}}, {{0, 0, 0}, {0, 0, 1}, {1, 0, 1}},
+    {{0, 0, 0}, {0, 1, 0}, {0, 1, 1}}, {{0, 0, 0}, {0, 0, 1}, {0, 1, 1}},
+    {{0, 0, 0}, {1, 1, 0}, {1, 1, 1}}, {{0, 0, 0}, {0, 0, 1}, {1, 1, 1}},
+};
+
+constexpr uint8_t pack_off(int dx, int dy, int dt) {
+  return (uint8_t)((dx + 1) | ((dy + 1) << 2) | ((dt + 1) << 4));
+}
+
+constexpr FaceTable make_face_table() {
+  FaceTable T{};
+  T.n = 0;
+  for (int o = 0; o < 8; o++) {
+    int ox = o & 1, oy = (o >> 1) & 1, ot = (o >> 2) & 1;  // vertex offset inside the face
+    for (int f = 0; f < 12; f++) {
+      int hit = -1;
+      for (int i = 0; i < 3; i++)
+        if (FTYPE[f][i][0] == ox && FTYPE[f][i][1] == oy && FTYPE[f][i][2] == ot) hit = i;
+      if (hit < 0) continue;
+      int j = 0;
+      uint8_t p[2] = {0, 0};
+      for (int i = 0; i < 3; i++)
+        if (i != hit) p[j++] = pack_off(FTYPE[f][i][0] - ox, FTYPE[f][i][1] - oy, FTYPE[f][i][2] - ot);
+      T.a[T.n] = p[0];
+      T.b[T.n] = p[1];
+      T.n++;
+    }
+  }
+  return T;
+}
+
+__device__ __forceinline__ int off_dx(uint8_t p) { return (int)(p & 3) - 1; }
+__device__ __forceinline__ int off_dy(uint8_t p) { return (int)((p >> 2) & 3) - 1; }
+__device__ __forceinline__ int off_dt(uint8_t p) { return (int)((p >> 4) & 3) - 1; }
+
+}  // namespace cpt

@@ -1,0 +1,370 @@
+// k_field.hip — field-level kernels: value range, fixed-point conversion,
+// SoS edge signs, space-time face masks (critical-point extraction), lossless
+// flags, compaction of crossed faces, device-wide exclusive scan and the
+// before/after comparison.
+//
+// Extraction follows Sec. III-C/E/F of the paper: every prism over a
+// main-diagonal triangle is split into three tetrahedra; a face is crossed
+// when the origin lies in the simulated-simplicity perturbation of its three
+// vector values.  Each vertex owns twelve faces and seven edges (the three
+// spatial edges to +x, +y, +x+y, the time edge, and the three diagonals to
+// the +x, +y, +x+y vertices of the next frame); a face is decided from the
+// SoS signs of its three edges, each computed once by the edge's owner.
+#include "cpt_device.hpp"
+#include "launch.hpp"
+
+namespace cpt {
+
+// ----------------------------------------------------------------- range
+__device__ __forceinline__ int ordered_key(uint32_t b) {
+  int s = (int)b;
+  return s >= 0 ? s : (s ^ 0x7FFFFFFF);
+}
+
+__global__ void k_range_init(int* r) {
+  if (threadIdx.x == 0) {
+    r[0] = 0x7FFFFFFF;   // min key
+    r[1] = (int)0x80000000;  // max key
+    r[2] = 0;            // max |x| bits
+    r[3] = 0;            // non-finite seen
+  }
+}
+
+__global__ __launch_bounds__(256) void k_range(const float* __restrict__ x, size_t n, int* r) {
+  int mn = 0x7FFFFFFF, mx = (int)0x80000000;
+  uint32_t ma = 0, bad = 0;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint32_t b = __float_as_uint(x[i]);
+    if (((b >> 23) & 0xFFu) == 0xFFu) bad = 1;
+    int key = ordered_key(b);
+    mn = min(mn, key);
+    mx = max(mx, key);
+    ma = max(ma, b & 0x7FFFFFFFu);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = min(mn, __shfl_xor(mn, o));
+    mx = max(mx, __shfl_xor(mx, o));
+    ma = max(ma, (uint32_t)__shfl_xor((int)ma, o));
+    bad |= (uint32_t)__shfl_xor((int)bad, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&r[0], mn);
+    atomicMax(&r[1], mx);
+    atomicMax((unsigned int*)&r[2], ma);
+    if (bad) atomicOr(&r[3], 1);
+  }
+}
+
+// ------------------------------------------------------------- conversion
+__global__ __launch_bounds__(256) void k_convert(const float* __restrict__ f, size_t N, int k,
+                                                 int2* __restrict__ cur) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  cur[i] = make_int2(to_fixed(f[i], k), to_fixed(f[N + i], k));
+}
+
+// ------------------------------------------------------------- edge signs
+// bit 0..2: spatial edges to +x, +y, +x+y at t; bit 3: time edge; bits 4..6:
+// diagonals to the +x, +y, +x+y vertices at t+1.  Bit set = positive sign.
+__global__ __launch_bounds__(256) void k_edges(const int2* __restrict__ cur, int H, int W, int T,
+                                               uint8_t* __restrict__ edges) {
+  size_t HW = (size_t)H * W;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= HW * T) return;
+  int t = (int)(i / HW);
+  int r = (int)(i - (size_t)t * HW);
+  int y = r / W, x = r - y * W;
+  int2 a = cur[i];
+  bool px = x + 1 < W, py = y + 1 < H, pt = t + 1 < T;
+  uint32_t e = 0;
+  if (px) e |= (sos_sign(a.x, a.y, cur[i + 1].x, cur[i + 1].y) > 0) << 0;
+  if (py) e |= (sos_sign(a.x, a.y, cur[i + W].x, cur[i + W].y) > 0) << 1;
+  if (px && py) e |= (sos_sign(a.x, a.y, cur[i + W + 1].x, cur[i + W + 1].y) > 0) << 2;
+  if (pt) {
+    const int2* n = cur + i + HW;
+    e |= (sos_sign(a.x, a.y, n[0].x, n[0].y) > 0) << 3;
+    if (px) e |= (sos_sign(a.x, a.y, n[1].x, n[1].y) > 0) << 4;
+    if (py) e |= (sos_sign(a.x, a.y, n[W].x, n[W].y) > 0) << 5;
+    if (px && py) e |= (sos_sign(a.x, a.y, n[W + 1].x, n[W + 1].y) > 0) << 6;
+  }
+  edges[i] = (uint8_t)e;
+}
+
+// crossed iff sigma(A,B) == sigma(B,C) == -sigma(A,C) for A < B < C
+__device__ __forceinline__ uint32_t face_bits(uint32_t sab, uint32_t sbc, uint32_t sac, int f) {
+  uint32_t crossed = (sab == sbc) && (sac != sbc);
+  return crossed ? ((1u << f) | (sab << (12 + f))) : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_faces(const uint8_t* __restrict__ edges, int H, int W, int T,
+                                               uint32_t* __restrict__ masks) {
+  size_t HW = (size_t)H * W;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= HW * T) return;
+  int t = (int)(i / HW);
+  int r = (int)(i - (size_t)t * HW);
+  int y = r / W, x = r - y * W;
+  bool px = x + 1 < W, py = y + 1 < H, pt = t + 1 < T;
+  uint32_t m = 0;
+  if (!(px || py)) {
+    masks[i] = 0;
+    return;
+  }
+  uint32_t ea = edges[i];
+  uint32_t eb = px ? edges[i + 1] : 0;
+  uint32_t ec = py ? edges[i + W] : 0;
+  uint32_t ed = (px && py) ? edges[i + W + 1] : 0;
+  uint32_t ea1 = pt ? edges[i + HW] : 0;
+  uint32_t eb1 = (pt && px) ? edges[i + HW + 1] : 0;
+  uint32_t ec1 = (pt && py) ? edges[i + HW + W] : 0;
+#define B(e, k) (((e) >> (k)) & 1u)
+  if (px && py) {
+    m |= face_bits(B(ea, 0), B(eb, 1), B(ea, 2), 0);
+    m |= face_bits(B(ea, 1), B(ec, 0), B(ea, 2), 1);
+    if (pt) {
+      m |= face_bits(B(ea, 0), B(eb, 5), B(ea, 6), 2);
+      m |= face_bits(B(ea, 4), B(eb1, 1), B(ea, 6), 3);
+      m |= face_bits(B(ea, 1), B(ec, 4), B(ea, 6), 4);
+      m |= face_bits(B(ea, 5), B(ec1, 0), B(ea, 6), 5);
+      m |= face_bits(B(ea, 2), B(ed, 3), B(ea, 6), 10);
+      m |= face_bits(B(ea, 3), B(ea1, 2), B(ea, 6), 11);
+    }
+  }
+  if (px && pt) {
+    m |= face_bits(B(ea, 0), B(eb, 3), B(ea, 4), 6);
+    m |= face_bits(B(ea, 3), B(ea1, 0), B(ea, 4), 7);
+  }
+  if (py && pt) {
+    m |= face_bits(B(ea, 1), B(ec, 3), B(ea, 5), 8);
+    m |= face_bits(B(ea, 3), B(ea1, 1), B(ea, 5), 9);
+  }
+#undef B
+  masks[i] = m;
+}
+
+// --------------------------------------------------------- lossless flags
+// INC[o]: face types whose vertex set contains offset o = (ox,oy,ot) from the
+// owner; a vertex is lossless when any face through it is crossed.
+struct IncTable {
+  uint16_t m[8];
+};
+constexpr IncTable make_inc() {
+  IncTable I{};
+  for (int o = 0; o < 8; o++) {
+    uint16_t m = 0;
+    for (int f = 0; f < 12; f++)
+      for (int i = 0; i < 3; i++)
+        if (FTYPE[f][i][0] == (o & 1) && FTYPE[f][i][1] == ((o >> 1) & 1) && FTYPE[f][i][2] == ((o >> 2) & 1))
+          m |= (uint16_t)(1u << f);
+    I.m[o] = m;
+  }
+  return I;
+}
+__constant__ IncTable c_inc = make_inc();
+
+__global__ __launch_bounds__(256) void k_flags(const uint32_t* __restrict__ masks, int H, int W, int T,
+                                               uint8_t* __restrict__ flags) {
+  size_t HW = (size_t)H * W;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= HW * T) return;
+  int t = (int)(i / HW);
+  int r = (int)(i - (size_t)t * HW);
+  int y = r / W, x = r - y * W;
+  uint32_t any = 0;
+#pragma unroll
+  for (int o = 0; o < 8; o++) {
+    int ox = o & 1, oy = (o >> 1) & 1, ot = (o >> 2) & 1;
+    if (x - ox < 0 || y - oy < 0 || t - ot < 0) continue;
+    any |= masks[i - ox - (size_t)oy * W - (size_t)ot * HW] & c_inc.m[o];
+  }
+  flags[i] = any ? 1 : 0;
+}
+
+// ------------------------------------------------------------- compaction
+__global__ __launch_bounds__(256) void k_count_faces(const uint32_t* __restrict__ masks, size_t N,
+                                                     uint32_t* __restrict__ cnt) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) cnt[i] = __popc(masks[i] & 0xFFFu);
+}
+
+__global__ __launch_bounds__(256) void k_write_codes(const uint32_t* __restrict__ masks,
+                                                     const uint32_t* __restrict__ ofs, size_t N,
+                                                     uint64_t* __restrict__ codes, size_t cap) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  uint32_t m = masks[i];
+  if (!(m & 0xFFFu)) return;
+  size_t o = ofs[i];
+  for (int f = 0; f < 12; f++)
+    if (m & (1u << f)) {
+      if (o < cap) codes[o] = (((uint64_t)i * 12 + f) << 1) | ((m >> (12 + f)) & 1u);
+      o++;
+    }
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive scan of n uint32 values in three passes; blocks of 256 threads
+// own 2048 consecutive values.
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
+
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[4];
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = (uint32_t)__shfl_up((int)x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (int w = 0; w < 4; w++) {
+    if (w < wid) base += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, size_t n,
+                                                     uint32_t* __restrict__ part) {
+  size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++)
+    if (base + j < n) s += in[base + j];
+  uint32_t tot;
+  block_exclusive(s, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_partials(uint32_t* __restrict__ part, size_t nb,
+                                                       uint32_t* __restrict__ total) {
+  uint32_t carry = 0;
+  for (size_t b0 = 0; b0 < nb; b0 += 256) {
+    size_t i = b0 + threadIdx.x;
+    uint32_t v = i < nb ? part[i] : 0;
+    uint32_t tot;
+    uint32_t ex = block_exclusive(v, &tot);
+    if (i < nb) part[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, size_t n,
+                                                    const uint32_t* __restrict__ part,
+                                                    uint32_t* __restrict__ out) {
+  size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
+  uint32_t v[SCAN_ITEMS];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++) {
+    v[j] = base + j < n ? in[base + j] : 0;
+    s += v[j];
+  }
+  uint32_t tot;
+  uint32_t ex = block_exclusive(s, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++) {
+    if (base + j < n) out[base + j] = ex;
+    ex += v[j];
+  }
+}
+
+// ---------------------------------------------------------------- compare
+__global__ __launch_bounds__(256) void k_compare(const uint32_t* __restrict__ ma, const uint32_t* __restrict__ mb,
+                                                 const float* __restrict__ a, const float* __restrict__ b,
+                                                 size_t N, unsigned long long* __restrict__ fc,
+                                                 double* __restrict__ part) {
+  // part[3*block]: max |a-b|, sum (a-b)^2 (fixed order within a block)
+  __shared__ double smax[256], ssum[256];
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double dm = 0.0, ds = 0.0;
+  uint32_t ft = 0, fs = 0;
+  if (i < N) {
+    uint32_t x = ma[i] ^ mb[i];
+    uint32_t crossed = ma[i] & 0xFFFu;
+    uint32_t bad = (x & 0xFFFu) | ((x >> 12) & crossed & 0xFFFu);
+    ft = __popc(bad & 3u);
+    fs = __popc(bad & ~3u);
+    for (int c = 0; c < 2; c++) {
+      double d = fabs((double)a[c * N + i] - (double)b[c * N + i]);
+      dm = fmax(dm, d);
+      ds = fma(d, d, ds);
+    }
+  }
+  if (ft) atomicAdd(&fc[0], (unsigned long long)ft);
+  if (fs) atomicAdd(&fc[1], (unsigned long long)fs);
+  smax[threadIdx.x] = dm;
+  ssum[threadIdx.x] = ds;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+      ssum[threadIdx.x] += ssum[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = smax[0];
+    part[2 * blockIdx.x + 1] = ssum[0];
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// ============================================================ launchers
+static inline unsigned nblk(size_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+void launch_range(const float* x, size_t n, int* r, hipStream_t s) {
+  k_range_init<<<1, 64, 0, s>>>(r);
+  unsigned g = nblk(n);
+  if (g > 4096) g = 4096;
+  if (g == 0) g = 1;
+  k_range<<<g, 256, 0, s>>>(x, n, r);
+}
+void launch_convert(const float* f, size_t N, int k, int2* cur, hipStream_t s) {
+  k_convert<<<nblk(N), 256, 0, s>>>(f, N, k, cur);
+}
+void launch_masks(const int2* cur, int H, int W, int T, uint8_t* edges, uint32_t* masks, hipStream_t s) {
+  size_t N = (size_t)H * W * T;
+  k_edges<<<nblk(N), 256, 0, s>>>(cur, H, W, T, edges);
+  k_faces<<<nblk(N), 256, 0, s>>>(edges, H, W, T, masks);
+}
+void launch_flags(const uint32_t* masks, int H, int W, int T, uint8_t* flags, hipStream_t s) {
+  size_t N = (size_t)H * W * T;
+  k_flags<<<nblk(N), 256, 0, s>>>(masks, H, W, T, flags);
+}
+size_t scan_partials_size(size_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+void launch_scan(const uint32_t* in, size_t n, uint32_t* out, uint32_t* part, uint32_t* total, hipStream_t s) {
+  size_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (nb == 0) {
+    k_scan_partials<<<1, 256, 0, s>>>(part, 0, total);
+    return;
+  }
+  k_scan_reduce<<<(unsigned)nb, 256, 0, s>>>(in, n, part);
+  k_scan_partials<<<1, 256, 0, s>>>(part, nb, total);
+  k_scan_apply<<<(unsigned)nb, 256, 0, s>>>(in, n, part, out);
+}
+void launch_count_faces(const uint32_t* masks, size_t N, uint32_t* cnt, hipStream_t s) {
+  k_count_faces<<<nblk(N), 256, 0, s>>>(masks, N, cnt);
+}
+void launch_write_codes(const uint32_t* masks, const uint32_t* ofs, size_t N, uint64_t* codes, size_t cap,
+                        hipStream_t s) {
+  k_write_codes<<<nblk(N), 256, 0, s>>>(masks, ofs, N, codes, cap);
+}
+size_t compare_partials(size_t N) { return nblk(N); }
+void launch_compare(const uint32_t* ma, const uint32_t* mb, const float* a, const float* b, size_t N,
+                    unsigned long long* fc, double* part, hipStream_t s) {
+  k_zero_u64<<<1, 64, 0, s>>>(fc, 2);
+  k_compare<<<nblk(N), 256, 0, s>>>(ma, mb, a, b, N, fc, part);
+}
+
+}  // namespace cpt

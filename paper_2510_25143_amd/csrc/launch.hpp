@@ -1,0 +1,86 @@
+// launch.hpp — host-side launchers of the libcptraj kernels (one per kernel
+// family), called by the C-ABI entry points in api.cpp.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cpt {
+
+// Per-field parameters of the compressor, fixed for one stream.
+struct FieldParams {
+  int H, W, T, k;
+  int eps;          // eps' in fixed-point units
+  int tx, ty;       // blocks per row / column
+  int predictor;    // 0 Lorenzo, 1 semi-Lagrangian, 2 mix K=2, 3 mix K=4, 4 learned K=4
+  int K;            // mode classes (1, 2 or 4)
+  int bt;           // frames per mode block
+  int64_t cx, sx, cy, sy;  // semi-Lagrangian displacement factors
+};
+
+// k_field.hip
+void launch_range(const float* x, size_t n, int* r, hipStream_t s);
+void launch_convert(const float* f, size_t N, int k, int2* cur, hipStream_t s);
+void launch_masks(const int2* cur, int H, int W, int T, uint8_t* edges, uint32_t* masks, hipStream_t s);
+void launch_flags(const uint32_t* masks, int H, int W, int T, uint8_t* flags, hipStream_t s);
+size_t scan_partials_size(size_t n);
+void launch_scan(const uint32_t* in, size_t n, uint32_t* out, uint32_t* part, uint32_t* total, hipStream_t s);
+void launch_count_faces(const uint32_t* masks, size_t N, uint32_t* cnt, hipStream_t s);
+void launch_write_codes(const uint32_t* masks, const uint32_t* ofs, size_t N, uint64_t* codes, size_t cap,
+                        hipStream_t s);
+size_t compare_partials(size_t N);
+void launch_compare(const uint32_t* ma, const uint32_t* mb, const float* a, const float* b, size_t N,
+                    unsigned long long* fc, double* part, hipStream_t s);
+
+// k_compress.hip
+// mode decision for all blocks of frame t (a decision frame); modes of the
+// frame's group are written at modes + group_base.
+void launch_modes(const int2* cur, const uint8_t* flags, const FieldParams& p, int t, size_t group_base,
+                  const int64_t* tlog, const uint16_t* selw, uint8_t* modes, float* feats, hipStream_t s);
+// one colour phase of frame t; mode_base < 0 when the frame has no decided modes
+void launch_phase(int2* cur, const uint8_t* flags, const uint8_t* modes, long long mode_base,
+                  const FieldParams& p, int t, int colour, uint8_t* xcode, uint32_t* qcode, int32_t* xi_dbg,
+                  hipStream_t s);
+
+// k_entropy.hip
+struct HuffTables {
+  uint32_t code[1024];
+  uint8_t len[1024];
+};
+void launch_hist(const uint8_t* xcode, const uint32_t* qcode, size_t N, uint32_t* xhist, uint32_t* qhist,
+                 uint32_t* nonll, uint32_t* nraw, hipStream_t s);
+void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
+// codebooks for both alphabets: tables + serialized codebook sections + used counts
+void launch_codebooks(const uint32_t* xhist, const uint32_t* qhist, HuffTables* xt, HuffTables* qt,
+                      uint32_t* xcb, uint32_t* qcb, uint32_t* used, hipStream_t s);
+void launch_gather_q(const uint8_t* xcode, const uint32_t* qcode, const uint32_t* qofs, size_t N,
+                     uint16_t* qsym, hipStream_t s);
+void launch_chunk_bits_x(const uint8_t* xcode, size_t N, const HuffTables* t, uint32_t* bits, uint32_t* words,
+                         hipStream_t s);
+void launch_chunk_bits_q(const uint16_t* qsym, size_t n, const HuffTables* t, uint32_t* bits, uint32_t* words,
+                         hipStream_t s);
+void launch_encode_x(const uint8_t* xcode, size_t N, const HuffTables* t, const uint32_t* wofs, uint32_t* out,
+                     hipStream_t s);
+void launch_encode_q(const uint16_t* qsym, size_t n, const HuffTables* t, const uint32_t* wofs, uint32_t* out,
+                     hipStream_t s);
+void launch_raw(const float* field, const uint8_t* xcode, const uint32_t* qcode, const uint32_t* rofs, size_t N,
+                uint32_t* out, hipStream_t s);
+void launch_raw_count(const uint8_t* xcode, const uint32_t* qcode, size_t N, uint32_t* cnt, uint32_t* nonll,
+                      hipStream_t s);
+// decoding: build the lookup tables from a codebook section; err receives a
+// nonzero code on any inconsistency
+void launch_build_lut(const uint32_t* cb, size_t cb_words, int nsym, uint32_t* lut, uint32_t* err,
+                      hipStream_t s);
+void launch_decode(const uint32_t* lut, const uint32_t* chunk_bits, const uint32_t* wofs, const uint32_t* bs,
+                   size_t bs_words, size_t nsym_total, int alphabet, uint16_t* out, uint32_t* err, hipStream_t s);
+void launch_words_from_bits(const uint32_t* bits, size_t n, uint32_t* words, hipStream_t s);
+
+// k_decompress.hip
+void launch_dec_counts(const uint16_t* xs, const uint16_t* qs, const uint32_t* qofs, size_t N, size_t nq,
+                       int eps, uint32_t* rcnt, uint32_t* err, hipStream_t s);
+void launch_dec_nonll(const uint16_t* xs, size_t N, uint32_t* nonll, hipStream_t s);
+void launch_reconstruct(int2* cur, float* field, const uint16_t* xs, const uint16_t* qs, const uint32_t* qofs,
+                        const uint32_t* raw, const uint32_t* rofs, const uint8_t* modes, long long mode_base,
+                        const FieldParams& p, int t, uint32_t* err, hipStream_t s);
+
+}  // namespace cpt

@@ -1,0 +1,72 @@
+"""The C-ABI library loads on a machine without a GPU and exports every entry
+point its header declares (no compute calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cptraj.h")
+LIB = os.path.join(ROOT, "paper_2510_25143_amd", "libcptraj.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cpt_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(LIB):
+        from paper_2510_25143_amd import build
+        build.build()
+    return LIB
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ["cpt_compress", "cpt_decompress", "cpt_extract_trajectories", "cpt_stream_info",
+              "cpt_compress_bound", "cpt_last_error"]:
+        assert n in names
+
+
+def test_library_loads_and_exports_every_declared_symbol(built):
+    L = ctypes.CDLL(built)
+    for n in declared():
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", built], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (cpt_[a-z_0-9]+)", out))
+    assert set(declared()) <= exported
+
+
+def test_binding_names_match_the_boundary(built):
+    import paper_2510_25143_amd as cpt
+    for n in cpt.EXPORTS:
+        assert n in declared()
+    for py in ["compress", "decompress", "extract_trajectories", "stream_info", "verify",
+               "field_params", "compress_bound", "compress_debug"]:
+        assert callable(getattr(cpt, py))
+
+
+def test_stream_info_rejects_garbage_on_host(built):
+    """cpt_stream_info parses host memory only, so it runs without a GPU."""
+    import numpy as np
+    import oracle
+    import synthfields
+    import paper_2510_25143_amd as cpt
+    import torch
+    f, _ = synthfields.workload(0)
+    b = oracle.compress(f.numpy(), 1e-2)
+    info = cpt.stream_info(torch.from_numpy(b))
+    ref = oracle.stream_info(b)
+    for k in ["H", "W", "T", "k", "eps", "K", "R", "total_len", "n_q", "n_raw"]:
+        assert info[k] == ref[k]
+    bad = b.copy()
+    bad[0] ^= 1
+    with pytest.raises(cpt.CptError):
+        cpt.stream_info(torch.from_numpy(bad))
+    with pytest.raises(cpt.CptError):
+        cpt.stream_info(torch.from_numpy(b[:100].copy()))
