@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Compress+decompress throughput of libcptraj on one MI355X.
+
+A step is one cpt_compress and one cpt_decompress of the whole field, with the
+field already resident in HBM.  The metric is raw bytes / (t_c + t_d) in GB/s
+at a fixed relative bound, counted only when every space-time face keeps its
+status (FC_t = FC_s = 0) and the pointwise bound holds; CR is reported beside
+it.  Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "compress+decompress GB/s at fixed rel-eb with 100% trajectories kept; CR"
+
+WORKLOADS = {
+    "wind": dict(cfg=1, name="lat-lon-like wind 720x1440x64 float32 (u,v), spectral k^-3 + zonal jet, "
+                              "semi-Lagrangian self-advection with 1% forcing"),
+    "turbulence": dict(cfg=2, name="turbulence-like 2048x2048x32 float32 (u,v), k^-5/3 self-advected "
+                                   "+ 64 translating vortices"),
+    "vortex": dict(cfg=0, name="4 translating Lamb-Oseen vortices 64x64x8 float32 (u,v) + N(0,1e-3)"),
+}
+
+# fp64 operations of one face bound (Alg. 2): three 2x2 determinants at three
+# operations each, two additions for their sum, three bound comparisons at two
+# operations each; 36 faces per vertex.
+OPS_PER_FACE = 17
+FACES_PER_VERTEX = 36
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="wind", choices=sorted(WORKLOADS))
+    ap.add_argument("--eb", type=float, default=1e-3)
+    ap.add_argument("--predictor", type=int, default=2)
+    ap.add_argument("--mode-bt", type=int, default=1)
+    ap.add_argument("--cpu-frames", type=int, default=4, help="frames of the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also run one device copy of the field (profiler counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2510_25143_amd as cpt
+    import synthfields
+
+    torch.cuda.set_device(0)
+    cpt.lib()
+    wl = WORKLOADS[args.workload]
+    log("generating workload %s on cuda:0" % args.workload)
+    f, meta = synthfields.workload(wl["cfg"], device="cuda")
+    f = f.contiguous()
+    torch.cuda.synchronize()
+    _, T, H, W = f.shape
+    raw = f.numel() * 4
+    dt = meta["dt_dx"]
+    eb = args.eb
+    out = torch.empty(cpt.compress_bound(H, W, T), dtype=torch.uint8, device="cuda")
+    dec = torch.empty_like(f)
+
+    def comp():
+        return cpt.compress(f, eb, predictor=args.predictor, mode_bt=args.mode_bt, dt_dx=dt, dt_dy=dt, out=out)
+
+    if args.calibration_copy:
+        log("calibration copy of %d bytes" % raw)
+        g = f.clone()
+        torch.cuda.synchronize()
+        del g
+
+    log("warmup x%d" % args.warmup)
+    s = None
+    for _ in range(max(args.warmup, 1)):
+        s = comp()
+        cpt.decompress(s, out=dec)
+    torch.cuda.synchronize()
+    k, eb_abs, eps = cpt.field_params(f, eb)
+    v = cpt.verify(f, dec, k)
+    ok = v["fc_t"] == 0 and v["fc_s"] == 0 and v["max_err"] <= eb_abs
+    if not ok:
+        raise SystemExit("guarantee violated: %s (eb_abs %g)" % (v, eb_abs))
+    clen = s.numel()
+    log("stream %d bytes, CR %.3f, FC_t %d FC_s %d, max err %.3g <= %.3g" %
+        (clen, raw / clen, v["fc_t"], v["fc_s"], v["max_err"], eb_abs))
+
+    log("timed x%d" % args.steps)
+    cpt.timing_enable(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        s = comp()
+        ev[i][1].record()
+        cpt.decompress(s, out=dec)
+        ev[i][2].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    tc = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    td = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
+    fam = {name: cpt.timing_read(name) for name in cpt.TIMING_FAMILIES}
+    cpt.timing_enable(False)
+    value = args.steps * raw / elapsed / 1e9
+
+    ms, n, units = fam["phase"]
+    avg_ms = ms / max(n, 1)
+    per_launch = units / max(n, 1)
+    achieved = OPS_PER_FACE * FACES_PER_VERTEX * per_launch / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None, "kernel": "k_phase",
+                "avg_launch_us": round(avg_ms * 1e3, 3), "vertices_per_launch": round(per_launch, 1),
+                "ops_per_vertex": OPS_PER_FACE * FACES_PER_VERTEX}
+    kernels = {name: {"ms_per_step": round(m / args.steps, 4), "launches_per_step": c // max(args.steps, 1)}
+               for name, (m, c, _) in fam.items() if c}
+
+    result = {
+        "metric": METRIC, "value": round(value, 4), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i32+f64(exact)", "data": "synthetic",
+        "config": {"workload": wl["name"], "shape_T_H_W": [T, H, W], "raw_bytes": raw, "eb_rel": eb,
+                   "eb_abs": eb_abs, "predictor": args.predictor, "mode_bt": args.mode_bt,
+                   "CR": round(raw / clen, 4), "stream_bytes": clen, "fc_t": v["fc_t"], "fc_s": v["fc_s"],
+                   "max_err": v["max_err"], "psnr": round(v["psnr"], 3),
+                   "compress_ms": round(tc, 4), "decompress_ms": round(td, 4),
+                   "compress_GBps": round(raw / tc / 1e6, 3), "decompress_GBps": round(raw / td / 1e6, 3),
+                   "kernels": kernels},
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        import numpy as np
+        import oracle
+        S = min(args.cpu_frames, T)
+        sample = f[:, :S].cpu().numpy()
+        log("CPU baseline: oracle on %d of %d frames (%dx%d)" % (S, T, H, W))
+        c0 = time.perf_counter()
+        b = oracle.compress(sample, eb, predictor=args.predictor, mode_bt=args.mode_bt, dt_dx=dt, dt_dy=dt)
+        c1 = time.perf_counter()
+        oracle.decompress(b)
+        c2 = time.perf_counter()
+        sraw = sample.size * 4
+        result["cpu_baseline"] = {
+            "value": round(sraw / (c2 - c0) / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d frames of the same field at full %dx%d resolution (%d bytes); "
+                      "compress %.2f s + decompress %.2f s, single thread" % (S, T, H, W, sraw, c1 - c0, c2 - c1)}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -144,6 +144,16 @@ cpt_status cpt_verify(const float* a, const float* b, int H, int W, int T, int k
 cpt_status cpt_field_params(const float* field, int H, int W, int T, int eb_mode, double eb, int* k,
                             double* eb_abs, int64_t* eps, void* stream);
 
+/* Kernel timing for benchmarks.  cpt_timing_enable(1) resets the counters
+ * and brackets every launch of the main kernel families with HIP events on
+ * the caller's stream; cpt_timing_read returns the accumulated device time,
+ * the number of launches and the work units (vertices or symbols) they
+ * covered.  Families: 0 per-vertex bound/predict/quantize phase, 1 predictor
+ * choice, 2 frame reconstruction, 3 Huffman decoding, 4 Huffman encoding,
+ * 5 face extraction.  Process-wide; not for concurrent callers. */
+cpt_status cpt_timing_enable(int on);
+cpt_status cpt_timing_read(int family, double* total_ms, uint64_t* launches, uint64_t* units);
+
 /* Message of the last failure on this thread. */
 const char* cpt_last_error(void);
 

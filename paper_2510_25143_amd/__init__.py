@@ -47,7 +47,7 @@ class VerifyResult(ctypes.Structure):
 
 EXPORTS = ["cpt_compress_bound", "cpt_compress", "cpt_compress_debug", "cpt_stream_info",
            "cpt_decompress", "cpt_extract_trajectories", "cpt_verify", "cpt_field_params",
-           "cpt_last_error"]
+           "cpt_timing_enable", "cpt_timing_read", "cpt_last_error"]
 
 _lib = None
 
@@ -70,6 +70,8 @@ def lib():
         "cpt_extract_trajectories": [P, i32, i32, i32, i32, P, sz, P, P],
         "cpt_verify": [P, P, i32, i32, i32, i32, P, P],
         "cpt_field_params": [P, i32, i32, i32, i32, dbl, P, P, P, P],
+        "cpt_timing_enable": [i32],
+        "cpt_timing_read": [i32, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -211,3 +213,18 @@ def field_params(field, eb, eb_mode=0):
     _check(lib().cpt_field_params(_ptr(f), H, W, T, eb_mode, eb, ctypes.byref(k), ctypes.byref(ea),
                                   ctypes.byref(eps), _stream()))
     return k.value, ea.value, eps.value
+
+
+TIMING_FAMILIES = {"phase": 0, "modes": 1, "reconstruct": 2, "decode": 3, "encode": 4, "extract": 5}
+
+
+def timing_enable(on=True):
+    """Bracket the main kernel launches with HIP events (resets counters)."""
+    _check(lib().cpt_timing_enable(1 if on else 0))
+
+
+def timing_read(family):
+    """(total ms, launches, units) accumulated for a kernel family."""
+    ms, n, u = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().cpt_timing_read(TIMING_FAMILIES[family], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(u)))
+    return ms.value, n.value, u.value

@@ -288,6 +288,87 @@ unsigned nb256(size_t n) { return (unsigned)((n + 255) / 256); }
 
 int mode_bits(int K) { return K == 4 ? 2 : (K == 2 ? 1 : 0); }
 
+// ------------------------------------------------------------ kernel timing
+// When enabled, launches of the main kernel families are bracketed by HIP
+// events on the caller's stream; elapsed times are harvested after the
+// call's final synchronisation.
+enum { FAM_PHASE = 0, FAM_MODES = 1, FAM_RECON = 2, FAM_DECODE = 3, FAM_ENCODE = 4, FAM_EXTRACT = 5, NFAM = 6 };
+
+struct Timing {
+  bool on = false;
+  std::mutex mu;
+  std::vector<hipEvent_t> pool;
+  struct Rec {
+    int fam;
+    hipEvent_t a, b;
+    uint64_t units;
+  };
+  std::vector<Rec> pending;
+  double ms[NFAM] = {0};
+  uint64_t launches[NFAM] = {0}, units[NFAM] = {0};
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void harvest() {
+    for (auto& r : pending) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.fam] += t;
+        launches[r.fam] += 1;
+        units[r.fam] += r.units;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+};
+Timing g_tim;
+
+struct TimeScope {
+  int fam;
+  uint64_t units;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  TimeScope(int f, uint64_t u, hipStream_t st) : fam(f), units(u), s(st) {
+    if (!g_tim.on) return;
+    std::lock_guard<std::mutex> lk(g_tim.mu);
+    a = g_tim.get();
+    (void)hipEventRecord(a, s);
+  }
+  ~TimeScope() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_tim.mu);
+    hipEvent_t b = g_tim.get();
+    (void)hipEventRecord(b, s);
+    g_tim.pending.push_back({fam, a, b, units});
+  }
+};
+
+void harvest_timing() {
+  if (!g_tim.on) return;
+  std::lock_guard<std::mutex> lk(g_tim.mu);
+  g_tim.harvest();
+}
+
+// vertices of colour c in one frame
+uint64_t colour_vertices(int H, int W, int c) {
+  int tx = (W + TILE - 1) / TILE, ty = (H + TILE - 1) / TILE;
+  uint64_t n = 0;
+  for (int by = 0; by < ty; by++)
+    for (int bx = 0; bx < tx; bx++)
+      if ((bx + by) % 3 == c) n += (uint64_t)std::min(TILE, W - bx * TILE) * std::min(TILE, H - by * TILE);
+  return n;
+}
+
 // ------------------------------------------------------------ compress
 cpt_status compress_impl(const float* field, int H, int W, int T, double eb, const cpt_options* opt_in,
                          uint8_t* out, size_t cap, size_t* out_len, int32_t* xi_dbg, uint8_t* xcode_dbg,
@@ -346,18 +427,27 @@ cpt_status compress_impl(const float* field, int H, int W, int T, double eb, con
 
   // Alg. 3: fixed point, crossed faces of the original field, lossless flags
   launch_convert(field, N, p.k, b.cur, s);
-  launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
+  {
+    TimeScope ts(FAM_EXTRACT, N, s);
+    launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
+  }
   launch_flags(b.masks, H, W, T, b.flags, s);
 
+  uint64_t cv[3] = {colour_vertices(H, W, 0), colour_vertices(H, W, 1), colour_vertices(H, W, 2)};
   for (int t = 0; t < T; t++) {
     int g = t / bt;
     bool dec = K > 1 && group_decided(g, bt, T);
     int td = g * bt > 1 ? g * bt : 1;
     size_t gbase = dec ? (size_t)decided_before(g, bt, T) * tx * ty : 0;
-    if (dec && t == td)
+    if (dec && t == td) {
+      TimeScope ts(FAM_MODES, (uint64_t)H * W, s);
       launch_modes(b.cur, b.flags, p, t, gbase, A.tlog, opt.selector_w, b.modes, feats_dbg, s);
+    }
     long long mbase = (dec && t >= 1) ? (long long)gbase : -1;
-    for (int c = 0; c < 3; c++) launch_phase(b.cur, b.flags, b.modes, mbase, p, t, c, b.xcode, b.qcode, xi_dbg, s);
+    for (int c = 0; c < 3; c++) {
+      TimeScope ts(FAM_PHASE, cv[c], s);
+      launch_phase(b.cur, b.flags, b.modes, mbase, p, t, c, b.xcode, b.qcode, xi_dbg, s);
+    }
   }
 
   // lossless_comp of Alg. 3: Huffman codes of both code streams, raw values
@@ -401,10 +491,16 @@ cpt_status compress_impl(const float* field, int H, int W, int T, double eb, con
   if (mwords) k_pack_modes<<<nb256(mwords), 256, 0, s>>>(b.modes, nblk, mb, (uint32_t*)(out + off[0]), mwords);
   HIPCHK(hipMemcpyAsync(out + off[1], b.xcb, sec[1], hipMemcpyDeviceToDevice, s));
   if (sec[2]) HIPCHK(hipMemcpyAsync(out + off[2], b.xbits, sec[2], hipMemcpyDeviceToDevice, s));
-  launch_encode_x(b.xcode, N, b.xt, b.xwofs, (uint32_t*)(out + off[3]), s);
+  {
+    TimeScope ts(FAM_ENCODE, N, s);
+    launch_encode_x(b.xcode, N, b.xt, b.xwofs, (uint32_t*)(out + off[3]), s);
+  }
   HIPCHK(hipMemcpyAsync(out + off[4], b.qcb, sec[4], hipMemcpyDeviceToDevice, s));
   if (sec[5]) HIPCHK(hipMemcpyAsync(out + off[5], b.qbits, sec[5], hipMemcpyDeviceToDevice, s));
-  launch_encode_q(b.qsym, nq, b.qt, b.qwofs, (uint32_t*)(out + off[6]), s);
+  {
+    TimeScope ts(FAM_ENCODE, nq, s);
+    launch_encode_q(b.qsym, nq, b.qt, b.qwofs, (uint32_t*)(out + off[6]), s);
+  }
   launch_raw(field, b.xcode, b.qcode, b.rofs, N, (uint32_t*)(out + off[7]), s);
   Header hd;
   uint64_t ebits;
@@ -422,6 +518,7 @@ cpt_status compress_impl(const float* field, int H, int W, int T, double eb, con
   if (modes_dbg && nblk) HIPCHK(hipMemcpyAsync(modes_dbg, b.modes, nblk, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
+  harvest_timing();
   return CPT_OK;
 }
 
@@ -530,12 +627,18 @@ cpt_status decompress_impl(const uint8_t* bytes, size_t len, float* field, hipSt
   launch_build_lut(sec32(4), P.sec[4] / 4, QSYM, b.qlut, b.err, s);
   launch_words_from_bits(sec32(2), nchx, b.xwords, s);
   launch_scan(b.xwords, nchx, b.xwofs, b.part, b.tot + 0, s);
-  launch_decode(b.xlut, sec32(2), b.xwofs, sec32(3), P.sec[3] / 4, N, XSYM, b.xs, b.err, s);
+  {
+    TimeScope ts(FAM_DECODE, N, s);
+    launch_decode(b.xlut, sec32(2), b.xwofs, sec32(3), P.sec[3] / 4, N, XSYM, b.xs, b.err, s);
+  }
   launch_dec_nonll(b.xs, N, b.nonll, s);
   launch_scan(b.nonll, N, b.qofs, b.part, b.tot + 1, s);
   launch_words_from_bits(sec32(5), nchq, b.qwords, s);
   launch_scan(b.qwords, nchq, b.qwofs, b.part, b.tot + 2, s);
-  launch_decode(b.qlut, sec32(5), b.qwofs, sec32(6), P.sec[6] / 4, nq, QSYM, b.qs, b.err, s);
+  {
+    TimeScope ts(FAM_DECODE, nq, s);
+    launch_decode(b.qlut, sec32(5), b.qwofs, sec32(6), P.sec[6] / 4, nq, QSYM, b.qs, b.err, s);
+  }
   launch_dec_counts(b.xs, b.qs, b.qofs, N, nq, (int)I.eps, b.rcnt, b.err, s);
   launch_scan(b.rcnt, N, b.rofs, b.part, b.tot + 3, s);
   HIPCHK(hipMemcpyAsync(A.host, b.tot, 16, hipMemcpyDeviceToHost, s));
@@ -564,11 +667,13 @@ cpt_status decompress_impl(const uint8_t* bytes, size_t len, float* field, hipSt
     int g = t / bt;
     bool dec = K > 1 && group_decided(g, bt, T);
     long long mbase = (dec && t >= 1) ? (long long)decided_before(g, bt, T) * tx * ty : -1;
+    TimeScope ts(FAM_RECON, (uint64_t)H * W, s);
     launch_reconstruct(b.cur, field, b.xs, b.qs, b.qofs, sec32(7), b.rofs, b.modes, mbase, p, t, b.err, s);
   }
   HIPCHK(hipMemcpyAsync(A.host, b.err, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
+  harvest_timing();
   if (h32[0]) return fail(CPT_ECORRUPT, "reconstruction failed a check (code " + std::to_string(h32[0]) + ")");
   return CPT_OK;
 }
@@ -579,6 +684,26 @@ cpt_status decompress_impl(const uint8_t* bytes, size_t len, float* field, hipSt
 extern "C" {
 
 const char* cpt_last_error(void) { return g_err.c_str(); }
+
+cpt_status cpt_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_tim.mu);
+  g_tim.on = on != 0;
+  for (int i = 0; i < NFAM; i++) {
+    g_tim.ms[i] = 0;
+    g_tim.launches[i] = 0;
+    g_tim.units[i] = 0;
+  }
+  return CPT_OK;
+}
+
+cpt_status cpt_timing_read(int family, double* total_ms, uint64_t* launches, uint64_t* units) {
+  if (family < 0 || family >= NFAM || !total_ms || !launches || !units) return fail(CPT_EINVAL, "bad timing query");
+  std::lock_guard<std::mutex> lk(g_tim.mu);
+  *total_ms = g_tim.ms[family];
+  *launches = g_tim.launches[family];
+  *units = g_tim.units[family];
+  return CPT_OK;
+}
 
 cpt_status cpt_compress_bound(int H, int W, int T, size_t* max_bytes) {
   if (!max_bytes) return fail(CPT_EINVAL, "null max_bytes");
