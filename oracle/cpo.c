@@ -38,7 +38,7 @@
 #define XSYM 25          /* bound-code alphabet; 24 = lossless */
 #define XLOSSLESS 24
 #define MAXLEN 12        /* longest Huffman codeword */
-#define CHUNK 4096       /* symbols per independently decodable chunk */
+#define CHUNK 1024       /* symbols per independently decodable chunk */
 #define STRIDE 2         /* micro-encoding statistics subsample (Sec. VI-B) */
 #define NMAX 32          /* maximum substeps, Sec. VI-A */
 #define HDR_SLOTS 32

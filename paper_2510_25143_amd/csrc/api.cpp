@@ -6,7 +6,7 @@
 // followed by eight sections, each a whole number of 32-bit words:
 //   0 predictor classes of the decided blocks, bit-packed LSB-first
 //   1 bound-code codebook      (count, then symbol | length << 16 per used symbol)
-//   2 bound-code chunk table   (bits per 4096-symbol chunk)
+//   2 bound-code chunk table   (bits per 1024-symbol chunk)
 //   3 bound-code bitstream     (MSB-first words, every chunk word-aligned)
 //   4..6 the same three for the residual codes
 //   7 raw float32 values of lossless vertices and unpredictable components

@@ -18,7 +18,7 @@ constexpr int QSYM = 2 * QR;     // residual code alphabet, code 0 = unpredictab
 constexpr int XSYM = 25;         // bound code alphabet, 24 = lossless
 constexpr int XLOSSLESS = 24;
 constexpr int MAXLEN = 12;       // longest Huffman codeword
-constexpr int CHUNK = 4096;      // symbols per independently decodable chunk
+constexpr int CHUNK = 1024;      // symbols per independently decodable chunk
 constexpr int NMAX = 32;         // maximum semi-Lagrangian substeps
 constexpr int HALO = TILE + 2;   // block plus one-vertex halo
 
@@ -82,16 +82,23 @@ __device__ __forceinline__ int sos_sign(int up, int vp, int uq, int vq) {
 
 // ------------------------------------------------ error bound of one face
 // floor((N-1)/D) capped at eps, for N >= 0 an exact integer in fp64, D > 0.
+// The quotient (< 2^23) is estimated with the hardware reciprocal and then
+// corrected exactly: every product below is an integer under 2^50.
 __device__ __forceinline__ int cand_capped(double N, int D, int eps) {
   if (N == 0.0) return 0;
   if (D <= 0) return eps;
   double Dd = (double)D, n1 = N - 1.0;
   if (n1 >= (double)eps * Dd) return eps;
-  int q = (int)floor(n1 / Dd);
+  int q = (int)(n1 * __builtin_amdgcn_rcp(Dd));
   double r = n1 - (double)q * Dd;
   if (r < 0.0) q--;
   else if (r >= Dd) q++;
   return q;
+}
+
+// exact 2x2 determinant u_a v_b - v_a u_b of 25-bit integers
+__device__ __forceinline__ double det2(int2 a, int2 b) {
+  return fma((double)a.x, (double)b.y, -((double)a.y * (double)b.x));
 }
 
 // Error bound for perturbing vertex 2 of a face, min(eps, bound): the three
@@ -116,6 +123,23 @@ __device__ __forceinline__ int face_bound(int u0, int v0, int u1, int v1, int u2
   return eb;
 }
 
+// Minimum over each row of 16 lanes (DPP row rotations; every lane of the
+// row receives the result).
+__device__ __forceinline__ int row16_min(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false));  // row_ror:8
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, false));  // row_ror:4
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x122, 0xF, 0xF, false));  // row_ror:2
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x121, 0xF, 0xF, false));  // row_ror:1
+  return v;
+}
+
+// Minimum over each quad of 4 lanes (DPP quad permutations).
+__device__ __forceinline__ int quad_min(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));  // quad_perm [2,3,0,1]
+  return v;
+}
+
 // Bound code: smallest q with (eps >> q) <= xi; 24 when xi == 0.
 __device__ __forceinline__ int xi_code(int eps, int xi) {
   if (xi <= 0) return XLOSSLESS;
@@ -126,7 +150,8 @@ __device__ __forceinline__ int xi_code(int eps, int xi) {
 }
 
 // Residual quantization with bin 2 xt + 1; returns the code (0 when the
-// component is unpredictable) and writes the reconstruction.
+// component is unpredictable) and writes the reconstruction.  The quotient
+// (|q| < 512) is estimated in fp32 and corrected exactly.
 __device__ __forceinline__ int quantize(int x, int pred, int xt, int* recon) {
   int num = x - pred + xt;
   int w = 2 * xt + 1;
@@ -135,7 +160,10 @@ __device__ __forceinline__ int quantize(int x, int pred, int xt, int* recon) {
     *recon = x;
     return 0;
   }
-  int q = floor_div32(num, w);
+  int q = (int)floorf((float)num * __builtin_amdgcn_rcpf((float)w));
+  int r = num - q * w;
+  if (r < 0) q--;
+  else if (r >= w) q++;
   *recon = pred + q * w;
   return q + QR;
 }

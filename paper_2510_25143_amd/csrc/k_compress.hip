@@ -91,10 +91,8 @@ __global__ __launch_bounds__(256) void k_modes(const int2* __restrict__ cur, con
                                                float* __restrict__ feats) {
   __shared__ int2 C[TILE][TILE];
   __shared__ int2 P[TILE][TILE];
-  __shared__ uint32_t hist[QSYM];
   __shared__ int64_t red[256];
   __shared__ int64_t R[4];
-  __shared__ int sn, sL;
   __shared__ float fin[10];
   __shared__ float h1[64], h2[64], lg[4];
 
@@ -202,50 +200,88 @@ __global__ __launch_bounds__(256) void k_modes(const int2* __restrict__ cur, con
   }
 
   // ---------------- exhaustive trial over the K candidates
-  for (int cls = 0; cls < p.K; cls++) {
-    for (int b = tid; b < QSYM; b += 256) hist[b] = 0;
-    if (tid == 0) {
-      sn = 0;
-      sL = 0;
-    }
-    C[ly][lx] = X;
-    __syncthreads();
-    int qu = 0, qv = 0;
-    if (cls == 0) {
-      for (int d = 0; d < 2 * TILE - 1; d++) {
-        if (valid && lx + ly == d) {
-          int pu = lorenzo_local(C, P, lx, ly, true, 0), pv = lorenzo_local(C, P, lx, ly, true, 1);
-          int ru, rv;
-          qu = quantize(X.x, pu, eps, &ru);
-          qv = quantize(X.y, pv, eps, &rv);
-          C[ly][lx] = make_int2(ru, rv);
-        }
-        __syncthreads();
+  // Lorenzo: wave 0 sweeps the anti-diagonals (lanes 0-15 u rows, 16-31 v
+  // rows) writing reconstructions into the candidate buffer; semi-Lagrangian
+  // candidates are computed by every thread for its own vertex.  Codes of
+  // the stride-2 subgrid go to SAMP[class][0..127] (slot 2 i + component of
+  // subgrid point i; -1 when absent).
+  __shared__ int CU[2][TILE][TILE];
+  __shared__ int SAMP[4][128];
+  for (int i = tid; i < 4 * 128; i += 256) (&SAMP[0][0])[i] = -1;
+  CU[0][ly][lx] = X.x;
+  CU[1][ly][lx] = X.y;
+  __syncthreads();
+  if (tid < 2 * TILE) {
+    const int c = tid >> 4, row = tid & 15;
+    for (int d = 0; d < 2 * TILE - 1; d++) {
+      const int col = d - row;
+      if (col >= 0 && col < TILE && x0 + col < W && y0 + row < H) {
+        int s = (col > 0 ? CU[c][row][col - 1] : 0) + (row > 0 ? CU[c][row - 1][col] : 0) -
+                (col > 0 && row > 0 ? CU[c][row - 1][col - 1] : 0);
+        const int2 pc = P[row][col];
+        const int2 pl = col > 0 ? P[row][col - 1] : make_int2(0, 0);
+        const int2 pu = row > 0 ? P[row - 1][col] : make_int2(0, 0);
+        const int2 plu = (col > 0 && row > 0) ? P[row - 1][col - 1] : make_int2(0, 0);
+        s += c ? (pc.y - pl.y - pu.y + plu.y) : (pc.x - pl.x - pu.x + plu.x);
+        const int2 xv = C[row][col];
+        int rec;
+        const int q = quantize(c ? xv.y : xv.x, s, eps, &rec);
+        CU[c][row][col] = rec;
+        if (((row | col) & 1) == 0) SAMP[0][2 * ((row >> 1) * 8 + (col >> 1)) + c] = q;
       }
-    } else if (valid) {
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
+  }
+  if (valid) {
+    for (int cls = 1; cls < p.K; cls++) {
+      const bool sub = ((lx | ly) & 1) == 0;
+      if (!sub) continue;
       int pu, pv, ru, rv;
       sl_predict(pf, H, W, x, y, slc, class_dmax(p.K, cls), &pu, &pv);
-      qu = quantize(X.x, pu, eps, &ru);
-      qv = quantize(X.y, pv, eps, &rv);
+      const int slot = 2 * ((ly >> 1) * 8 + (lx >> 1));
+      SAMP[cls][slot] = quantize(X.x, pu, eps, &ru);
+      SAMP[cls][slot + 1] = quantize(X.y, pv, eps, &rv);
     }
-    if (valid && (lx & 1) == 0 && (ly & 1) == 0) {
-      if (qu == 0) atomicAdd(&sL, 1);
-      else {
-        atomicAdd(&hist[qu], 1u);
-        atomicAdd(&sn, 1);
+  }
+  __syncthreads();
+  // rate score per candidate: thread (class, sample) counts the equal codes;
+  // the first occurrence of a code adds T[count]
+  for (int c0 = 0; c0 < p.K; c0 += 2) {
+    const int cls = c0 + (tid >> 7), i = tid & 127;
+    int64_t tsum = 0, nvalid = 0, nover = 0;
+    if (cls < p.K) {
+      const int v = SAMP[cls][i];
+      if (v > 0) {
+        int cnt = 0;
+        bool first = true;
+        for (int jj = 0; jj < 128; jj++) {
+          const int w2 = SAMP[cls][jj];
+          cnt += w2 == v;
+          first &= !(w2 == v && jj < i);
+        }
+        if (first) tsum = tlog[cnt];
+        nvalid = 1;
+      } else if (v == 0) {
+        nover = 1;
       }
-      if (qv == 0) atomicAdd(&sL, 1);
-      else {
-        atomicAdd(&hist[qv], 1u);
-        atomicAdd(&sn, 1);
-      }
+    }
+    // reduce over the 128 threads of this class (two waves)
+    for (int o = 32; o > 0; o >>= 1) {
+      tsum += __shfl_xor(tsum, o);
+      nvalid += __shfl_xor(nvalid, o);
+      nover += __shfl_xor(nover, o);
+    }
+    __shared__ int64_t part[4][3];
+    if ((tid & 63) == 0) {
+      part[tid >> 6][0] = tsum;
+      part[tid >> 6][1] = nvalid;
+      part[tid >> 6][2] = nover;
     }
     __syncthreads();
-    int64_t ts = 0;
-    for (int b = tid; b < QSYM; b += 256) ts += tlog[hist[b]];
-    ts = block_reduce(ts, red, [](int64_t a, int64_t b) { return a + b; });
-    if (tid == 0) {
-      int64_t n = sn, L = sL;
+    if ((tid & 127) == 0 && cls < p.K) {
+      const int w0 = (tid >> 6);
+      int64_t ts = part[w0][0] + part[w0 + 1][0], n = part[w0][1] + part[w0 + 1][1], L = part[w0][2] + part[w0 + 1][2];
       int64_t h0 = n > 0 ? floor_div64(tlog[n] - ts, n) : 0;
       int64_t pen = (n + L) > 0 ? floor_div64((int64_t)16 * 65536 * L, n + L) : 0;
       int64_t lgK = p.K == 4 ? 2 : 1;
@@ -264,13 +300,109 @@ __global__ __launch_bounds__(256) void k_modes(const int2* __restrict__ cur, con
 }
 
 // --------------------------------------------------------------- the phase
-__global__ __launch_bounds__(256) void k_phase(int2* __restrict__ cur, const uint8_t* __restrict__ flags,
+// The 14 space-time neighbours of a vertex; the first three are the raster
+// predecessors inside the block (they change during the sweep).
+struct NbrTable {
+  int8_t dx[14], dy[14], dt[14];
+};
+constexpr NbrTable NBR = {{-1, 0, -1, 1, 0, 1, 0, -1, 0, -1, 0, 1, 0, 1},
+                          {0, -1, -1, 0, 1, 1, 0, 0, -1, -1, 0, 0, 1, 1},
+                          {0, 0, 0, 0, 0, 0, -1, -1, -1, -1, 1, 1, 1, 1}};
+
+constexpr int nbr_index(uint8_t packed) {
+  for (int j = 0; j < 14; j++)
+    if (pack_off(NBR.dx[j], NBR.dy[j], NBR.dt[j]) == packed) return j;
+  return -1;
+}
+struct PairTable {
+  int8_t a[36], b[36];
+};
+constexpr PairTable make_pairs() {
+  PairTable P{};
+  FaceTable T = make_face_table();
+  for (int f = 0; f < 36; f++) {
+    P.a[f] = (int8_t)nbr_index(T.a[f]);
+    P.b[f] = (int8_t)nbr_index(T.b[f]);
+  }
+  return P;
+}
+constexpr PairTable PAIRS = make_pairs();
+struct DynPairs {
+  int8_t a[16], b[16];
+};
+constexpr DynPairs make_dyn_pairs() {
+  DynPairs D{};
+  int n = 0;
+  for (int f = 0; f < 36; f++)
+    if (PAIRS.a[f] < 3 || PAIRS.b[f] < 3) {
+      D.a[n] = PAIRS.a[f];
+      D.b[n] = PAIRS.b[f];
+      n++;
+    }
+  for (; n < 16; n++) {
+    D.a[n] = -1;
+    D.b[n] = -1;
+  }
+  return D;
+}
+__constant__ DynPairs c_dynp = make_dyn_pairs();
+__constant__ NbrTable c_nbr = NBR;
+__device__ __forceinline__ int c_nbr_dx(int j) { return c_nbr.dx[j]; }
+__device__ __forceinline__ int c_nbr_dy(int j) { return c_nbr.dy[j]; }
+__device__ __forceinline__ int c_nbr_dt(int j) { return c_nbr.dt[j]; }
+static_assert(make_pairs().a[0] >= 0 && make_dyn_pairs().a[13] >= 0 && make_dyn_pairs().a[14] < 0,
+              "face and neighbour tables are consistent");
+
+// Running minimum of Alg. 2 bounds.  For the face (me, n0, n1) with
+// d0 = det(me, n0), d1 = det(me, n1):  Alg. 2 returns 0 when M = d0 - d1 +
+// det(n0, n1) is 0 or a neighbour is the zero vector; otherwise the minimum
+// of floor((N-1)/D) over (|M|, |u1-u0|+|v0-v1|), (|d1|, |u1|+|v1|),
+// (|d0|, |u0|+|v0|), raised to |u2|-1 (|v2|-1) when the u (v) components
+// share a strict sign.  A face whose raise already reaches the running
+// minimum xi cannot lower it, so its quotients are skipped; a quotient is
+// only evaluated when it beats the current value (N - 1 < e D, exact).
+__device__ __forceinline__ void lower_to(int& e, double N, int D) {
+  if (N == 0.0) {
+    e = 0;
+    return;
+  }
+  double Dd = (double)D, n1 = N - 1.0;
+  if (n1 >= (double)e * Dd) return;
+  int q = (int)(n1 * __builtin_amdgcn_rcp(Dd));
+  double r = n1 - (double)q * Dd;
+  if (r < 0.0) q--;
+  else if (r >= Dd) q++;
+  e = q;
+}
+
+__device__ __forceinline__ void face_update(int& xi, int2 me, int2 n0, int2 n1, double d0, double d1) {
+  double M = (d0 - d1) + det2(n0, n1);
+  int a0 = iabs(n0.x) + iabs(n0.y), a1 = iabs(n1.x) + iabs(n1.y);
+  if (M == 0.0 || a0 == 0 || a1 == 0) {
+    xi = 0;
+    return;
+  }
+  int relax = -1;
+  if ((n0.x > 0 && n1.x > 0 && me.x > 0) || (n0.x < 0 && n1.x < 0 && me.x < 0)) relax = iabs(me.x) - 1;
+  if ((n0.y > 0 && n1.y > 0 && me.y > 0) || (n0.y < 0 && n1.y < 0 && me.y < 0)) relax = max(relax, iabs(me.y) - 1);
+  if (relax >= xi) return;
+  int e = xi;
+  lower_to(e, fabs(M), iabs(n1.x - n0.x) + iabs(n0.y - n1.y));
+  lower_to(e, fabs(d1), a1);
+  lower_to(e, fabs(d0), a0);
+  xi = min(xi, max(e, relax));
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_phase(int2* __restrict__ cur, const uint8_t* __restrict__ flags,
                                                const uint8_t* __restrict__ modes, long long mode_base,
                                                FieldParams p, int t, int colour, uint8_t* __restrict__ xcode,
                                                uint32_t* __restrict__ qcode, int32_t* __restrict__ xi_dbg) {
   __shared__ int2 V[3][HALO][HALO];  // frames t-1, t, t+1 around the block
-  __shared__ int XS[TILE][TILE];     // bound from the faces fixed for the whole sweep
+  __shared__ int XS[TILE][TILE];     // bound from the faces fixed for the whole sweep; -1 = lossless
   __shared__ int2 SLP[TILE][TILE];   // semi-Lagrangian predictions
+  __shared__ uint32_t OQ[TILE][TILE];  // outputs, written once after the sweep
+  __shared__ int OX[TILE][TILE];
+  __shared__ uint8_t OC[TILE][TILE];
   const int tid = threadIdx.x;
   const int by = blockIdx.y;
   const int b0 = ((colour - by) % 3 + 3) % 3;
@@ -304,26 +436,31 @@ __global__ __launch_bounds__(256) void k_phase(int2* __restrict__ cur, const uin
   // ---- faces whose other vertices stay fixed during the sweep
   {
     const int lx = tid & 15, ly = tid >> 4, x = x0 + lx, y = y0 + ly;
-    int xi = 0;
+    int xi = -1;
     if (x < W && y < H) {
       const size_t gv = (size_t)t * HW + (size_t)y * W + x;
       if (!flags[gv]) {
         xi = eps;
         const int2 me = V[1][ly + 1][lx + 1];
-        for (int f = 0; f < 36 && xi > 0; f++) {
-          uint8_t a = c_ft.a[f], b = c_ft.b[f];
-          int ax = off_dx(a), ay = off_dy(a), at = off_dt(a);
-          int bxo = off_dx(b), byo = off_dy(b), bto = off_dt(b);
-          if (x + ax < 0 || x + ax >= W || y + ay < 0 || y + ay >= H || t + at < 0 || t + at >= T) continue;
-          if (x + bxo < 0 || x + bxo >= W || y + byo < 0 || y + byo >= H || t + bto < 0 || t + bto >= T) continue;
-          bool da = at == 0 && ((ax == -1 && ay == 0 && lx > 0) || (ax == 0 && ay == -1 && ly > 0) ||
-                                (ax == -1 && ay == -1 && lx > 0 && ly > 0));
-          bool db = bto == 0 && ((bxo == -1 && byo == 0 && lx > 0) || (bxo == 0 && byo == -1 && ly > 0) ||
-                                 (bxo == -1 && byo == -1 && lx > 0 && ly > 0));
-          if (da || db) continue;
-          int2 pa = V[1 + at][ly + 1 + ay][lx + 1 + ax];
-          int2 pb = V[1 + bto][ly + 1 + byo][lx + 1 + bxo];
-          xi = min(xi, face_bound(pa.x, pa.y, pb.x, pb.y, me.x, me.y, eps));
+        // neighbour present in the domain and not a raster predecessor
+        uint32_t ok = 0;
+#pragma unroll
+        for (int j = 0; j < 14; j++) {
+          int xx = x + NBR.dx[j], yy = y + NBR.dy[j], tt = t + NBR.dt[j];
+          bool in = xx >= 0 && xx < W && yy >= 0 && yy < H && tt >= 0 && tt < T;
+          bool dyn = (j == 0 && lx > 0) || (j == 1 && ly > 0) || (j == 2 && lx > 0 && ly > 0);
+          ok |= (in && !dyn) ? (1u << j) : 0u;
+        }
+        double d[14];
+#pragma unroll
+        for (int j = 0; j < 14; j++) d[j] = det2(me, V[1 + NBR.dt[j]][ly + 1 + NBR.dy[j]][lx + 1 + NBR.dx[j]]);
+#pragma unroll
+        for (int f = 0; f < 36; f++) {
+          const int a = PAIRS.a[f], b = PAIRS.b[f];
+          if (((ok >> a) & (ok >> b) & 1u) == 0) continue;
+          int2 na = V[1 + NBR.dt[a]][ly + 1 + NBR.dy[a]][lx + 1 + NBR.dx[a]];
+          int2 nb = V[1 + NBR.dt[b]][ly + 1 + NBR.dy[b]][lx + 1 + NBR.dx[b]];
+          face_update(xi, me, na, nb, d[a], d[b]);
         }
       }
       if (cls != 0) {
@@ -336,80 +473,78 @@ __global__ __launch_bounds__(256) void k_phase(int2* __restrict__ cur, const uin
   }
   __syncthreads();
 
-  // ---- anti-diagonal sweep: row g of the block, dynamic face j
+  // ---- anti-diagonal sweep: row g of the block, lane j takes the j-th face
+  // that meets a raster predecessor; lanes 0 and 1 then quantize u and v
   const int g = tid >> 4, j = tid & 15;
   const int y = y0 + g;
+  const int fa = c_dynp.a[j], fb = c_dynp.b[j];
+  const int axo = fa >= 0 ? c_nbr_dx(fa) : 0, ayo = fa >= 0 ? c_nbr_dy(fa) : 0, ato = fa >= 0 ? c_nbr_dt(fa) : 0;
+  const int bxo = fb >= 0 ? c_nbr_dx(fb) : 0, byo = fb >= 0 ? c_nbr_dy(fb) : 0, bto = fb >= 0 ? c_nbr_dt(fb) : 0;
+  const int comp = j & 1;
   for (int d = 0; d < 2 * TILE - 1; d++) {
     const int lx = d - g, x = x0 + lx;
     const bool active = lx >= 0 && lx < TILE && x < W && y < H;
-    int e = eps;
-    size_t gv = 0;
-    bool lossless = true;
+    int e = eps, xs = -1, lorenzo = 0;
     if (active) {
-      gv = (size_t)t * HW + (size_t)y * W + x;
-      lossless = flags[gv] != 0;
-      if (!lossless && j < 14) {
-        const int f = c_dyn.idx[j];
-        uint8_t a = c_ft.a[f], b = c_ft.b[f];
-        int ax = off_dx(a), ay = off_dy(a), at = off_dt(a);
-        int bxo = off_dx(b), byo = off_dy(b), bto = off_dt(b);
-        bool ok = !(x + ax < 0 || x + ax >= W || y + ay < 0 || y + ay >= H || t + at < 0 || t + at >= T) &&
-                  !(x + bxo < 0 || x + bxo >= W || y + byo < 0 || y + byo >= H || t + bto < 0 || t + bto >= T);
-        bool da = at == 0 && ((ax == -1 && ay == 0 && lx > 0) || (ax == 0 && ay == -1 && g > 0) ||
-                              (ax == -1 && ay == -1 && lx > 0 && g > 0));
-        bool db = bto == 0 && ((bxo == -1 && byo == 0 && lx > 0) || (bxo == 0 && byo == -1 && g > 0) ||
-                               (bxo == -1 && byo == -1 && lx > 0 && g > 0));
-        if (ok && (da || db)) {
+      xs = XS[g][lx];
+      e = xs >= 0 ? xs : eps;
+      if (xs >= 0 && fa >= 0) {
+        bool ina = x + axo >= 0 && x + axo < W && y + ayo >= 0 && y + ayo < H && t + ato >= 0 && t + ato < T;
+        bool inb = x + bxo >= 0 && x + bxo < W && y + byo >= 0 && y + byo < H && t + bto >= 0 && t + bto < T;
+        bool dyna = (fa == 0 && lx > 0) || (fa == 1 && g > 0) || (fa == 2 && lx > 0 && g > 0);
+        bool dynb = (fb == 0 && lx > 0) || (fb == 1 && g > 0) || (fb == 2 && lx > 0 && g > 0);
+        if (ina && inb && (dyna || dynb)) {
           int2 me = V[1][g + 1][lx + 1];
-          int2 pa = V[1 + at][g + 1 + ay][lx + 1 + ax];
+          int2 pa = V[1 + ato][g + 1 + ayo][lx + 1 + axo];
           int2 pb = V[1 + bto][g + 1 + byo][lx + 1 + bxo];
-          e = face_bound(pa.x, pa.y, pb.x, pb.y, me.x, me.y, eps);
+          face_update(e, me, pa, pb, det2(me, pa), det2(me, pb));
         }
+      }
+      if (j < 2 && cls == 0) {
+        // Lorenzo neighbours of this step's vertex (final after the last barrier)
+        auto cmp = [&](int2 v) { return comp ? v.y : v.x; };
+        const int l = lx > 0 ? cmp(V[1][g + 1][lx]) : 0;
+        const int u = g > 0 ? cmp(V[1][g][lx + 1]) : 0;
+        const int lu = (lx > 0 && g > 0) ? cmp(V[1][g][lx]) : 0;
+        const int pc = cmp(V[0][g + 1][lx + 1]);
+        const int pl = lx > 0 ? cmp(V[0][g + 1][lx]) : 0;
+        const int pu_ = g > 0 ? cmp(V[0][g][lx + 1]) : 0;
+        const int plu = (lx > 0 && g > 0) ? cmp(V[0][g][lx]) : 0;
+        lorenzo = l + u - lu + pc - pl - pu_ + plu;
       }
     }
-    e = min(e, __shfl_xor(e, 8, 16));
-    e = min(e, __shfl_xor(e, 4, 16));
-    e = min(e, __shfl_xor(e, 2, 16));
-    e = min(e, __shfl_xor(e, 1, 16));
-    if (active && j == 0) {
-      int xi = lossless ? 0 : min(XS[g][lx], e);
+    e = row16_min(e);
+    if (active && j < 2) {
+      int xi = xs < 0 ? 0 : min(xs, e);
       int code = xi_code(eps, xi);
-      uint32_t qc = 0;
+      int qc = 0;
       if (code != XLOSSLESS) {
-        int xt = eps >> code;
-        int pu, pv;
-        if (cls == 0) {
-          pu = 0;
-          pv = 0;
-          // tile-local 3-D Lorenzo on the staged frames
-          auto val = [&](int f, int i, int jj, int comp) -> int {
-            if (i < 0 || jj < 0) return 0;
-            int2 q = V[f][jj + 1][i + 1];
-            return comp ? q.y : q.x;
-          };
-          for (int comp = 0; comp < 2; comp++) {
-            int s = val(1, lx - 1, g, comp) + val(1, lx, g - 1, comp) - val(1, lx - 1, g - 1, comp);
-            if (t > 0) s += val(0, lx, g, comp) - val(0, lx - 1, g, comp) - val(0, lx, g - 1, comp) +
-                            val(0, lx - 1, g - 1, comp);
-            if (comp) pv = s; else pu = s;
-          }
-        } else {
-          pu = SLP[g][lx].x;
-          pv = SLP[g][lx].y;
-        }
-        int2 me = V[1][g + 1][lx + 1];
-        int ru, rv;
-        int cu = quantize(me.x, pu, xt, &ru);
-        int cvv = quantize(me.y, pv, xt, &rv);
-        qc = (uint32_t)cu | ((uint32_t)cvv << 16);
-        V[1][g + 1][lx + 1] = make_int2(ru, rv);
-        cur[gv] = make_int2(ru, rv);
+        const int xt = eps >> code;
+        const int2 me = V[1][g + 1][lx + 1];
+        const int pred = cls == 0 ? lorenzo : (comp ? SLP[g][lx].y : SLP[g][lx].x);
+        int rec;
+        qc = quantize(comp ? me.y : me.x, pred, xt, &rec);
+        ((int*)&V[1][g + 1][lx + 1])[comp] = rec;
       }
-      xcode[gv] = (uint8_t)code;
-      qcode[gv] = qc;
-      if (xi_dbg) xi_dbg[gv] = xi;
+      ((uint16_t*)&OQ[g][lx])[comp] = (uint16_t)qc;
+      if (!comp) {
+        OC[g][lx] = (uint8_t)code;
+        OX[g][lx] = xi;
+      }
     }
     __syncthreads();
+  }
+
+  // ---- results of the block, one coalesced write per array
+  {
+    const int lx = tid & 15, ly = tid >> 4, x = x0 + lx, yy = y0 + ly;
+    if (x < W && yy < H) {
+      const size_t gv = (size_t)t * HW + (size_t)yy * W + x;
+      cur[gv] = V[1][ly + 1][lx + 1];
+      xcode[gv] = OC[ly][lx];
+      qcode[gv] = OQ[ly][lx];
+      if (xi_dbg) xi_dbg[gv] = OX[ly][lx];
+    }
   }
 }
 

@@ -46,8 +46,10 @@ __global__ __launch_bounds__(256) void k_reconstruct(int2* __restrict__ cur, flo
                                                      const uint32_t* __restrict__ rofs,
                                                      const uint8_t* __restrict__ modes, long long mode_base,
                                                      FieldParams p, int t, uint32_t* __restrict__ err) {
-  __shared__ int2 C[TILE][TILE];
-  __shared__ int2 P[TILE][TILE];
+  __shared__ int C[2][TILE][TILE];     // reconstructed fixed-point values (u, v)
+  __shared__ int P[2][TILE][TILE];     // previous frame, for the Lorenzo predictor
+  __shared__ int DQ[2][TILE][TILE];    // q (2 xi~ + 1) of components still to predict
+  __shared__ uint8_t KN[2][TILE][TILE];  // component already known (raw or semi-Lagrangian)
   const int tid = threadIdx.x, lx = tid & 15, ly = tid >> 4;
   const int bx = blockIdx.x, by = blockIdx.y;
   const int x = bx * TILE + lx, y = by * TILE + ly;
@@ -61,72 +63,92 @@ __global__ __launch_bounds__(256) void k_reconstruct(int2* __restrict__ cur, flo
     else if (mode_base >= 0) cls = modes[(size_t)mode_base + (size_t)by * p.tx + bx];
   }
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
-  P[ly][lx] = (valid && t > 0) ? cur[gv - HW] : make_int2(0, 0);
-  C[ly][lx] = make_int2(0, 0);
+  const int2 pv2 = (valid && t > 0) ? cur[gv - HW] : make_int2(0, 0);
+  P[0][ly][lx] = pv2.x;
+  P[1][ly][lx] = pv2.y;
 
   // everything that does not depend on the block's own reconstruction
-  int code = XLOSSLESS, qu = 0, qv = 0, xt = 0, pu = 0, pv = 0;
-  uint32_t ro = 0;
   if (valid) {
-    code = xs[gv];
-    ro = rofs[gv];
+    const int code = xs[gv];
+    uint32_t r = rofs[gv];
+    int q[2] = {0, 0}, pr[2] = {0, 0};
+    int64_t w = 0;
     if (code != XLOSSLESS) {
       size_t o = 2 * (size_t)qofs[gv];
-      qu = qs[o];
-      qv = qs[o + 1];
-      xt = p.eps >> code;
-      if (cls != 0) sl_predict(cur + (size_t)(t - 1) * HW, H, W, x, y, SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pu, &pv);
+      q[0] = qs[o];
+      q[1] = qs[o + 1];
+      w = 2 * (int64_t)(p.eps >> code) + 1;
+      if (cls != 0) sl_predict(cur + (size_t)(t - 1) * HW, H, W, x, y, SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pr[0], &pr[1]);
+    }
+    for (int c = 0; c < 2; c++) {
+      if (code == XLOSSLESS || q[c] == 0) {
+        uint32_t b = raw[r++];
+        if (((b >> 23) & 0xFFu) == 0xFFu) atomicOr(err, 64u);
+        C[c][ly][lx] = to_fixed(__uint_as_float(b), p.k);
+        KN[c][ly][lx] = 1;
+      } else {
+        int64_t dq = (int64_t)(q[c] - QR) * w;
+        if (cls != 0) {
+          int64_t rv = (int64_t)pr[c] + dq;
+          if (rv >= (1 << 25) || rv <= -(1 << 25)) {
+            atomicOr(err, 128u);
+            rv = 0;
+          }
+          C[c][ly][lx] = (int)rv;
+          KN[c][ly][lx] = 1;
+        } else {
+          DQ[c][ly][lx] = (int)dq;
+          KN[c][ly][lx] = 0;
+        }
+      }
     }
   }
-  auto finish = [&](int pu_, int pv_) {
-    int comp_pred[2] = {pu_, pv_};
-    int comp_q[2] = {qu, qv};
-    int outv[2];
-    uint32_t r = ro;
-    for (int c = 0; c < 2; c++) {
-      float f;
-      int fx;
-      if (code == XLOSSLESS || comp_q[c] == 0) {
-        uint32_t b = raw[r++];
-        f = __uint_as_float(b);
-        if (((b >> 23) & 0xFFu) == 0xFFu) atomicOr(err, 64u);
-        fx = to_fixed(f, p.k);
-      } else {
-        int64_t rv = (int64_t)comp_pred[c] + (int64_t)(comp_q[c] - QR) * (2 * (int64_t)xt + 1);
+  __syncthreads();
+
+  // Lorenzo blocks: one wave sweeps the anti-diagonals, lanes 0-15 the rows
+  // of u and lanes 16-31 the rows of v; no workgroup barrier inside
+  if (cls == 0 && tid < 2 * TILE) {
+    const int c = tid >> 4, row = tid & 15;
+    const bool has_prev = t > 0;
+    for (int d = 0; d < 2 * TILE - 1; d++) {
+      const int col = d - row;
+      if (col >= 0 && col < TILE && bx * TILE + col < W && by * TILE + row < H && !KN[c][row][col]) {
+        int s = (col > 0 ? C[c][row][col - 1] : 0) + (row > 0 ? C[c][row - 1][col] : 0) -
+                (col > 0 && row > 0 ? C[c][row - 1][col - 1] : 0);
+        if (has_prev)
+          s += P[c][row][col] - (col > 0 ? P[c][row][col - 1] : 0) - (row > 0 ? P[c][row - 1][col] : 0) +
+               (col > 0 && row > 0 ? P[c][row - 1][col - 1] : 0);
+        int64_t rv = (int64_t)s + DQ[c][row][col];
         if (rv >= (1 << 25) || rv <= -(1 << 25)) {
           atomicOr(err, 128u);
           rv = 0;
         }
-        fx = (int)rv;
-        f = from_fixed(fx, p.k);
+        C[c][row][col] = (int)rv;
       }
-      outv[c] = fx;
-      field[(size_t)c * N + gv] = f;
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
-    C[ly][lx] = make_int2(outv[0], outv[1]);
-    cur[gv] = make_int2(outv[0], outv[1]);
-  };
-  __syncthreads();
-  if (cls != 0) {
-    if (valid) finish(pu, pv);
-    return;
   }
-  for (int d = 0; d < 2 * TILE - 1; d++) {
-    if (valid && lx + ly == d) {
-      int pr[2] = {0, 0};
-      if (code != XLOSSLESS) {
-        for (int c = 0; c < 2; c++) {
-          auto g = [&](const int2 (*A)[TILE], int i, int j) -> int {
-            if (i < 0 || j < 0) return 0;
-            return c ? A[j][i].y : A[j][i].x;
-          };
-          pr[c] = g(C, lx - 1, ly) + g(C, lx, ly - 1) - g(C, lx - 1, ly - 1) + g(P, lx, ly) - g(P, lx - 1, ly) -
-                  g(P, lx, ly - 1) + g(P, lx - 1, ly - 1);
-        }
-      }
-      finish(pr[0], pr[1]);
+  __syncthreads();
+  if (valid) {
+    const int u = C[0][ly][lx], v = C[1][ly][lx];
+    cur[gv] = make_int2(u, v);
+    // known raw components are restored bit-exactly; the rest are exact
+    // multiples of 2^-k
+    const uint32_t r0 = rofs[gv];
+    const int code = xs[gv];
+    float fu, fv;
+    if (code == XLOSSLESS) {
+      fu = __uint_as_float(raw[r0]);
+      fv = __uint_as_float(raw[r0 + 1]);
+    } else {
+      size_t o = 2 * (size_t)qofs[gv];
+      uint32_t r = r0;
+      fu = qs[o] == 0 ? __uint_as_float(raw[r++]) : from_fixed(u, p.k);
+      fv = qs[o + 1] == 0 ? __uint_as_float(raw[r]) : from_fixed(v, p.k);
     }
-    __syncthreads();
+    field[gv] = fu;
+    field[N + gv] = fv;
   }
 }
 

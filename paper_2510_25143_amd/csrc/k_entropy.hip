@@ -4,7 +4,7 @@
 // Two canonical codes, one for the bound codes (25 symbols) and one for the
 // residual codes (1024 symbols), lengths limited to 12 bits by package-merge
 // (leaves ordered by (count, symbol); a leaf precedes a package of equal
-// weight).  Symbols are cut into chunks of 4096; every chunk is coded
+// weight).  Symbols are cut into chunks of 1024; every chunk is coded
 // MSB-first into its own run of 32-bit words, so encoding and decoding run
 // one chunk per workgroup / lane.  The codebook is built by one workgroup
 // on the device, so compression needs no host round trip for it.

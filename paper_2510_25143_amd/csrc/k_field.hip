@@ -30,18 +30,31 @@ __global__ void k_range_init(int* r) {
   }
 }
 
+__device__ __forceinline__ void range_acc(uint32_t b, int& mn, int& mx, uint32_t& ma, uint32_t& bad) {
+  if (((b >> 23) & 0xFFu) == 0xFFu) bad = 1;
+  int key = ordered_key(b);
+  mn = min(mn, key);
+  mx = max(mx, key);
+  ma = max(ma, b & 0x7FFFFFFFu);
+}
+
+// min, max (as ordered keys), max |x| bits and a non-finite flag; four
+// floats per load
 __global__ __launch_bounds__(256) void k_range(const float* __restrict__ x, size_t n, int* r) {
   int mn = 0x7FFFFFFF, mx = (int)0x80000000;
   uint32_t ma = 0, bad = 0;
   size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    uint32_t b = __float_as_uint(x[i]);
-    if (((b >> 23) & 0xFFu) == 0xFFu) bad = 1;
-    int key = ordered_key(b);
-    mn = min(mn, key);
-    mx = max(mx, key);
-    ma = max(ma, b & 0x7FFFFFFFu);
+  size_t n4 = ((uintptr_t)x & 15) == 0 ? n / 4 : 0;
+  const uint4* x4 = (const uint4*)x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+    uint4 v = x4[i];
+    range_acc(v.x, mn, mx, ma, bad);
+    range_acc(v.y, mn, mx, ma, bad);
+    range_acc(v.z, mn, mx, ma, bad);
+    range_acc(v.w, mn, mx, ma, bad);
   }
+  for (size_t i = 4 * n4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    range_acc(__float_as_uint(x[i]), mn, mx, ma, bad);
   for (int o = 32; o > 0; o >>= 1) {
     mn = min(mn, __shfl_xor(mn, o));
     mx = max(mx, __shfl_xor(mx, o));
@@ -325,8 +338,8 @@ static inline unsigned nblk(size_t n, int b = 256) { return (unsigned)((n + b - 
 
 void launch_range(const float* x, size_t n, int* r, hipStream_t s) {
   k_range_init<<<1, 64, 0, s>>>(r);
-  unsigned g = nblk(n);
-  if (g > 4096) g = 4096;
+  unsigned g = nblk((n + 3) / 4);
+  if (g > 2048) g = 2048;
   if (g == 0) g = 1;
   k_range<<<g, 256, 0, s>>>(x, n, r);
 }
