@@ -144,6 +144,37 @@ cpt_status cpt_verify(const float* a, const float* b, int H, int W, int T, int k
 cpt_status cpt_field_params(const float* field, int H, int W, int T, int eb_mode, double eb, int* k,
                             double* eb_abs, int64_t* eps, void* stream);
 
+/* ---- Learned predictor selector (training on the device) ----
+ * Network: 10 inputs (the block features written by cpt_compress_debug),
+ * ReLU hidden layers of 64 and 64, 4 outputs (Lorenzo, semi-Lagrangian with
+ * d_max 1, 2, 4 cells).  Weight layout (5124 values): W1[64][10], b1[64],
+ * W2[64][64], b2[64], W3[4][64], b3[4].  Inference (in cpt_compress with
+ * CPT_PRED_LEARNED) uses the bf16 copy with fp32 fused multiply-add in input
+ * order and picks the first largest logit. */
+typedef struct {
+  uint32_t struct_size;  /* sizeof(cpt_train_options) */
+  int32_t epochs;        /* passes over the data (default 20) */
+  int32_t batch;         /* minibatch size (default 1024) */
+  float lr;              /* Adam step size (default 2e-3) */
+  uint64_t seed;         /* sample-order seed */
+} cpt_train_options;
+
+/* Mean softmax cross-entropy of the network with fp32 master weights `w`
+ * (device, rounded to bf16 for the forward pass) over n samples (device:
+ * feats [n][10] float32, labels [n] int32 in 0..3), and its gradient with
+ * respect to the rounded weights (device grad [5124]); loss is a host
+ * float.  Deterministic.  Synchronises `stream`. */
+cpt_status cpt_selector_grad(const float* w, const float* feats, const int32_t* labels, int n, float* grad,
+                             float* loss, void* stream);
+
+/* Adam training of the network on n samples (device arrays as above).  `w`
+ * (device, 5124 float32) holds the initial weights and receives the trained
+ * master weights; `w_bf16` (device, 5124) receives their bf16 rounding.
+ * final_loss (host, may be NULL) receives the full-data loss after training.
+ * Deterministic for a given seed.  Synchronises `stream`. */
+cpt_status cpt_selector_train(const float* feats, const int32_t* labels, int n, float* w, uint16_t* w_bf16,
+                              const cpt_train_options* opt, float* final_loss, void* stream);
+
 /* Kernel timing for benchmarks.  cpt_timing_enable(1) resets the counters
  * and brackets every launch of the main kernel families with HIP events on
  * the caller's stream; cpt_timing_read returns the accumulated device time,

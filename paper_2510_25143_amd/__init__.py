@@ -40,6 +40,11 @@ class Info(ctypes.Structure):
                 ("n_q", ctypes.c_uint64), ("n_raw", ctypes.c_uint64)]
 
 
+class TrainOptions(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
 class VerifyResult(ctypes.Structure):
     _fields_ = [("fc_t", ctypes.c_uint64), ("fc_s", ctypes.c_uint64),
                 ("max_err", ctypes.c_double), ("psnr", ctypes.c_double)]
@@ -47,7 +52,8 @@ class VerifyResult(ctypes.Structure):
 
 EXPORTS = ["cpt_compress_bound", "cpt_compress", "cpt_compress_debug", "cpt_stream_info",
            "cpt_decompress", "cpt_extract_trajectories", "cpt_verify", "cpt_field_params",
-           "cpt_timing_enable", "cpt_timing_read", "cpt_last_error"]
+           "cpt_selector_grad", "cpt_selector_train", "cpt_timing_enable", "cpt_timing_read",
+           "cpt_last_error"]
 
 _lib = None
 
@@ -70,6 +76,8 @@ def lib():
         "cpt_extract_trajectories": [P, i32, i32, i32, i32, P, sz, P, P],
         "cpt_verify": [P, P, i32, i32, i32, i32, P, P],
         "cpt_field_params": [P, i32, i32, i32, i32, dbl, P, P, P, P],
+        "cpt_selector_grad": [P, P, P, i32, P, P, P],
+        "cpt_selector_train": [P, P, i32, P, P, P, P, P],
         "cpt_timing_enable": [i32],
         "cpt_timing_read": [i32, P, P, P],
     }
@@ -228,3 +236,38 @@ def timing_read(family):
     ms, n, u = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64()
     _check(lib().cpt_timing_read(TIMING_FAMILIES[family], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(u)))
     return ms.value, n.value, u.value
+
+
+def selector_init(seed=0, device="cuda"):
+    """He-initialised fp32 selector weights (5124 values) on ``device``."""
+    g = torch.Generator().manual_seed(seed)
+    w = torch.zeros(SELECTOR_PARAMS, dtype=torch.float32)
+    w[0:640] = torch.randn(640, generator=g) * (2.0 / 10) ** 0.5 * 0.1
+    w[704:4800] = torch.randn(4096, generator=g) * (2.0 / 64) ** 0.5
+    w[4864:5120] = torch.randn(256, generator=g) * (1.0 / 64) ** 0.5
+    return w.to(device)
+
+
+def selector_grad(w, feats, labels):
+    """(gradient tensor, mean loss) of the selector network on the device."""
+    n = labels.numel()
+    grad = torch.empty(SELECTOR_PARAMS, dtype=torch.float32, device=w.device)
+    loss = ctypes.c_float()
+    _check(lib().cpt_selector_grad(_ptr(w.contiguous()), _ptr(feats.contiguous()), _ptr(labels.contiguous()), n,
+                                   _ptr(grad), ctypes.byref(loss), _stream()))
+    return grad, loss.value
+
+
+def selector_train(feats, labels, w=None, epochs=20, batch=1024, lr=2e-3, seed=0):
+    """Train the selector on the device; returns (fp32 weights, bf16 weights as
+    int16 tensor, final mean loss)."""
+    if w is None:
+        w = selector_init(seed, feats.device)
+    w = w.contiguous().clone()
+    wbf = torch.empty(SELECTOR_PARAMS, dtype=torch.int16, device=w.device)
+    o = TrainOptions(ctypes.sizeof(TrainOptions), epochs, batch, lr, seed)
+    loss = ctypes.c_float()
+    _check(lib().cpt_selector_train(_ptr(feats.contiguous()), _ptr(labels.to(torch.int32).contiguous()),
+                                    labels.numel(), _ptr(w), _ptr(wbf), ctypes.byref(o), ctypes.byref(loss),
+                                    _stream()))
+    return w, wbf, loss.value

@@ -685,6 +685,115 @@ extern "C" {
 
 const char* cpt_last_error(void) { return g_err.c_str(); }
 
+// selector training scratch (grow-only, per process)
+namespace {
+struct TrainBufs {
+  float *m = nullptr, *v = nullptr, *grad = nullptr, *part = nullptr, *lpart = nullptr, *loss = nullptr;
+  int32_t* idx = nullptr;
+  size_t parts_cap = 0, n_cap = 0;
+};
+TrainBufs g_tb;
+std::mutex g_tb_mu;
+constexpr int SEL_NW = 5124;
+constexpr int SEL_PER_BLOCK = 16;
+
+cpt_status train_bufs(int n, int batch) {
+  size_t parts = (size_t)selector_parts(std::max(n, batch), SEL_PER_BLOCK);
+  if (!g_tb.m) {
+    if (hipMalloc((void**)&g_tb.m, SEL_NW * 4) != hipSuccess || hipMalloc((void**)&g_tb.v, SEL_NW * 4) != hipSuccess ||
+        hipMalloc((void**)&g_tb.grad, SEL_NW * 4) != hipSuccess || hipMalloc((void**)&g_tb.loss, 16) != hipSuccess)
+      return fail(CPT_ENOMEM, "selector buffers");
+  }
+  if (parts > g_tb.parts_cap) {
+    if (g_tb.part) (void)hipFree(g_tb.part);
+    if (g_tb.lpart) (void)hipFree(g_tb.lpart);
+    if (hipMalloc((void**)&g_tb.part, parts * SEL_NW * 4) != hipSuccess ||
+        hipMalloc((void**)&g_tb.lpart, parts * 4) != hipSuccess)
+      return fail(CPT_ENOMEM, "selector partial buffers");
+    g_tb.parts_cap = parts;
+  }
+  if ((size_t)n > g_tb.n_cap) {
+    if (g_tb.idx) (void)hipFree(g_tb.idx);
+    if (hipMalloc((void**)&g_tb.idx, (size_t)n * 4) != hipSuccess) return fail(CPT_ENOMEM, "selector index buffer");
+    g_tb.n_cap = n;
+  }
+  return CPT_OK;
+}
+
+long long gcd_ll(long long a, long long b) {
+  while (b) {
+    long long t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+}  // namespace
+
+cpt_status cpt_selector_grad(const float* w, const float* feats, const int32_t* labels, int n, float* grad,
+                             float* loss, void* stream) {
+  if (!w || !feats || !labels || !grad || !loss || n <= 0) return fail(CPT_EINVAL, "bad selector_grad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_tb_mu);
+  cpt_status st = train_bufs(n, n);
+  if (st) return st;
+  launch_perm(g_tb.idx, n, 1, 0, s);
+  launch_mlp_grad(w, feats, labels, g_tb.idx, n, SEL_PER_BLOCK, 1.0f / (float)n, g_tb.part, g_tb.lpart, grad,
+                  g_tb.loss, s);
+  HIPCHK(hipMemcpyAsync(loss, g_tb.loss, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return CPT_OK;
+}
+
+cpt_status cpt_selector_train(const float* feats, const int32_t* labels, int n, float* w, uint16_t* w_bf16,
+                              const cpt_train_options* opt_in, float* final_loss, void* stream) {
+  if (!feats || !labels || !w || !w_bf16 || n <= 0) return fail(CPT_EINVAL, "bad selector_train arguments");
+  cpt_train_options opt{sizeof(cpt_train_options), 20, 1024, 2e-3f, 0};
+  if (opt_in) {
+    if (opt_in->struct_size != sizeof(cpt_train_options)) return fail(CPT_EINVAL, "cpt_train_options.struct_size");
+    opt = *opt_in;
+  }
+  if (opt.epochs < 0 || opt.batch < 1 || !(opt.lr > 0.f)) return fail(CPT_EINVAL, "bad training options");
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_tb_mu);
+  const int batch = std::min(opt.batch, n);
+  cpt_status st = train_bufs(n, batch);
+  if (st) return st;
+  HIPCHK(hipMemsetAsync(g_tb.m, 0, SEL_NW * 4, s));
+  HIPCHK(hipMemsetAsync(g_tb.v, 0, SEL_NW * 4, s));
+  // per-epoch sample order i -> (a i + c) mod n with gcd(a, n) = 1
+  long long a = 2654435761LL % n;
+  if (a == 0) a = 1;
+  while (gcd_ll(a, n) != 1) a++;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  double p1 = 1.0, p2 = 1.0;
+  uint64_t state = opt.seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  for (int e = 0; e < opt.epochs; e++) {
+    state ^= state >> 33;
+    state *= 0xFF51AFD7ED558CCDull;
+    state ^= state >> 33;
+    launch_perm(g_tb.idx, n, a, (long long)(state % (uint64_t)n), s);
+    for (int b0 = 0; b0 + batch <= n; b0 += batch) {
+      launch_mlp_grad(w, feats, labels, g_tb.idx + b0, batch, SEL_PER_BLOCK, 1.0f / (float)batch, g_tb.part,
+                      g_tb.lpart, g_tb.grad, g_tb.loss, s);
+      p1 *= b1;
+      p2 *= b2;
+      launch_adam(w, g_tb.m, g_tb.v, g_tb.grad, opt.lr, b1, b2, eps, (float)(1.0 - p1), (float)(1.0 - p2), w_bf16, s);
+    }
+  }
+  launch_to_bf16(w, w_bf16, s);
+  if (final_loss) {
+    launch_perm(g_tb.idx, n, 1, 0, s);
+    launch_mlp_grad(w, feats, labels, g_tb.idx, n, SEL_PER_BLOCK, 1.0f / (float)n, g_tb.part, g_tb.lpart, g_tb.grad,
+                    g_tb.loss, s);
+    HIPCHK(hipMemcpyAsync(final_loss, g_tb.loss, 4, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return CPT_OK;
+}
+
 cpt_status cpt_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_tim.mu);
   g_tim.on = on != 0;

@@ -83,4 +83,14 @@ void launch_reconstruct(int2* cur, float* field, const uint16_t* xs, const uint1
                         const uint32_t* raw, const uint32_t* rofs, const uint8_t* modes, long long mode_base,
                         const FieldParams& p, int t, uint32_t* err, hipStream_t s);
 
+// k_selector.hip
+int selector_parts(int nbatch, int per_block);
+void launch_mlp_grad(const float* w, const float* feats, const int32_t* labels, const int32_t* idx, int nbatch,
+                     int per_block, float inv_n, float* part, float* loss_part, float* grad, float* loss,
+                     hipStream_t s);
+void launch_adam(float* w, float* m, float* v, const float* g, float lr, float b1, float b2, float eps, float c1,
+                 float c2, uint16_t* wbf, hipStream_t s);
+void launch_perm(int32_t* idx, int n, long long a, long long c, hipStream_t s);
+void launch_to_bf16(const float* w, uint16_t* wbf, hipStream_t s);
+
 }  // namespace cpt
