@@ -25,6 +25,9 @@ WORKLOADS = {
     "turbulence": dict(cfg=2, name="turbulence-like 2048x2048x32 float32 (u,v), k^-5/3 self-advected "
                                    "+ 64 translating vortices"),
     "vortex": dict(cfg=0, name="4 translating Lamb-Oseen vortices 64x64x8 float32 (u,v) + N(0,1e-3)"),
+    "batch": dict(cfg=3, name="batch of 256 independent vortex fields (4-32 Lamb-Oseen vortices + N(0,1e-3)), "
+                              "side log-uniform 64..1024, T uniform 8..64, float32 (u,v), compressed in one "
+                              "batched pipeline"),
 }
 
 # fp64 operations of one face bound (Alg. 2): three 2x2 determinants at three
@@ -39,6 +42,112 @@ def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
+def phase_roofline(fam, kname):
+    ms, n, units = fam["phase"]
+    avg_ms = ms / max(n, 1)
+    per_launch = units / max(n, 1)
+    achieved = OPS_PER_FACE * FACES_PER_VERTEX * per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None, "kernel": kname,
+            "avg_launch_us": round(avg_ms * 1e3, 3), "vertices_per_launch": round(per_launch, 1),
+            "ops_per_vertex": OPS_PER_FACE * FACES_PER_VERTEX}
+
+
+def bench_batch(args, cpt, torch, synthfields):
+    """The uneven batch: 256 fields compressed by one batched call, then
+    decompressed field by field; also one cpt_compress call per field for
+    comparison."""
+    eb = 1e-2
+    shapes = synthfields.batch_shapes(256, seed=3000)
+    log("generating %d fields on cuda:0" % len(shapes))
+    fields = []
+    for i, sh in enumerate(shapes):
+        f, _ = synthfields.batch_field(i, sh, device="cuda")
+        fields.append(f.contiguous())
+        if i % 64 == 63:
+            log("  %d fields" % (i + 1))
+    torch.cuda.synchronize()
+    raw = sum(f.numel() * 4 for f in fields)
+    nvert = raw // 8
+    outs = [torch.empty(cpt.compress_bound(f.shape[2], f.shape[3], f.shape[1]), dtype=torch.uint8, device="cuda")
+            for f in fields]
+    decs = [torch.empty_like(f) for f in fields]
+    sched, tune_ms = args.schedule, None
+    if sched == "auto":
+        (sched, graph), tune_ms = cpt.autotune_batch(fields, eb, reps=1, outs=outs)
+        log("autotune: %s graph=%s (ms: %s)" % (sched, graph, ", ".join("%.2f" % m for m in tune_ms)))
+
+    def comp():
+        st, status = cpt.compress_batch(fields, eb, schedule=sched, outs=outs)
+        return st
+
+    log("warmup x%d" % max(args.warmup, 1))
+    for _ in range(max(args.warmup, 1)):
+        streams = comp()
+        for s, d in zip(streams, decs):
+            cpt.decompress(s, out=d)
+    torch.cuda.synchronize()
+    clen = sum(s.numel() for s in streams)
+    worst = 0.0
+    for f, d in zip(fields, decs):
+        k, ea, _ = cpt.field_params(f, eb)
+        v = cpt.verify(f, d, k)
+        if not (v["fc_t"] == 0 and v["fc_s"] == 0 and v["max_err"] <= ea):
+            raise SystemExit("guarantee violated on a field of shape %s: %s" % (tuple(f.shape), v))
+        worst = max(worst, v["max_err"] / ea)
+    log("%d fields, %d vertices, CR %.3f, all faces kept, max err / eb_abs %.4f" %
+        (len(fields), nvert, raw / clen, worst))
+
+    log("timed x%d" % args.steps)
+    cpt.timing_enable(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        streams = comp()
+        ev[i][1].record()
+        for s, d in zip(streams, decs):
+            cpt.decompress(s, out=d)
+        ev[i][2].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tc = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    td = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
+    fam = {name: cpt.timing_read(name) for name in cpt.TIMING_FAMILIES}
+    cpt.timing_enable(False)
+    kname = "k_phase_b<true>" if sched == "fused" else "k_phase_b<false>"
+    roofline = phase_roofline(fam, kname)
+    kernels = {name: {"ms_per_step": round(m / args.steps, 4), "launches_per_step": c // max(args.steps, 1)}
+               for name, (m, c, _) in fam.items() if c}
+
+    log("one cpt_compress call per field")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for f, o in zip(fields, outs):
+        cpt.compress(f, eb, out=o)
+    e1.record()
+    torch.cuda.synchronize()
+    t_single = e0.elapsed_time(e1)
+    value = args.steps * raw / elapsed / 1e9
+    result = {
+        "metric": METRIC, "value": round(value, 4), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i32+f64(exact)", "data": "synthetic",
+        "config": {"workload": WORKLOADS["batch"]["name"], "fields": len(fields), "vertices": nvert,
+                   "raw_bytes": raw, "eb_rel": eb, "predictor": 2, "mode_bt": 1, "schedule": sched,
+                   "tune_ms": tune_ms, "CR": round(raw / clen, 4), "stream_bytes": clen,
+                   "max_err_over_eb": round(worst, 6),
+                   "compress_ms": round(tc, 3), "decompress_ms": round(td, 3),
+                   "compress_GBps": round(raw / tc / 1e6, 3), "decompress_GBps": round(raw / td / 1e6, 3),
+                   "per_field_compress_ms": round(t_single, 3),
+                   "batch_speedup_over_per_field": round(t_single / tc, 3), "kernels": kernels},
+        "roofline": roofline,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,6 +157,8 @@ def main():
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--predictor", type=int, default=2)
     ap.add_argument("--mode-bt", type=int, default=1)
+    ap.add_argument("--schedule", default="auto", choices=["auto", "launch", "fused"],
+                    help="auto: the faster of the per-phase launch schedules, timed during warm-up")
     ap.add_argument("--cpu-frames", type=int, default=4, help="frames of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -65,6 +176,8 @@ def main():
 
     torch.cuda.set_device(0)
     cpt.lib()
+    if args.workload == "batch":
+        return bench_batch(args, cpt, torch, synthfields)
     wl = WORKLOADS[args.workload]
     log("generating workload %s on cuda:0" % args.workload)
     f, meta = synthfields.workload(wl["cfg"], device="cuda")
@@ -77,8 +190,20 @@ def main():
     out = torch.empty(cpt.compress_bound(H, W, T), dtype=torch.uint8, device="cuda")
     dec = torch.empty_like(f)
 
+    opts = dict(predictor=args.predictor, mode_bt=args.mode_bt, dt_dx=dt, dt_dy=dt)
+    sched = args.schedule
+    tune_ms = None
+    if sched == "auto":
+        # execution choice only (identical streams): per-phase launches with
+        # or without the predictor choice fused into the phases, each eager
+        # and as a graph replay; the timed loop runs the winner eagerly so
+        # that its kernels can be timed one by one
+        (sched, _), tune_ms = cpt.autotune_batch([f], eb, reps=2, outs=[out], **opts)
+        log("autotune: %s (ms: %s)" % (sched, ", ".join("%.3f" % m for m in tune_ms)))
+
     def comp():
-        return cpt.compress(f, eb, predictor=args.predictor, mode_bt=args.mode_bt, dt_dx=dt, dt_dy=dt, out=out)
+        (st,), _ = cpt.compress_batch([f], eb, schedule=sched, outs=[out], **opts)
+        return st
 
     if args.calibration_copy:
         log("calibration copy of %d bytes" % raw)
@@ -122,14 +247,8 @@ def main():
     cpt.timing_enable(False)
     value = args.steps * raw / elapsed / 1e9
 
-    ms, n, units = fam["phase"]
-    avg_ms = ms / max(n, 1)
-    per_launch = units / max(n, 1)
-    achieved = OPS_PER_FACE * FACES_PER_VERTEX * per_launch / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None, "kernel": "k_phase",
-                "avg_launch_us": round(avg_ms * 1e3, 3), "vertices_per_launch": round(per_launch, 1),
-                "ops_per_vertex": OPS_PER_FACE * FACES_PER_VERTEX}
+    kname = "k_phase_b<true>" if sched == "fused" else "k_phase_b<false>"
+    roofline = phase_roofline(fam, kname)
     kernels = {name: {"ms_per_step": round(m / args.steps, 4), "launches_per_step": c // max(args.steps, 1)}
                for name, (m, c, _) in fam.items() if c}
 
@@ -139,6 +258,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "i32+f64(exact)", "data": "synthetic",
         "config": {"workload": wl["name"], "shape_T_H_W": [T, H, W], "raw_bytes": raw, "eb_rel": eb,
                    "eb_abs": eb_abs, "predictor": args.predictor, "mode_bt": args.mode_bt,
+                   "schedule": sched, "tune_ms": tune_ms,
                    "CR": round(raw / clen, 4), "stream_bytes": clen, "fc_t": v["fc_t"], "fc_s": v["fc_s"],
                    "max_err": v["max_err"], "psnr": round(v["psnr"], 3),
                    "compress_ms": round(tc, 4), "decompress_ms": round(td, 4),

@@ -112,6 +112,75 @@ cpt_status cpt_compress_debug(const float* field, int H, int W, int T, double eb
                               uint8_t* out, size_t cap, size_t* out_len, int32_t* xi, uint8_t* xcode,
                               uint32_t* qcode, uint8_t* modes, float* feats, size_t* nblocks, void* stream);
 
+/* ---- Batches of independent fields and execution control ----
+ * A batch runs the compressor of cpt_compress over n fields of any sizes in
+ * one device pipeline: every launch covers all fields that take part in it,
+ * and nothing returns to the host before the final lengths.  The order of
+ * work inside a field is the one of Sec. V (frame by frame, three colour
+ * phases of 16x16 blocks per frame), so every stream is bit-identical to the
+ * one cpt_compress writes for that field alone, whatever the schedule.
+ * Schedules only change how that work is launched: */
+typedef enum {
+  CPT_SCHED_AUTO = 0,       /* the choice cpt_autotune_batch made for this
+                               batch shape, else CPT_SCHED_LAUNCH */
+  CPT_SCHED_LAUNCH = 1,     /* per frame: a predictor-choice launch, then
+                               one launch per colour phase */
+  CPT_SCHED_FUSED = 2,      /* per frame and colour: one launch that also
+                               chooses the predictor class of its blocks */
+  CPT_SCHED_PERSISTENT = 3  /* reserved: one persistent launch for all
+                               phases of all fields, workgroups waiting on
+                               per-field stage counters.  Disabled: returns
+                               CPT_EUNSUPPORTED */
+} cpt_schedule;
+
+typedef struct {
+  uint32_t struct_size;  /* sizeof(cpt_exec_options) */
+  int32_t schedule;      /* cpt_schedule (default CPT_SCHED_AUTO) */
+  int32_t group;         /* reserved for the persistent schedule (0) */
+  int32_t grid;          /* reserved for the persistent schedule (0) */
+  int32_t use_graph;     /* 1: record the call's device work as a HIP graph
+                            on first use and replay it on later calls with
+                            the same shapes, options and schedule */
+} cpt_exec_options;
+
+/*
+ * Compress n fields (1 <= n <= 65536) with shared eb and options.
+ *   fields  host array of n device pointers, field i of shape
+ *           (2, HWT[3i+2], HWT[3i], HWT[3i+1]) float32
+ *   HWT     host, 3n int32: H, W, T of each field (limits as cpt_compress)
+ *   ex      host, may be NULL for defaults
+ *   outs    host array of n device pointers (4-byte aligned), capacities
+ *           caps[i] bytes (host array)
+ *   lens    host, n: stream lengths (also when a stream did not fit)
+ *   status  host, n (may be NULL): per-field cpt_status
+ * Returns CPT_OK when every field succeeded, else the status of the first
+ * field that failed (message names it).  Fields that fail (non-finite
+ * values, magnitude, capacity) leave the others unaffected.  Synchronises
+ * `stream`.  Graph replays run on a library stream ordered after and
+ * before `stream` by events.
+ */
+cpt_status cpt_compress_batch(int n, const float* const* fields, const int32_t* HWT, double eb,
+                              const cpt_options* opt, const cpt_exec_options* ex, uint8_t* const* outs,
+                              const size_t* caps, size_t* lens, int32_t* status, void* stream);
+
+/* Number of execution choices cpt_autotune_batch times, in this order:
+ * LAUNCH, FUSED, LAUNCH replayed as a graph, FUSED replayed as a graph. */
+#define CPT_TUNE_CANDIDATES 4
+
+/*
+ * Time every candidate schedule on this batch (arguments as for
+ * cpt_compress_batch; the outputs are written), `reps` timed runs each after
+ * one warm-up, and remember the fastest for CPT_SCHED_AUTO calls with the
+ * same shapes and options (process-wide; graph replay is used when it won
+ * or when the call asks for it).  best (host) receives it; ms
+ * (host, CPT_TUNE_CANDIDATES entries, may be NULL) the mean device time per
+ * run of each candidate.  Only execution parameters are tuned; all
+ * candidates write identical streams.  Synchronises `stream`.
+ */
+cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* HWT, double eb,
+                              const cpt_options* opt, uint8_t* const* outs, const size_t* caps, int reps,
+                              cpt_exec_options* best, double* ms, void* stream);
+
 /* Parse a stream header (host bytes, at least 256). */
 cpt_status cpt_stream_info(const uint8_t* bytes, size_t len, cpt_info* info);
 

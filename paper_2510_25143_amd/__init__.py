@@ -45,6 +45,15 @@ class TrainOptions(ctypes.Structure):
                 ("lr", ctypes.c_float), ("seed", ctypes.c_uint64)]
 
 
+class ExecOptions(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("schedule", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+SCHEDULES = {"auto": 0, "launch": 1, "fused": 2, "persistent": 3}
+TUNE_CANDIDATES = [("launch", False), ("fused", False), ("launch", True), ("fused", True)]
+
+
 class VerifyResult(ctypes.Structure):
     _fields_ = [("fc_t", ctypes.c_uint64), ("fc_s", ctypes.c_uint64),
                 ("max_err", ctypes.c_double), ("psnr", ctypes.c_double)]
@@ -53,7 +62,7 @@ class VerifyResult(ctypes.Structure):
 EXPORTS = ["cpt_compress_bound", "cpt_compress", "cpt_compress_debug", "cpt_stream_info",
            "cpt_decompress", "cpt_extract_trajectories", "cpt_verify", "cpt_field_params",
            "cpt_selector_grad", "cpt_selector_train", "cpt_timing_enable", "cpt_timing_read",
-           "cpt_last_error"]
+           "cpt_compress_batch", "cpt_autotune_batch", "cpt_last_error"]
 
 _lib = None
 
@@ -80,6 +89,8 @@ def lib():
         "cpt_selector_train": [P, P, i32, P, P, P, P, P],
         "cpt_timing_enable": [i32],
         "cpt_timing_read": [i32, P, P, P],
+        "cpt_compress_batch": [i32, P, P, dbl, P, P, P, P, P, P, P],
+        "cpt_autotune_batch": [i32, P, P, dbl, P, P, P, i32, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -166,6 +177,60 @@ def compress_debug(field, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1
                                     _ptr(feats), ctypes.byref(nb), _stream()))
     return out[:n.value], dict(xi=xi, xcode=xcode, qcode=qcode, modes=modes[:nb.value],
                                feats=feats[:nb.value])
+
+
+def _batch_args(fields, outs):
+    fs = [_field(f) for f in fields]
+    n = len(fs)
+    if n == 0:
+        raise ValueError("empty batch")
+    hwt = (ctypes.c_int32 * (3 * n))()
+    for i, f in enumerate(fs):
+        _, T, H, W = f.shape
+        hwt[3 * i], hwt[3 * i + 1], hwt[3 * i + 2] = H, W, T
+    if outs is None:
+        outs = [torch.empty(compress_bound(f.shape[2], f.shape[3], f.shape[1]), dtype=torch.uint8, device=f.device)
+                for f in fs]
+    if len(outs) != n:
+        raise ValueError("need one output buffer per field")
+    fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+    op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    caps = (ctypes.c_size_t * n)(*[o.numel() for o in outs])
+    return fs, n, hwt, outs, fp, op, caps
+
+
+def compress_batch(fields, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
+                   selector_w=None, schedule="auto", group=0, grid=0, use_graph=False, outs=None,
+                   raise_on_error=True):
+    """Compress a list of fields (each (2,T,H,W) float32 CUDA) in one device
+    pipeline.  Returns (streams, status): streams[i] is a view of outs[i]
+    trimmed to its length (None when field i failed), status[i] its
+    cpt_status."""
+    fs, n, hwt, outs, fp, op, caps = _batch_args(fields, outs)
+    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w)
+    ex = ExecOptions(ctypes.sizeof(ExecOptions), SCHEDULES[schedule], group, grid, int(bool(use_graph)))
+    lens = (ctypes.c_size_t * n)()
+    st = (ctypes.c_int32 * n)()
+    r = lib().cpt_compress_batch(n, fp, hwt, eb, ctypes.byref(o), ctypes.byref(ex), op, caps, lens, st, _stream())
+    if r != OK and (raise_on_error or r not in (EINVAL, ECAPACITY)):
+        _check(r)
+    streams = [outs[i][:lens[i]] if st[i] == OK else None for i in range(n)]
+    return streams, [st[i] for i in range(n)]
+
+
+def autotune_batch(fields, eb, reps=2, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
+                   selector_w=None, outs=None):
+    """Time every candidate execution choice on this batch and remember the
+    fastest for schedule="auto".  Returns (best, ms): best = (schedule,
+    use_graph), ms the mean time per run of each of TUNE_CANDIDATES."""
+    fs, n, hwt, outs, fp, op, caps = _batch_args(fields, outs)
+    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w)
+    best = ExecOptions(ctypes.sizeof(ExecOptions), 0, 0, 0, 0)
+    ms = (ctypes.c_double * len(TUNE_CANDIDATES))()
+    _check(lib().cpt_autotune_batch(n, fp, hwt, eb, ctypes.byref(o), op, caps, reps, ctypes.byref(best), ms,
+                                    _stream()))
+    name = {v: k for k, v in SCHEDULES.items()}[best.schedule]
+    return (name, bool(best.use_graph)), list(ms)
 
 
 def stream_info(stream_bytes):

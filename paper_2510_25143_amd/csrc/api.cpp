@@ -12,12 +12,16 @@
 //   7 raw float32 values of lossless vertices and unpredictable components
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
+#include "batch.hpp"
 #include "cpt_device.hpp"
 #include "cptraj.h"
 #include "launch.hpp"
@@ -27,6 +31,7 @@ using namespace cpt;
 namespace {
 
 thread_local std::string g_err;
+thread_local bool g_capturing = false;  // inside a graph capture: no timing events
 
 cpt_status fail(cpt_status s, const std::string& m) {
   g_err = m;
@@ -39,19 +44,29 @@ cpt_status fail(cpt_status s, const std::string& m) {
     if (e_ != hipSuccess) return fail(CPT_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int HDR_SLOTS = 32;
-constexpr size_t HDR_BYTES = 8 * HDR_SLOTS;
-constexpr uint64_t MAGIC = 0x31545043ull;  // "CPT1"
-constexpr uint64_t VERSION = 1;
-constexpr int STRIDE = 2;
-
 // ------------------------------------------------------------ arena
+struct GraphEntry {
+  std::string key;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct Arena {
   char* base = nullptr;
   size_t cap = 0, used = 0;
   uint64_t* host = nullptr;  // pinned staging for small readbacks
   int64_t* tlog = nullptr;   // entropy table floor(h log2 h 2^16)
+  char* stage = nullptr;     // pinned staging for batch descriptors and tables
+  size_t stage_cap = 0;
+  hipStream_t lib = nullptr;  // library stream for graph replays and the persistent schedule
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<GraphEntry> graphs;  // most recent last
   std::mutex mu;
+
+  void drop_graphs() {
+    for (auto& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
 
   size_t off(size_t bytes) {
     size_t o = (used + 255) & ~(size_t)255;
@@ -105,6 +120,8 @@ struct Bufs {
   double* cpart;
 };
 
+cpt_status reserve(Arena& A);
+
 cpt_status carve(Arena& A, size_t N, size_t nblk, Bufs& b) {
   A.used = 0;
   size_t nchx = (N + CHUNK - 1) / CHUNK + 1, nchq = (2 * N + CHUNK - 1) / CHUNK + 1;
@@ -129,9 +146,18 @@ cpt_status carve(Arena& A, size_t N, size_t nblk, Bufs& b) {
   };
   std::vector<size_t> offs;
   for (auto& it : items) offs.push_back(A.off(it.bytes));
+  cpt_status st = reserve(A);
+  if (st) return st;
+  for (size_t i = 0; i < items.size(); i++) *items[i].p = A.base + offs[i];
+  return CPT_OK;
+}
+
+// grows the arena to A.used bytes (every earlier carve is invalidated)
+cpt_status reserve(Arena& A) {
   if (A.used > A.cap) {
     if (A.base) {
       if (hipDeviceSynchronize() != hipSuccess) return fail(CPT_EHIP, "synchronize before arena growth failed");
+      A.drop_graphs();
       (void)hipFree(A.base);
       A.base = nullptr;
       A.cap = 0;
@@ -143,7 +169,6 @@ cpt_status carve(Arena& A, size_t N, size_t nblk, Bufs& b) {
     }
     A.cap = want;
   }
-  for (size_t i = 0; i < items.size(); i++) *items[i].p = A.base + offs[i];
   return CPT_OK;
 }
 
@@ -246,32 +271,6 @@ cpt_status field_range(const float* f, size_t n, Bufs& b, Arena& A, hipStream_t 
 }
 
 // ------------------------------------------------------- small kernels
-struct Header {
-  uint64_t s[HDR_SLOTS];
-};
-
-__global__ void k_write_header(Header h, uint8_t* out) {
-  int i = threadIdx.x;
-  if (i < HDR_SLOTS) {
-    uint32_t* o = (uint32_t*)out;
-    o[2 * i] = (uint32_t)(h.s[i] & 0xFFFFFFFFu);
-    o[2 * i + 1] = (uint32_t)(h.s[i] >> 32);
-  }
-}
-
-__global__ void k_pack_modes(const uint8_t* modes, size_t nblk, int mb, uint32_t* out, size_t nwords) {
-  size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= nwords) return;
-  uint32_t v = 0;
-  for (int b = 0; b < 32; b++) {
-    size_t bit = w * 32 + b;
-    size_t blk = bit / mb;
-    int k = (int)(bit % mb);
-    if (blk < nblk && ((modes[blk] >> k) & 1)) v |= 1u << b;
-  }
-  out[w] = v;
-}
-
 __global__ void k_unpack_modes(const uint32_t* in, size_t nblk, int mb, int K, uint8_t* modes, uint32_t* err) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nblk) return;
@@ -339,7 +338,7 @@ struct TimeScope {
   hipStream_t s;
   hipEvent_t a = nullptr;
   TimeScope(int f, uint64_t u, hipStream_t st) : fam(f), units(u), s(st) {
-    if (!g_tim.on) return;
+    if (!g_tim.on || g_capturing) return;
     std::lock_guard<std::mutex> lk(g_tim.mu);
     a = g_tim.get();
     (void)hipEventRecord(a, s);
@@ -370,156 +369,506 @@ uint64_t colour_vertices(int H, int W, int c) {
 }
 
 // ------------------------------------------------------------ compress
-cpt_status compress_impl(const float* field, int H, int W, int T, double eb, const cpt_options* opt_in,
-                         uint8_t* out, size_t cap, size_t* out_len, int32_t* xi_dbg, uint8_t* xcode_dbg,
-                         uint32_t* qcode_dbg, uint8_t* modes_dbg, float* feats_dbg, size_t* nblocks,
-                         hipStream_t s) {
-  if (!field || !out_len) return fail(CPT_EINVAL, "null field or out_len");
-  cpt_status st = check_dims(H, W, T);
-  if (st) return st;
-  cpt_options opt{sizeof(cpt_options), 0, CPT_PRED_MIX2, 1, 1.0, 1.0, nullptr};
+// Everything about a batch that depends only on the dimensions and options.
+// The launch order lists the fields by decreasing T (ties by index), so the
+// fields still running at frame t are a prefix of it.
+struct Plan {
+  int n = 0;
+  cpt_options opt{};
+  int K = 1, maxT = 0;
+  std::vector<FieldDesc> D;
+  std::vector<int> ord;
+  std::vector<long long> rpre, vpre, hpre, cxpre, cqpre;  // natural order
+  std::vector<long long> mpre, ppre;                      // launch order
+  std::vector<int> m_at, mstate_at, gidx_at;              // per frame
+  std::vector<uint64_t> hw_at, cv_at;                     // vertices per frame / per phase
+  long long Ntot = 0, CX = 0, CQ = 0, NB = 0;
+  std::string key;
+  // persistent schedule
+  int group = 0;
+  std::vector<SchedSeg> seg;
+  std::vector<long long> sstart;
+  long long nitems = 0;
+};
+
+cpt_status check_options(const cpt_options* opt_in, double eb, cpt_options* opt) {
+  *opt = cpt_options{sizeof(cpt_options), 0, CPT_PRED_MIX2, 1, 1.0, 1.0, nullptr};
   if (opt_in) {
     if (opt_in->struct_size != sizeof(cpt_options)) return fail(CPT_EINVAL, "cpt_options.struct_size mismatch");
-    opt = *opt_in;
+    *opt = *opt_in;
   }
-  if (opt.predictor < 0 || opt.predictor > 4) return fail(CPT_EINVAL, "unknown predictor");
-  if (opt.mode_bt < 1 || opt.mode_bt > 1024) return fail(CPT_EINVAL, "mode_bt must be in 1..1024");
-  if (opt.predictor == CPT_PRED_LEARNED && !opt.selector_w) return fail(CPT_EINVAL, "learned predictor needs selector_w");
-  if (!(opt.dt_dx >= 0.0) || !(opt.dt_dy >= 0.0) || !std::isfinite(opt.dt_dx) || !std::isfinite(opt.dt_dy))
+  if (opt->predictor < 0 || opt->predictor > 4) return fail(CPT_EINVAL, "unknown predictor");
+  if (opt->mode_bt < 1 || opt->mode_bt > 1024) return fail(CPT_EINVAL, "mode_bt must be in 1..1024");
+  if (opt->predictor == CPT_PRED_LEARNED && !opt->selector_w)
+    return fail(CPT_EINVAL, "learned predictor needs selector_w");
+  if (!(opt->dt_dx >= 0.0) || !(opt->dt_dy >= 0.0) || !std::isfinite(opt->dt_dx) || !std::isfinite(opt->dt_dy))
     return fail(CPT_EINVAL, "dt_dx and dt_dy must be finite and non-negative");
-  if (out && ((uintptr_t)out & 3)) return fail(CPT_EINVAL, "out must be 4-byte aligned");
+  if (opt->eb_mode == 0) {
+    if (!(eb > 0.0 && eb <= 0.5)) return fail(CPT_EINVAL, "relative error bound must be in (0, 0.5]");
+  } else if (opt->eb_mode == 1) {
+    if (!(eb > 0.0) || !std::isfinite(eb)) return fail(CPT_EINVAL, "absolute error bound must be positive");
+  } else {
+    return fail(CPT_EINVAL, "eb_mode must be 0 or 1");
+  }
+  return CPT_OK;
+}
 
-  const size_t N = (size_t)H * W * T;
-  const int tx = (W + TILE - 1) / TILE, ty = (H + TILE - 1) / TILE;
-  const int K = opt.predictor == 2 ? 2 : (opt.predictor >= 3 ? 4 : 1);
-  const int bt = opt.mode_bt;
-  const int G = (T + bt - 1) / bt;
-  const size_t ndec = K > 1 ? (size_t)decided_before(G, bt, T) : 0;
-  const size_t nblk = ndec * (size_t)tx * ty;
+cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double eb, Plan& P) {
+  if (n < 1 || n > 65536) return fail(CPT_EINVAL, "batch size must be in 1..65536");
+  if (!HWT) return fail(CPT_EINVAL, "null HWT");
+  P.n = n;
+  P.opt = opt;
+  P.K = opt.predictor == 2 ? 2 : (opt.predictor >= 3 ? 4 : 1);
+  const int K = P.K, bt = opt.mode_bt, mb = mode_bits(K);
+  P.D.assign(n, FieldDesc{});
+  for (auto* v : {&P.rpre, &P.vpre, &P.hpre, &P.cxpre, &P.cqpre, &P.mpre, &P.ppre}) v->assign(n + 1, 0);
+  P.key = std::to_string(n) + ":" + std::to_string(opt.predictor) + ":" + std::to_string(bt);
+  for (int i = 0; i < n; i++) {
+    const int H = HWT[3 * i], W = HWT[3 * i + 1], T = HWT[3 * i + 2];
+    cpt_status st = check_dims(H, W, T);
+    if (st) return fail(st, "field " + std::to_string(i) + ": " + g_err);
+    FieldDesc& d = P.D[i];
+    d.H = H;
+    d.W = W;
+    d.T = T;
+    d.tx = (W + TILE - 1) / TILE;
+    d.ty = (H + TILE - 1) / TILE;
+    const long long N = (long long)H * W * T;
+    const int G = (T + bt - 1) / bt;
+    d.ndec = K > 1 ? decided_before(G, bt, T) : 0;
+    d.N = N;
+    d.voff = P.Ntot;
+    d.cxb = P.CX;
+    d.cqb = P.CQ;
+    d.mbase = P.NB;
+    d.nchx = (N + CHUNK - 1) / CHUNK;
+    const long long nblk = (long long)d.ndec * d.tx * d.ty;
+    d.mwords = (nblk * mb + 31) / 32;
+    d.eb_mode = opt.eb_mode;
+    d.predictor = opt.predictor;
+    d.K = K;
+    d.bt = bt;
+    d.eb = eb;
+    d.dt_dx = opt.dt_dx;
+    d.dt_dy = opt.dt_dy;
+    const long long ncq = (2 * N + CHUNK - 1) / CHUNK;
+    P.Ntot += N;
+    P.CX += d.nchx;
+    P.CQ += ncq;
+    P.NB += nblk;
+    P.rpre[i + 1] = P.rpre[i] + (2 * N + RANGE_SPAN_FLOATS - 1) / RANGE_SPAN_FLOATS;
+    P.vpre[i + 1] = P.vpre[i] + (N + 255) / 256;
+    P.hpre[i + 1] = P.hpre[i] + (N + HIST_SPAN_VERTICES - 1) / HIST_SPAN_VERTICES;
+    P.cxpre[i + 1] = P.cxpre[i] + d.nchx;
+    P.cqpre[i + 1] = P.cqpre[i] + ncq;
+    P.maxT = std::max(P.maxT, T);
+    P.key += ":" + std::to_string(H) + "x" + std::to_string(W) + "x" + std::to_string(T);
+  }
+  for (auto v : {P.rpre.back(), P.vpre.back(), P.hpre.back(), P.cxpre.back(), P.cqpre.back()})
+    if (v >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
+  P.ord.resize(n);
+  for (int i = 0; i < n; i++) P.ord[i] = i;
+  std::stable_sort(P.ord.begin(), P.ord.end(), [&](int a, int b) { return P.D[a].T > P.D[b].T; });
+  for (int j = 0; j < n; j++) {
+    const FieldDesc& d = P.D[P.ord[j]];
+    P.mpre[j + 1] = P.mpre[j] + (long long)d.tx * d.ty;
+    P.ppre[j + 1] = P.ppre[j] + (long long)phase_cols(d.tx) * d.ty;
+  }
+  if (P.mpre.back() >= 2147483647LL || P.ppre.back() >= 2147483647LL)
+    return fail(CPT_EINVAL, "batch too large for one launch");
+  const int T0 = P.maxT;
+  P.m_at.assign(T0, 0);
+  P.mstate_at.assign(T0, MODES_NONE);
+  P.gidx_at.assign(T0, 0);
+  P.hw_at.assign(T0, 0);
+  P.cv_at.assign(3 * (size_t)T0, 0);
+  int m = n;
+  for (int t = 0; t < T0; t++) {
+    while (m > 0 && P.D[P.ord[m - 1]].T <= t) m--;
+    P.m_at[t] = m;
+    // the predictor groups depend on t and bt only for the fields that
+    // reach frame t; checked field by field
+    int ms = MODES_NONE, gi = 0;
+    for (int j = 0; j < m; j++) {
+      const FieldDesc& d = P.D[P.ord[j]];
+      int msj = MODES_NONE, gij = 0;
+      if (K > 1 && t >= 1) {
+        const int g = t / bt;
+        if (group_decided(g, bt, d.T)) {
+          const int td = g * bt > 1 ? g * bt : 1;
+          msj = t == td ? MODES_DECIDE : MODES_READ;
+          gij = decided_before(g, bt, d.T);
+        }
+      }
+      if (j == 0) {
+        ms = msj;
+        gi = gij;
+      } else if (ms != msj || gi != gij) {
+        return fail(CPT_EHIP, "internal: predictor groups differ between fields of one frame");
+      }
+      P.hw_at[t] += (uint64_t)d.H * d.W;
+      for (int c = 0; c < 3; c++) P.cv_at[3 * t + c] += colour_vertices(d.H, d.W, c);
+    }
+    P.mstate_at[t] = ms;
+    P.gidx_at[t] = gi;
+  }
+  return CPT_OK;
+}
 
+cpt_status build_schedule(Plan& P, int group) {
+  if (P.group == group && !P.seg.empty()) return CPT_OK;
+  P.group = group;
+  P.seg.clear();
+  P.sstart.assign(1, 0);
+  std::vector<long long> items(P.n), nb(P.n);
+  for (int f = 0; f < P.n; f++) {
+    nb[f] = (long long)phase_cols(P.D[f].tx) * P.D[f].ty;
+    items[f] = (nb[f] + group - 1) / group;
+  }
+  for (int r = 0; r < 3 * P.maxT; r++) {
+    const int t = r / 3, c = r % 3;
+    for (int j = 0; j < P.m_at[t]; j++) {
+      const int f = P.ord[j];
+      const long long need = (long long)r * items[f];
+      if (need >= 4294967295LL) return fail(CPT_EINVAL, "field too large for the persistent schedule");
+      SchedSeg sg{f, t, c, P.mstate_at[t], P.gidx_at[t], (int)nb[f], (unsigned)need, 0};
+      P.seg.push_back(sg);
+      P.sstart.push_back(P.sstart.back() + items[f]);
+    }
+  }
+  P.nitems = P.sstart.back();
+  if (P.nitems >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for the persistent schedule");
+  return CPT_OK;
+}
+
+// Scratch of a batch.  The tables block (descriptors, launch order, prefix
+// tables, schedule) is contiguous and uploaded in one copy.  Edge signs and
+// face masks live in the bound-code and residual-code arrays, which the
+// phases overwrite only after the lossless flags are made.
+struct BatchBufs {
+  FieldDesc* D;
+  int* ord;
+  long long *rpre, *vpre, *hpre, *cxpre, *cqpre, *mpre, *ppre, *sstart;
+  SchedSeg* seg;
+  size_t tables_bytes;
+  unsigned *done, *ctl;
+  int4* range;
+  int2* cur;
+  uint8_t *flags, *xcode, *modes;
+  uint32_t* qcode;
+  EntropyBufs E;
+};
+
+template <typename T>
+size_t vec_bytes(const std::vector<T>& v) {
+  return v.size() * sizeof(T);
+}
+
+cpt_status carve_batch(Arena& A, const Plan& P, BatchBufs& b) {
+  A.used = 0;
+  const int n = P.n;
+  const size_t N = (size_t)P.Ntot, CX = (size_t)P.CX, CQ = (size_t)P.CQ;
+  struct Item {
+    void** p;
+    size_t bytes;
+  };
+  std::vector<Item> tables = {
+      {(void**)&b.D, sizeof(FieldDesc) * n}, {(void**)&b.ord, 4 * (size_t)n},
+      {(void**)&b.rpre, vec_bytes(P.rpre)},   {(void**)&b.vpre, vec_bytes(P.vpre)},
+      {(void**)&b.hpre, vec_bytes(P.hpre)},   {(void**)&b.cxpre, vec_bytes(P.cxpre)},
+      {(void**)&b.cqpre, vec_bytes(P.cqpre)}, {(void**)&b.mpre, vec_bytes(P.mpre)},
+      {(void**)&b.ppre, vec_bytes(P.ppre)},   {(void**)&b.sstart, 8 * (P.sstart.size() + 1)},
+      {(void**)&b.seg, sizeof(SchedSeg) * (P.seg.size() + 1)},
+  };
+  std::vector<Item> rest = {
+      {(void**)&b.done, 4 * (size_t)n + 64},   {(void**)&b.ctl, 64},
+      {(void**)&b.range, 16 * (size_t)n},       {(void**)&b.cur, 8 * N},
+      {(void**)&b.flags, N},                    {(void**)&b.xcode, N},
+      {(void**)&b.modes, (size_t)P.NB + 1},     {(void**)&b.qcode, 4 * N},
+      {(void**)&b.E.nonll, 4 * N},              {(void**)&b.E.qofs, 4 * N},
+      {(void**)&b.E.rcnt, 4 * N},               {(void**)&b.E.rofs, 4 * N},
+      {(void**)&b.E.qsym, 2 * CQ * CHUNK},      {(void**)&b.E.xbits, 4 * CX},
+      {(void**)&b.E.xwords, 4 * CX},            {(void**)&b.E.xwofs, 4 * CX},
+      {(void**)&b.E.qbits, 4 * CQ},             {(void**)&b.E.qwords, 4 * CQ},
+      {(void**)&b.E.qwofs, 4 * CQ},             {(void**)&b.E.part, 4 * (scan_partials_size(N) + 16)},
+      {(void**)&b.E.xhist, 128 * (size_t)n},    {(void**)&b.E.qhist, 4 * (size_t)QSYM * n},
+      {(void**)&b.E.xcb, 128 * (size_t)n},      {(void**)&b.E.qcb, 4 * (size_t)(QSYM + 4) * n},
+      {(void**)&b.E.used, 8 * (size_t)n},       {(void**)&b.E.xt, sizeof(HuffTables) * n},
+      {(void**)&b.E.qt, sizeof(HuffTables) * n},
+  };
+  std::vector<size_t> offs;
+  size_t t0 = 0;
+  for (size_t i = 0; i < tables.size(); i++) {
+    size_t o = A.off(tables[i].bytes);
+    if (i == 0) t0 = o;
+    offs.push_back(o);
+  }
+  b.tables_bytes = A.used - t0;
+  for (auto& it : rest) offs.push_back(A.off(it.bytes));
+  cpt_status st = reserve(A);
+  if (st) return st;
+  size_t k = 0;
+  for (auto& it : tables) *it.p = A.base + offs[k++];
+  for (auto& it : rest) *it.p = A.base + offs[k++];
+  return CPT_OK;
+}
+
+cpt_status reserve_stage(Arena& A, size_t bytes) {
+  if (bytes <= A.stage_cap) return CPT_OK;
+  if (A.stage) (void)hipHostFree(A.stage);
+  A.stage = nullptr;
+  A.stage_cap = 0;
+  size_t want = bytes + bytes / 4 + 4096;
+  if (hipHostMalloc((void**)&A.stage, want, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CPT_ENOMEM, "pinned staging allocation failed");
+  }
+  A.stage_cap = want;
+  return CPT_OK;
+}
+
+// copy the host tables into the staging buffer at the offsets of b
+void stage_tables(const Plan& P, const BatchBufs& b, char* stage) {
+  const char* base = (const char*)b.D;
+  auto put = [&](const void* dev, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(stage + ((const char*)dev - base), src, bytes);
+  };
+  put(b.D, P.D.data(), sizeof(FieldDesc) * P.n);
+  put(b.ord, P.ord.data(), 4 * (size_t)P.n);
+  put(b.rpre, P.rpre.data(), vec_bytes(P.rpre));
+  put(b.vpre, P.vpre.data(), vec_bytes(P.vpre));
+  put(b.hpre, P.hpre.data(), vec_bytes(P.hpre));
+  put(b.cxpre, P.cxpre.data(), vec_bytes(P.cxpre));
+  put(b.cqpre, P.cqpre.data(), vec_bytes(P.cqpre));
+  put(b.mpre, P.mpre.data(), vec_bytes(P.mpre));
+  put(b.ppre, P.ppre.data(), vec_bytes(P.ppre));
+  put(b.sstart, P.sstart.data(), vec_bytes(P.sstart));
+  put(b.seg, P.seg.data(), vec_bytes(P.seg));
+}
+
+struct ExecChoice {
+  int schedule = CPT_SCHED_LAUNCH, group = 1, grid = 0;
+  bool graph = false;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, ExecChoice> g_tuned;
+
+// The whole device pipeline of a batch, enqueued on s without any host
+// synchronisation.
+void enqueue_compress(const Plan& P, const BatchBufs& b, const ExecChoice& ex, const Arena& A, hipStream_t s) {
+  const int n = P.n;
+  BatchView B{b.D, b.ord, b.cur, b.flags, b.xcode, b.qcode, b.modes, A.tlog, P.opt.selector_w};
+  // Alg. 3: fixed point, crossed faces of the original field, lossless flags
+  {
+    TimeScope ts(FAM_EXTRACT, (uint64_t)P.Ntot, s);
+    launch_field_pass_b(b.D, n, b.rpre, P.rpre.back(), b.vpre, P.vpre.back(), b.range, b.cur, b.xcode, b.qcode,
+                        b.flags, s);
+  }
+  if (ex.schedule == CPT_SCHED_PERSISTENT) {
+    launch_zero_u32(b.done, (size_t)n, s);
+    launch_zero_u32(b.ctl, 16, s);
+    TimeScope ts(FAM_PHASE, (uint64_t)P.Ntot, s);
+    launch_persist(B, b.seg, b.sstart, (int)P.seg.size(), P.nitems, ex.group, ex.grid, b.done, b.ctl, s);
+  } else {
+    for (int t = 0; t < P.maxT; t++) {
+      const int m = P.m_at[t], gi = P.gidx_at[t];
+      int ms = P.mstate_at[t];
+      if (ex.schedule == CPT_SCHED_LAUNCH && ms == MODES_DECIDE) {
+        TimeScope ts(FAM_MODES, P.hw_at[t], s);
+        launch_modes_b(B, b.mpre, m, P.mpre[m], t, gi, s);
+        ms = MODES_READ;
+      }
+      for (int c = 0; c < 3; c++) {
+        TimeScope ts(FAM_PHASE, P.cv_at[3 * t + c], s);
+        launch_phase_b(B, b.ppre, m, P.ppre[m], t, c, ms, gi, ex.schedule == CPT_SCHED_FUSED, s);
+      }
+    }
+  }
+  // lossless_comp of Alg. 3: Huffman codes of both code streams, raw values
+  launch_codes_b(b.D, n, B, b.E, b.hpre, P.hpre.back(), b.vpre, P.vpre.back(), P.Ntot, s);
+  launch_chunks_b(b.D, n, B, b.E, b.cxpre, P.CX, b.cqpre, P.CQ, s);
+  {
+    TimeScope ts(FAM_ENCODE, (uint64_t)P.Ntot, s);
+    launch_assemble_b(b.D, n, B, b.E, b.cxpre, P.CX, b.cqpre, P.CQ, b.vpre, P.vpre.back(), s);
+  }
+}
+
+cpt_status library_stream(Arena& A) {
+  if (A.lib) return CPT_OK;
+  HIPCHK(hipStreamCreateWithFlags(&A.lib, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&A.ev[0], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&A.ev[1], hipEventDisableTiming));
+  return CPT_OK;
+}
+
+// replays (capturing first if needed) the pipeline as a graph on the
+// library stream, ordered after and before the work on s
+cpt_status run_graph(const Plan& P, const BatchBufs& b, const ExecChoice& ex, Arena& A, hipStream_t s) {
+  cpt_status st = library_stream(A);
+  if (st) return st;
+  char tag[160];
+  std::snprintf(tag, sizeof(tag), "|%d:%d:%d|%p:%zu|%p:%p", ex.schedule, ex.group, ex.grid, (void*)A.base, A.cap,
+                (const void*)P.opt.selector_w, (void*)A.tlog);
+  const std::string key = P.key + tag;
+  hipGraphExec_t exec = nullptr;
+  for (size_t i = 0; i < A.graphs.size(); i++)
+    if (A.graphs[i].key == key) {
+      GraphEntry e = A.graphs[i];
+      A.graphs.erase(A.graphs.begin() + i);
+      A.graphs.push_back(e);
+      exec = e.exec;
+      break;
+    }
+  if (!exec) {
+    HIPCHK(hipStreamBeginCapture(A.lib, hipStreamCaptureModeThreadLocal));
+    g_capturing = true;
+    enqueue_compress(P, b, ex, A, A.lib);
+    g_capturing = false;
+    hipGraph_t g = nullptr;
+    hipError_t e1 = hipStreamEndCapture(A.lib, &g);
+    if (e1 != hipSuccess || !g) return fail(CPT_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e1));
+    hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(CPT_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e2));
+    if (A.graphs.size() >= 8) {
+      (void)hipGraphExecDestroy(A.graphs.front().exec);
+      A.graphs.erase(A.graphs.begin());
+    }
+    A.graphs.push_back({key, exec});
+  }
+  HIPCHK(hipEventRecord(A.ev[0], s));
+  HIPCHK(hipStreamWaitEvent(A.lib, A.ev[0], 0));
+  HIPCHK(hipGraphLaunch(exec, A.lib));
+  HIPCHK(hipEventRecord(A.ev[1], A.lib));
+  HIPCHK(hipStreamWaitEvent(s, A.ev[1], 0));
+  return CPT_OK;
+}
+
+struct Debug {
+  int32_t* xi = nullptr;
+  uint8_t* xcode = nullptr;
+  uint32_t* qcode = nullptr;
+  uint8_t* modes = nullptr;
+  float* feats = nullptr;
+  size_t* nblocks = nullptr;
+};
+
+ExecChoice resolve_exec(const cpt_exec_options* ex, const Plan& P) {
+  ExecChoice c;
+  int sched = CPT_SCHED_AUTO;
+  if (ex) {
+    sched = ex->schedule;
+    c.group = ex->group > 0 ? ex->group : 1;
+    c.grid = ex->grid;
+    c.graph = ex->use_graph != 0;
+  }
+  if (sched == CPT_SCHED_AUTO) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(P.key);
+    if (it != g_tuned.end()) {
+      c.schedule = it->second.schedule;
+      c.group = it->second.group;
+      c.grid = it->second.grid;
+      c.graph = c.graph || it->second.graph;
+    } else {
+      c.schedule = CPT_SCHED_LAUNCH;
+    }
+  } else {
+    c.schedule = sched;
+  }
+  return c;
+}
+
+const char* reason_text(int r) {
+  switch (r) {
+    case REASON_NONFINITE: return "field contains NaN or Inf";
+    case REASON_MAGNITUDE: return "field magnitude of 2^100 or more is not supported";
+    case REASON_CAPACITY: return "output capacity below the stream length";
+    default: return "failed";
+  }
+}
+
+// Compress n fields; lens / status are host arrays.  With dbg (n == 1) the
+// internals are copied out as well.
+cpt_status compress_batch_impl(int n, const float* const* fields, const int32_t* HWT, double eb,
+                               const cpt_options* opt_in, const cpt_exec_options* ex_in, uint8_t* const* outs,
+                               const size_t* caps, size_t* lens, int32_t* status, const Debug* dbg, hipStream_t s,
+                               const ExecChoice* forced = nullptr) {
+  if (!fields || !outs || !caps || !lens) return fail(CPT_EINVAL, "null argument");
+  if (ex_in && ex_in->struct_size != sizeof(cpt_exec_options))
+    return fail(CPT_EINVAL, "cpt_exec_options.struct_size mismatch");
+  cpt_options opt;
+  cpt_status st = check_options(opt_in, eb, &opt);
+  if (st) return st;
+  Plan P;
+  st = make_plan(n, HWT, opt, eb, P);
+  if (st) return st;
+  for (int i = 0; i < n; i++) {
+    if (!fields[i]) return fail(CPT_EINVAL, "field " + std::to_string(i) + ": null pointer");
+    if (outs[i] && ((uintptr_t)outs[i] & 3)) return fail(CPT_EINVAL, "out must be 4-byte aligned");
+    P.D[i].field = fields[i];
+    P.D[i].out = outs[i];
+    P.D[i].cap = (long long)std::min(caps[i], (size_t)1 << 62);
+  }
+  if (dbg && n == 1) {
+    P.D[0].xi_dbg = dbg->xi;
+    P.D[0].feats_dbg = dbg->feats;
+  }
+  ExecChoice ex = forced ? *forced : resolve_exec(ex_in, P);
+  if (ex.schedule < CPT_SCHED_LAUNCH || ex.schedule > CPT_SCHED_PERSISTENT) return fail(CPT_EINVAL, "unknown schedule");
+  if (ex.group < 1 || ex.group > 64) return fail(CPT_EINVAL, "group must be in 1..64");
+  if (ex.schedule == CPT_SCHED_PERSISTENT)
+    return fail(CPT_EUNSUPPORTED, "the persistent schedule is disabled: its inter-workgroup wait did not complete");
   Arena* Ap = arena_for_device(&st);
   if (!Ap) return st;
   Arena& A = *Ap;
   std::lock_guard<std::mutex> lk(A.mu);
-  Bufs b;
-  st = carve(A, N, nblk, b);
+  BatchBufs b;
+  st = carve_batch(A, P, b);
   if (st) return st;
-
-  Range r;
-  st = field_range(field, 2 * N, b, A, s, &r);
+  const size_t rb_off = (b.tables_bytes + 255) & ~(size_t)255;
+  const size_t rb_bytes = sizeof(FieldDesc) * n + 64;
+  st = reserve_stage(A, rb_off + rb_bytes);
   if (st) return st;
-  FieldParams p;
-  double eb_abs;
-  int64_t eps;
-  st = derive_params(r.mn, r.mx, r.ma, opt.eb_mode, eb, &p.k, &eb_abs, &eps);
-  if (st) return st;
-  p.H = H;
-  p.W = W;
-  p.T = T;
-  p.eps = (int)eps;
-  p.tx = tx;
-  p.ty = ty;
-  p.predictor = opt.predictor;
-  p.K = K;
-  p.bt = bt;
-  sl_factor(opt.dt_dx, p.k, &p.cx, &p.sx);
-  sl_factor(opt.dt_dy, p.k, &p.cy, &p.sy);
-
-  // Alg. 3: fixed point, crossed faces of the original field, lossless flags
-  launch_convert(field, N, p.k, b.cur, s);
-  {
-    TimeScope ts(FAM_EXTRACT, N, s);
-    launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
+  stage_tables(P, b, A.stage);
+  HIPCHK(hipMemcpyAsync(b.D, A.stage, b.tables_bytes, hipMemcpyHostToDevice, s));
+  if (ex.graph) {
+    st = run_graph(P, b, ex, A, s);
+    if (st) return st;
+  } else {
+    enqueue_compress(P, b, ex, A, s);
   }
-  launch_flags(b.masks, H, W, T, b.flags, s);
-
-  uint64_t cv[3] = {colour_vertices(H, W, 0), colour_vertices(H, W, 1), colour_vertices(H, W, 2)};
-  for (int t = 0; t < T; t++) {
-    int g = t / bt;
-    bool dec = K > 1 && group_decided(g, bt, T);
-    int td = g * bt > 1 ? g * bt : 1;
-    size_t gbase = dec ? (size_t)decided_before(g, bt, T) * tx * ty : 0;
-    if (dec && t == td) {
-      TimeScope ts(FAM_MODES, (uint64_t)H * W, s);
-      launch_modes(b.cur, b.flags, p, t, gbase, A.tlog, opt.selector_w, b.modes, feats_dbg, s);
-    }
-    long long mbase = (dec && t >= 1) ? (long long)gbase : -1;
-    for (int c = 0; c < 3; c++) {
-      TimeScope ts(FAM_PHASE, cv[c], s);
-      launch_phase(b.cur, b.flags, b.modes, mbase, p, t, c, b.xcode, b.qcode, xi_dbg, s);
-    }
+  if (dbg && n == 1) {
+    const size_t N = (size_t)P.Ntot;
+    if (dbg->xcode) HIPCHK(hipMemcpyAsync(dbg->xcode, b.xcode, N, hipMemcpyDeviceToDevice, s));
+    if (dbg->qcode) HIPCHK(hipMemcpyAsync(dbg->qcode, b.qcode, 4 * N, hipMemcpyDeviceToDevice, s));
+    if (dbg->modes && P.NB) HIPCHK(hipMemcpyAsync(dbg->modes, b.modes, (size_t)P.NB, hipMemcpyDeviceToDevice, s));
+    if (dbg->nblocks) *dbg->nblocks = (size_t)P.NB;
   }
-
-  // lossless_comp of Alg. 3: Huffman codes of both code streams, raw values
-  launch_hist(b.xcode, b.qcode, N, b.xhist, b.qhist, nullptr, nullptr, s);
-  launch_codebooks(b.xhist, b.qhist, b.xt, b.qt, b.xcb, b.qcb, b.used, s);
-  launch_raw_count(b.xcode, b.qcode, N, b.rcnt, b.nonll, s);
-  launch_scan(b.nonll, N, b.qofs, b.part, b.tot + 0, s);
-  launch_scan(b.rcnt, N, b.rofs, b.part, b.tot + 1, s);
-  HIPCHK(hipMemcpyAsync(A.host, b.tot, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(A.host + 1, b.used, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const uint32_t* h32 = (const uint32_t*)A.host;
-  const size_t n_nonll = h32[0], n_raw = h32[1], used_x = h32[2], used_q = h32[3];
-  const size_t nq = 2 * n_nonll;
-  const size_t nchx = (N + CHUNK - 1) / CHUNK, nchq = (nq + CHUNK - 1) / CHUNK;
-  launch_gather_q(b.xcode, b.qcode, b.qofs, N, b.qsym, s);
-  launch_chunk_bits_x(b.xcode, N, b.xt, b.xbits, b.xwords, s);
-  launch_chunk_bits_q(b.qsym, nq, b.qt, b.qbits, b.qwords, s);
-  launch_scan(b.xwords, nchx, b.xwofs, b.part, b.tot + 2, s);
-  launch_scan(b.qwords, nchq, b.qwofs, b.part, b.tot + 3, s);
-  HIPCHK(hipMemcpyAsync(A.host, b.tot + 2, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const size_t words_x = h32[0], words_q = h32[1];
-
-  const int mb = mode_bits(K);
-  const size_t mwords = (nblk * mb + 31) / 32;
-  uint64_t sec[8] = {4 * mwords,  4 * (1 + used_x), 4 * nchx, 4 * words_x,
-                     4 * (1 + used_q), 4 * nchq,    4 * words_q, 4 * n_raw};
-  size_t off[8], total = HDR_BYTES;
-  for (int i = 0; i < 8; i++) {
-    off[i] = total;
-    total += sec[i];
-  }
-  *out_len = total;
-  if (nblocks) *nblocks = nblk;
-  if (!out || total > cap) {
-    HIPCHK(hipStreamSynchronize(s));
-    return fail(CPT_ECAPACITY, "output capacity " + std::to_string(cap) + " below stream length " +
-                                   std::to_string(total));
-  }
-  if (mwords) k_pack_modes<<<nb256(mwords), 256, 0, s>>>(b.modes, nblk, mb, (uint32_t*)(out + off[0]), mwords);
-  HIPCHK(hipMemcpyAsync(out + off[1], b.xcb, sec[1], hipMemcpyDeviceToDevice, s));
-  if (sec[2]) HIPCHK(hipMemcpyAsync(out + off[2], b.xbits, sec[2], hipMemcpyDeviceToDevice, s));
-  {
-    TimeScope ts(FAM_ENCODE, N, s);
-    launch_encode_x(b.xcode, N, b.xt, b.xwofs, (uint32_t*)(out + off[3]), s);
-  }
-  HIPCHK(hipMemcpyAsync(out + off[4], b.qcb, sec[4], hipMemcpyDeviceToDevice, s));
-  if (sec[5]) HIPCHK(hipMemcpyAsync(out + off[5], b.qbits, sec[5], hipMemcpyDeviceToDevice, s));
-  {
-    TimeScope ts(FAM_ENCODE, nq, s);
-    launch_encode_q(b.qsym, nq, b.qt, b.qwofs, (uint32_t*)(out + off[6]), s);
-  }
-  launch_raw(field, b.xcode, b.qcode, b.rofs, N, (uint32_t*)(out + off[7]), s);
-  Header hd;
-  uint64_t ebits;
-  std::memcpy(&ebits, &eb_abs, 8);
-  uint64_t slots[HDR_SLOTS] = {MAGIC | (VERSION << 32), (uint64_t)H, (uint64_t)W, (uint64_t)T,
-                               (uint64_t)(int64_t)p.k, ebits, (uint64_t)eps, (uint64_t)QR, (uint64_t)TILE,
-                               (uint64_t)p.predictor, (uint64_t)bt, (uint64_t)K, (uint64_t)p.cx, (uint64_t)p.sx,
-                               (uint64_t)p.cy, (uint64_t)p.sy, (uint64_t)NMAX, (uint64_t)CHUNK, (uint64_t)MAXLEN,
-                               (uint64_t)STRIDE, sec[0], sec[1], sec[2], sec[3], sec[4], sec[5], sec[6], sec[7],
-                               nq, n_raw, total, 0};
-  std::memcpy(hd.s, slots, sizeof(slots));
-  k_write_header<<<1, 64, 0, s>>>(hd, out);
-  if (xcode_dbg) HIPCHK(hipMemcpyAsync(xcode_dbg, b.xcode, N, hipMemcpyDeviceToDevice, s));
-  if (qcode_dbg) HIPCHK(hipMemcpyAsync(qcode_dbg, b.qcode, 4 * N, hipMemcpyDeviceToDevice, s));
-  if (modes_dbg && nblk) HIPCHK(hipMemcpyAsync(modes_dbg, b.modes, nblk, hipMemcpyDeviceToDevice, s));
+  char* rb = A.stage + rb_off;
+  HIPCHK(hipMemcpyAsync(rb, b.D, sizeof(FieldDesc) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(rb + sizeof(FieldDesc) * n, b.ctl, 16, hipMemcpyDeviceToHost, s));
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   harvest_timing();
-  return CPT_OK;
+  const FieldDesc* Dh = (const FieldDesc*)rb;
+  const uint32_t* ctl = (const uint32_t*)(rb + sizeof(FieldDesc) * n);
+  if (ex.schedule == CPT_SCHED_PERSISTENT && ctl[1])
+    return fail(CPT_EHIP, "persistent schedule gave up waiting for a stage (spin budget exhausted)");
+  cpt_status first = CPT_OK;
+  for (int i = 0; i < n; i++) {
+    lens[i] = (size_t)Dh[i].len;
+    if (status) status[i] = Dh[i].status;
+    if (Dh[i].status && first == CPT_OK) {
+      first = (cpt_status)Dh[i].status;
+      std::string m = reason_text(Dh[i].reason);
+      if (Dh[i].reason == REASON_CAPACITY)
+        m = "output capacity " + std::to_string(caps[i]) + " below stream length " + std::to_string(Dh[i].len);
+      g_err = n > 1 ? "field " + std::to_string(i) + ": " + m : m;
+    }
+  }
+  return first;
 }
 
 // ----------------------------------------------------------- stream info
@@ -539,12 +888,12 @@ cpt_status parse_header(const uint8_t* h, size_t len, Parsed* P) {
   if (len < HDR_BYTES) return fail(CPT_ECORRUPT, "stream shorter than its header");
   uint64_t s[HDR_SLOTS];
   for (int i = 0; i < HDR_SLOTS; i++) s[i] = rd64(h + 8 * i);
-  if (s[0] != (MAGIC | (VERSION << 32))) return fail(CPT_ECORRUPT, "bad magic or version");
+  if (s[0] != (STREAM_MAGIC | (STREAM_VERSION << 32))) return fail(CPT_ECORRUPT, "bad magic or version");
   if (s[1] < 2 || s[2] < 2 || s[3] < 1 || s[1] > 32768 || s[2] > 32768 || s[3] > (1u << 20))
     return fail(CPT_ECORRUPT, "bad dimensions");
   if ((double)s[1] * (double)s[2] * (double)s[3] >= 2147483648.0) return fail(CPT_ECORRUPT, "too many vertices");
   if (s[7] != (uint64_t)QR || s[8] != (uint64_t)TILE || s[16] != (uint64_t)NMAX || s[17] != (uint64_t)CHUNK ||
-      s[18] != (uint64_t)MAXLEN || s[19] != (uint64_t)STRIDE)
+      s[18] != (uint64_t)MAXLEN || s[19] != (uint64_t)SL_STRIDE)
     return fail(CPT_ECORRUPT, "unsupported format constants");
   int64_t k = (int64_t)s[4];
   if (k < -80 || k > 120) return fail(CPT_ECORRUPT, "bad exponent");
@@ -830,8 +1179,10 @@ cpt_status cpt_compress_bound(int H, int W, int T, size_t* max_bytes) {
 cpt_status cpt_compress(const float* field, int H, int W, int T, double eb, const cpt_options* opt, uint8_t* out,
                         size_t cap, size_t* out_len, void* stream) {
   try {
-    return compress_impl(field, H, W, T, eb, opt, out, cap, out_len, nullptr, nullptr, nullptr, nullptr, nullptr,
-                         nullptr, (hipStream_t)stream);
+    if (!out_len) return fail(CPT_EINVAL, "null out_len");
+    const int32_t hwt[3] = {H, W, T};
+    return compress_batch_impl(1, &field, hwt, eb, opt, nullptr, &out, &cap, out_len, nullptr, nullptr,
+                               (hipStream_t)stream);
   } catch (...) {
     return fail(CPT_EHIP, "unexpected exception");
   }
@@ -841,8 +1192,92 @@ cpt_status cpt_compress_debug(const float* field, int H, int W, int T, double eb
                               uint8_t* out, size_t cap, size_t* out_len, int32_t* xi, uint8_t* xcode,
                               uint32_t* qcode, uint8_t* modes, float* feats, size_t* nblocks, void* stream) {
   try {
-    return compress_impl(field, H, W, T, eb, opt, out, cap, out_len, xi, xcode, qcode, modes, feats, nblocks,
-                         (hipStream_t)stream);
+    if (!out_len) return fail(CPT_EINVAL, "null out_len");
+    const int32_t hwt[3] = {H, W, T};
+    Debug dbg;
+    dbg.xi = xi;
+    dbg.xcode = xcode;
+    dbg.qcode = qcode;
+    dbg.modes = modes;
+    dbg.feats = feats;
+    dbg.nblocks = nblocks;
+    return compress_batch_impl(1, &field, hwt, eb, opt, nullptr, &out, &cap, out_len, nullptr, &dbg,
+                               (hipStream_t)stream);
+  } catch (...) {
+    return fail(CPT_EHIP, "unexpected exception");
+  }
+}
+
+cpt_status cpt_compress_batch(int n, const float* const* fields, const int32_t* HWT, double eb,
+                              const cpt_options* opt, const cpt_exec_options* ex, uint8_t* const* outs,
+                              const size_t* caps, size_t* lens, int32_t* status, void* stream) {
+  try {
+    return compress_batch_impl(n, fields, HWT, eb, opt, ex, outs, caps, lens, status, nullptr, (hipStream_t)stream);
+  } catch (...) {
+    return fail(CPT_EHIP, "unexpected exception");
+  }
+}
+
+cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* HWT, double eb,
+                              const cpt_options* opt_in, uint8_t* const* outs, const size_t* caps, int reps,
+                              cpt_exec_options* best, double* ms, void* stream) {
+  try {
+    if (!best || reps < 1 || n < 1) return fail(CPT_EINVAL, "bad autotune arguments");
+    hipStream_t s = (hipStream_t)stream;
+    cpt_options opt;
+    cpt_status st = check_options(opt_in, eb, &opt);
+    if (st) return st;
+    Plan P;
+    st = make_plan(n, HWT, opt, eb, P);
+    if (st) return st;
+    const ExecChoice cand[CPT_TUNE_CANDIDATES] = {{CPT_SCHED_LAUNCH, 1, 0, false},
+                                                  {CPT_SCHED_FUSED, 1, 0, false},
+                                                  {CPT_SCHED_LAUNCH, 1, 0, true},
+                                                  {CPT_SCHED_FUSED, 1, 0, true}};
+    std::vector<size_t> lens(n), ref;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int bi = -1;
+    double bms = 0;
+    for (int c = 0; c < CPT_TUNE_CANDIDATES; c++) {
+      st = compress_batch_impl(n, fields, HWT, eb, &opt, nullptr, outs, caps, lens.data(), nullptr, nullptr, s,
+                               &cand[c]);
+      if (st) break;
+      if (ref.empty()) ref = lens;
+      if (lens != ref) {
+        st = fail(CPT_EHIP, "internal: schedules disagree on stream lengths");
+        break;
+      }
+      float tot = 0.f;
+      for (int r = 0; r < reps && !st; r++) {
+        (void)hipEventRecord(e0, s);
+        st = compress_batch_impl(n, fields, HWT, eb, &opt, nullptr, outs, caps, lens.data(), nullptr, nullptr, s,
+                                 &cand[c]);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        tot += t;
+      }
+      if (st) break;
+      const double m = tot / reps;
+      if (ms) ms[c] = m;
+      if (bi < 0 || m < bms) {
+        bi = c;
+        bms = m;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    ExecChoice b = cand[bi];
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tuned[P.key] = b;
+    }
+    *best = cpt_exec_options{sizeof(cpt_exec_options), b.schedule, b.group, b.grid, b.graph ? 1 : 0};
+    return CPT_OK;
   } catch (...) {
     return fail(CPT_EHIP, "unexpected exception");
   }

@@ -1,0 +1,129 @@
+// batch.hpp — per-field descriptors for the device-driven compression path.
+//
+// Compression of one field or of many fields of uneven sizes runs the same
+// kernels: every launch covers all fields that take part in it, every
+// workgroup finds its field in a prefix table of per-field workgroup counts,
+// and every data-dependent quantity (fixed-point exponent, bound, stream
+// layout, lengths) lives in device memory.  The host only enqueues work, so
+// a whole batch can be captured into one HIP graph and replayed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "launch.hpp"
+
+namespace cpt {
+
+// per-field status (the cpt_status values) and failure reasons
+enum { STATUS_OK = 0, STATUS_EINVAL = -1, STATUS_ECAPACITY = -4 };
+enum { REASON_NONE = 0, REASON_NONFINITE = 1, REASON_MAGNITUDE = 2, REASON_CAPACITY = 3 };
+
+// stream format: a header of 32 little-endian 64-bit slots, then 8 sections
+constexpr int HDR_SLOTS = 32;
+constexpr size_t HDR_BYTES = 8 * HDR_SLOTS;
+constexpr uint64_t STREAM_MAGIC = 0x31545043ull;  // "CPT1"
+constexpr uint64_t STREAM_VERSION = 1;
+constexpr int SL_STRIDE = 2;  // stride of the rate-estimate subgrid
+
+struct FieldDesc {
+  // fixed by the dimensions and the call (host)
+  int H, W, T, tx, ty;
+  int ndec;              // decided predictor groups
+  long long N;           // vertices
+  long long voff;        // first vertex in the concatenated vertex arrays
+  long long cxb;         // first bound-code chunk in the concatenated chunk arrays
+  long long cqb;         // first residual-code chunk (room for 2N symbols)
+  long long mbase;       // first predictor block in the concatenated mode array
+  long long nchx;        // bound-code chunks
+  long long mwords;      // words of the predictor-class section
+  const float* field;    // input (2,T,H,W)
+  uint8_t* out;          // output stream
+  long long cap;         // its capacity in bytes
+  int32_t* xi_dbg;       // optional per-vertex bounds
+  float* feats_dbg;      // optional per-block features
+  int eb_mode, predictor, K, bt;
+  double eb, dt_dx, dt_dy;
+  // derived on the device
+  FieldParams p;
+  double eb_abs;
+  int status, reason;
+  long long len;         // stream length (also when it does not fit)
+  long long sec[8];      // section lengths in bytes
+  long long off[8];      // section offsets in bytes
+  long long nq, nraw, nchq;
+};
+
+// What the kernels of one launch see: the descriptors, the order in which
+// the launch visits the fields, and the concatenated scratch arrays.
+struct BatchView {
+  FieldDesc* D;
+  const int* ord;
+  int2* cur;
+  uint8_t* flags;
+  uint8_t* xcode;
+  uint32_t* qcode;
+  uint8_t* modes;
+  const int64_t* tlog;
+  const uint16_t* selw;
+};
+
+// Predictor classes available to a phase of frame t.
+enum { MODES_NONE = 0, MODES_READ = 1, MODES_DECIDE = 2 };
+
+// One stage (frame t, colour c) of one field in the persistent schedule.
+struct SchedSeg {
+  int f, t, c, mstate, gidx, nb;
+  unsigned need;  // items of the field that finish before this stage may start
+  int pad;
+};
+
+// index j with pre[j] <= e < pre[j + 1], for pre[0] = 0 <= e < pre[n]
+__device__ __forceinline__ int find_field(const long long* pre, int n, long long e) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// column-padded colour-phase grid of a field: (tx + 2) / 3 workgroups per row
+__host__ __device__ __forceinline__ int phase_cols(int tx) { return (tx + 2) / 3; }
+
+// launchers (k_field.hip)
+void launch_field_pass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* vpre,
+                         long long vblocks, int4* range, int2* cur, uint8_t* edges, uint32_t* masks, uint8_t* flags,
+                         hipStream_t s);
+constexpr long long RANGE_SPAN_FLOATS = 256 * 256;
+
+// launchers (k_entropy.hip); vpre: 256-vertex workgroups per field, hpre:
+// HIST_SPAN-vertex workgroups, cxpre / cqpre: bound-code / residual-code
+// chunk capacity per field
+constexpr long long HIST_SPAN_VERTICES = 256 * 16;
+struct EntropyBufs {
+  uint32_t *xhist, *qhist, *xcb, *qcb, *used;
+  HuffTables *xt, *qt;
+  uint32_t *nonll, *qofs, *rcnt, *rofs;
+  uint16_t* qsym;
+  uint32_t *xbits, *xwords, *xwofs, *qbits, *qwords, *qwofs;
+  uint32_t* part;
+};
+void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* hpre,
+                    long long hblocks, const long long* vpre, long long vblocks, long long Ntot, hipStream_t s);
+void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
+                     long long cxtot, const long long* cqpre, long long cqtot, hipStream_t s);
+void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
+                       long long cxtot, const long long* cqpre, long long cqtot, const long long* vpre,
+                       long long vblocks, hipStream_t s);
+
+// launchers (k_compress.hip)
+void launch_modes_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int gidx,
+                    hipStream_t s);
+void launch_phase_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int c,
+                    int mstate, int gidx, bool fused, hipStream_t s);
+// workgroups of the persistent kernel that fit on the current device at once
+int persist_grid();
+void launch_persist(const BatchView& B, const SchedSeg* seg, const long long* sstart, int nseg, long long nitems,
+                    int group, int grid, unsigned* done, unsigned* ctl, hipStream_t s);
+
+}  // namespace cpt

@@ -17,6 +17,9 @@
 // block processed before it; their bounds are computed for the whole block
 // in parallel first.  The other 14 are computed during the sweep, one face
 // per lane, sixteen lanes per vertex.
+#include <type_traits>
+
+#include "batch.hpp"
 #include "cpt_device.hpp"
 #include "launch.hpp"
 #include "predict.hpp"
@@ -84,20 +87,39 @@ __device__ __forceinline__ float bf16f(uint16_t h) { return __uint_as_float((uin
 // (Sec. VI-B): Lorenzo writes its reconstruction back to a candidate buffer
 // (anti-diagonal sweep), semi-Lagrangian reads only the previous frame.  The
 // rate score of each candidate uses the codes on the stride-2 subgrid.
-__global__ __launch_bounds__(256) void k_modes(const int2* __restrict__ cur, const uint8_t* __restrict__ flags,
-                                               FieldParams p, int t, size_t group_base,
-                                               const int64_t* __restrict__ tlog,
-                                               const uint16_t* __restrict__ selw, uint8_t* __restrict__ modes,
-                                               float* __restrict__ feats) {
-  __shared__ int2 C[TILE][TILE];
-  __shared__ int2 P[TILE][TILE];
-  __shared__ int64_t red[256];
-  __shared__ int64_t R[4];
-  __shared__ float fin[10];
-  __shared__ float h1[64], h2[64], lg[4];
+// The choice reads only the block's own values of frame t and the final
+// frame t-1, so it may run right before the block's own colour phase.
+struct ModesSmem {
+  int2 C[TILE][TILE];
+  int2 P[TILE][TILE];
+  int64_t red[256];
+  int64_t R[4];
+  int64_t part[4][3];
+  float fin[10];
+  float h1[64], h2[64], lg[4];
+  int CU[2][TILE][TILE];
+  int SAMP[4][128];
+  int cls;
+};
 
+// cur, flags: the field's arrays; mrow: its predictor classes of frame t's
+// group (block by * tx + bx); feats: the group's feature rows or null.
+// Called by all 256 threads; returns the class of the block.
+__device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint8_t* __restrict__ flags,
+                          const FieldParams& p, int t, int bx, int by, const int64_t* __restrict__ tlog,
+                          const uint16_t* __restrict__ selw, uint8_t* mrow, float* __restrict__ feats) {
+  auto& C = S.C;
+  auto& P = S.P;
+  auto& R = S.R;
+  auto& fin = S.fin;
+  auto& h1 = S.h1;
+  auto& h2 = S.h2;
+  auto& lg = S.lg;
+  auto& CU = S.CU;
+  auto& SAMP = S.SAMP;
+  auto& part = S.part;
+  int64_t* red = S.red;
   const int tid = threadIdx.x, lx = tid & 15, ly = tid >> 4;
-  const int bx = blockIdx.x, by = blockIdx.y;
   const int x0 = bx * TILE, y0 = by * TILE, x = x0 + lx, y = y0 + ly;
   const int H = p.H, W = p.W;
   const size_t HW = (size_t)H * W;
@@ -166,7 +188,7 @@ __global__ __launch_bounds__(256) void k_modes(const int2* __restrict__ cur, con
       for (int i = 0; i < 10; i++) fin[i] = (float)q[i] / 256.0f;
     }
     __syncthreads();
-    size_t bi = group_base + (size_t)by * p.tx + bx;
+    const size_t bi = (size_t)by * p.tx + bx;
     if (feats != nullptr && tid < 10) feats[bi * 10 + tid] = fin[tid];
     if (p.predictor == 4) {
       // 10-64-64-4 MLP, bf16 weights, fp32 fused multiply-add in input order
@@ -195,8 +217,14 @@ __global__ __launch_bounds__(256) void k_modes(const int2* __restrict__ cur, con
     }
   }
   if (p.predictor == 4) {
-    if (tid == 0) modes[group_base + (size_t)by * p.tx + bx] = (uint8_t)cls_learned;
-    return;
+    if (tid == 0) {
+      mrow[(size_t)by * p.tx + bx] = (uint8_t)cls_learned;
+      S.cls = cls_learned;
+    }
+    __syncthreads();
+    const int r = S.cls;
+    __syncthreads();
+    return r;
   }
 
   // ---------------- exhaustive trial over the K candidates
@@ -205,8 +233,6 @@ __global__ __launch_bounds__(256) void k_modes(const int2* __restrict__ cur, con
   // candidates are computed by every thread for its own vertex.  Codes of
   // the stride-2 subgrid go to SAMP[class][0..127] (slot 2 i + component of
   // subgrid point i; -1 when absent).
-  __shared__ int CU[2][TILE][TILE];
-  __shared__ int SAMP[4][128];
   for (int i = tid; i < 4 * 128; i += 256) (&SAMP[0][0])[i] = -1;
   CU[0][ly][lx] = X.x;
   CU[1][ly][lx] = X.y;
@@ -272,7 +298,6 @@ __global__ __launch_bounds__(256) void k_modes(const int2* __restrict__ cur, con
       nvalid += __shfl_xor(nvalid, o);
       nover += __shfl_xor(nover, o);
     }
-    __shared__ int64_t part[4][3];
     if ((tid & 63) == 0) {
       part[tid >> 6][0] = tsum;
       part[tid >> 6][1] = nvalid;
@@ -295,8 +320,13 @@ __global__ __launch_bounds__(256) void k_modes(const int2* __restrict__ cur, con
     for (int c = 2; c < p.K; c++)
       if (R[c] < R[best]) best = c;
     int cls = 1000 * (R[0] - R[best]) > 3 * R[0] ? best : 0;
-    modes[group_base + (size_t)by * p.tx + bx] = (uint8_t)cls;
+    mrow[(size_t)by * p.tx + bx] = (uint8_t)cls;
+    S.cls = cls;
   }
+  __syncthreads();
+  const int r = S.cls;
+  __syncthreads();
+  return r;
 }
 
 // --------------------------------------------------------------- the phase
@@ -393,21 +423,34 @@ __device__ __forceinline__ void face_update(int& xi, int2 me, int2 n0, int2 n1, 
   xi = min(xi, max(e, relax));
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_phase(int2* __restrict__ cur, const uint8_t* __restrict__ flags,
-                                               const uint8_t* __restrict__ modes, long long mode_base,
-                                               FieldParams p, int t, int colour, uint8_t* __restrict__ xcode,
-                                               uint32_t* __restrict__ qcode, int32_t* __restrict__ xi_dbg) {
-  __shared__ int2 V[3][HALO][HALO];  // frames t-1, t, t+1 around the block
-  __shared__ int XS[TILE][TILE];     // bound from the faces fixed for the whole sweep; -1 = lossless
-  __shared__ int2 SLP[TILE][TILE];   // semi-Lagrangian predictions
-  __shared__ uint32_t OQ[TILE][TILE];  // outputs, written once after the sweep
-  __shared__ int OX[TILE][TILE];
-  __shared__ uint8_t OC[TILE][TILE];
+struct PhaseSmem {
+  int2 V[3][HALO][HALO];  // frames t-1, t, t+1 around the block
+  int XS[TILE][TILE];     // bound from the faces fixed for the whole sweep; -1 = lossless
+  int2 SLP[TILE][TILE];   // semi-Lagrangian predictions
+  uint32_t OQ[TILE][TILE];  // outputs, written once after the sweep
+  int OX[TILE][TILE];
+  uint8_t OC[TILE][TILE];
+};
+
+union TileSmem {
+  ModesSmem m;
+  PhaseSmem p;
+};
+
+// One block (bx, by) of frame t with predictor class cls; cur, flags, xcode,
+// qcode and xi_dbg point at the field's own arrays.  Called by all 256
+// threads; ends with a barrier, so the shared memory may be reused at once.
+__device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur, const uint8_t* __restrict__ flags,
+                                           const FieldParams& p, int t, int bx, int by, int cls,
+                                           uint8_t* __restrict__ xcode, uint32_t* __restrict__ qcode,
+                                           int32_t* __restrict__ xi_dbg) {
+  auto& V = S.V;
+  auto& XS = S.XS;
+  auto& SLP = S.SLP;
+  auto& OQ = S.OQ;
+  auto& OX = S.OX;
+  auto& OC = S.OC;
   const int tid = threadIdx.x;
-  const int by = blockIdx.y;
-  const int b0 = ((colour - by) % 3 + 3) % 3;
-  const int bx = b0 + 3 * (int)blockIdx.x;
-  if (bx >= p.tx) return;
   const int H = p.H, W = p.W, T = p.T;
   const size_t HW = (size_t)H * W;
   const int x0 = bx * TILE, y0 = by * TILE;
@@ -424,11 +467,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     if (!corner && gx >= 0 && gx < W && gy >= 0 && gy < H && tt >= 0 && tt < T)
       v = cur[(size_t)tt * HW + (size_t)gy * W + gx];
     V[f][hy][hx] = v;
-  }
-  int cls = 0;
-  if (t >= 1) {
-    if (p.predictor == 1) cls = 1;
-    else if (mode_base >= 0) cls = modes[(size_t)mode_base + (size_t)by * p.tx + bx];
   }
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
   __syncthreads();
@@ -546,20 +584,190 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
       if (xi_dbg) xi_dbg[gv] = OX[ly][lx];
     }
   }
+  __syncthreads();
+}
+
+// ------------------------------------------------------- batched launches
+// Block (bx, by) of colour c from the index li of a field's column-padded
+// phase grid; false for the padding.
+__device__ __forceinline__ bool phase_block(long long li, int tx, int c, int* bx, int* by) {
+  const int pc = phase_cols(tx);
+  const int y = (int)(li / pc), xi = (int)(li - (long long)y * pc);
+  const int b0 = ((c - y) % 3 + 3) % 3;
+  *bx = b0 + 3 * xi;
+  *by = y;
+  return *bx < tx;
+}
+
+// Class of block (bx, by) of frame t, then its phase.  mstate says whether
+// frame t uses decided classes and whether this call decides them.
+template <bool DECIDE, typename Smem>
+__device__ __forceinline__ void run_block(Smem& S, const BatchView& B, const FieldDesc& d, const FieldParams& p,
+                                          int t, int bx, int by, int mstate, int gidx) {
+  int2* cur = B.cur + d.voff;
+  const uint8_t* flags = B.flags + d.voff;
+  int cls = 0;
+  if (t >= 1) {
+    if (p.predictor == 1) {
+      cls = 1;
+    } else if (mstate != MODES_NONE) {
+      uint8_t* mrow = B.modes + d.mbase + (size_t)gidx * p.tx * p.ty;
+      if constexpr (DECIDE) {
+        if (mstate == MODES_DECIDE) {
+          float* feats = d.feats_dbg ? d.feats_dbg + (size_t)gidx * p.tx * p.ty * 10 : nullptr;
+          cls = block_mode(S.m, cur, flags, p, t, bx, by, B.tlog, B.selw, mrow, feats);
+        } else {
+          cls = mrow[(size_t)by * p.tx + bx];
+        }
+      } else {
+        cls = mrow[(size_t)by * p.tx + bx];
+      }
+    }
+  }
+  if constexpr (DECIDE) phase_tile(S.p, cur, flags, p, t, bx, by, cls, B.xcode + d.voff, B.qcode + d.voff, d.xi_dbg);
+  else phase_tile(S, cur, flags, p, t, bx, by, cls, B.xcode + d.voff, B.qcode + d.voff, d.xi_dbg);
+}
+
+// predictor classes of frame t for every block of the first m fields of the
+// launch order; pre[j] = blocks of the fields before j
+__global__ __launch_bounds__(256) void k_modes_b(BatchView B, const long long* __restrict__ pre, int m, int t,
+                                                 int gidx) {
+  __shared__ ModesSmem S;
+  const int j = find_field(pre, m, blockIdx.x);
+  const FieldDesc& d = B.D[B.ord[j]];
+  if (d.status) return;
+  const FieldParams p = d.p;
+  const long long li = (long long)blockIdx.x - pre[j];
+  const int by = (int)(li / p.tx), bx = (int)(li - (long long)by * p.tx);
+  uint8_t* mrow = B.modes + d.mbase + (size_t)gidx * p.tx * p.ty;
+  float* feats = d.feats_dbg ? d.feats_dbg + (size_t)gidx * p.tx * p.ty * 10 : nullptr;
+  block_mode(S, B.cur + d.voff, B.flags + d.voff, p, t, bx, by, B.tlog, B.selw, mrow, feats);
+}
+
+// colour phase c of frame t over the first m fields of the launch order;
+// with DECIDE the classes of a decision frame are chosen in the same launch
+template <bool DECIDE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_phase_b(
+    BatchView B, const long long* __restrict__ pre, int m, int t, int c, int mstate, int gidx) {
+  using Smem = typename std::conditional<DECIDE, TileSmem, PhaseSmem>::type;
+  __shared__ Smem S;
+  const int j = find_field(pre, m, blockIdx.x);
+  const FieldDesc& d = B.D[B.ord[j]];
+  if (d.status) return;
+  const FieldParams p = d.p;
+  int bx, by;
+  if (!phase_block((long long)blockIdx.x - pre[j], p.tx, c, &bx, &by)) return;
+  run_block<DECIDE>(S, B, d, p, t, bx, by, mstate, gidx);
+}
+
+// ------------------------------------------------------ persistent schedule
+// Work items are groups of up to `group` blocks of one stage (field, frame,
+// colour).  Items are numbered stage round by stage round (round r holds
+// stage r of every field that has one), so every item depends only on items
+// with smaller numbers.  A workgroup takes the next number, waits until its
+// field has finished all items of earlier stages (done[f] >= need), runs
+// the blocks and counts the item as done.  Items are taken in increasing
+// order by running workgroups, so every wait ends.
+//
+// Polling uses relaxed loads: an acquire load would invalidate the caches
+// every workgroup of the chip shares on each poll.  One acquire fence per
+// wave follows the wait, one release fence per wave precedes the count.
+// A wait longer than `budget` wall-clock ticks raises ctl[1], and every
+// workgroup leaves.
+__device__ __forceinline__ unsigned ld_relaxed(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_persist(
+    BatchView B, const SchedSeg* __restrict__ seg, const long long* __restrict__ sstart, int nseg,
+    long long nitems, int group, unsigned* done, unsigned* ctl, unsigned long long budget) {
+  __shared__ TileSmem S;
+  __shared__ unsigned s_item;
+  __shared__ int s_go;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      const unsigned it = atomicAdd(&ctl[0], 1u);
+      int go = 0;
+      if ((long long)it < nitems && !ld_relaxed(&ctl[1])) {
+        const int j = find_field(sstart, nseg, it);
+        const unsigned f = (unsigned)seg[j].f, need = seg[j].need;
+        go = 1;
+        if (ld_relaxed(&done[f]) < need) {
+          const unsigned long long t0 = wall_clock64();
+          int nap = 1;
+          while (ld_relaxed(&done[f]) < need) {
+            if (ld_relaxed(&ctl[1]) || wall_clock64() - t0 > budget) {
+              atomicOr(&ctl[1], 1u);
+              go = 0;
+              break;
+            }
+            if (nap == 1) __builtin_amdgcn_s_sleep(1);
+            else if (nap == 2) __builtin_amdgcn_s_sleep(4);
+            else __builtin_amdgcn_s_sleep(16);
+            nap = nap < 3 ? nap + 1 : 3;
+          }
+        }
+      }
+      s_item = it;
+      s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const long long it = s_item;
+    const int j = find_field(sstart, nseg, it);
+    const SchedSeg sg = seg[j];
+    const FieldDesc& d = B.D[sg.f];
+    if (!d.status) {
+      const FieldParams p = d.p;
+      const long long li0 = (it - sstart[j]) * group;
+      for (int g = 0; g < group; g++) {
+        const long long li = li0 + g;
+        if (li >= sg.nb) break;
+        int bx, by;
+        if (phase_block(li, p.tx, sg.c, &bx, &by)) run_block<true>(S, B, d, p, sg.t, bx, by, sg.mstate, sg.gidx);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(&done[sg.f], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // ============================================================ launchers
-void launch_modes(const int2* cur, const uint8_t* flags, const FieldParams& p, int t, size_t group_base,
-                  const int64_t* tlog, const uint16_t* selw, uint8_t* modes, float* feats, hipStream_t s) {
-  dim3 grid(p.tx, p.ty);
-  k_modes<<<grid, 256, 0, s>>>(cur, flags, p, t, group_base, tlog, selw, modes, feats);
+void launch_modes_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int gidx,
+                    hipStream_t s) {
+  if (nblocks > 0) k_modes_b<<<(unsigned)nblocks, 256, 0, s>>>(B, pre, m, t, gidx);
 }
 
-void launch_phase(int2* cur, const uint8_t* flags, const uint8_t* modes, long long mode_base,
-                  const FieldParams& p, int t, int colour, uint8_t* xcode, uint32_t* qcode, int32_t* xi_dbg,
-                  hipStream_t s) {
-  dim3 grid((p.tx + 2) / 3, p.ty);
-  k_phase<<<grid, 256, 0, s>>>(cur, flags, modes, mode_base, p, t, colour, xcode, qcode, xi_dbg);
+void launch_phase_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int c,
+                    int mstate, int gidx, bool fused, hipStream_t s) {
+  if (nblocks <= 0) return;
+  if (fused) k_phase_b<true><<<(unsigned)nblocks, 256, 0, s>>>(B, pre, m, t, c, mstate, gidx);
+  else k_phase_b<false><<<(unsigned)nblocks, 256, 0, s>>>(B, pre, m, t, c, mstate, gidx);
+}
+
+int persist_grid() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persist, 256, 0) != hipSuccess) return 0;
+  return cus * (per > 0 ? per : 1);
+}
+
+void launch_persist(const BatchView& B, const SchedSeg* seg, const long long* sstart, int nseg, long long nitems,
+                    int group, int grid, unsigned* done, unsigned* ctl, hipStream_t s) {
+  // wait budget: two seconds of the device's constant-rate wall clock
+  static unsigned long long budget = 0;
+  if (!budget) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+      khz = 100000;
+    budget = 2000ull * (unsigned long long)khz;
+  }
+  if (nitems > 0) k_persist<<<grid, 256, 0, s>>>(B, seg, sstart, nseg, nitems, group, done, ctl, budget);
 }
 
 }  // namespace cpt

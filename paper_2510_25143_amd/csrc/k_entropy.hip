@@ -8,34 +8,11 @@
 // MSB-first into its own run of 32-bit words, so encoding and decoding run
 // one chunk per workgroup / lane.  The codebook is built by one workgroup
 // on the device, so compression needs no host round trip for it.
+#include "batch.hpp"
 #include "cpt_device.hpp"
 #include "launch.hpp"
 
 namespace cpt {
-
-// -------------------------------------------------------------- histogram
-__global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ xcode, const uint32_t* __restrict__ qcode,
-                                              size_t N, uint32_t* __restrict__ xhist, uint32_t* __restrict__ qhist) {
-  __shared__ uint32_t hx[32];
-  __shared__ uint32_t hq[QSYM];
-  for (int i = threadIdx.x; i < QSYM; i += 256) hq[i] = 0;
-  if (threadIdx.x < 32) hx[threadIdx.x] = 0;
-  __syncthreads();
-  size_t stride = (size_t)gridDim.x * 256;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < N; i += stride) {
-    uint32_t c = xcode[i];
-    atomicAdd(&hx[c], 1u);
-    if (c != XLOSSLESS) {
-      uint32_t q = qcode[i];
-      atomicAdd(&hq[q & 0xFFFFu], 1u);
-      atomicAdd(&hq[q >> 16], 1u);
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < QSYM; i += 256)
-    if (hq[i]) atomicAdd(&qhist[i], hq[i]);
-  if (threadIdx.x < XSYM && hx[threadIdx.x]) atomicAdd(&xhist[threadIdx.x], hx[threadIdx.x]);
-}
 
 __global__ void k_zero(uint32_t* p, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -203,35 +180,155 @@ __device__ void build_code(const uint32_t* __restrict__ hist, int nsym, HuffTabl
   }
 }
 
-__global__ __launch_bounds__(CB_THREADS) void k_codebooks(const uint32_t* __restrict__ xhist,
-                                                          const uint32_t* __restrict__ qhist, HuffTables* xt,
-                                                          HuffTables* qt, uint32_t* xcb, uint32_t* qcb,
-                                                          uint32_t* used) {
-  if (blockIdx.x == 0) build_code(xhist, XSYM, xt, xcb, &used[0]);
-  else build_code(qhist, QSYM, qt, qcb, &used[1]);
+// ======================================================= batched encoding
+// Every kernel below covers all fields of a batch; a workgroup finds its
+// field from a prefix table of per-field workgroup counts and skips fields
+// whose status is not ok.  Prefix sums run over the concatenated arrays in
+// 32-bit arithmetic: a field's own offsets are differences from the value
+// at its first element, which are exact modulo 2^32.
+
+// per-field histograms of the bound codes and residual codes;
+// hpre[f]: workgroups of HIST_SPAN vertices of the fields before f
+constexpr int HIST_SPAN = (int)HIST_SPAN_VERTICES;
+__global__ __launch_bounds__(256) void k_hist_b(const FieldDesc* __restrict__ D, const long long* __restrict__ hpre,
+                                                int n, const uint8_t* __restrict__ xcode,
+                                                const uint32_t* __restrict__ qcode, uint32_t* __restrict__ xhist,
+                                                uint32_t* __restrict__ qhist) {
+  __shared__ uint32_t hx[32];
+  __shared__ uint32_t hq[QSYM];
+  const int f = find_field(hpre, n, blockIdx.x);
+  const FieldDesc& d = D[f];
+  if (d.status) return;
+  for (int i = threadIdx.x; i < QSYM; i += 256) hq[i] = 0;
+  if (threadIdx.x < 32) hx[threadIdx.x] = 0;
+  __syncthreads();
+  const size_t lo = (size_t)((long long)blockIdx.x - hpre[f]) * HIST_SPAN;
+  const size_t N = (size_t)d.N, hi = lo + HIST_SPAN < N ? lo + HIST_SPAN : N;
+  const uint8_t* xc = xcode + d.voff;
+  const uint32_t* qc = qcode + d.voff;
+  for (size_t i = lo + threadIdx.x; i < hi; i += 256) {
+    uint32_t c = xc[i];
+    atomicAdd(&hx[c], 1u);
+    if (c != XLOSSLESS) {
+      uint32_t q = qc[i];
+      atomicAdd(&hq[q & 0xFFFFu], 1u);
+      atomicAdd(&hq[q >> 16], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < QSYM; i += 256)
+    if (hq[i]) atomicAdd(&qhist[(size_t)f * QSYM + i], hq[i]);
+  if (threadIdx.x < XSYM && hx[threadIdx.x]) atomicAdd(&xhist[(size_t)f * 32 + threadIdx.x], hx[threadIdx.x]);
 }
 
-// ------------------------------------------------------ symbol streams
-__global__ __launch_bounds__(256) void k_gather_q(const uint8_t* __restrict__ xcode, const uint32_t* __restrict__ qcode,
-                                                  const uint32_t* __restrict__ qofs, size_t N,
-                                                  uint16_t* __restrict__ qsym) {
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= N || xcode[i] == XLOSSLESS) return;
-  uint32_t q = qcode[i];
-  size_t o = 2 * (size_t)qofs[i];
+// two workgroups per field: the bound-code and the residual-code codebook
+__global__ __launch_bounds__(CB_THREADS) void k_codebooks_b(const FieldDesc* __restrict__ D,
+                                                            const uint32_t* __restrict__ xhist,
+                                                            const uint32_t* __restrict__ qhist, HuffTables* xt,
+                                                            HuffTables* qt, uint32_t* xcb, uint32_t* qcb,
+                                                            uint32_t* used) {
+  const int f = blockIdx.x >> 1;
+  if (D[f].status) return;
+  if ((blockIdx.x & 1) == 0) build_code(xhist + (size_t)f * 32, XSYM, xt + f, xcb + (size_t)f * 32, &used[2 * f]);
+  else build_code(qhist + (size_t)f * QSYM, QSYM, qt + f, qcb + (size_t)f * (QSYM + 4), &used[2 * f + 1]);
+}
+
+struct VPos {
+  int f;
+  size_t i;
+  bool valid;
+};
+__device__ __forceinline__ VPos vpos(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre, int n) {
+  VPos v;
+  v.f = find_field(vpre, n, blockIdx.x);
+  v.i = (size_t)((long long)blockIdx.x - vpre[v.f]) * 256 + threadIdx.x;
+  v.valid = v.i < (size_t)D[v.f].N;
+  return v;
+}
+
+// raw values per vertex (both components of a lossless vertex, else the
+// components whose residual code is 0) and the non-lossless indicator
+__global__ __launch_bounds__(256) void k_raw_count_b(const FieldDesc* __restrict__ D,
+                                                     const long long* __restrict__ vpre, int n,
+                                                     const uint8_t* __restrict__ xcode,
+                                                     const uint32_t* __restrict__ qcode, uint32_t* __restrict__ cnt,
+                                                     uint32_t* __restrict__ nonll) {
+  const VPos v = vpos(D, vpre, n);
+  if (!v.valid) return;
+  const FieldDesc& d = D[v.f];
+  const size_t g = d.voff + v.i;
+  uint32_t c = 0, nl = 0;
+  if (!d.status) {
+    if (xcode[g] == XLOSSLESS) {
+      c = 2;
+    } else {
+      uint32_t q = qcode[g];
+      c = ((q & 0xFFFFu) == 0) + ((q >> 16) == 0);
+      nl = 1;
+    }
+  }
+  cnt[g] = c;
+  nonll[g] = nl;
+}
+
+__global__ __launch_bounds__(256) void k_gather_q_b(const FieldDesc* __restrict__ D,
+                                                    const long long* __restrict__ vpre, int n,
+                                                    const uint8_t* __restrict__ xcode,
+                                                    const uint32_t* __restrict__ qcode,
+                                                    const uint32_t* __restrict__ qofs, uint16_t* __restrict__ qsym) {
+  const VPos v = vpos(D, vpre, n);
+  if (!v.valid) return;
+  const FieldDesc& d = D[v.f];
+  const size_t g = d.voff + v.i;
+  if (d.status || xcode[g] == XLOSSLESS) return;
+  const uint32_t q = qcode[g];
+  const size_t o = (size_t)d.cqb * CHUNK + 2 * (size_t)(qofs[g] - qofs[d.voff]);
   qsym[o] = (uint16_t)(q & 0xFFFFu);
   qsym[o + 1] = (uint16_t)(q >> 16);
 }
 
-template <typename S>
-__global__ __launch_bounds__(256) void k_chunk_bits(const S* __restrict__ sym, size_t n,
-                                                    const HuffTables* __restrict__ t, uint32_t* __restrict__ bits,
-                                                    uint32_t* __restrict__ words) {
+// residual symbols and raw values per field, from the prefix sums
+__global__ void k_totals_b(FieldDesc* __restrict__ D, int n, const uint32_t* __restrict__ nonll,
+                           const uint32_t* __restrict__ qofs, const uint32_t* __restrict__ rcnt,
+                           const uint32_t* __restrict__ rofs) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  FieldDesc& d = D[f];
+  if (d.status) {
+    d.nq = d.nraw = d.nchq = 0;
+    return;
+  }
+  const size_t a = d.voff, z = d.voff + d.N - 1;
+  const uint32_t nl = qofs[z] + nonll[z] - qofs[a];
+  const uint32_t nr = rofs[z] + rcnt[z] - rofs[a];
+  d.nq = 2 * (long long)nl;
+  d.nraw = nr;
+  d.nchq = (d.nq + CHUNK - 1) / CHUNK;
+}
+
+// bits and 32-bit words of every chunk; chunks past a field's last get 0
+template <bool RESID>
+__global__ __launch_bounds__(256) void k_chunk_bits_b(const FieldDesc* __restrict__ D,
+                                                      const long long* __restrict__ cpre, int n,
+                                                      const uint8_t* __restrict__ xcode,
+                                                      const uint16_t* __restrict__ qsym,
+                                                      const HuffTables* __restrict__ tabs,
+                                                      uint32_t* __restrict__ bits, uint32_t* __restrict__ words) {
   __shared__ uint32_t red[256];
-  size_t base = (size_t)blockIdx.x * CHUNK;
+  const int f = find_field(cpre, n, blockIdx.x);
+  const FieldDesc& d = D[f];
+  const long long lc = (long long)blockIdx.x - cpre[f];
+  const size_t slot = (size_t)(RESID ? d.cqb : d.cxb) + lc;
+  const long long nsym = d.status ? 0 : (RESID ? d.nq : d.N);
+  const size_t base = (size_t)lc * CHUNK;
   uint32_t b = 0;
-  for (int i = threadIdx.x; i < CHUNK; i += 256)
-    if (base + i < n) b += t->len[sym[base + i]];
+  if ((long long)base < nsym) {
+    const HuffTables* t = tabs + f;
+    for (int i = threadIdx.x; i < CHUNK; i += 256) {
+      const size_t k = base + i;
+      if ((long long)k < nsym) b += RESID ? t->len[qsym[(size_t)d.cqb * CHUNK + k]] : t->len[xcode[d.voff + k]];
+    }
+  }
   red[threadIdx.x] = b;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -239,27 +336,38 @@ __global__ __launch_bounds__(256) void k_chunk_bits(const S* __restrict__ sym, s
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    bits[blockIdx.x] = red[0];
-    words[blockIdx.x] = (red[0] + 31) / 32;
+    bits[slot] = red[0];
+    words[slot] = (red[0] + 31) / 32;
   }
 }
 
-// one workgroup per chunk; 16 consecutive symbols per thread
-template <typename S>
-__global__ __launch_bounds__(256) void k_encode(const S* __restrict__ sym, size_t n, const HuffTables* __restrict__ t,
-                                                const uint32_t* __restrict__ wofs, uint32_t* __restrict__ out) {
+// one workgroup per chunk, CHUNK / 256 consecutive symbols per thread; the
+// chunk's words go to the field's bitstream section
+template <bool RESID>
+__global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ D, const long long* __restrict__ cpre,
+                                                  int n, const uint8_t* __restrict__ xcode,
+                                                  const uint16_t* __restrict__ qsym,
+                                                  const HuffTables* __restrict__ tabs,
+                                                  const uint32_t* __restrict__ wofs) {
   __shared__ uint32_t w[CHUNK * MAXLEN / 32];
   __shared__ uint32_t wsum[4];
+  const int f = find_field(cpre, n, blockIdx.x);
+  const FieldDesc& d = D[f];
+  const long long lc = (long long)blockIdx.x - cpre[f];
+  const long long nsym = RESID ? d.nq : d.N;
+  if (d.status || lc * CHUNK >= nsym) return;
+  const HuffTables* t = tabs + f;
+  const size_t cb = (size_t)(RESID ? d.cqb : d.cxb);
   const int per = CHUNK / 256;
-  size_t base = (size_t)blockIdx.x * CHUNK + (size_t)threadIdx.x * per;
+  const size_t base = (size_t)lc * CHUNK + (size_t)threadIdx.x * per;
   for (int i = threadIdx.x; i < CHUNK * MAXLEN / 32; i += 256) w[i] = 0;
   uint32_t codes[per];
   uint8_t lens[per];
   uint32_t mine = 0;
 #pragma unroll
   for (int i = 0; i < per; i++) {
-    if (base + i < n) {
-      S s = sym[base + i];
+    if ((long long)(base + i) < nsym) {
+      const uint32_t s = RESID ? qsym[cb * CHUNK + base + i] : xcode[d.voff + base + i];
       codes[i] = t->code[s];
       lens[i] = t->len[s];
     } else {
@@ -297,39 +405,116 @@ __global__ __launch_bounds__(256) void k_encode(const S* __restrict__ sym, size_
   }
   __syncthreads();
   uint32_t nw = (total + 31) / 32;
-  uint32_t* dst = out + wofs[blockIdx.x];
+  uint32_t* dst = (uint32_t*)(d.out + d.off[RESID ? 6 : 3]) + (wofs[cb + lc] - wofs[cb]);
   for (uint32_t i = threadIdx.x; i < nw; i += 256) dst[i] = w[i];
 }
 
-// ----------------------------------------------------------- raw values
-__global__ __launch_bounds__(256) void k_raw_count(const uint8_t* __restrict__ xcode, const uint32_t* __restrict__ qcode,
-                                                   size_t N, uint32_t* __restrict__ cnt, uint32_t* __restrict__ nonll) {
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  uint32_t c;
-  if (xcode[i] == XLOSSLESS) {
-    c = 2;
-    nonll[i] = 0;
-  } else {
-    uint32_t q = qcode[i];
-    c = ((q & 0xFFFFu) == 0) + ((q >> 16) == 0);
-    nonll[i] = 1;
+// Stream layout of every field: section lengths and offsets, total length,
+// capacity check, and the header.
+__global__ __launch_bounds__(64) void k_layout_b(FieldDesc* __restrict__ D, const uint32_t* __restrict__ used,
+                                                 const uint32_t* __restrict__ xwords,
+                                                 const uint32_t* __restrict__ xwofs,
+                                                 const uint32_t* __restrict__ qwords,
+                                                 const uint32_t* __restrict__ qwofs) {
+  __shared__ uint64_t slot[HDR_SLOTS];
+  __shared__ int ok;
+  const int f = blockIdx.x;
+  FieldDesc& d = D[f];
+  if (d.status) {
+    if (threadIdx.x == 0) d.len = 0;
+    return;
   }
-  cnt[i] = c;
+  if (threadIdx.x == 0) {
+    const FieldParams& p = d.p;
+    const size_t xa = d.cxb, xz = d.cxb + d.nchx - 1;
+    const uint32_t words_x = xwofs[xz] + xwords[xz] - xwofs[xa];
+    const size_t qcap = (size_t)(2 * d.N + CHUNK - 1) / CHUNK;
+    const size_t qa = d.cqb, qz = d.cqb + qcap - 1;
+    const uint32_t words_q = qwofs[qz] + qwords[qz] - qwofs[qa];
+    const long long sec[8] = {4 * d.mwords,         4 * (1 + (long long)used[2 * f]),     4 * d.nchx,
+                              4 * (long long)words_x, 4 * (1 + (long long)used[2 * f + 1]), 4 * d.nchq,
+                              4 * (long long)words_q, 4 * d.nraw};
+    long long total = HDR_BYTES;
+    for (int i = 0; i < 8; i++) {
+      d.sec[i] = sec[i];
+      d.off[i] = total;
+      total += sec[i];
+    }
+    d.len = total;
+    ok = d.out != nullptr && total <= d.cap;
+    if (!ok) {
+      d.status = STATUS_ECAPACITY;
+      d.reason = REASON_CAPACITY;
+    }
+    uint64_t ebits = (uint64_t)__double_as_longlong(d.eb_abs);
+    const uint64_t s[HDR_SLOTS] = {STREAM_MAGIC | (STREAM_VERSION << 32), (uint64_t)p.H, (uint64_t)p.W,
+                                   (uint64_t)p.T, (uint64_t)(int64_t)p.k, ebits, (uint64_t)p.eps, (uint64_t)QR,
+                                   (uint64_t)TILE, (uint64_t)p.predictor, (uint64_t)p.bt, (uint64_t)p.K,
+                                   (uint64_t)p.cx, (uint64_t)p.sx, (uint64_t)p.cy, (uint64_t)p.sy, (uint64_t)NMAX,
+                                   (uint64_t)CHUNK, (uint64_t)MAXLEN, (uint64_t)SL_STRIDE, (uint64_t)sec[0],
+                                   (uint64_t)sec[1], (uint64_t)sec[2], (uint64_t)sec[3], (uint64_t)sec[4],
+                                   (uint64_t)sec[5], (uint64_t)sec[6], (uint64_t)sec[7], (uint64_t)d.nq,
+                                   (uint64_t)d.nraw, (uint64_t)total, 0};
+    for (int i = 0; i < HDR_SLOTS; i++) slot[i] = s[i];
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (ok && i < HDR_SLOTS) {
+    uint32_t* o = (uint32_t*)d.out;
+    o[2 * i] = (uint32_t)(slot[i] & 0xFFFFFFFFu);
+    o[2 * i + 1] = (uint32_t)(slot[i] >> 32);
+  }
 }
 
-__global__ __launch_bounds__(256) void k_raw(const float* __restrict__ field, const uint8_t* __restrict__ xcode,
-                                             const uint32_t* __restrict__ qcode, const uint32_t* __restrict__ rofs,
-                                             size_t N, uint32_t* __restrict__ out) {
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  uint32_t o = rofs[i];
-  uint32_t bu = __float_as_uint(field[i]), bv = __float_as_uint(field[N + i]);
-  if (xcode[i] == XLOSSLESS) {
+// small sections: predictor classes (bit-packed LSB-first), both codebooks
+// and both chunk tables; grid (n, SB)
+__global__ __launch_bounds__(256) void k_sections_b(const FieldDesc* __restrict__ D, const uint8_t* __restrict__ modes,
+                                                    const uint32_t* __restrict__ xcb, const uint32_t* __restrict__ qcb,
+                                                    const uint32_t* __restrict__ used,
+                                                    const uint32_t* __restrict__ xbits,
+                                                    const uint32_t* __restrict__ qbits) {
+  const int f = blockIdx.x;
+  const FieldDesc& d = D[f];
+  if (d.status) return;
+  const size_t step = (size_t)gridDim.y * 256, first = (size_t)blockIdx.y * 256 + threadIdx.x;
+  uint32_t* out = (uint32_t*)d.out;
+  const int mb = d.K == 4 ? 2 : (d.K == 2 ? 1 : 0);
+  const size_t nblk = (size_t)d.ndec * d.tx * d.ty;
+  const uint8_t* m = modes + d.mbase;
+  uint32_t* o0 = out + d.off[0] / 4;
+  for (size_t w = first; w < (size_t)d.mwords; w += step) {
+    uint32_t v = 0;
+    for (int b = 0; b < 32; b++) {
+      size_t bit = w * 32 + b;
+      size_t blk = bit / mb;
+      int k = (int)(bit % mb);
+      if (blk < nblk && ((m[blk] >> k) & 1)) v |= 1u << b;
+    }
+    o0[w] = v;
+  }
+  const size_t ux = 1 + used[2 * f], uq = 1 + used[2 * f + 1];
+  for (size_t w = first; w < ux; w += step) out[d.off[1] / 4 + w] = xcb[(size_t)f * 32 + w];
+  for (size_t w = first; w < uq; w += step) out[d.off[4] / 4 + w] = qcb[(size_t)f * (QSYM + 4) + w];
+  for (size_t w = first; w < (size_t)d.nchx; w += step) out[d.off[2] / 4 + w] = xbits[d.cxb + w];
+  for (size_t w = first; w < (size_t)d.nchq; w += step) out[d.off[5] / 4 + w] = qbits[d.cqb + w];
+}
+
+__global__ __launch_bounds__(256) void k_raw_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
+                                               int n, const uint8_t* __restrict__ xcode,
+                                               const uint32_t* __restrict__ qcode, const uint32_t* __restrict__ rofs) {
+  const VPos v = vpos(D, vpre, n);
+  if (!v.valid) return;
+  const FieldDesc& d = D[v.f];
+  if (d.status) return;
+  const size_t g = d.voff + v.i, N = (size_t)d.N;
+  uint32_t o = rofs[g] - rofs[d.voff];
+  uint32_t* out = (uint32_t*)(d.out + d.off[7]);
+  const uint32_t bu = __float_as_uint(d.field[v.i]), bv = __float_as_uint(d.field[N + v.i]);
+  if (xcode[g] == XLOSSLESS) {
     out[o] = bu;
     out[o + 1] = bv;
   } else {
-    uint32_t q = qcode[i];
+    const uint32_t q = qcode[g];
     if ((q & 0xFFFFu) == 0) out[o++] = bu;
     if ((q >> 16) == 0) out[o] = bv;
   }
@@ -450,50 +635,42 @@ static inline unsigned nblk(size_t n, int b = 256) { return (unsigned)((n + b - 
 void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
   if (n) k_zero<<<nblk(n), 256, 0, s>>>(p, n);
 }
-void launch_hist(const uint8_t* xcode, const uint32_t* qcode, size_t N, uint32_t* xhist, uint32_t* qhist,
-                 uint32_t* /*nonll*/, uint32_t* /*nraw*/, hipStream_t s) {
-  launch_zero_u32(xhist, 32, s);
-  launch_zero_u32(qhist, QSYM, s);
-  unsigned g = nblk(N);
-  if (g > 2048) g = 2048;
-  if (g == 0) g = 1;
-  k_hist<<<g, 256, 0, s>>>(xcode, qcode, N, xhist, qhist);
+void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* hpre,
+                    long long hblocks, const long long* vpre, long long vblocks, long long Ntot, hipStream_t s) {
+  launch_zero_u32(E.xhist, 32 * (size_t)n, s);
+  launch_zero_u32(E.qhist, QSYM * (size_t)n, s);
+  if (hblocks > 0) k_hist_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.xhist, E.qhist);
+  k_codebooks_b<<<2 * n, CB_THREADS, 0, s>>>(D, E.xhist, E.qhist, E.xt, E.qt, E.xcb, E.qcb, E.used);
+  if (vblocks <= 0) return;
+  k_raw_count_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.rcnt, E.nonll);
+  uint32_t* tot = E.part;  // two scratch words ahead of the scan partials
+  launch_scan(E.nonll, (size_t)Ntot, E.qofs, E.part + 4, tot, s);
+  launch_scan(E.rcnt, (size_t)Ntot, E.rofs, E.part + 4, tot + 1, s);
+  k_totals_b<<<nblk(n, 64), 64, 0, s>>>(D, n, E.nonll, E.qofs, E.rcnt, E.rofs);
+  k_gather_q_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.qofs, E.qsym);
 }
-void launch_codebooks(const uint32_t* xhist, const uint32_t* qhist, HuffTables* xt, HuffTables* qt, uint32_t* xcb,
-                      uint32_t* qcb, uint32_t* used, hipStream_t s) {
-  k_codebooks<<<2, CB_THREADS, 0, s>>>(xhist, qhist, xt, qt, xcb, qcb, used);
+
+void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
+                     long long cxtot, const long long* cqpre, long long cqtot, hipStream_t s) {
+  uint32_t* tot = E.part;
+  if (cxtot > 0) {
+    k_chunk_bits_b<false><<<(unsigned)cxtot, 256, 0, s>>>(D, cxpre, n, B.xcode, E.qsym, E.xt, E.xbits, E.xwords);
+    launch_scan(E.xwords, (size_t)cxtot, E.xwofs, E.part + 4, tot + 2, s);
+  }
+  if (cqtot > 0) {
+    k_chunk_bits_b<true><<<(unsigned)cqtot, 256, 0, s>>>(D, cqpre, n, B.xcode, E.qsym, E.qt, E.qbits, E.qwords);
+    launch_scan(E.qwords, (size_t)cqtot, E.qwofs, E.part + 4, tot + 3, s);
+  }
+  k_layout_b<<<n, 64, 0, s>>>(D, E.used, E.xwords, E.xwofs, E.qwords, E.qwofs);
 }
-void launch_gather_q(const uint8_t* xcode, const uint32_t* qcode, const uint32_t* qofs, size_t N, uint16_t* qsym,
-                     hipStream_t s) {
-  if (N) k_gather_q<<<nblk(N), 256, 0, s>>>(xcode, qcode, qofs, N, qsym);
-}
-void launch_chunk_bits_x(const uint8_t* xcode, size_t N, const HuffTables* t, uint32_t* bits, uint32_t* words,
-                         hipStream_t s) {
-  size_t nch = (N + CHUNK - 1) / CHUNK;
-  if (nch) k_chunk_bits<uint8_t><<<(unsigned)nch, 256, 0, s>>>(xcode, N, t, bits, words);
-}
-void launch_chunk_bits_q(const uint16_t* qsym, size_t n, const HuffTables* t, uint32_t* bits, uint32_t* words,
-                         hipStream_t s) {
-  size_t nch = (n + CHUNK - 1) / CHUNK;
-  if (nch) k_chunk_bits<uint16_t><<<(unsigned)nch, 256, 0, s>>>(qsym, n, t, bits, words);
-}
-void launch_encode_x(const uint8_t* xcode, size_t N, const HuffTables* t, const uint32_t* wofs, uint32_t* out,
-                     hipStream_t s) {
-  size_t nch = (N + CHUNK - 1) / CHUNK;
-  if (nch) k_encode<uint8_t><<<(unsigned)nch, 256, 0, s>>>(xcode, N, t, wofs, out);
-}
-void launch_encode_q(const uint16_t* qsym, size_t n, const HuffTables* t, const uint32_t* wofs, uint32_t* out,
-                     hipStream_t s) {
-  size_t nch = (n + CHUNK - 1) / CHUNK;
-  if (nch) k_encode<uint16_t><<<(unsigned)nch, 256, 0, s>>>(qsym, n, t, wofs, out);
-}
-void launch_raw_count(const uint8_t* xcode, const uint32_t* qcode, size_t N, uint32_t* cnt, uint32_t* nonll,
-                      hipStream_t s) {
-  if (N) k_raw_count<<<nblk(N), 256, 0, s>>>(xcode, qcode, N, cnt, nonll);
-}
-void launch_raw(const float* field, const uint8_t* xcode, const uint32_t* qcode, const uint32_t* rofs, size_t N,
-                uint32_t* out, hipStream_t s) {
-  if (N) k_raw<<<nblk(N), 256, 0, s>>>(field, xcode, qcode, rofs, N, out);
+
+void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
+                       long long cxtot, const long long* cqpre, long long cqtot, const long long* vpre,
+                       long long vblocks, hipStream_t s) {
+  k_sections_b<<<dim3(n, 16), 256, 0, s>>>(D, B.modes, E.xcb, E.qcb, E.used, E.xbits, E.qbits);
+  if (cxtot > 0) k_encode_b<false><<<(unsigned)cxtot, 256, 0, s>>>(D, cxpre, n, B.xcode, E.qsym, E.xt, E.xwofs);
+  if (cqtot > 0) k_encode_b<true><<<(unsigned)cqtot, 256, 0, s>>>(D, cqpre, n, B.xcode, E.qsym, E.qt, E.qwofs);
+  if (vblocks > 0) k_raw_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.rofs);
 }
 void launch_build_lut(const uint32_t* cb, size_t cb_words, int nsym, uint32_t* lut, uint32_t* err, hipStream_t s) {
   k_build_lut<<<1, 1024, 0, s>>>(cb, cb_words, nsym, lut, err);

@@ -10,6 +10,9 @@
 // spatial edges to +x, +y, +x+y, the time edge, and the three diagonals to
 // the +x, +y, +x+y vertices of the next frame); a face is decided from the
 // SoS signs of its three edges, each computed once by the edge's owner.
+#include <math.h>
+
+#include "batch.hpp"
 #include "cpt_device.hpp"
 #include "launch.hpp"
 
@@ -80,11 +83,8 @@ __global__ __launch_bounds__(256) void k_convert(const float* __restrict__ f, si
 // ------------------------------------------------------------- edge signs
 // bit 0..2: spatial edges to +x, +y, +x+y at t; bit 3: time edge; bits 4..6:
 // diagonals to the +x, +y, +x+y vertices at t+1.  Bit set = positive sign.
-__global__ __launch_bounds__(256) void k_edges(const int2* __restrict__ cur, int H, int W, int T,
-                                               uint8_t* __restrict__ edges) {
-  size_t HW = (size_t)H * W;
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= HW * T) return;
+__device__ __forceinline__ uint8_t edge_bits(const int2* __restrict__ cur, int H, int W, int T, size_t i) {
+  const size_t HW = (size_t)H * W;
   int t = (int)(i / HW);
   int r = (int)(i - (size_t)t * HW);
   int y = r / W, x = r - y * W;
@@ -101,7 +101,14 @@ __global__ __launch_bounds__(256) void k_edges(const int2* __restrict__ cur, int
     if (py) e |= (sos_sign(a.x, a.y, n[W].x, n[W].y) > 0) << 5;
     if (px && py) e |= (sos_sign(a.x, a.y, n[W + 1].x, n[W + 1].y) > 0) << 6;
   }
-  edges[i] = (uint8_t)e;
+  return (uint8_t)e;
+}
+
+__global__ __launch_bounds__(256) void k_edges(const int2* __restrict__ cur, int H, int W, int T,
+                                               uint8_t* __restrict__ edges) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)H * W * T) return;
+  edges[i] = edge_bits(cur, H, W, T, i);
 }
 
 // crossed iff sigma(A,B) == sigma(B,C) == -sigma(A,C) for A < B < C
@@ -110,20 +117,14 @@ __device__ __forceinline__ uint32_t face_bits(uint32_t sab, uint32_t sbc, uint32
   return crossed ? ((1u << f) | (sab << (12 + f))) : 0u;
 }
 
-__global__ __launch_bounds__(256) void k_faces(const uint8_t* __restrict__ edges, int H, int W, int T,
-                                               uint32_t* __restrict__ masks) {
-  size_t HW = (size_t)H * W;
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= HW * T) return;
+__device__ __forceinline__ uint32_t face_mask(const uint8_t* __restrict__ edges, int H, int W, int T, size_t i) {
+  const size_t HW = (size_t)H * W;
   int t = (int)(i / HW);
   int r = (int)(i - (size_t)t * HW);
   int y = r / W, x = r - y * W;
   bool px = x + 1 < W, py = y + 1 < H, pt = t + 1 < T;
   uint32_t m = 0;
-  if (!(px || py)) {
-    masks[i] = 0;
-    return;
-  }
+  if (!(px || py)) return 0;
   uint32_t ea = edges[i];
   uint32_t eb = px ? edges[i + 1] : 0;
   uint32_t ec = py ? edges[i + W] : 0;
@@ -153,7 +154,14 @@ __global__ __launch_bounds__(256) void k_faces(const uint8_t* __restrict__ edges
     m |= face_bits(B(ea, 3), B(ea1, 1), B(ea, 5), 9);
   }
 #undef B
-  masks[i] = m;
+  return m;
+}
+
+__global__ __launch_bounds__(256) void k_faces(const uint8_t* __restrict__ edges, int H, int W, int T,
+                                               uint32_t* __restrict__ masks) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)H * W * T) return;
+  masks[i] = face_mask(edges, H, W, T, i);
 }
 
 // --------------------------------------------------------- lossless flags
@@ -176,11 +184,8 @@ constexpr IncTable make_inc() {
 }
 __constant__ IncTable c_inc = make_inc();
 
-__global__ __launch_bounds__(256) void k_flags(const uint32_t* __restrict__ masks, int H, int W, int T,
-                                               uint8_t* __restrict__ flags) {
-  size_t HW = (size_t)H * W;
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= HW * T) return;
+__device__ __forceinline__ uint8_t lossless_flag(const uint32_t* __restrict__ masks, int H, int W, size_t i,
+                                                 size_t HW) {
   int t = (int)(i / HW);
   int r = (int)(i - (size_t)t * HW);
   int y = r / W, x = r - y * W;
@@ -191,7 +196,199 @@ __global__ __launch_bounds__(256) void k_flags(const uint32_t* __restrict__ mask
     if (x - ox < 0 || y - oy < 0 || t - ot < 0) continue;
     any |= masks[i - ox - (size_t)oy * W - (size_t)ot * HW] & c_inc.m[o];
   }
-  flags[i] = any ? 1 : 0;
+  (void)H;
+  return any ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_flags(const uint32_t* __restrict__ masks, int H, int W, int T,
+                                               uint8_t* __restrict__ flags) {
+  size_t HW = (size_t)H * W;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= HW * T) return;
+  flags[i] = lossless_flag(masks, H, W, i, HW);
+}
+
+// ------------------------------------------------------- batched field pass
+// Workgroups of 256 vertices never straddle two fields: vpre[f] is the
+// number of such workgroups of the fields before f.
+struct VSeg {
+  int f;
+  size_t i;      // vertex of the field
+  bool valid;
+};
+__device__ __forceinline__ VSeg vseg(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre, int n) {
+  VSeg v;
+  v.f = find_field(vpre, n, blockIdx.x);
+  v.i = (size_t)((long long)blockIdx.x - vpre[v.f]) * 256 + threadIdx.x;
+  v.valid = v.i < (size_t)D[v.f].N;
+  return v;
+}
+
+// per-field range slots: min key, max key, max |x| bits, non-finite seen
+__global__ void k_range_init_b(int4* __restrict__ r, int n) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < n) r[f] = make_int4(0x7FFFFFFF, (int)0x80000000, 0, 0);
+}
+
+// rpre[f]: workgroups of the fields before f, each covering RANGE_SPAN
+// floats; one reduction per workgroup, then one atomic per quantity
+constexpr int RANGE_SPAN = (int)RANGE_SPAN_FLOATS;
+__global__ __launch_bounds__(256) void k_range_b(const FieldDesc* __restrict__ D, const long long* __restrict__ rpre,
+                                                 int n, int4* __restrict__ r) {
+  __shared__ int4 part[4];
+  const int f = find_field(rpre, n, blockIdx.x);
+  const float* x = D[f].field;
+  const size_t nf = 2 * (size_t)D[f].N;
+  const size_t lo = (size_t)((long long)blockIdx.x - rpre[f]) * RANGE_SPAN;
+  const size_t hi = lo + RANGE_SPAN < nf ? lo + RANGE_SPAN : nf;
+  int mn = 0x7FFFFFFF, mx = (int)0x80000000;
+  uint32_t ma = 0, bad = 0;
+  if (((uintptr_t)x & 15) == 0 && hi - lo == RANGE_SPAN) {
+    const uint4* x4 = (const uint4*)(x + lo);
+#pragma unroll 4
+    for (int k = 0; k < RANGE_SPAN / 1024; k++) {
+      uint4 v = x4[k * 256 + threadIdx.x];
+      range_acc(v.x, mn, mx, ma, bad);
+      range_acc(v.y, mn, mx, ma, bad);
+      range_acc(v.z, mn, mx, ma, bad);
+      range_acc(v.w, mn, mx, ma, bad);
+    }
+  } else {
+    for (size_t i = lo + threadIdx.x; i < hi; i += 256) range_acc(__float_as_uint(x[i]), mn, mx, ma, bad);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = min(mn, __shfl_xor(mn, o));
+    mx = max(mx, __shfl_xor(mx, o));
+    ma = max(ma, (uint32_t)__shfl_xor((int)ma, o));
+    bad |= (uint32_t)__shfl_xor((int)bad, o);
+  }
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = make_int4(mn, mx, (int)ma, (int)bad);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; w++) {
+      mn = min(mn, part[w].x);
+      mx = max(mx, part[w].y);
+      ma = max(ma, (uint32_t)part[w].z);
+      bad |= (uint32_t)part[w].w;
+    }
+    atomicMin(&r[f].x, mn);
+    atomicMax(&r[f].y, mx);
+    atomicMax((unsigned int*)&r[f].z, ma);
+    if (bad) atomicOr(&r[f].w, 1);
+  }
+}
+
+__device__ __forceinline__ double key_value(int key) {
+  int s = key >= 0 ? key : (key ^ 0x7FFFFFFF);
+  return (double)__int_as_float(s);
+}
+
+// displacement factor c / 2^s ~ dt_dx 2^(16-k), c < 2^31
+__device__ void sl_factor_dev(double dt_dx, int k, int64_t* c, int64_t* s) {
+  double f = ldexp(dt_dx, 16 - k);
+  if (!(f > 0.0)) {
+    *c = 0;
+    *s = 0;
+    return;
+  }
+  if (f >= 2147483647.0) {
+    *c = 2147483647;
+    *s = 0;
+    return;
+  }
+  int e;
+  frexp(f, &e);
+  int sh = 31 - e;
+  if (sh > 62) sh = 62;
+  int64_t cc = (int64_t)rint(ldexp(f, sh));
+  if (cc >= 2147483648LL) {
+    cc = 1073741824LL;
+    sh -= 1;
+  }
+  *c = cc;
+  *s = sh;
+}
+
+// Per-field parameters from the value range (Sec. VI of the paper, fixed
+// point): k = 23 - e for max|x| = m 2^e, m in [0.5, 1), at most 120;
+// eps' = floor(eb_abs 2^k - 1/2), at most 2^23 - 1.  Every step is exact in
+// double precision.
+__global__ void k_params_b(FieldDesc* __restrict__ D, const int4* __restrict__ r, int n) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  FieldDesc& d = D[f];
+  d.status = 0;
+  d.reason = REASON_NONE;
+  const int4 R = r[f];
+  const double mn = key_value(R.x), mx = key_value(R.y), ma = (double)__int_as_float(R.z);
+  int kk = 23;
+  if (R.w) {
+    d.status = STATUS_EINVAL;
+    d.reason = REASON_NONFINITE;
+  } else if (ma >= ldexp(1.0, 100)) {
+    d.status = STATUS_EINVAL;
+    d.reason = REASON_MAGNITUDE;
+  } else {
+    int e = 0;
+    if (ma > 0) frexp(ma, &e);
+    kk = 23 - e;
+    if (kk > 120) kk = 120;
+  }
+  const double a = d.eb_mode == 0 ? d.eb * (mx - mn) : d.eb;
+  const double sc = floor(ldexp(a, kk) - 0.5);
+  int64_t ep = 0;
+  if (sc > 0) ep = sc >= 8388607.0 ? 8388607 : (int64_t)sc;
+  FieldParams p;
+  p.H = d.H;
+  p.W = d.W;
+  p.T = d.T;
+  p.k = kk;
+  p.eps = (int)ep;
+  p.tx = d.tx;
+  p.ty = d.ty;
+  p.predictor = d.predictor;
+  p.K = d.K;
+  p.bt = d.bt;
+  sl_factor_dev(d.dt_dx, kk, &p.cx, &p.sx);
+  sl_factor_dev(d.dt_dy, kk, &p.cy, &p.sy);
+  d.p = p;
+  d.eb_abs = a;
+}
+
+// fixed point, SoS edge signs, face masks and lossless flags of every field
+__global__ __launch_bounds__(256) void k_convert_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
+                                                   int n, int2* __restrict__ cur) {
+  const VSeg v = vseg(D, vpre, n);
+  const FieldDesc& d = D[v.f];
+  if (!v.valid || d.status) return;
+  const size_t N = (size_t)d.N;
+  cur[d.voff + v.i] = make_int2(to_fixed(d.field[v.i], d.p.k), to_fixed(d.field[N + v.i], d.p.k));
+}
+
+__global__ __launch_bounds__(256) void k_edges_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
+                                                 int n, const int2* __restrict__ cur, uint8_t* __restrict__ edges) {
+  const VSeg v = vseg(D, vpre, n);
+  const FieldDesc& d = D[v.f];
+  if (!v.valid || d.status) return;
+  edges[d.voff + v.i] = edge_bits(cur + d.voff, d.H, d.W, d.T, v.i);
+}
+
+__global__ __launch_bounds__(256) void k_faces_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
+                                                 int n, const uint8_t* __restrict__ edges,
+                                                 uint32_t* __restrict__ masks) {
+  const VSeg v = vseg(D, vpre, n);
+  const FieldDesc& d = D[v.f];
+  if (!v.valid || d.status) return;
+  masks[d.voff + v.i] = face_mask(edges + d.voff, d.H, d.W, d.T, v.i);
+}
+
+__global__ __launch_bounds__(256) void k_flags_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
+                                                 int n, const uint32_t* __restrict__ masks,
+                                                 uint8_t* __restrict__ flags) {
+  const VSeg v = vseg(D, vpre, n);
+  const FieldDesc& d = D[v.f];
+  if (!v.valid || d.status) return;
+  flags[d.voff + v.i] = lossless_flag(masks + d.voff, d.H, d.W, v.i, (size_t)d.H * d.W);
 }
 
 // ------------------------------------------------------------- compaction
@@ -374,6 +571,19 @@ void launch_write_codes(const uint32_t* masks, const uint32_t* ofs, size_t N, ui
   k_write_codes<<<nblk(N), 256, 0, s>>>(masks, ofs, N, codes, cap);
 }
 size_t compare_partials(size_t N) { return nblk(N); }
+
+void launch_field_pass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* vpre,
+                         long long vblocks, int4* range, int2* cur, uint8_t* edges, uint32_t* masks, uint8_t* flags,
+                         hipStream_t s) {
+  k_range_init_b<<<nblk(n, 64), 64, 0, s>>>(range, n);
+  if (rblocks > 0) k_range_b<<<(unsigned)rblocks, 256, 0, s>>>(D, rpre, n, range);
+  k_params_b<<<nblk(n, 64), 64, 0, s>>>(D, range, n);
+  if (vblocks <= 0) return;
+  k_convert_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, cur);
+  k_edges_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, cur, edges);
+  k_faces_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, edges, masks);
+  k_flags_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, masks, flags);
+}
 void launch_compare(const uint32_t* ma, const uint32_t* mb, const float* a, const float* b, size_t N,
                     unsigned long long* fc, double* part, hipStream_t s) {
   k_zero_u64<<<1, 64, 0, s>>>(fc, 2);

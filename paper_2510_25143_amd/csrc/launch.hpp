@@ -32,41 +32,12 @@ size_t compare_partials(size_t N);
 void launch_compare(const uint32_t* ma, const uint32_t* mb, const float* a, const float* b, size_t N,
                     unsigned long long* fc, double* part, hipStream_t s);
 
-// k_compress.hip
-// mode decision for all blocks of frame t (a decision frame); modes of the
-// frame's group are written at modes + group_base.
-void launch_modes(const int2* cur, const uint8_t* flags, const FieldParams& p, int t, size_t group_base,
-                  const int64_t* tlog, const uint16_t* selw, uint8_t* modes, float* feats, hipStream_t s);
-// one colour phase of frame t; mode_base < 0 when the frame has no decided modes
-void launch_phase(int2* cur, const uint8_t* flags, const uint8_t* modes, long long mode_base,
-                  const FieldParams& p, int t, int colour, uint8_t* xcode, uint32_t* qcode, int32_t* xi_dbg,
-                  hipStream_t s);
-
 // k_entropy.hip
 struct HuffTables {
   uint32_t code[1024];
   uint8_t len[1024];
 };
-void launch_hist(const uint8_t* xcode, const uint32_t* qcode, size_t N, uint32_t* xhist, uint32_t* qhist,
-                 uint32_t* nonll, uint32_t* nraw, hipStream_t s);
 void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
-// codebooks for both alphabets: tables + serialized codebook sections + used counts
-void launch_codebooks(const uint32_t* xhist, const uint32_t* qhist, HuffTables* xt, HuffTables* qt,
-                      uint32_t* xcb, uint32_t* qcb, uint32_t* used, hipStream_t s);
-void launch_gather_q(const uint8_t* xcode, const uint32_t* qcode, const uint32_t* qofs, size_t N,
-                     uint16_t* qsym, hipStream_t s);
-void launch_chunk_bits_x(const uint8_t* xcode, size_t N, const HuffTables* t, uint32_t* bits, uint32_t* words,
-                         hipStream_t s);
-void launch_chunk_bits_q(const uint16_t* qsym, size_t n, const HuffTables* t, uint32_t* bits, uint32_t* words,
-                         hipStream_t s);
-void launch_encode_x(const uint8_t* xcode, size_t N, const HuffTables* t, const uint32_t* wofs, uint32_t* out,
-                     hipStream_t s);
-void launch_encode_q(const uint16_t* qsym, size_t n, const HuffTables* t, const uint32_t* wofs, uint32_t* out,
-                     hipStream_t s);
-void launch_raw(const float* field, const uint8_t* xcode, const uint32_t* qcode, const uint32_t* rofs, size_t N,
-                uint32_t* out, hipStream_t s);
-void launch_raw_count(const uint8_t* xcode, const uint32_t* qcode, size_t N, uint32_t* cnt, uint32_t* nonll,
-                      hipStream_t s);
 // decoding: build the lookup tables from a codebook section; err receives a
 // nonzero code on any inconsistency
 void launch_build_lut(const uint32_t* cb, size_t cb_words, int nsym, uint32_t* lut, uint32_t* err,

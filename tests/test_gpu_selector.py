@@ -72,9 +72,10 @@ def test_trained_selector_gain(cpt):
     res = {}
     for name, kw in [("exhaustive", dict(predictor=3)), ("learned", dict(predictor=4, selector_w=wb)),
                      ("lorenzo", dict(predictor=0))]:
-        cpt.compress(fe, 1e-3, mode_bt=4, dt_dx=dt, dt_dy=dt, **kw)
+        # separate predictor-choice launches, so that their time can be read
+        cpt.compress_batch([fe], 1e-3, mode_bt=4, dt_dx=dt, dt_dy=dt, schedule="launch", **kw)
         cpt.timing_enable(True)
-        s = cpt.compress(fe, 1e-3, mode_bt=4, dt_dx=dt, dt_dy=dt, **kw)
+        (s,), _ = cpt.compress_batch([fe], 1e-3, mode_bt=4, dt_dx=dt, dt_dy=dt, schedule="launch", **kw)
         res[name] = dict(CR=fe.numel() * 4 / s.numel(), modes_ms=cpt.timing_read("modes")[0])
         cpt.timing_enable(False)
         k, ea, _ = cpt.field_params(fe, 1e-3)
@@ -87,4 +88,4 @@ def test_trained_selector_gain(cpt):
     assert agree >= 0.9
     assert res["learned"]["CR"] >= 0.98 * res["exhaustive"]["CR"]
     assert res["learned"]["CR"] > res["lorenzo"]["CR"]
-    assert res["learned"]["modes_ms"] < res["exhaustive"]["modes_ms"]
+    assert 0 < res["learned"]["modes_ms"] < res["exhaustive"]["modes_ms"]
