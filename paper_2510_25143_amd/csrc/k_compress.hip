@@ -13,10 +13,10 @@
 // the original field is stored losslessly; otherwise its bound is the
 // minimum of eps' and the Alg. 2 bound of each of its (up to 36) faces,
 // evaluated on the current values — reconstructed where already processed,
-// original elsewhere.  22 of the 36 faces never touch a vertex of the same
-// block processed before it; their bounds are computed for the whole block
-// in parallel first.  The other 14 are computed during the sweep, one face
-// per lane, sixteen lanes per vertex.
+// original elsewhere.  22 of the 36 faces never touch the left, upper or
+// upper-left neighbour of the vertex (its raster predecessors); their bounds
+// are computed for the whole block in parallel first.  The other 14 are
+// computed during the sweep, one face per lane, sixteen lanes per vertex.
 #include <type_traits>
 
 #include "batch.hpp"
@@ -376,6 +376,27 @@ constexpr DynPairs make_dyn_pairs() {
   return D;
 }
 __constant__ DynPairs c_dynp = make_dyn_pairs();
+struct StaticPairs {
+  int8_t a[22], b[22];
+};
+constexpr StaticPairs make_static_pairs() {
+  StaticPairs S{};
+  int n = 0;
+  for (int f = 0; f < 36; f++)
+    if (PAIRS.a[f] >= 3 && PAIRS.b[f] >= 3) {
+      S.a[n] = PAIRS.a[f];
+      S.b[n] = PAIRS.b[f];
+      n++;
+    }
+  return S;
+}
+constexpr StaticPairs SPAIRS = make_static_pairs();
+constexpr int count_static() {
+  int n = 0;
+  for (int f = 0; f < 36; f++) n += (PAIRS.a[f] >= 3 && PAIRS.b[f] >= 3) ? 1 : 0;
+  return n;
+}
+static_assert(count_static() == 22, "22 faces avoid the raster predecessors");
 __constant__ NbrTable c_nbr = NBR;
 __device__ __forceinline__ int c_nbr_dx(int j) { return c_nbr.dx[j]; }
 __device__ __forceinline__ int c_nbr_dy(int j) { return c_nbr.dy[j]; }
@@ -480,25 +501,22 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
       if (!flags[gv]) {
         xi = eps;
         const int2 me = V[1][ly + 1][lx + 1];
-        // neighbour present in the domain and not a raster predecessor
+        // Faces through a raster predecessor (left, up, up-left) are all
+        // evaluated in the sweep, also where that neighbour lies outside the
+        // block; the other 22 are evaluated here for every vertex alike.
         uint32_t ok = 0;
 #pragma unroll
-        for (int j = 0; j < 14; j++) {
+        for (int j = 3; j < 14; j++) {
           int xx = x + NBR.dx[j], yy = y + NBR.dy[j], tt = t + NBR.dt[j];
-          bool in = xx >= 0 && xx < W && yy >= 0 && yy < H && tt >= 0 && tt < T;
-          bool dyn = (j == 0 && lx > 0) || (j == 1 && ly > 0) || (j == 2 && lx > 0 && ly > 0);
-          ok |= (in && !dyn) ? (1u << j) : 0u;
+          ok |= (xx >= 0 && xx < W && yy >= 0 && yy < H && tt >= 0 && tt < T) ? (1u << j) : 0u;
         }
-        double d[14];
 #pragma unroll
-        for (int j = 0; j < 14; j++) d[j] = det2(me, V[1 + NBR.dt[j]][ly + 1 + NBR.dy[j]][lx + 1 + NBR.dx[j]]);
-#pragma unroll
-        for (int f = 0; f < 36; f++) {
-          const int a = PAIRS.a[f], b = PAIRS.b[f];
+        for (int f = 0; f < 22; f++) {
+          const int a = SPAIRS.a[f], b = SPAIRS.b[f];
           if (((ok >> a) & (ok >> b) & 1u) == 0) continue;
           int2 na = V[1 + NBR.dt[a]][ly + 1 + NBR.dy[a]][lx + 1 + NBR.dx[a]];
           int2 nb = V[1 + NBR.dt[b]][ly + 1 + NBR.dy[b]][lx + 1 + NBR.dx[b]];
-          face_update(xi, me, na, nb, d[a], d[b]);
+          face_update(xi, me, na, nb, det2(me, na), det2(me, nb));
         }
       }
       if (cls != 0) {
@@ -529,9 +547,7 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
       if (xs >= 0 && fa >= 0) {
         bool ina = x + axo >= 0 && x + axo < W && y + ayo >= 0 && y + ayo < H && t + ato >= 0 && t + ato < T;
         bool inb = x + bxo >= 0 && x + bxo < W && y + byo >= 0 && y + byo < H && t + bto >= 0 && t + bto < T;
-        bool dyna = (fa == 0 && lx > 0) || (fa == 1 && g > 0) || (fa == 2 && lx > 0 && g > 0);
-        bool dynb = (fb == 0 && lx > 0) || (fb == 1 && g > 0) || (fb == 2 && lx > 0 && g > 0);
-        if (ina && inb && (dyna || dynb)) {
+        if (ina && inb) {
           int2 me = V[1][g + 1][lx + 1];
           int2 pa = V[1 + ato][g + 1 + ayo][lx + 1 + axo];
           int2 pb = V[1 + bto][g + 1 + byo][lx + 1 + bxo];
