@@ -42,13 +42,35 @@ def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def phase_roofline(fam, kname):
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary (profiles/*_hbm_traffic.md) taken on this workload, or None when
+    there is none or the kernel's source has changed since it was taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md")):
+        kv = {}
+        for line in open(path):
+            if ": " in line and not line.startswith(("#", "|", " ")):
+                k, v = line.rstrip("\n").split(": ", 1)
+                kv[k] = v
+        if kv.get("workload") != workload or not kv.get("kernel", "").endswith(kernel):
+            continue
+        src = os.path.join(ROOT, kv.get("source", ""))
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("source_sha256"):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    return None
+
+
+def phase_roofline(fam, kname, workload=None):
     ms, n, units = fam["phase"]
     avg_ms = ms / max(n, 1)
     per_launch = units / max(n, 1)
     achieved = OPS_PER_FACE * FACES_PER_VERTEX * per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    traffic = profiled_traffic(kname, workload) if workload else None
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None, "kernel": kname,
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": traffic, "kernel": kname,
             "avg_launch_us": round(avg_ms * 1e3, 3), "vertices_per_launch": round(per_launch, 1),
             "ops_per_vertex": OPS_PER_FACE * FACES_PER_VERTEX}
 
@@ -248,7 +270,7 @@ def main():
     value = args.steps * raw / elapsed / 1e9
 
     kname = "k_phase_b<true>" if sched == "fused" else "k_phase_b<false>"
-    roofline = phase_roofline(fam, kname)
+    roofline = phase_roofline(fam, kname, args.workload)
     kernels = {name: {"ms_per_step": round(m / args.steps, 4), "launches_per_step": c // max(args.steps, 1)}
                for name, (m, c, _) in fam.items() if c}
 

@@ -80,47 +80,9 @@ __device__ __forceinline__ int sos_sign(int up, int vp, int uq, int vq) {
   return 1;
 }
 
-// ------------------------------------------------ error bound of one face
-// floor((N-1)/D) capped at eps, for N >= 0 an exact integer in fp64, D > 0.
-// The quotient (< 2^23) is estimated with the hardware reciprocal and then
-// corrected exactly: every product below is an integer under 2^50.
-__device__ __forceinline__ int cand_capped(double N, int D, int eps) {
-  if (N == 0.0) return 0;
-  if (D <= 0) return eps;
-  double Dd = (double)D, n1 = N - 1.0;
-  if (n1 >= (double)eps * Dd) return eps;
-  int q = (int)(n1 * __builtin_amdgcn_rcp(Dd));
-  double r = n1 - (double)q * Dd;
-  if (r < 0.0) q--;
-  else if (r >= Dd) q++;
-  return q;
-}
-
 // exact 2x2 determinant u_a v_b - v_a u_b of 25-bit integers
 __device__ __forceinline__ double det2(int2 a, int2 b) {
   return fma((double)a.x, (double)b.y, -((double)a.y * (double)b.x));
-}
-
-// Error bound for perturbing vertex 2 of a face, min(eps, bound): the three
-// determinants M0 = det(p2,p0), M1 = det(p1,p2), M2 = det(p0,p1) and their
-// sum keep their signs for any perturbation strictly below each quotient;
-// the same-sign relaxations use |u2|-1 and |v2|-1.
-__device__ __forceinline__ int face_bound(int u0, int v0, int u1, int v1, int u2, int v2, int eps) {
-  double M0 = fma((double)u2, (double)v0, -((double)u0 * (double)v2));
-  double M1 = fma((double)u1, (double)v2, -((double)u2 * (double)v1));
-  double M2 = fma((double)u0, (double)v1, -((double)u1 * (double)v0));
-  double M = (M0 + M1) + M2;
-  if (M == 0.0) return 0;
-  int eb = cand_capped(fabs(M), iabs(u1 - u0) + iabs(v0 - v1), eps);
-  int a1 = iabs(u1) + iabs(v1);
-  if (a1 == 0) return 0;
-  eb = min(eb, cand_capped(fabs(M1), a1, eps));
-  int a0 = iabs(u0) + iabs(v0);
-  if (a0 == 0) return 0;
-  eb = min(eb, cand_capped(fabs(M0), a0, eps));
-  if ((u0 > 0 && u1 > 0 && u2 > 0) || (u0 < 0 && u1 < 0 && u2 < 0)) eb = max(eb, min(iabs(u2) - 1, eps));
-  if ((v0 > 0 && v1 > 0 && v2 > 0) || (v0 < 0 && v1 < 0 && v2 < 0)) eb = max(eb, min(iabs(v2) - 1, eps));
-  return eb;
 }
 
 // Minimum over each row of 16 lanes (DPP row rotations; every lane of the
