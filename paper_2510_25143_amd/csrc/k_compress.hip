@@ -259,15 +259,17 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
   }
-  if (valid) {
-    for (int cls = 1; cls < p.K; cls++) {
-      const bool sub = ((lx | ly) & 1) == 0;
-      if (!sub) continue;
+  // semi-Lagrangian candidates on waves 1-3 while wave 0 sweeps: task
+  // (class, subgrid point) for threads 64.. (64 points per class)
+  for (int task = tid - 64; task >= 0 && task < 64 * (p.K - 1); task += 192) {
+    const int cls = 1 + (task >> 6), pt = task & 63;
+    const int sx = 2 * (pt & 7), sy = 2 * (pt >> 3);
+    if (x0 + sx < W && y0 + sy < H) {
+      const int2 Xs = C[sy][sx];
       int pu, pv, ru, rv;
-      sl_predict(pf, H, W, x, y, slc, class_dmax(p.K, cls), &pu, &pv);
-      const int slot = 2 * ((ly >> 1) * 8 + (lx >> 1));
-      SAMP[cls][slot] = quantize(X.x, pu, eps, &ru);
-      SAMP[cls][slot + 1] = quantize(X.y, pv, eps, &rv);
+      sl_predict(pf, H, W, x0 + sx, y0 + sy, slc, class_dmax(p.K, cls), &pu, &pv);
+      SAMP[cls][2 * pt] = quantize(Xs.x, pu, eps, &ru);
+      SAMP[cls][2 * pt + 1] = quantize(Xs.y, pv, eps, &rv);
     }
   }
   __syncthreads();

@@ -584,49 +584,90 @@ __global__ __launch_bounds__(256) void k_words_from_bits(const uint32_t* __restr
   if (i < n) words[i] = (bits[i] + 31) / 32;
 }
 
-// one lane per chunk
+// One lane per chunk.  Lanes decode DEC_STEP symbols at a time into a
+// per-wave staging buffer, then the wave writes the 64 chunks' pieces as
+// 32-bit words, each piece contiguous (16 lanes per 64-byte piece).
+constexpr int DEC_STEP = 32;
 __global__ __launch_bounds__(256) void k_decode(const uint32_t* __restrict__ lut_g, const uint32_t* __restrict__ cbits,
                                                 const uint32_t* __restrict__ wofs, const uint32_t* __restrict__ bs,
                                                 size_t bs_words, size_t nsym_total, int alphabet,
                                                 uint16_t* __restrict__ out, uint32_t* __restrict__ err) {
   __shared__ uint32_t lut[1 << MAXLEN];
+  __shared__ uint32_t stage[4][64][DEC_STEP / 2 + 1];  // per wave, per lane: DEC_STEP symbols
   for (int i = threadIdx.x; i < (1 << MAXLEN); i += 256) lut[i] = lut_g[i];
   __syncthreads();
-  size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
-  size_t nch = (nsym_total + CHUNK - 1) / CHUNK;
-  if (c >= nch) return;
-  uint32_t nbits = cbits[c];
-  size_t w0 = wofs[c];
-  size_t nw = (nbits + 31) / 32;
-  if (w0 + nw > bs_words || nbits > (uint32_t)CHUNK * MAXLEN) {
-    atomicOr(err, 2u);
-    return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const size_t nch = (nsym_total + CHUNK - 1) / CHUNK;
+  const size_t c0 = (size_t)blockIdx.x * 256 + (size_t)wv * 64;  // first chunk of this wave
+  if (c0 >= nch) return;  // whole wave past the end
+  const size_t c = c0 + lane;
+  bool live = c < nch;
+  uint32_t nbits = 0;
+  size_t w0 = 0, nw = 0;
+  if (live) {
+    nbits = cbits[c];
+    w0 = wofs[c];
+    nw = (nbits + 31) / 32;
+    if (w0 + nw > bs_words || nbits > (uint32_t)CHUNK * MAXLEN) {
+      atomicOr(err, 2u);
+      live = false;
+    }
   }
-  size_t lo = c * CHUNK, hi = lo + CHUNK < nsym_total ? lo + CHUNK : nsym_total;
+  const size_t lo = c * CHUNK;
+  const size_t hi = live ? (lo + CHUNK < nsym_total ? lo + CHUNK : nsym_total) : lo;
   uint64_t buf = 0;
   int have = 0;
   size_t wi = 0;
   uint32_t consumed = 0;
-  for (size_t i = lo; i < hi; i++) {
-    while (have <= 32) {
-      uint64_t nxt = wi < nw ? bs[w0 + wi] : 0;
-      wi++;
-      buf |= nxt << (32 - have);
-      have += 32;
+  bool bad = false;
+  for (int base = 0; base < CHUNK; base += DEC_STEP) {
+    // decode this lane's next DEC_STEP symbols into the staging buffer
+    uint32_t pair = 0;
+    for (int k = 0; k < DEC_STEP; k++) {
+      const size_t i = lo + base + k;
+      uint32_t sym = 0;
+      if (!bad && i < hi) {
+        while (have <= 32) {
+          uint64_t nxt = wi < nw ? bs[w0 + wi] : 0;
+          wi++;
+          buf |= nxt << (32 - have);
+          have += 32;
+        }
+        const uint32_t e = lut[(uint32_t)(buf >> (64 - MAXLEN))];
+        const uint32_t l = e >> 16;
+        if (e == 0xFFFFFFFFu || consumed + l > nbits || (int)(e & 0xFFFFu) >= alphabet) {
+          atomicOr(err, 4u);
+          bad = true;
+        } else {
+          sym = e & 0xFFFFu;
+          buf <<= l;
+          have -= (int)l;
+          consumed += l;
+        }
+      }
+      if (k & 1) stage[wv][lane][k >> 1] = pair | (sym << 16);
+      else pair = sym;
     }
-    uint32_t peek = (uint32_t)(buf >> (64 - MAXLEN));
-    uint32_t e = lut[peek];
-    uint32_t l = e >> 16;
-    if (e == 0xFFFFFFFFu || consumed + l > nbits || (int)(e & 0xFFFFu) >= alphabet) {
-      atomicOr(err, 4u);
-      return;
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    // write: piece (chunk c0 + q, symbols base .. base + DEC_STEP) as 16 words
+    for (int d = lane; d < 64 * (DEC_STEP / 2); d += 64) {
+      const int q = d / (DEC_STEP / 2), w = d - q * (DEC_STEP / 2);
+      const size_t cc = c0 + q;
+      if (cc >= nch) continue;
+      const size_t s0 = cc * CHUNK + base + 2 * w;
+      const size_t top = cc * CHUNK + CHUNK < nsym_total ? cc * CHUNK + CHUNK : nsym_total;
+      const uint32_t v = stage[wv][q][w];
+      if (s0 + 1 < top) {
+        *(uint32_t*)(out + s0) = v;
+      } else if (s0 < top) {
+        out[s0] = (uint16_t)(v & 0xFFFFu);
+      }
     }
-    out[i] = (uint16_t)(e & 0xFFFFu);
-    buf <<= l;
-    have -= (int)l;
-    consumed += l;
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
-  if (consumed != nbits) atomicOr(err, 8u);
+  if (live && !bad && consumed != nbits) atomicOr(err, 8u);
 }
 
 // ============================================================ launchers

@@ -443,26 +443,48 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
                                                      uint32_t* __restrict__ part) {
   size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
   uint32_t s = 0;
-#pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; j++)
-    if (base + j < n) s += in[base + j];
+  if (base + SCAN_ITEMS <= n) {
+    const uint4* p4 = (const uint4*)(in + base);
+    const uint4 a = p4[0], b = p4[1];
+    s = a.x + a.y + a.z + a.w + b.x + b.y + b.z + b.w;
+  } else {
+    for (int j = 0; j < SCAN_ITEMS; j++)
+      if (base + j < n) s += in[base + j];
+  }
   uint32_t tot;
   block_exclusive(s, &tot);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_scan_partials(uint32_t* __restrict__ part, size_t nb,
-                                                       uint32_t* __restrict__ total) {
-  uint32_t carry = 0;
-  for (size_t b0 = 0; b0 < nb; b0 += 256) {
-    size_t i = b0 + threadIdx.x;
-    uint32_t v = i < nb ? part[i] : 0;
-    uint32_t tot;
-    uint32_t ex = block_exclusive(v, &tot);
-    if (i < nb) part[i] = carry + ex;
-    carry += tot;
+// exclusive scan of the nb partials by one workgroup of 1024 threads, each
+// owning a run of consecutive partials
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* __restrict__ part, size_t nb,
+                                                        uint32_t* __restrict__ total) {
+  __shared__ uint32_t wsum[16];
+  const size_t per = (nb + 1023) / 1024;
+  const size_t lo = (size_t)threadIdx.x * per, hi = lo + per < nb ? lo + per : nb;
+  uint32_t s = 0;
+  for (size_t i = lo; i < hi; i++) s += part[i];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = (uint32_t)__shfl_up((int)x, o);
+    if (lane >= o) x += y;
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  uint32_t carry = 0, tot = 0;
+  for (int w = 0; w < 16; w++) {
+    if (w < wid) carry += wsum[w];
+    tot += wsum[w];
+  }
+  uint32_t run = carry + x - s;
+  for (size_t i = lo; i < hi; i++) {
+    const uint32_t v = part[i];
+    part[i] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0) *total = tot;
 }
 
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, size_t n,
@@ -470,18 +492,34 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
                                                     uint32_t* __restrict__ out) {
   size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_ITEMS;
   uint32_t v[SCAN_ITEMS];
+  const bool full = base + SCAN_ITEMS <= n;
+  if (full) {
+    const uint4* p4 = (const uint4*)(in + base);
+    const uint4 a = p4[0], b = p4[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) v[j] = base + j < n ? in[base + j] : 0;
+  }
   uint32_t s = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; j++) {
-    v[j] = base + j < n ? in[base + j] : 0;
-    s += v[j];
-  }
+  for (int j = 0; j < SCAN_ITEMS; j++) s += v[j];
   uint32_t tot;
   uint32_t ex = block_exclusive(s, &tot) + part[blockIdx.x];
+  uint32_t o[SCAN_ITEMS];
 #pragma unroll
   for (int j = 0; j < SCAN_ITEMS; j++) {
-    if (base + j < n) out[base + j] = ex;
+    o[j] = ex;
     ex += v[j];
+  }
+  if (full) {
+    uint4* q4 = (uint4*)(out + base);
+    q4[0] = make_uint4(o[0], o[1], o[2], o[3]);
+    q4[1] = make_uint4(o[4], o[5], o[6], o[7]);
+  } else {
+    for (int j = 0; j < SCAN_ITEMS; j++)
+      if (base + j < n) out[base + j] = o[j];
   }
 }
 
@@ -556,11 +594,11 @@ size_t scan_partials_size(size_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1
 void launch_scan(const uint32_t* in, size_t n, uint32_t* out, uint32_t* part, uint32_t* total, hipStream_t s) {
   size_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   if (nb == 0) {
-    k_scan_partials<<<1, 256, 0, s>>>(part, 0, total);
+    k_scan_partials<<<1, 1024, 0, s>>>(part, 0, total);
     return;
   }
   k_scan_reduce<<<(unsigned)nb, 256, 0, s>>>(in, n, part);
-  k_scan_partials<<<1, 256, 0, s>>>(part, nb, total);
+  k_scan_partials<<<1, 1024, 0, s>>>(part, nb, total);
   k_scan_apply<<<(unsigned)nb, 256, 0, s>>>(in, n, part, out);
 }
 void launch_count_faces(const uint32_t* masks, size_t N, uint32_t* cnt, hipStream_t s) {
