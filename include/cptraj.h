@@ -244,13 +244,16 @@ cpt_status cpt_selector_grad(const float* w, const float* feats, const int32_t* 
 cpt_status cpt_selector_train(const float* feats, const int32_t* labels, int n, float* w, uint16_t* w_bf16,
                               const cpt_train_options* opt, float* final_loss, void* stream);
 
-/* Kernel timing for benchmarks.  cpt_timing_enable(1) resets the counters
- * and brackets every launch of the main kernel families with HIP events on
- * the caller's stream; cpt_timing_read returns the accumulated device time,
- * the number of launches and the work units (vertices or symbols) they
- * covered.  Families: 0 per-vertex bound/predict/quantize phase, 1 predictor
- * choice, 2 frame reconstruction, 3 Huffman decoding, 4 Huffman encoding,
- * 5 face extraction.  Process-wide; not for concurrent callers. */
+/* Kernel timing for benchmarks.  cpt_timing_enable(n) with n >= 1 resets
+ * the counters and brackets every n-th launch of each of the main kernel
+ * families with HIP events on the stream it is launched on (0 disables;
+ * every bracket adds a gap of several microseconds between kernels, so a
+ * period above 1 keeps the timed work close to an untimed run).
+ * cpt_timing_read returns the accumulated device time, the number of
+ * bracketed launches and the work units (vertices or symbols) they covered.
+ * Families: 0 per-vertex bound/predict/quantize phase, 1 predictor choice,
+ * 2 frame reconstruction, 3 Huffman decoding, 4 Huffman encoding, 5 face
+ * extraction.  Process-wide; not for concurrent callers. */
 cpt_status cpt_timing_enable(int on);
 cpt_status cpt_timing_read(int family, double* total_ms, uint64_t* launches, uint64_t* units);
 

@@ -291,9 +291,10 @@ def field_params(field, eb, eb_mode=0):
 TIMING_FAMILIES = {"phase": 0, "modes": 1, "reconstruct": 2, "decode": 3, "encode": 4, "extract": 5}
 
 
-def timing_enable(on=True):
-    """Bracket the main kernel launches with HIP events (resets counters)."""
-    _check(lib().cpt_timing_enable(1 if on else 0))
+def timing_enable(on=True, period=1):
+    """Bracket every `period`-th launch of each main kernel family with HIP
+    events (resets counters); on=False disables."""
+    _check(lib().cpt_timing_enable(max(int(period), 1) if on else 0))
 
 
 def timing_read(family):

@@ -295,6 +295,8 @@ enum { FAM_PHASE = 0, FAM_MODES = 1, FAM_RECON = 2, FAM_DECODE = 3, FAM_ENCODE =
 
 struct Timing {
   bool on = false;
+  int period = 1;              // bracket every period-th launch of a family
+  uint64_t seen[NFAM] = {0};  // launches of each family since enabling
   std::mutex mu;
   std::vector<hipEvent_t> pool;
   struct Rec {
@@ -340,6 +342,7 @@ struct TimeScope {
   TimeScope(int f, uint64_t u, hipStream_t st) : fam(f), units(u), s(st) {
     if (!g_tim.on || g_capturing) return;
     std::lock_guard<std::mutex> lk(g_tim.mu);
+    if (g_tim.seen[fam]++ % (uint64_t)g_tim.period != 0) return;
     a = g_tim.get();
     (void)hipEventRecord(a, s);
   }
@@ -1145,8 +1148,10 @@ cpt_status cpt_selector_train(const float* feats, const int32_t* labels, int n, 
 
 cpt_status cpt_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_tim.mu);
-  g_tim.on = on != 0;
+  g_tim.on = on > 0;
+  g_tim.period = on > 0 ? on : 1;
   for (int i = 0; i < NFAM; i++) {
+    g_tim.seen[i] = 0;
     g_tim.ms[i] = 0;
     g_tim.launches[i] = 0;
     g_tim.units[i] = 0;

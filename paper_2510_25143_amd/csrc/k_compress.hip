@@ -65,203 +65,200 @@ __device__ __forceinline__ int64_t featq_num(int64_t num, int64_t den) {
   return q < -65536 ? -65536 : (q > 65536 ? 65536 : q);
 }
 
-template <typename T, typename Op>
-__device__ __forceinline__ T block_reduce(T v, T* sh, Op op) {
-  int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) sh[tid] = op(sh[tid], sh[tid + s]);
-    __syncthreads();
-  }
-  T r = sh[0];
-  __syncthreads();
-  return r;
-}
-
 __device__ __forceinline__ float bf16f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ------------------------------------------------------------ mode choice
-// One workgroup per block of a decision frame.  Exhaustive trial: each
-// candidate is micro-encoded over the block with the global bound eps'
-// (Sec. VI-B): Lorenzo writes its reconstruction back to a candidate buffer
-// (anti-diagonal sweep), semi-Lagrangian reads only the previous frame.  The
-// rate score of each candidate uses the codes on the stride-2 subgrid.
-// The choice reads only the block's own values of frame t and the final
-// frame t-1, so it may run right before the block's own colour phase.
+// One wave decides the predictor class of one block of a decision frame.
+// Exhaustive trial: each candidate is micro-encoded over the block with the
+// global bound eps' (Sec. VI-B): Lorenzo writes its reconstruction back to a
+// candidate buffer (anti-diagonal sweep), semi-Lagrangian reads only the
+// previous frame.  The rate score of each candidate uses the codes on the
+// stride-2 subgrid.  The choice reads only the block's own values of frame t
+// and the final frame t-1, so it may run right before the block's own colour
+// phase.  A single wave per block keeps every block of a frame resident at
+// once; the sequential Lorenzo sweep sets the block's latency.
 struct ModesSmem {
   int2 C[TILE][TILE];
   int2 P[TILE][TILE];
-  int64_t red[256];
   int64_t R[4];
-  int64_t part[4][3];
   float fin[10];
   float h1[64], h2[64], lg[4];
-  int CU[2][TILE][TILE];
   int SAMP[4][128];
+  uint32_t hist[4][256];  // per class: 1024 codes, one byte each
   int cls;
 };
+static_assert(QSYM == 4 * 256, "one histogram byte per residual code");
+
+// LDS writes of one lane become visible to the other lanes of its wave
+// (the wave's LDS operations complete in order; this keeps the compiler from
+// reordering across it)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T v, Op op) {
+  for (int o = 32; o > 0; o >>= 1) v = op(v, (T)__shfl_xor(v, o));
+  return v;
+}
 
 // cur, flags: the field's arrays; mrow: its predictor classes of frame t's
 // group (block by * tx + bx); feats: the group's feature rows or null.
-// Called by all 256 threads; returns the class of the block.
+// Called by the 64 lanes of one wave (threads 0..63 of the workgroup), with
+// no workgroup barrier inside; returns the class of the block.
 __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint8_t* __restrict__ flags,
                           const FieldParams& p, int t, int bx, int by, const int64_t* __restrict__ tlog,
                           const uint16_t* __restrict__ selw, uint8_t* mrow, float* __restrict__ feats) {
   auto& C = S.C;
   auto& P = S.P;
-  auto& R = S.R;
-  auto& fin = S.fin;
-  auto& h1 = S.h1;
-  auto& h2 = S.h2;
-  auto& lg = S.lg;
-  auto& CU = S.CU;
   auto& SAMP = S.SAMP;
-  auto& part = S.part;
-  int64_t* red = S.red;
-  const int tid = threadIdx.x, lx = tid & 15, ly = tid >> 4;
-  const int x0 = bx * TILE, y0 = by * TILE, x = x0 + lx, y = y0 + ly;
+  const int lane = threadIdx.x & 63;
+  const int x0 = bx * TILE, y0 = by * TILE;
   const int H = p.H, W = p.W;
   const size_t HW = (size_t)H * W;
-  const bool valid = x < W && y < H;
-  const size_t gi = (size_t)y * W + x;
   const int2* cf = cur + (size_t)t * HW;
   const int2* pf = cur + (size_t)(t - 1) * HW;
-  const int2 X = valid ? cf[gi] : make_int2(0, 0);
-  const int2 Pv = valid ? pf[gi] : make_int2(0, 0);
-  C[ly][lx] = X;
-  P[ly][lx] = Pv;
   const SLConst slc{p.cx, p.sx, p.cy, p.sy};
   const int eps = p.eps;
-  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int v = lane + 64 * k, lx = v & 15, ly = v >> 4, x = x0 + lx, y = y0 + ly;
+    const bool valid = x < W && y < H;
+    const size_t gi = (size_t)y * W + x;
+    const int2 X = valid ? cf[gi] : make_int2(0, 0);
+    C[ly][lx] = X;
+    P[ly][lx] = valid ? pf[gi] : make_int2(0, 0);
+  }
+  for (int i = lane; i < 4 * 128; i += 64) (&SAMP[0][0])[i] = -1;
+  for (int i = lane; i < 4 * 256; i += 64) (&S.hist[0][0])[i] = 0u;
+  wave_sync();
 
   // ---------------- block features (also the selector's input)
   int cls_learned = -1;
   if (feats != nullptr || p.predictor == 4) {
-    int64_t s = eps > 1 ? eps : 1;
+    const int64_t s = eps > 1 ? eps : 1;
     int64_t S0 = 0, S1 = 0, S2 = 0, Dm = 0, Ds = 0, Sx = 0, Sy = 0, nf = 0, S6 = 0, S7 = 0, n = 0, m = 0;
-    if (valid) {
-      n = 1;
-      S0 = (int64_t)iabs(X.x - Pv.x) + iabs(X.y - Pv.y);
-      int lu = lorenzo_local(C, P, lx, ly, true, 0), lv = lorenzo_local(C, P, lx, ly, true, 1);
-      int64_t r3 = (int64_t)iabs(X.x - lu) + iabs(X.y - lv);
-      S1 = r3;
+    for (int k = 0; k < 4; k++) {
+      const int v = lane + 64 * k, lx = v & 15, ly = v >> 4, x = x0 + lx, y = y0 + ly;
+      if (!(x < W && y < H)) continue;
+      const size_t gi = (size_t)y * W + x;
+      const int2 X = C[ly][lx], Pv = P[ly][lx];
+      n += 1;
+      S0 += (int64_t)iabs(X.x - Pv.x) + iabs(X.y - Pv.y);
+      const int lu = lorenzo_local(C, P, lx, ly, true, 0), lv = lorenzo_local(C, P, lx, ly, true, 1);
+      const int64_t r3 = (int64_t)iabs(X.x - lu) + iabs(X.y - lv);
+      S1 += r3;
       if (lx + 1 < TILE && x + 1 < W) S2 += (int64_t)iabs(C[ly][lx + 1].x - X.x) + iabs(C[ly][lx + 1].y - X.y);
       if (ly + 1 < TILE && y + 1 < H) S2 += (int64_t)iabs(C[ly + 1][lx].x - X.x) + iabs(C[ly + 1][lx].y - X.y);
       const int64_t DCAP = (int64_t)1 << 40;
-      int64_t dx = clamp64(sl_disp(Pv.x, p.cx, p.sx), -DCAP, DCAP);
-      int64_t dy = clamp64(sl_disp(Pv.y, p.cy, p.sy), -DCAP, DCAP);
-      int64_t ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
-      int64_t d = ax > ay ? ax : ay;
-      Dm = d;
-      Ds = d;
-      Sx = dx;
-      Sy = dy;
-      nf = flags[(size_t)t * HW + gi] ? 1 : 0;
+      const int64_t dx = clamp64(sl_disp(Pv.x, p.cx, p.sx), -DCAP, DCAP);
+      const int64_t dy = clamp64(sl_disp(Pv.y, p.cy, p.sy), -DCAP, DCAP);
+      const int64_t ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
+      const int64_t d = ax > ay ? ax : ay;
+      Dm = Dm > d ? Dm : d;
+      Ds += d;
+      Sx += dx;
+      Sy += dy;
+      nf += flags[(size_t)t * HW + gi] ? 1 : 0;
       if ((lx & 3) == 0 && (ly & 3) == 0) {
         int pu, pv;
         sl_predict(pf, H, W, x, y, slc, 2, &pu, &pv);
-        S6 = (int64_t)iabs(X.x - pu) + iabs(X.y - pv);
-        S7 = r3;
-        m = 1;
+        S6 += (int64_t)iabs(X.x - pu) + iabs(X.y - pv);
+        S7 += r3;
+        m += 1;
       }
     }
     auto add = [](int64_t a, int64_t b) { return a + b; };
     auto mx = [](int64_t a, int64_t b) { return a > b ? a : b; };
-    S0 = block_reduce(S0, red, add);
-    S1 = block_reduce(S1, red, add);
-    S2 = block_reduce(S2, red, add);
-    Dm = block_reduce(Dm, red, mx);
-    Ds = block_reduce(Ds, red, add);
-    Sx = block_reduce(Sx, red, add);
-    Sy = block_reduce(Sy, red, add);
-    nf = block_reduce(nf, red, add);
-    S6 = block_reduce(S6, red, add);
-    S7 = block_reduce(S7, red, add);
-    n = block_reduce(n, red, add);
-    m = block_reduce(m, red, add);
-    if (tid == 0) {
+    S0 = wave_reduce(S0, add);
+    S1 = wave_reduce(S1, add);
+    S2 = wave_reduce(S2, add);
+    Dm = wave_reduce(Dm, mx);
+    Ds = wave_reduce(Ds, add);
+    Sx = wave_reduce(Sx, add);
+    Sy = wave_reduce(Sy, add);
+    nf = wave_reduce(nf, add);
+    S6 = wave_reduce(S6, add);
+    S7 = wave_reduce(S7, add);
+    n = wave_reduce(n, add);
+    m = wave_reduce(m, add);
+    if (lane == 0) {
       int64_t q[10] = {featq_num(S0, 2 * n * s), featq_num(S1, 2 * n * s), featq_num(S2, 2 * n * s),
                        featq_num(Dm, 65536),     featq_num(Ds, n * 65536),  featq_num(nf, n),
                        featq_num(S6, 2 * m * s), featq_num(S7, 2 * m * s),  featq_num(Sx, n * 65536),
                        featq_num(Sy, n * 65536)};
-      for (int i = 0; i < 10; i++) fin[i] = (float)q[i] / 256.0f;
+      for (int i = 0; i < 10; i++) S.fin[i] = (float)q[i] / 256.0f;
     }
-    __syncthreads();
+    wave_sync();
     const size_t bi = (size_t)by * p.tx + bx;
-    if (feats != nullptr && tid < 10) feats[bi * 10 + tid] = fin[tid];
+    if (feats != nullptr && lane < 10) feats[bi * 10 + lane] = S.fin[lane];
     if (p.predictor == 4) {
       // 10-64-64-4 MLP, bf16 weights, fp32 fused multiply-add in input order
-      if (tid < 64) {
-        float a = bf16f(selw[640 + tid]);
-        for (int i = 0; i < 10; i++) a = fmaf(bf16f(selw[tid * 10 + i]), fin[i], a);
-        h1[tid] = a > 0.0f ? a : 0.0f;
+      {
+        float a = bf16f(selw[640 + lane]);
+        for (int i = 0; i < 10; i++) a = fmaf(bf16f(selw[lane * 10 + i]), S.fin[i], a);
+        S.h1[lane] = a > 0.0f ? a : 0.0f;
       }
-      __syncthreads();
-      if (tid < 64) {
-        float a = bf16f(selw[4800 + tid]);
-        for (int i = 0; i < 64; i++) a = fmaf(bf16f(selw[704 + tid * 64 + i]), h1[i], a);
-        h2[tid] = a > 0.0f ? a : 0.0f;
+      wave_sync();
+      {
+        float a = bf16f(selw[4800 + lane]);
+        for (int i = 0; i < 64; i++) a = fmaf(bf16f(selw[704 + lane * 64 + i]), S.h1[i], a);
+        S.h2[lane] = a > 0.0f ? a : 0.0f;
       }
-      __syncthreads();
-      if (tid < 4) {
-        float a = bf16f(selw[5120 + tid]);
-        for (int i = 0; i < 64; i++) a = fmaf(bf16f(selw[4864 + tid * 64 + i]), h2[i], a);
-        lg[tid] = a;
+      wave_sync();
+      if (lane < 4) {
+        float a = bf16f(selw[5120 + lane]);
+        for (int i = 0; i < 64; i++) a = fmaf(bf16f(selw[4864 + lane * 64 + i]), S.h2[i], a);
+        S.lg[lane] = a;
       }
-      __syncthreads();
+      wave_sync();
       int best = 0;
       for (int c = 1; c < 4; c++)
-        if (lg[c] > lg[best]) best = c;
+        if (S.lg[c] > S.lg[best]) best = c;
       cls_learned = best;
     }
   }
   if (p.predictor == 4) {
-    if (tid == 0) {
-      mrow[(size_t)by * p.tx + bx] = (uint8_t)cls_learned;
-      S.cls = cls_learned;
-    }
-    __syncthreads();
-    const int r = S.cls;
-    __syncthreads();
-    return r;
+    if (lane == 0) mrow[(size_t)by * p.tx + bx] = (uint8_t)cls_learned;
+    return cls_learned;
   }
 
   // ---------------- exhaustive trial over the K candidates
-  // Lorenzo: wave 0 sweeps the anti-diagonals (lanes 0-15 u rows, 16-31 v
-  // rows) writing reconstructions into the candidate buffer; semi-Lagrangian
-  // candidates are computed by every thread for its own vertex.  Codes of
-  // the stride-2 subgrid go to SAMP[class][0..127] (slot 2 i + component of
+  // Lorenzo: lanes 0-15 sweep the rows of u, lanes 16-31 those of v, carrying
+  // the candidate reconstructions in registers; then every lane takes
+  // semi-Lagrangian candidates (class, stride-2 point).  Codes of the
+  // stride-2 subgrid go to SAMP[class][0..127] (slot 2 i + component of
   // subgrid point i; -1 when absent).
-  for (int i = tid; i < 4 * 128; i += 256) (&SAMP[0][0])[i] = -1;
-  CU[0][ly][lx] = X.x;
-  CU[1][ly][lx] = X.y;
-  __syncthreads();
-  if (tid < 2 * TILE) {
-    const int c = tid >> 4, row = tid & 15;
+  {
+    // A lane keeps its own last reconstruction (the left neighbour of its
+    // next vertex); the row above arrives from the previous lane of the same
+    // 16-lane DPP row by a row shift of that lane's last value.  All 64 lanes
+    // step together (DPP reads need active source lanes); lanes 32-63 have
+    // no vertices.
+    const int c = (lane >> 4) & 1, row = lane & 15;
+    const bool mine = lane < 2 * TILE;
+    int last = 0, upl = 0;
     for (int d = 0; d < 2 * TILE - 1; d++) {
       const int col = d - row;
-      if (col >= 0 && col < TILE && x0 + col < W && y0 + row < H) {
-        int s = (col > 0 ? CU[c][row][col - 1] : 0) + (row > 0 ? CU[c][row - 1][col] : 0) -
-                (col > 0 && row > 0 ? CU[c][row - 1][col - 1] : 0);
+      const int up = __builtin_amdgcn_update_dpp(0, last, 0x111, 0xF, 0xF, true);  // row_shr:1
+      if (mine && col >= 0 && col < TILE && x0 + col < W && y0 + row < H) {
+        int sm = (col > 0 ? last : 0) + (row > 0 ? up : 0) - (col > 0 && row > 0 ? upl : 0);
         const int2 pc = P[row][col];
         const int2 pl = col > 0 ? P[row][col - 1] : make_int2(0, 0);
         const int2 pu = row > 0 ? P[row - 1][col] : make_int2(0, 0);
         const int2 plu = (col > 0 && row > 0) ? P[row - 1][col - 1] : make_int2(0, 0);
-        s += c ? (pc.y - pl.y - pu.y + plu.y) : (pc.x - pl.x - pu.x + plu.x);
+        sm += c ? (pc.y - pl.y - pu.y + plu.y) : (pc.x - pl.x - pu.x + plu.x);
         const int2 xv = C[row][col];
         int rec;
-        const int q = quantize(c ? xv.y : xv.x, s, eps, &rec);
-        CU[c][row][col] = rec;
+        const int q = quantize(c ? xv.y : xv.x, sm, eps, &rec);
+        last = rec;
         if (((row | col) & 1) == 0) SAMP[0][2 * ((row >> 1) * 8 + (col >> 1)) + c] = q;
       }
-      __builtin_amdgcn_wave_barrier();
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      upl = up;
     }
   }
-  // semi-Lagrangian candidates on waves 1-3 while wave 0 sweeps: task
-  // (class, subgrid point) for threads 64.. (64 points per class)
-  for (int task = tid - 64; task >= 0 && task < 64 * (p.K - 1); task += 192) {
+  for (int task = lane; task < 64 * (p.K - 1); task += 64) {
     const int cls = 1 + (task >> 6), pt = task & 63;
     const int sx = 2 * (pt & 7), sy = 2 * (pt >> 3);
     if (x0 + sx < W && y0 + sy < H) {
@@ -272,63 +269,44 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
       SAMP[cls][2 * pt + 1] = quantize(Xs.y, pv, eps, &rv);
     }
   }
-  __syncthreads();
-  // rate score per candidate: thread (class, sample) counts the equal codes;
-  // the first occurrence of a code adds T[count]
-  for (int c0 = 0; c0 < p.K; c0 += 2) {
-    const int cls = c0 + (tid >> 7), i = tid & 127;
-    int64_t tsum = 0, nvalid = 0, nover = 0;
-    if (cls < p.K) {
-      const int v = SAMP[cls][i];
-      if (v > 0) {
-        int cnt = 0;
-        bool first = true;
-        for (int jj = 0; jj < 128; jj++) {
-          const int w2 = SAMP[cls][jj];
-          cnt += w2 == v;
-          first &= !(w2 == v && jj < i);
-        }
-        if (first) tsum = tlog[cnt];
-        nvalid = 1;
-      } else if (v == 0) {
-        nover = 1;
-      }
+  wave_sync();
+  // rate score per candidate: a byte histogram of the class's 128 codes
+  // (counts <= 128); the lane whose atomic add finds a code's count still 0
+  // holds its first occurrence and adds T[final count] for it
+  for (int cls = 0; cls < p.K; cls++) {
+    const int a0 = SAMP[cls][lane], a1 = SAMP[cls][lane + 64];
+    const int s0 = 8 * (a0 & 3), s1 = 8 * (a1 & 3);
+    bool f0 = false, f1 = false;
+    if (a0 > 0) f0 = ((atomicAdd(&S.hist[cls][a0 >> 2], 1u << s0) >> s0) & 0xFFu) == 0u;
+    if (a1 > 0) f1 = ((atomicAdd(&S.hist[cls][a1 >> 2], 1u << s1) >> s1) & 0xFFu) == 0u;
+    wave_sync();
+    int64_t tsum = 0;
+    if (f0) tsum += tlog[(S.hist[cls][a0 >> 2] >> s0) & 0xFFu];
+    if (f1) tsum += tlog[(S.hist[cls][a1 >> 2] >> s1) & 0xFFu];
+    int64_t nvalid = (a0 > 0) + (a1 > 0), nover = (a0 == 0) + (a1 == 0);
+    auto add = [](int64_t a, int64_t b) { return a + b; };
+    tsum = wave_reduce(tsum, add);
+    nvalid = wave_reduce(nvalid, add);
+    nover = wave_reduce(nover, add);
+    if (lane == 0) {
+      const int64_t n = nvalid, L = nover;
+      const int64_t h0 = n > 0 ? floor_div64(tlog[n] - tsum, n) : 0;
+      const int64_t pen = (n + L) > 0 ? floor_div64((int64_t)16 * 65536 * L, n + L) : 0;
+      const int64_t lgK = p.K == 4 ? 2 : 1;
+      const int64_t meta = floor_div64(65536 * lgK, (int64_t)512 * p.bt);
+      S.R[cls] = h0 + pen + meta;
     }
-    // reduce over the 128 threads of this class (two waves)
-    for (int o = 32; o > 0; o >>= 1) {
-      tsum += __shfl_xor(tsum, o);
-      nvalid += __shfl_xor(nvalid, o);
-      nover += __shfl_xor(nover, o);
-    }
-    if ((tid & 63) == 0) {
-      part[tid >> 6][0] = tsum;
-      part[tid >> 6][1] = nvalid;
-      part[tid >> 6][2] = nover;
-    }
-    __syncthreads();
-    if ((tid & 127) == 0 && cls < p.K) {
-      const int w0 = (tid >> 6);
-      int64_t ts = part[w0][0] + part[w0 + 1][0], n = part[w0][1] + part[w0 + 1][1], L = part[w0][2] + part[w0 + 1][2];
-      int64_t h0 = n > 0 ? floor_div64(tlog[n] - ts, n) : 0;
-      int64_t pen = (n + L) > 0 ? floor_div64((int64_t)16 * 65536 * L, n + L) : 0;
-      int64_t lgK = p.K == 4 ? 2 : 1;
-      int64_t meta = floor_div64(65536 * lgK, (int64_t)512 * p.bt);
-      R[cls] = h0 + pen + meta;
-    }
-    __syncthreads();
   }
-  if (tid == 0) {
+  if (lane == 0) {
     int best = 1;
     for (int c = 2; c < p.K; c++)
-      if (R[c] < R[best]) best = c;
-    int cls = 1000 * (R[0] - R[best]) > 3 * R[0] ? best : 0;
+      if (S.R[c] < S.R[best]) best = c;
+    const int cls = 1000 * (S.R[0] - S.R[best]) > 3 * S.R[0] ? best : 0;
     mrow[(size_t)by * p.tx + bx] = (uint8_t)cls;
     S.cls = cls;
   }
-  __syncthreads();
-  const int r = S.cls;
-  __syncthreads();
-  return r;
+  wave_sync();
+  return S.cls;
 }
 
 // --------------------------------------------------------------- the phase
@@ -633,7 +611,13 @@ __device__ __forceinline__ void run_block(Smem& S, const BatchView& B, const Fie
       if constexpr (DECIDE) {
         if (mstate == MODES_DECIDE) {
           float* feats = d.feats_dbg ? d.feats_dbg + (size_t)gidx * p.tx * p.ty * 10 : nullptr;
-          cls = block_mode(S.m, cur, flags, p, t, bx, by, B.tlog, B.selw, mrow, feats);
+          if (threadIdx.x < 64) {
+            const int c = block_mode(S.m, cur, flags, p, t, bx, by, B.tlog, B.selw, mrow, feats);
+            if (threadIdx.x == 0) S.m.cls = c;
+          }
+          __syncthreads();
+          cls = S.m.cls;
+          __syncthreads();
         } else {
           cls = mrow[(size_t)by * p.tx + bx];
         }
@@ -648,8 +632,8 @@ __device__ __forceinline__ void run_block(Smem& S, const BatchView& B, const Fie
 
 // predictor classes of frame t for every block of the first m fields of the
 // launch order; pre[j] = blocks of the fields before j
-__global__ __launch_bounds__(256) void k_modes_b(BatchView B, const long long* __restrict__ pre, int m, int t,
-                                                 int gidx) {
+__global__ __launch_bounds__(64) void k_modes_b(BatchView B, const long long* __restrict__ pre, int m, int t,
+                                                int gidx) {
   __shared__ ModesSmem S;
   const int j = find_field(pre, m, blockIdx.x);
   const FieldDesc& d = B.D[B.ord[j]];
@@ -756,7 +740,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 // ============================================================ launchers
 void launch_modes_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int gidx,
                     hipStream_t s) {
-  if (nblocks > 0) k_modes_b<<<(unsigned)nblocks, 256, 0, s>>>(B, pre, m, t, gidx);
+  if (nblocks > 0) k_modes_b<<<(unsigned)nblocks, 64, 0, s>>>(B, pre, m, t, gidx);
 }
 
 void launch_phase_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int c,

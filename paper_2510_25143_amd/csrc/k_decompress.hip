@@ -105,28 +105,37 @@ __global__ __launch_bounds__(256) void k_reconstruct(int2* __restrict__ cur, flo
   }
   __syncthreads();
 
-  // Lorenzo blocks: one wave sweeps the anti-diagonals, lanes 0-15 the rows
-  // of u and lanes 16-31 the rows of v; no workgroup barrier inside
-  if (cls == 0 && tid < 2 * TILE) {
-    const int c = tid >> 4, row = tid & 15;
+  // Lorenzo blocks: wave 0 sweeps the anti-diagonals, lanes 0-15 the rows of
+  // u and lanes 16-31 the rows of v.  A lane keeps its last value (the left
+  // neighbour of its next vertex); the row above arrives from the previous
+  // lane of the same 16-lane DPP row by a row shift.  All 64 lanes of the
+  // wave step together (DPP reads need active source lanes).
+  if (cls == 0 && tid < 64) {
+    const int c = (tid >> 4) & 1, row = tid & 15;
+    const bool mine = tid < 2 * TILE;
     const bool has_prev = t > 0;
+    int last = 0, upl = 0;
     for (int d = 0; d < 2 * TILE - 1; d++) {
       const int col = d - row;
-      if (col >= 0 && col < TILE && bx * TILE + col < W && by * TILE + row < H && !KN[c][row][col]) {
-        int s = (col > 0 ? C[c][row][col - 1] : 0) + (row > 0 ? C[c][row - 1][col] : 0) -
-                (col > 0 && row > 0 ? C[c][row - 1][col - 1] : 0);
-        if (has_prev)
-          s += P[c][row][col] - (col > 0 ? P[c][row][col - 1] : 0) - (row > 0 ? P[c][row - 1][col] : 0) +
-               (col > 0 && row > 0 ? P[c][row - 1][col - 1] : 0);
-        int64_t rv = (int64_t)s + DQ[c][row][col];
-        if (rv >= (1 << 25) || rv <= -(1 << 25)) {
-          atomicOr(err, 128u);
-          rv = 0;
+      const int up = __builtin_amdgcn_update_dpp(0, last, 0x111, 0xF, 0xF, true);  // row_shr:1
+      if (mine && col >= 0 && col < TILE && bx * TILE + col < W && by * TILE + row < H) {
+        if (KN[c][row][col]) {
+          last = C[c][row][col];
+        } else {
+          int s = (col > 0 ? last : 0) + (row > 0 ? up : 0) - (col > 0 && row > 0 ? upl : 0);
+          if (has_prev)
+            s += P[c][row][col] - (col > 0 ? P[c][row][col - 1] : 0) - (row > 0 ? P[c][row - 1][col] : 0) +
+                 (col > 0 && row > 0 ? P[c][row - 1][col - 1] : 0);
+          int64_t rv = (int64_t)s + DQ[c][row][col];
+          if (rv >= (1 << 25) || rv <= -(1 << 25)) {
+            atomicOr(err, 128u);
+            rv = 0;
+          }
+          last = (int)rv;
+          C[c][row][col] = last;
         }
-        C[c][row][col] = (int)rv;
       }
-      __builtin_amdgcn_wave_barrier();
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      upl = up;
     }
   }
   __syncthreads();
