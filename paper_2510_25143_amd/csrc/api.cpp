@@ -381,7 +381,7 @@ struct Plan {
   int K = 1, maxT = 0;
   std::vector<FieldDesc> D;
   std::vector<int> ord;
-  std::vector<long long> rpre, vpre, hpre, cxpre, cqpre;  // natural order
+  std::vector<long long> rpre, vpre, hpre, cxpre, cqpre, fpre;  // natural order
   std::vector<long long> mpre, ppre;                      // launch order
   std::vector<int> m_at, mstate_at, gidx_at;              // per frame
   std::vector<uint64_t> hw_at, cv_at;                     // vertices per frame / per phase
@@ -424,7 +424,7 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
   P.K = opt.predictor == 2 ? 2 : (opt.predictor >= 3 ? 4 : 1);
   const int K = P.K, bt = opt.mode_bt, mb = mode_bits(K);
   P.D.assign(n, FieldDesc{});
-  for (auto* v : {&P.rpre, &P.vpre, &P.hpre, &P.cxpre, &P.cqpre, &P.mpre, &P.ppre}) v->assign(n + 1, 0);
+  for (auto* v : {&P.rpre, &P.vpre, &P.hpre, &P.cxpre, &P.cqpre, &P.fpre, &P.mpre, &P.ppre}) v->assign(n + 1, 0);
   P.key = std::to_string(n) + ":" + std::to_string(opt.predictor) + ":" + std::to_string(bt);
   for (int i = 0; i < n; i++) {
     const int H = HWT[3 * i], W = HWT[3 * i + 1], T = HWT[3 * i + 2];
@@ -464,10 +464,11 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
     P.hpre[i + 1] = P.hpre[i] + (N + HIST_SPAN_VERTICES - 1) / HIST_SPAN_VERTICES;
     P.cxpre[i + 1] = P.cxpre[i] + d.nchx;
     P.cqpre[i + 1] = P.cqpre[i] + ncq;
+    P.fpre[i + 1] = P.fpre[i] + (long long)((W + FIELDPASS_TW - 1) / FIELDPASS_TW) * ((H + FIELDPASS_TH - 1) / FIELDPASS_TH);
     P.maxT = std::max(P.maxT, T);
     P.key += ":" + std::to_string(H) + "x" + std::to_string(W) + "x" + std::to_string(T);
   }
-  for (auto v : {P.rpre.back(), P.vpre.back(), P.hpre.back(), P.cxpre.back(), P.cqpre.back()})
+  for (auto v : {P.rpre.back(), P.vpre.back(), P.hpre.back(), P.cxpre.back(), P.cqpre.back(), P.fpre.back()})
     if (v >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
   P.ord.resize(n);
   for (int i = 0; i < n; i++) P.ord[i] = i;
@@ -545,13 +546,11 @@ cpt_status build_schedule(Plan& P, int group) {
 }
 
 // Scratch of a batch.  The tables block (descriptors, launch order, prefix
-// tables, schedule) is contiguous and uploaded in one copy.  Edge signs and
-// face masks live in the bound-code and residual-code arrays, which the
-// phases overwrite only after the lossless flags are made.
+// tables, schedule) is contiguous and uploaded in one copy.
 struct BatchBufs {
   FieldDesc* D;
   int* ord;
-  long long *rpre, *vpre, *hpre, *cxpre, *cqpre, *mpre, *ppre, *sstart;
+  long long *rpre, *vpre, *hpre, *cxpre, *cqpre, *fpre, *mpre, *ppre, *sstart;
   SchedSeg* seg;
   size_t tables_bytes;
   unsigned *done, *ctl;
@@ -579,7 +578,8 @@ cpt_status carve_batch(Arena& A, const Plan& P, BatchBufs& b) {
       {(void**)&b.D, sizeof(FieldDesc) * n}, {(void**)&b.ord, 4 * (size_t)n},
       {(void**)&b.rpre, vec_bytes(P.rpre)},   {(void**)&b.vpre, vec_bytes(P.vpre)},
       {(void**)&b.hpre, vec_bytes(P.hpre)},   {(void**)&b.cxpre, vec_bytes(P.cxpre)},
-      {(void**)&b.cqpre, vec_bytes(P.cqpre)}, {(void**)&b.mpre, vec_bytes(P.mpre)},
+      {(void**)&b.cqpre, vec_bytes(P.cqpre)}, {(void**)&b.fpre, vec_bytes(P.fpre)},
+      {(void**)&b.mpre, vec_bytes(P.mpre)},
       {(void**)&b.ppre, vec_bytes(P.ppre)},   {(void**)&b.sstart, 8 * (P.sstart.size() + 1)},
       {(void**)&b.seg, sizeof(SchedSeg) * (P.seg.size() + 1)},
   };
@@ -643,6 +643,7 @@ void stage_tables(const Plan& P, const BatchBufs& b, char* stage) {
   put(b.hpre, P.hpre.data(), vec_bytes(P.hpre));
   put(b.cxpre, P.cxpre.data(), vec_bytes(P.cxpre));
   put(b.cqpre, P.cqpre.data(), vec_bytes(P.cqpre));
+  put(b.fpre, P.fpre.data(), vec_bytes(P.fpre));
   put(b.mpre, P.mpre.data(), vec_bytes(P.mpre));
   put(b.ppre, P.ppre.data(), vec_bytes(P.ppre));
   put(b.sstart, P.sstart.data(), vec_bytes(P.sstart));
@@ -665,8 +666,7 @@ void enqueue_compress(const Plan& P, const BatchBufs& b, const ExecChoice& ex, c
   // Alg. 3: fixed point, crossed faces of the original field, lossless flags
   {
     TimeScope ts(FAM_EXTRACT, (uint64_t)P.Ntot, s);
-    launch_field_pass_b(b.D, n, b.rpre, P.rpre.back(), b.vpre, P.vpre.back(), b.range, b.cur, b.xcode, b.qcode,
-                        b.flags, s);
+    launch_fieldpass_b(b.D, n, b.rpre, P.rpre.back(), b.fpre, P.fpre.back(), b.range, b.cur, b.flags, s);
   }
   if (ex.schedule == CPT_SCHED_PERSISTENT) {
     launch_zero_u32(b.done, (size_t)n, s);

@@ -95,6 +95,11 @@ void launch_field_pass_b(FieldDesc* D, int n, const long long* rpre, long long r
                          long long vblocks, int4* range, int2* cur, uint8_t* edges, uint32_t* masks, uint8_t* flags,
                          hipStream_t s);
 constexpr long long RANGE_SPAN_FLOATS = 256 * 256;
+// the same with conversion, edges, faces and flags fused in one time-marching
+// kernel over 32x16 tiles (fpre: tiles per field)
+void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* fpre,
+                        long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s);
+constexpr int FIELDPASS_TW = 32, FIELDPASS_TH = 16;
 
 // launchers (k_entropy.hip); vpre: 256-vertex workgroups per field, hpre:
 // HIST_SPAN-vertex workgroups, cxpre / cqpre: bound-code / residual-code

@@ -85,6 +85,7 @@ struct ModesSmem {
   float h1[64], h2[64], lg[4];
   int SAMP[4][128];
   uint32_t hist[4][256];  // per class: 1024 codes, one byte each
+  int64_t T[129];         // T[h] = floor(h log2 h 2^16) for h <= 128
   int cls;
 };
 static_assert(QSYM == 4 * 256, "one histogram byte per residual code");
@@ -132,6 +133,7 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
   }
   for (int i = lane; i < 4 * 128; i += 64) (&SAMP[0][0])[i] = -1;
   for (int i = lane; i < 4 * 256; i += 64) (&S.hist[0][0])[i] = 0u;
+  for (int i = lane; i <= 128; i += 64) S.T[i] = tlog[i];
   wave_sync();
 
   // ---------------- block features (also the selector's input)
@@ -281,8 +283,8 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
     if (a1 > 0) f1 = ((atomicAdd(&S.hist[cls][a1 >> 2], 1u << s1) >> s1) & 0xFFu) == 0u;
     wave_sync();
     int64_t tsum = 0;
-    if (f0) tsum += tlog[(S.hist[cls][a0 >> 2] >> s0) & 0xFFu];
-    if (f1) tsum += tlog[(S.hist[cls][a1 >> 2] >> s1) & 0xFFu];
+    if (f0) tsum += S.T[(S.hist[cls][a0 >> 2] >> s0) & 0xFFu];
+    if (f1) tsum += S.T[(S.hist[cls][a1 >> 2] >> s1) & 0xFFu];
     int64_t nvalid = (a0 > 0) + (a1 > 0), nover = (a0 == 0) + (a1 == 0);
     auto add = [](int64_t a, int64_t b) { return a + b; };
     tsum = wave_reduce(tsum, add);
@@ -290,7 +292,7 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
     nover = wave_reduce(nover, add);
     if (lane == 0) {
       const int64_t n = nvalid, L = nover;
-      const int64_t h0 = n > 0 ? floor_div64(tlog[n] - tsum, n) : 0;
+      const int64_t h0 = n > 0 ? floor_div64(S.T[n] - tsum, n) : 0;
       const int64_t pen = (n + L) > 0 ? floor_div64((int64_t)16 * 65536 * L, n + L) : 0;
       const int64_t lgK = p.K == 4 ? 2 : 1;
       const int64_t meta = floor_div64(65536 * lgK, (int64_t)512 * p.bt);

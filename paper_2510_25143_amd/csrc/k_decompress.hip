@@ -40,35 +40,52 @@ __global__ __launch_bounds__(256) void k_dec_counts(const uint16_t* __restrict__
   rcnt[i] = r;
 }
 
-__global__ __launch_bounds__(256) void k_reconstruct(int2* __restrict__ cur, float* __restrict__ field,
-                                                     const uint16_t* __restrict__ xs, const uint16_t* __restrict__ qs,
-                                                     const uint32_t* __restrict__ qofs, const uint32_t* __restrict__ raw,
-                                                     const uint32_t* __restrict__ rofs,
-                                                     const uint8_t* __restrict__ modes, long long mode_base,
-                                                     FieldParams p, int t, uint32_t* __restrict__ err) {
+// One wave per block: each lane prepares four vertices (v = lane + 64 k),
+// lanes 0-31 then sweep the Lorenzo anti-diagonals, and each lane writes its
+// four vertices.  With one wave per block every block of a frame is
+// resident at once.
+__device__ __forceinline__ void rc_wave_sync() {
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__global__ __launch_bounds__(64) void k_reconstruct(int2* __restrict__ cur, float* __restrict__ field,
+                                                    const uint16_t* __restrict__ xs, const uint16_t* __restrict__ qs,
+                                                    const uint32_t* __restrict__ qofs, const uint32_t* __restrict__ raw,
+                                                    const uint32_t* __restrict__ rofs,
+                                                    const uint8_t* __restrict__ modes, long long mode_base,
+                                                    FieldParams p, int t, uint32_t* __restrict__ err) {
   __shared__ int C[2][TILE][TILE];     // reconstructed fixed-point values (u, v)
   __shared__ int P[2][TILE][TILE];     // previous frame, for the Lorenzo predictor
   __shared__ int DQ[2][TILE][TILE];    // q (2 xi~ + 1) of components still to predict
   __shared__ uint8_t KN[2][TILE][TILE];  // component already known (raw or semi-Lagrangian)
-  const int tid = threadIdx.x, lx = tid & 15, ly = tid >> 4;
+  const int lane = threadIdx.x;
   const int bx = blockIdx.x, by = blockIdx.y;
-  const int x = bx * TILE + lx, y = by * TILE + ly;
   const int H = p.H, W = p.W;
   const size_t HW = (size_t)H * W, N = HW * (size_t)p.T;
-  const bool valid = x < W && y < H;
-  const size_t gi = (size_t)y * W + x, gv = (size_t)t * HW + gi;
   int cls = 0;
   if (t >= 1) {
     if (p.predictor == 1) cls = 1;
     else if (mode_base >= 0) cls = modes[(size_t)mode_base + (size_t)by * p.tx + bx];
   }
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
-  const int2 pv2 = (valid && t > 0) ? cur[gv - HW] : make_int2(0, 0);
-  P[0][ly][lx] = pv2.x;
-  P[1][ly][lx] = pv2.y;
+  int vcode[4], vq[4];
+  uint32_t vr[4];
 
   // everything that does not depend on the block's own reconstruction
-  if (valid) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
+    const int x = bx * TILE + lx, y = by * TILE + ly;
+    const bool valid = x < W && y < H;
+    const size_t gv = (size_t)t * HW + (size_t)y * W + x;
+    const int2 pv2 = (valid && t > 0) ? cur[gv - HW] : make_int2(0, 0);
+    P[0][ly][lx] = pv2.x;
+    P[1][ly][lx] = pv2.y;
+    vcode[k] = XLOSSLESS;
+    vq[k] = 0;
+    vr[k] = 0;
+    if (!valid) continue;
     const int code = xs[gv];
     uint32_t r = rofs[gv];
     int q[2] = {0, 0}, pr[2] = {0, 0};
@@ -80,6 +97,9 @@ __global__ __launch_bounds__(256) void k_reconstruct(int2* __restrict__ cur, flo
       w = 2 * (int64_t)(p.eps >> code) + 1;
       if (cls != 0) sl_predict(cur + (size_t)(t - 1) * HW, H, W, x, y, SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pr[0], &pr[1]);
     }
+    vcode[k] = code;
+    vq[k] = q[0] | (q[1] << 16);
+    vr[k] = r;
     for (int c = 0; c < 2; c++) {
       if (code == XLOSSLESS || q[c] == 0) {
         uint32_t b = raw[r++];
@@ -103,16 +123,16 @@ __global__ __launch_bounds__(256) void k_reconstruct(int2* __restrict__ cur, flo
       }
     }
   }
-  __syncthreads();
+  rc_wave_sync();
 
-  // Lorenzo blocks: wave 0 sweeps the anti-diagonals, lanes 0-15 the rows of
-  // u and lanes 16-31 the rows of v.  A lane keeps its last value (the left
+  // Lorenzo blocks: lanes 0-15 sweep the rows of u and lanes 16-31 the rows
+  // of v along the anti-diagonals.  A lane keeps its last value (the left
   // neighbour of its next vertex); the row above arrives from the previous
-  // lane of the same 16-lane DPP row by a row shift.  All 64 lanes of the
-  // wave step together (DPP reads need active source lanes).
-  if (cls == 0 && tid < 64) {
-    const int c = (tid >> 4) & 1, row = tid & 15;
-    const bool mine = tid < 2 * TILE;
+  // lane of the same 16-lane DPP row by a row shift.  All 64 lanes step
+  // together (DPP reads need active source lanes).
+  if (cls == 0) {
+    const int c = (lane >> 4) & 1, row = lane & 15;
+    const bool mine = lane < 2 * TILE;
     const bool has_prev = t > 0;
     int last = 0, upl = 0;
     for (int d = 0; d < 2 * TILE - 1; d++) {
@@ -137,24 +157,27 @@ __global__ __launch_bounds__(256) void k_reconstruct(int2* __restrict__ cur, flo
       }
       upl = up;
     }
+    rc_wave_sync();
   }
-  __syncthreads();
-  if (valid) {
-    const int u = C[0][ly][lx], v = C[1][ly][lx];
-    cur[gv] = make_int2(u, v);
-    // known raw components are restored bit-exactly; the rest are exact
-    // multiples of 2^-k
-    const uint32_t r0 = rofs[gv];
-    const int code = xs[gv];
+  // known raw components are restored bit-exactly; the rest are exact
+  // multiples of 2^-k
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
+    const int x = bx * TILE + lx, y = by * TILE + ly;
+    if (!(x < W && y < H)) continue;
+    const size_t gv = (size_t)t * HW + (size_t)y * W + x;
+    const int u = C[0][ly][lx], vv = C[1][ly][lx];
+    cur[gv] = make_int2(u, vv);
+    const uint32_t r0 = vr[k];
     float fu, fv;
-    if (code == XLOSSLESS) {
+    if (vcode[k] == XLOSSLESS) {
       fu = __uint_as_float(raw[r0]);
       fv = __uint_as_float(raw[r0 + 1]);
     } else {
-      size_t o = 2 * (size_t)qofs[gv];
       uint32_t r = r0;
-      fu = qs[o] == 0 ? __uint_as_float(raw[r++]) : from_fixed(u, p.k);
-      fv = qs[o + 1] == 0 ? __uint_as_float(raw[r]) : from_fixed(v, p.k);
+      fu = (vq[k] & 0xFFFF) == 0 ? __uint_as_float(raw[r++]) : from_fixed(u, p.k);
+      fv = (vq[k] >> 16) == 0 ? __uint_as_float(raw[r]) : from_fixed(vv, p.k);
     }
     field[gv] = fu;
     field[N + gv] = fv;
@@ -175,7 +198,7 @@ void launch_reconstruct(int2* cur, float* field, const uint16_t* xs, const uint1
                         const uint32_t* raw, const uint32_t* rofs, const uint8_t* modes, long long mode_base,
                         const FieldParams& p, int t, uint32_t* err, hipStream_t s) {
   dim3 grid(p.tx, p.ty);
-  k_reconstruct<<<grid, 256, 0, s>>>(cur, field, xs, qs, qofs, raw, rofs, modes, mode_base, p, t, err);
+  k_reconstruct<<<grid, 64, 0, s>>>(cur, field, xs, qs, qofs, raw, rofs, modes, mode_base, p, t, err);
 }
 
 }  // namespace cpt

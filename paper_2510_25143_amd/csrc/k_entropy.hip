@@ -615,6 +615,11 @@ __global__ __launch_bounds__(256) void k_decode(const uint32_t* __restrict__ lut
   }
   const size_t lo = c * CHUNK;
   const size_t hi = live ? (lo + CHUNK < nsym_total ? lo + CHUNK : nsym_total) : lo;
+  // the chunk's words reach the 64-bit bit buffer through a queue of four
+  // words loaded ahead of use (only words inside the chunk are loaded)
+  uint32_t ahead[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) ahead[k] = (size_t)k < nw ? bs[w0 + k] : 0u;
   uint64_t buf = 0;
   int have = 0;
   size_t wi = 0;
@@ -628,7 +633,11 @@ __global__ __launch_bounds__(256) void k_decode(const uint32_t* __restrict__ lut
       uint32_t sym = 0;
       if (!bad && i < hi) {
         while (have <= 32) {
-          uint64_t nxt = wi < nw ? bs[w0 + wi] : 0;
+          const uint64_t nxt = ahead[0];
+          ahead[0] = ahead[1];
+          ahead[1] = ahead[2];
+          ahead[2] = ahead[3];
+          ahead[3] = wi + 4 < nw ? bs[w0 + wi + 4] : 0u;
           wi++;
           buf |= nxt << (32 - have);
           have += 32;

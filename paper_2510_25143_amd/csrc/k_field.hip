@@ -391,6 +391,183 @@ __global__ __launch_bounds__(256) void k_flags_b(const FieldDesc* __restrict__ D
   flags[d.voff + v.i] = lossless_flag(masks + d.voff, d.H, d.W, v.i, (size_t)d.H * d.W);
 }
 
+// ------------------------------------------------------ fused field pass
+// One workgroup per 32x16 tile of one field marches through the frames:
+// per frame it converts the tile (plus halo) to fixed point, computes the
+// SoS edge signs, the face masks and the lossless flags in shared memory,
+// and writes only the fixed-point values and the flags.  At step s the
+// edges of frame s+1 need frames s+1 and s+2, the masks of frame s need the
+// edges of s and s+1, the flags of frame s need the masks of s and s-1; two
+// frames of each are kept.  Halos: values [-1, 34) x [-1, 18), edges
+// [-1, 33) x [-1, 17), masks [-1, 32) x [-1, 16) relative to the tile.
+constexpr int FP_TW = 32, FP_TH = 16;
+constexpr int FP_CW = FP_TW + 3, FP_CH = FP_TH + 3;
+constexpr int FP_EW = FP_TW + 2, FP_EH = FP_TH + 2;
+constexpr int FP_MW = FP_TW + 1, FP_MH = FP_TH + 1;
+constexpr int FP_NC = FP_CW * FP_CH;  // 665 values per frame, 3 per thread
+static_assert(FP_NC <= 3 * 256, "three halo values per thread");
+
+struct FieldPassSmem {
+  int2 cur[2][FP_CH][FP_CW];
+  uint8_t edg[2][FP_EH][FP_EW];
+  uint32_t msk[2][FP_MH][FP_MW];
+};
+
+__device__ __forceinline__ uint32_t fp_edges(const int2 (*A)[FP_CW], const int2 (*B)[FP_CW], int cx, int cy, bool px,
+                                             bool py, bool pt) {
+  const int2 a = A[cy][cx];
+  uint32_t e = 0;
+  if (px) e |= (sos_sign(a.x, a.y, A[cy][cx + 1].x, A[cy][cx + 1].y) > 0) << 0;
+  if (py) e |= (sos_sign(a.x, a.y, A[cy + 1][cx].x, A[cy + 1][cx].y) > 0) << 1;
+  if (px && py) e |= (sos_sign(a.x, a.y, A[cy + 1][cx + 1].x, A[cy + 1][cx + 1].y) > 0) << 2;
+  if (pt) {
+    e |= (sos_sign(a.x, a.y, B[cy][cx].x, B[cy][cx].y) > 0) << 3;
+    if (px) e |= (sos_sign(a.x, a.y, B[cy][cx + 1].x, B[cy][cx + 1].y) > 0) << 4;
+    if (py) e |= (sos_sign(a.x, a.y, B[cy + 1][cx].x, B[cy + 1][cx].y) > 0) << 5;
+    if (px && py) e |= (sos_sign(a.x, a.y, B[cy + 1][cx + 1].x, B[cy + 1][cx + 1].y) > 0) << 6;
+  }
+  return e;
+}
+
+__device__ __forceinline__ uint32_t fp_mask(const uint8_t (*E0)[FP_EW], const uint8_t (*E1)[FP_EW], int ex, int ey,
+                                            bool px, bool py, bool pt) {
+  if (!(px || py)) return 0;
+  const uint32_t ea = E0[ey][ex];
+  const uint32_t eb = px ? E0[ey][ex + 1] : 0;
+  const uint32_t ec = py ? E0[ey + 1][ex] : 0;
+  const uint32_t ed = (px && py) ? E0[ey + 1][ex + 1] : 0;
+  const uint32_t ea1 = pt ? E1[ey][ex] : 0;
+  const uint32_t eb1 = (pt && px) ? E1[ey][ex + 1] : 0;
+  const uint32_t ec1 = (pt && py) ? E1[ey + 1][ex] : 0;
+  uint32_t m = 0;
+#define B(e, k) (((e) >> (k)) & 1u)
+  if (px && py) {
+    m |= face_bits(B(ea, 0), B(eb, 1), B(ea, 2), 0);
+    m |= face_bits(B(ea, 1), B(ec, 0), B(ea, 2), 1);
+    if (pt) {
+      m |= face_bits(B(ea, 0), B(eb, 5), B(ea, 6), 2);
+      m |= face_bits(B(ea, 4), B(eb1, 1), B(ea, 6), 3);
+      m |= face_bits(B(ea, 1), B(ec, 4), B(ea, 6), 4);
+      m |= face_bits(B(ea, 5), B(ec1, 0), B(ea, 6), 5);
+      m |= face_bits(B(ea, 2), B(ed, 3), B(ea, 6), 10);
+      m |= face_bits(B(ea, 3), B(ea1, 2), B(ea, 6), 11);
+    }
+  }
+  if (px && pt) {
+    m |= face_bits(B(ea, 0), B(eb, 3), B(ea, 4), 6);
+    m |= face_bits(B(ea, 3), B(ea1, 0), B(ea, 4), 7);
+  }
+  if (py && pt) {
+    m |= face_bits(B(ea, 1), B(ec, 3), B(ea, 5), 8);
+    m |= face_bits(B(ea, 3), B(ea1, 1), B(ea, 5), 9);
+  }
+#undef B
+  return m;
+}
+
+// fpre[f]: tiles of the fields before f
+__global__ __launch_bounds__(256) void k_fieldpass_b(const FieldDesc* __restrict__ D,
+                                                     const long long* __restrict__ fpre, int n,
+                                                     int2* __restrict__ cur_all, uint8_t* __restrict__ flags_all) {
+  __shared__ FieldPassSmem S;
+  const int f = find_field(fpre, n, blockIdx.x);
+  const FieldDesc& d = D[f];
+  if (d.status) return;
+  const int H = d.H, W = d.W, T = d.T, k = d.p.k;
+  const int ntx = (W + FP_TW - 1) / FP_TW;
+  const int tile = (int)((long long)blockIdx.x - fpre[f]);
+  const int x0 = (tile % ntx) * FP_TW, y0 = (tile / ntx) * FP_TH;
+  const size_t HW = (size_t)H * W, N = (size_t)d.N;
+  const float* fu = d.field;
+  const float* fv = d.field + N;
+  int2* cur = cur_all + d.voff;
+  uint8_t* flags = flags_all + d.voff;
+  const int tid = threadIdx.x;
+
+  // halo value j of frame t: fixed-point pair (0 outside the domain)
+  float ru[3], rv[3];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      const int j = tid + 256 * q;
+      const int cy = j / FP_CW, cx = j - cy * FP_CW;
+      const int x = x0 + cx - 1, y = y0 + cy - 1;
+      ru[q] = rv[q] = 0.f;
+      if (j < FP_NC && t < T && x >= 0 && x < W && y >= 0 && y < H) {
+        const size_t g = (size_t)t * HW + (size_t)y * W + x;
+        ru[q] = fu[g];
+        rv[q] = fv[g];
+      }
+    }
+  };
+  auto store = [&](int t) {
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      const int j = tid + 256 * q;
+      if (j >= FP_NC) continue;
+      const int cy = j / FP_CW, cx = j - cy * FP_CW;
+      const int x = x0 + cx - 1, y = y0 + cy - 1;
+      const bool in = t < T && x >= 0 && x < W && y >= 0 && y < H;
+      const int2 v = in ? make_int2(to_fixed(ru[q], k), to_fixed(rv[q], k)) : make_int2(0, 0);
+      S.cur[t & 1][cy][cx] = v;
+      if (in && cx >= 1 && cx <= FP_TW && cy >= 1 && cy <= FP_TH) cur[(size_t)t * HW + (size_t)y * W + x] = v;
+    }
+  };
+  auto edges_of = [&](int t) {  // edges of frame t (t + 1 < T uses frame t + 1)
+    for (int j = tid; j < FP_EW * FP_EH; j += 256) {
+      const int ey = j / FP_EW, ex = j - ey * FP_EW;
+      const int x = x0 + ex - 1, y = y0 + ey - 1;
+      uint32_t e = 0;
+      if (x >= 0 && x < W && y >= 0 && y < H)
+        e = fp_edges(S.cur[t & 1], S.cur[(t + 1) & 1], ex, ey, x + 1 < W, y + 1 < H, t + 1 < T);
+      S.edg[t & 1][ey][ex] = (uint8_t)e;
+    }
+  };
+
+  // prologue: frames 0 and 1, edges of frame 0
+  fetch(0);
+  store(0);
+  fetch(1);
+  store(1);
+  fetch(2);
+  __syncthreads();
+  edges_of(0);
+  __syncthreads();
+  for (int s = 0; s < T; s++) {
+    // values of frame s + 2 (loaded during the previous step), then start
+    // loading frame s + 3
+    if (s + 2 < T) store(s + 2);
+    fetch(s + 3);
+    __syncthreads();
+    if (s + 1 < T) edges_of(s + 1);
+    __syncthreads();
+    // masks of frame s
+    for (int j = tid; j < FP_MW * FP_MH; j += 256) {
+      const int my = j / FP_MW, mx = j - my * FP_MW;
+      const int x = x0 + mx - 1, y = y0 + my - 1;
+      uint32_t m = 0;
+      if (x >= 0 && x < W && y >= 0 && y < H)
+        m = fp_mask(S.edg[s & 1], S.edg[(s + 1) & 1], mx, my, x + 1 < W, y + 1 < H, s + 1 < T);
+      S.msk[s & 1][my][mx] = m;
+    }
+    __syncthreads();
+    // lossless flags of frame s: any crossed face through the vertex
+    for (int j = tid; j < FP_TW * FP_TH; j += 256) {
+      const int iy = j / FP_TW, ix = j - iy * FP_TW;
+      const int x = x0 + ix, y = y0 + iy;
+      if (x >= W || y >= H) continue;
+      uint32_t any = 0;
+#pragma unroll
+      for (int o = 0; o < 8; o++) {
+        const int ox = o & 1, oy = (o >> 1) & 1, ot = (o >> 2) & 1;
+        if (x - ox < 0 || y - oy < 0 || s - ot < 0) continue;
+        any |= S.msk[(s - ot) & 1][iy + 1 - oy][ix + 1 - ox] & c_inc.m[o];
+      }
+      flags[(size_t)s * HW + (size_t)y * W + x] = any ? 1 : 0;
+    }
+  }
+}
+
 // ------------------------------------------------------------- compaction
 __global__ __launch_bounds__(256) void k_count_faces(const uint32_t* __restrict__ masks, size_t N,
                                                      uint32_t* __restrict__ cnt) {
@@ -621,6 +798,14 @@ void launch_field_pass_b(FieldDesc* D, int n, const long long* rpre, long long r
   k_edges_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, cur, edges);
   k_faces_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, edges, masks);
   k_flags_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, masks, flags);
+}
+
+void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* fpre,
+                        long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s) {
+  k_range_init_b<<<nblk(n, 64), 64, 0, s>>>(range, n);
+  if (rblocks > 0) k_range_b<<<(unsigned)rblocks, 256, 0, s>>>(D, rpre, n, range);
+  k_params_b<<<nblk(n, 64), 64, 0, s>>>(D, range, n);
+  if (fblocks > 0) k_fieldpass_b<<<(unsigned)fblocks, 256, 0, s>>>(D, fpre, n, cur, flags);
 }
 void launch_compare(const uint32_t* ma, const uint32_t* mb, const float* a, const float* b, size_t N,
                     unsigned long long* fc, double* part, hipStream_t s) {
