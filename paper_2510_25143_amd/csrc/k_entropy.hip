@@ -187,33 +187,116 @@ __device__ void build_code(const uint32_t* __restrict__ hist, int nsym, HuffTabl
 // 32-bit arithmetic: a field's own offsets are differences from the value
 // at its first element, which are exact modulo 2^32.
 
-// per-field histograms of the bound codes and residual codes;
-// hpre[f]: workgroups of HIST_SPAN vertices of the fields before f
+// Per-field histograms of the bound codes and residual codes, and per
+// vertex the raw-value count (both components of a lossless vertex, else
+// the components whose residual code is 0) and the non-lossless indicator.
+// hpre[f]: workgroups of HIST_SPAN vertices of the fields before f; each
+// thread takes 16 consecutive vertices and merges runs of equal codes in
+// registers before adding them to the shared histograms.
 constexpr int HIST_SPAN = (int)HIST_SPAN_VERTICES;
+static_assert(HIST_SPAN == 256 * 16, "16 consecutive vertices per thread");
+
+struct RunAdd {
+  uint32_t v = 0xFFFFFFFFu, c = 0;
+  __device__ __forceinline__ void add(uint32_t* h, uint32_t x) {
+    if (x == v) {
+      c++;
+    } else {
+      if (c) atomicAdd(&h[v], c);
+      v = x;
+      c = 1;
+    }
+  }
+  __device__ __forceinline__ void flush(uint32_t* h) {
+    if (c) atomicAdd(&h[v], c);
+  }
+};
+
 __global__ __launch_bounds__(256) void k_hist_b(const FieldDesc* __restrict__ D, const long long* __restrict__ hpre,
                                                 int n, const uint8_t* __restrict__ xcode,
                                                 const uint32_t* __restrict__ qcode, uint32_t* __restrict__ xhist,
-                                                uint32_t* __restrict__ qhist) {
+                                                uint32_t* __restrict__ qhist, uint32_t* __restrict__ rcnt,
+                                                uint32_t* __restrict__ nonll) {
   __shared__ uint32_t hx[32];
   __shared__ uint32_t hq[QSYM];
   const int f = find_field(hpre, n, blockIdx.x);
   const FieldDesc& d = D[f];
-  if (d.status) return;
+  const size_t lo = (size_t)((long long)blockIdx.x - hpre[f]) * HIST_SPAN;
+  const size_t N = (size_t)d.N, hi = lo + HIST_SPAN < N ? lo + HIST_SPAN : N;
+  const size_t base = (size_t)d.voff;
+  if (d.status) {
+    for (size_t i = lo + threadIdx.x; i < hi; i += 256) {
+      rcnt[base + i] = 0;
+      nonll[base + i] = 0;
+    }
+    return;
+  }
   for (int i = threadIdx.x; i < QSYM; i += 256) hq[i] = 0;
   if (threadIdx.x < 32) hx[threadIdx.x] = 0;
   __syncthreads();
-  const size_t lo = (size_t)((long long)blockIdx.x - hpre[f]) * HIST_SPAN;
-  const size_t N = (size_t)d.N, hi = lo + HIST_SPAN < N ? lo + HIST_SPAN : N;
-  const uint8_t* xc = xcode + d.voff;
-  const uint32_t* qc = qcode + d.voff;
-  for (size_t i = lo + threadIdx.x; i < hi; i += 256) {
-    uint32_t c = xc[i];
-    atomicAdd(&hx[c], 1u);
-    if (c != XLOSSLESS) {
-      uint32_t q = qc[i];
-      atomicAdd(&hq[q & 0xFFFFu], 1u);
-      atomicAdd(&hq[q >> 16], 1u);
+  const size_t i0 = lo + (size_t)threadIdx.x * 16;
+  RunAdd rx, ru, rv;
+  uint8_t xc[16];
+  uint32_t qc[16];
+  const bool full = i0 + 16 <= hi && ((base + i0) & 15) == 0;
+  if (full) {
+    const uint4 xa = *(const uint4*)(xcode + base + i0);
+    const uint32_t xw[4] = {xa.x, xa.y, xa.z, xa.w};
+#pragma unroll
+    for (int j = 0; j < 16; j++) xc[j] = (uint8_t)(xw[j >> 2] >> (8 * (j & 3)));
+    const uint4* q4 = (const uint4*)(qcode + base + i0);
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const uint4 w = q4[j];
+      qc[4 * j] = w.x;
+      qc[4 * j + 1] = w.y;
+      qc[4 * j + 2] = w.z;
+      qc[4 * j + 3] = w.w;
     }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      const bool in = i0 + j < hi;
+      xc[j] = in ? xcode[base + i0 + j] : (uint8_t)0xFF;
+      qc[j] = in ? qcode[base + i0 + j] : 0u;
+    }
+  }
+  uint32_t rc[16], nl[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const uint32_t c = xc[j];
+    rc[j] = 0;
+    nl[j] = 0;
+    if (c == 0xFF) continue;  // past the end
+    rx.add(hx, c);
+    if (c == XLOSSLESS) {
+      rc[j] = 2;
+    } else {
+      const uint32_t u = qc[j] & 0xFFFFu, v = qc[j] >> 16;
+      ru.add(hq, u);
+      rv.add(hq, v);
+      rc[j] = (u == 0) + (v == 0);
+      nl[j] = 1;
+    }
+  }
+  rx.flush(hx);
+  ru.flush(hq);
+  rv.flush(hq);
+  if (full) {
+    uint4* r4 = (uint4*)(rcnt + base + i0);
+    uint4* n4 = (uint4*)(nonll + base + i0);
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      r4[j] = make_uint4(rc[4 * j], rc[4 * j + 1], rc[4 * j + 2], rc[4 * j + 3]);
+      n4[j] = make_uint4(nl[4 * j], nl[4 * j + 1], nl[4 * j + 2], nl[4 * j + 3]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      if (i0 + j < hi) {
+        rcnt[base + i0 + j] = rc[j];
+        nonll[base + i0 + j] = nl[j];
+      }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < QSYM; i += 256)
@@ -244,31 +327,6 @@ __device__ __forceinline__ VPos vpos(const FieldDesc* __restrict__ D, const long
   v.i = (size_t)((long long)blockIdx.x - vpre[v.f]) * 256 + threadIdx.x;
   v.valid = v.i < (size_t)D[v.f].N;
   return v;
-}
-
-// raw values per vertex (both components of a lossless vertex, else the
-// components whose residual code is 0) and the non-lossless indicator
-__global__ __launch_bounds__(256) void k_raw_count_b(const FieldDesc* __restrict__ D,
-                                                     const long long* __restrict__ vpre, int n,
-                                                     const uint8_t* __restrict__ xcode,
-                                                     const uint32_t* __restrict__ qcode, uint32_t* __restrict__ cnt,
-                                                     uint32_t* __restrict__ nonll) {
-  const VPos v = vpos(D, vpre, n);
-  if (!v.valid) return;
-  const FieldDesc& d = D[v.f];
-  const size_t g = d.voff + v.i;
-  uint32_t c = 0, nl = 0;
-  if (!d.status) {
-    if (xcode[g] == XLOSSLESS) {
-      c = 2;
-    } else {
-      uint32_t q = qcode[g];
-      c = ((q & 0xFFFFu) == 0) + ((q >> 16) == 0);
-      nl = 1;
-    }
-  }
-  cnt[g] = c;
-  nonll[g] = nl;
 }
 
 __global__ __launch_bounds__(256) void k_gather_q_b(const FieldDesc* __restrict__ D,
@@ -689,10 +747,10 @@ void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& 
                     long long hblocks, const long long* vpre, long long vblocks, long long Ntot, hipStream_t s) {
   launch_zero_u32(E.xhist, 32 * (size_t)n, s);
   launch_zero_u32(E.qhist, QSYM * (size_t)n, s);
-  if (hblocks > 0) k_hist_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.xhist, E.qhist);
+  if (hblocks > 0)
+    k_hist_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.xhist, E.qhist, E.rcnt, E.nonll);
   k_codebooks_b<<<2 * n, CB_THREADS, 0, s>>>(D, E.xhist, E.qhist, E.xt, E.qt, E.xcb, E.qcb, E.used);
   if (vblocks <= 0) return;
-  k_raw_count_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.rcnt, E.nonll);
   uint32_t* tot = E.part;  // two scratch words ahead of the scan partials
   launch_scan(E.nonll, (size_t)Ntot, E.qofs, E.part + 4, tot, s);
   launch_scan(E.rcnt, (size_t)Ntot, E.rofs, E.part + 4, tot + 1, s);
