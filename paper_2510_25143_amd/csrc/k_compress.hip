@@ -265,8 +265,12 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
     const int sx = 2 * (pt & 7), sy = 2 * (pt >> 3);
     if (x0 + sx < W && y0 + sy < H) {
       const int2 Xs = C[sy][sx];
+      auto F = [&](int xx, int yy) {
+        const int tx_ = xx - x0, ty_ = yy - y0;
+        return (tx_ >= 0 && tx_ < TILE && ty_ >= 0 && ty_ < TILE) ? P[ty_][tx_] : pf[(size_t)yy * W + xx];
+      };
       int pu, pv, ru, rv;
-      sl_predict(pf, H, W, x0 + sx, y0 + sy, slc, class_dmax(p.K, cls), &pu, &pv);
+      sl_predict_f(F, H, W, x0 + sx, y0 + sy, slc, class_dmax(p.K, cls), &pu, &pv);
       SAMP[cls][2 * pt] = quantize(Xs.x, pu, eps, &ru);
       SAMP[cls][2 * pt + 1] = quantize(Xs.y, pv, eps, &rv);
     }
@@ -502,8 +506,17 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
         }
       }
       if (cls != 0) {
+        // frame t-1 from the staged halo where it covers the sample (all of
+        // it but the two unstaged corners), else from global memory
+        const int2* prev = cur + (size_t)(t - 1) * HW;
+        auto F = [&](int xx, int yy) {
+          const int hx = xx - x0 + 1, hy = yy - y0 + 1;
+          const bool staged = hx >= 0 && hx < HALO && hy >= 0 && hy < HALO && !(hx == HALO - 1 && hy == 0) &&
+                              !(hx == 0 && hy == HALO - 1);
+          return staged ? V[0][hy][hx] : prev[(size_t)yy * W + xx];
+        };
         int pu, pv;
-        sl_predict(cur + (size_t)(t - 1) * HW, H, W, x, y, SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pu, &pv);
+        sl_predict_f(F, H, W, x, y, SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pu, &pv);
         SLP[ly][lx] = make_int2(pu, pv);
       }
     }

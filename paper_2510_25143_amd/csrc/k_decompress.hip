@@ -71,17 +71,33 @@ __global__ __launch_bounds__(64) void k_reconstruct(int2* __restrict__ cur, floa
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
   int vcode[4], vq[4];
   uint32_t vr[4];
-
-  // everything that does not depend on the block's own reconstruction
+  const int x0 = bx * TILE, y0 = by * TILE;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
-    const int x = bx * TILE + lx, y = by * TILE + ly;
+    const int x = x0 + lx, y = y0 + ly;
     const bool valid = x < W && y < H;
     const size_t gv = (size_t)t * HW + (size_t)y * W + x;
     const int2 pv2 = (valid && t > 0) ? cur[gv - HW] : make_int2(0, 0);
     P[0][ly][lx] = pv2.x;
     P[1][ly][lx] = pv2.y;
+  }
+  rc_wave_sync();
+  // frame t-1 from the staged block where it covers the sample
+  const int2* prevf = t > 0 ? cur + (size_t)(t - 1) * HW : cur;
+  auto F = [&](int xx, int yy) {
+    const int tx_ = xx - x0, ty_ = yy - y0;
+    return (tx_ >= 0 && tx_ < TILE && ty_ >= 0 && ty_ < TILE) ? make_int2(P[0][ty_][tx_], P[1][ty_][tx_])
+                                                               : prevf[(size_t)yy * W + xx];
+  };
+
+  // everything that does not depend on the block's own reconstruction
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool valid = x < W && y < H;
+    const size_t gv = (size_t)t * HW + (size_t)y * W + x;
     vcode[k] = XLOSSLESS;
     vq[k] = 0;
     vr[k] = 0;
@@ -95,7 +111,7 @@ __global__ __launch_bounds__(64) void k_reconstruct(int2* __restrict__ cur, floa
       q[0] = qs[o];
       q[1] = qs[o + 1];
       w = 2 * (int64_t)(p.eps >> code) + 1;
-      if (cls != 0) sl_predict(cur + (size_t)(t - 1) * HW, H, W, x, y, SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pr[0], &pr[1]);
+      if (cls != 0) sl_predict_f(F, H, W, x, y, SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pr[0], &pr[1]);
     }
     vcode[k] = code;
     vq[k] = q[0] | (q[1] << 16);

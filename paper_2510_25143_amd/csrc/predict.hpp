@@ -24,14 +24,16 @@ __device__ __forceinline__ int64_t clamp64(int64_t a, int64_t lo, int64_t hi) {
   return a < lo ? lo : (a > hi ? hi : a);
 }
 
-// bilinear sample of both components of frame F ([H][W] int2) at Q16 (px, py)
-__device__ __forceinline__ void bilinear2(const int2* __restrict__ F, int H, int W, int64_t px, int64_t py,
-                                          int64_t* ou, int64_t* ov) {
+// Bilinear sample of both components of the previous frame at Q16 (px, py)
+// inside the domain; F(x, y) returns its int2 value at a grid point.
+template <typename Fetch>
+__device__ __forceinline__ void bilinear2f(const Fetch& F, int H, int W, int64_t px, int64_t py, int64_t* ou,
+                                           int64_t* ov) {
   int x0 = (int)(px >> 16), y0 = (int)(py >> 16);
   int64_t fx = px & 65535, fy = py & 65535;
   int x1 = x0 + 1 < W ? x0 + 1 : x0, y1 = y0 + 1 < H ? y0 + 1 : y0;
-  int2 a = F[(size_t)y0 * W + x0], b = F[(size_t)y0 * W + x1];
-  int2 c = F[(size_t)y1 * W + x0], d = F[(size_t)y1 * W + x1];
+  int2 a = F(x0, y0), b = F(x1, y0);
+  int2 c = F(x0, y1), d = F(x1, y1);
   int64_t gx = 65536 - fx, gy = 65536 - fy;
   int64_t r0u = (int64_t)a.x * gx + (int64_t)b.x * fx, r1u = (int64_t)c.x * gx + (int64_t)d.x * fx;
   int64_t r0v = (int64_t)a.y * gx + (int64_t)b.y * fx, r1v = (int64_t)c.y * gx + (int64_t)d.y * fx;
@@ -39,11 +41,12 @@ __device__ __forceinline__ void bilinear2(const int2* __restrict__ F, int H, int
   *ov = (r0v * gy + r1v * fy + (1LL << 31)) >> 32;
 }
 
-__device__ __forceinline__ void sl_predict(const int2* __restrict__ prev, int H, int W, int x, int y,
-                                           const SLConst& k, int dmax, int* pu, int* pv) {
+template <typename Fetch>
+__device__ __forceinline__ void sl_predict_f(const Fetch& F, int H, int W, int x, int y, const SLConst& k, int dmax,
+                                             int* pu, int* pv) {
   const int64_t XM = (int64_t)(W - 1) << 16, YM = (int64_t)(H - 1) << 16;
   const int64_t px = (int64_t)x << 16, py = (int64_t)y << 16;
-  int2 g = prev[(size_t)y * W + x];
+  int2 g = F(x, y);
   int64_t dx = sl_disp(g.x, k.cx, k.sx), dy = sl_disp(g.y, k.cy, k.sy);
   int64_t ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
   int64_t dinf = ax > ay ? ax : ay;
@@ -52,7 +55,7 @@ __device__ __forceinline__ void sl_predict(const int2* __restrict__ prev, int H,
   if (dinf <= lim) {
     int64_t hx = clamp64(px - (dx >> 1), 0, XM), hy = clamp64(py - (dy >> 1), 0, YM);
     int64_t uh, vh;
-    bilinear2(prev, H, W, hx, hy, &uh, &vh);
+    bilinear2f(F, H, W, hx, hy, &uh, &vh);
     qx = clamp64(px - sl_disp(uh, k.cx, k.sx), 0, XM);
     qy = clamp64(py - sl_disp(vh, k.cy, k.sy), 0, YM);
   } else {
@@ -62,7 +65,7 @@ __device__ __forceinline__ void sl_predict(const int2* __restrict__ prev, int H,
     qy = py;
     for (int s = 0; s < n; s++) {
       int64_t us, vs;
-      bilinear2(prev, H, W, qx, qy, &us, &vs);
+      bilinear2f(F, H, W, qx, qy, &us, &vs);
       int64_t nx = qx - floor_div64(sl_disp(us, k.cx, k.sx), n);
       int64_t ny = qy - floor_div64(sl_disp(vs, k.cy, k.sy), n);
       qx = clamp64(nx, 0, XM);
@@ -70,9 +73,16 @@ __device__ __forceinline__ void sl_predict(const int2* __restrict__ prev, int H,
     }
   }
   int64_t ru, rv;
-  bilinear2(prev, H, W, qx, qy, &ru, &rv);
+  bilinear2f(F, H, W, qx, qy, &ru, &rv);
   *pu = (int)ru;
   *pv = (int)rv;
+}
+
+// the same reading every sample from the previous frame in global memory
+__device__ __forceinline__ void sl_predict(const int2* __restrict__ prev, int H, int W, int x, int y,
+                                           const SLConst& k, int dmax, int* pu, int* pv) {
+  auto F = [&](int xx, int yy) { return prev[(size_t)yy * W + xx]; };
+  sl_predict_f(F, H, W, x, y, k, dmax, pu, pv);
 }
 
 // Class table: 0 = 3-D Lorenzo; otherwise semi-Lagrangian with d_max cells.
