@@ -433,7 +433,7 @@ __device__ __forceinline__ void face_update(int& xi, int2 me, int2 n0, int2 n1, 
 struct PhaseSmem {
   int2 V[3][HALO][HALO];  // frames t-1, t, t+1 around the block
   int XS[TILE][TILE];     // bound from the faces fixed for the whole sweep; -1 = lossless
-  int2 SLP[TILE][TILE];   // semi-Lagrangian predictions
+  int2 SLP[TILE][TILE];   // semi-Lagrangian predictions, or the frame t-1 part of the Lorenzo prediction
   uint32_t OQ[TILE][TILE];  // outputs, written once after the sweep
   int OX[TILE][TILE];
   uint8_t OC[TILE][TILE];
@@ -505,7 +505,14 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
           face_update(xi, me, na, nb, det2(me, na), det2(me, nb));
         }
       }
-      if (cls != 0) {
+      if (cls == 0) {
+        // the frame t-1 part of the 3-D Lorenzo prediction (fixed during the sweep)
+        const int2 pc = V[0][ly + 1][lx + 1];
+        const int2 pl = lx > 0 ? V[0][ly + 1][lx] : make_int2(0, 0);
+        const int2 pu = ly > 0 ? V[0][ly][lx + 1] : make_int2(0, 0);
+        const int2 plu = (lx > 0 && ly > 0) ? V[0][ly][lx] : make_int2(0, 0);
+        SLP[ly][lx] = make_int2(pc.x - pl.x - pu.x + plu.x, pc.y - pl.y - pu.y + plu.y);
+      } else {
         // frame t-1 from the staged halo where it covers the sample (all of
         // it but the two unstaged corners), else from global memory
         const int2* prev = cur + (size_t)(t - 1) * HW;
@@ -532,6 +539,14 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
   const int axo = fa >= 0 ? c_nbr_dx(fa) : 0, ayo = fa >= 0 ? c_nbr_dy(fa) : 0, ato = fa >= 0 ? c_nbr_dt(fa) : 0;
   const int bxo = fb >= 0 ? c_nbr_dx(fb) : 0, byo = fb >= 0 ? c_nbr_dy(fb) : 0, bto = fb >= 0 ? c_nbr_dt(fb) : 0;
   const int comp = j & 1;
+  // this lane's face exists for x in [xlo, xhi) (both neighbours inside the
+  // domain); y and t do not change during the sweep
+  const bool face_yt = fa >= 0 && y + ayo >= 0 && y + ayo < H && t + ato >= 0 && t + ato < T && y + byo >= 0 &&
+                       y + byo < H && t + bto >= 0 && t + bto < T;
+  const int xlo = max(-min(axo, bxo), 0), xhi = W - max(max(axo, bxo), 0);
+  const int2* Vme = &V[1][g + 1][1];
+  const int2* Va = &V[1 + ato][g + 1 + ayo][1 + axo];
+  const int2* Vb = &V[1 + bto][g + 1 + byo][1 + bxo];
   for (int d = 0; d < 2 * TILE - 1; d++) {
     const int lx = d - g, x = x0 + lx;
     const bool active = lx >= 0 && lx < TILE && x < W && y < H;
@@ -539,27 +554,18 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
     if (active) {
       xs = XS[g][lx];
       e = xs >= 0 ? xs : eps;
-      if (xs >= 0 && fa >= 0) {
-        bool ina = x + axo >= 0 && x + axo < W && y + ayo >= 0 && y + ayo < H && t + ato >= 0 && t + ato < T;
-        bool inb = x + bxo >= 0 && x + bxo < W && y + byo >= 0 && y + byo < H && t + bto >= 0 && t + bto < T;
-        if (ina && inb) {
-          int2 me = V[1][g + 1][lx + 1];
-          int2 pa = V[1 + ato][g + 1 + ayo][lx + 1 + axo];
-          int2 pb = V[1 + bto][g + 1 + byo][lx + 1 + bxo];
-          face_update(e, me, pa, pb, det2(me, pa), det2(me, pb));
-        }
+      if (xs >= 0 && face_yt && x >= xlo && x < xhi) {
+        const int2 me = Vme[lx], pa = Va[lx], pb = Vb[lx];
+        face_update(e, me, pa, pb, det2(me, pa), det2(me, pb));
       }
       if (j < 2 && cls == 0) {
-        // Lorenzo neighbours of this step's vertex (final after the last barrier)
+        // Lorenzo neighbours of this step's vertex (final after the last
+        // barrier) plus the frame t-1 part computed before the sweep
         auto cmp = [&](int2 v) { return comp ? v.y : v.x; };
         const int l = lx > 0 ? cmp(V[1][g + 1][lx]) : 0;
         const int u = g > 0 ? cmp(V[1][g][lx + 1]) : 0;
         const int lu = (lx > 0 && g > 0) ? cmp(V[1][g][lx]) : 0;
-        const int pc = cmp(V[0][g + 1][lx + 1]);
-        const int pl = lx > 0 ? cmp(V[0][g + 1][lx]) : 0;
-        const int pu_ = g > 0 ? cmp(V[0][g][lx + 1]) : 0;
-        const int plu = (lx > 0 && g > 0) ? cmp(V[0][g][lx]) : 0;
-        lorenzo = l + u - lu + pc - pl - pu_ + plu;
+        lorenzo = l + u - lu + cmp(SLP[g][lx]);
       }
     }
     e = row16_min(e);
