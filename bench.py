@@ -25,6 +25,9 @@ WORKLOADS = {
     "turbulence": dict(cfg=2, name="turbulence-like 2048x2048x32 float32 (u,v), k^-5/3 self-advected "
                                    "+ 64 translating vortices"),
     "vortex": dict(cfg=0, name="4 translating Lamb-Oseen vortices 64x64x8 float32 (u,v) + N(0,1e-3)"),
+    "selector": dict(cfg=4, name="turbulence-like 1024x1024x128 float32 (u,v), k^-5/3 self-advected + 64 "
+                                   "translating vortices; learned predictor selector (bf16 10-64-64-4 MLP) "
+                                   "against the exhaustive 4-class trial, 16x16x4 predictor blocks"),
     "batch": dict(cfg=3, name="batch of 256 independent vortex fields (4-32 Lamb-Oseen vortices + N(0,1e-3)), "
                               "side log-uniform 64..1024, T uniform 8..64, float32 (u,v), compressed in one "
                               "batched pipeline"),
@@ -79,9 +82,9 @@ def phase_roofline(fam, kname, workload=None):
 
 
 def bench_batch(args, cpt, torch, synthfields):
-    """The uneven batch: 256 fields compressed by one batched call, then
-    decompressed field by field; also one cpt_compress call per field for
-    comparison."""
+    """The uneven batch: 256 fields compressed by one batched call and
+    decompressed by one batched call; also one cpt_compress and one
+    cpt_decompress call per field for comparison."""
     eb = 1e-2
     shapes = synthfields.batch_shapes(256, seed=3000)
     log("generating %d fields on cuda:0" % len(shapes))
@@ -109,8 +112,7 @@ def bench_batch(args, cpt, torch, synthfields):
     log("warmup x%d" % max(args.warmup, 1))
     for _ in range(max(args.warmup, 1)):
         streams = comp()
-        for s, d in zip(streams, decs):
-            cpt.decompress(s, out=d)
+        cpt.decompress_batch(streams, outs=decs)
     torch.cuda.synchronize()
     clen = sum(s.numel() for s in streams)
     worst = 0.0
@@ -133,8 +135,7 @@ def bench_batch(args, cpt, torch, synthfields):
         ev[i][0].record()
         streams = comp()
         ev[i][1].record()
-        for s, d in zip(streams, decs):
-            cpt.decompress(s, out=d)
+        cpt.decompress_batch(streams, outs=decs)
         ev[i][2].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -147,14 +148,17 @@ def bench_batch(args, cpt, torch, synthfields):
     kernels = {name: {"avg_launch_us": round(m / c * 1e3, 3), "sampled_launches": c}
                for name, (m, c, _) in fam.items() if c}
 
-    log("one cpt_compress call per field")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    log("one cpt_compress and one cpt_decompress call per field")
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     e0.record()
-    for f, o in zip(fields, outs):
-        cpt.compress(f, eb, out=o)
+    single = [cpt.compress(f, eb, out=o) for f, o in zip(fields, outs)]
     e1.record()
+    for st_, d in zip(single, decs):
+        cpt.decompress(st_, out=d)
+    e2.record()
     torch.cuda.synchronize()
     t_single = e0.elapsed_time(e1)
+    t_single_d = e1.elapsed_time(e2)
     value = args.steps * raw / elapsed / 1e9
     result = {
         "metric": METRIC, "value": round(value, 4), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -166,9 +170,95 @@ def bench_batch(args, cpt, torch, synthfields):
                    "max_err_over_eb": round(worst, 6),
                    "compress_ms": round(tc, 3), "decompress_ms": round(td, 3),
                    "compress_GBps": round(raw / tc / 1e6, 3), "decompress_GBps": round(raw / td / 1e6, 3),
-                   "per_field_compress_ms": round(t_single, 3),
-                   "batch_speedup_over_per_field": round(t_single / tc, 3), "kernels": kernels},
+                   "per_field_compress_ms": round(t_single, 3), "per_field_decompress_ms": round(t_single_d, 3),
+                   "batch_speedup_over_per_field": round(t_single / tc, 3),
+                   "batch_decompress_speedup_over_per_field": round(t_single_d / td, 3), "kernels": kernels},
         "roofline": roofline,
+    }
+    print(json.dumps(result), flush=True)
+
+
+def bench_selector(args, cpt, torch, synthfields):
+    """The learned selector against the exhaustive trial on the 1024x1024x128
+    turbulence field: train on exhaustive-trial labels of two other flows,
+    then time compress + decompress with each choice."""
+    eb, bt = 1e-3, 4
+    log("training data: exhaustive 4-class trial on wind 360x720x16 and turbulence 512x512x16")
+    X, Y = [], []
+    for cfg, shape in ((1, (360, 720, 16)), (2, (512, 512, 16))):
+        g, mg = synthfields.workload(cfg, device="cuda", shape=shape)
+        _, dbg = cpt.compress_debug(g.contiguous(), eb, predictor=3, mode_bt=bt, dt_dx=mg["dt_dx"], dt_dy=mg["dt_dx"])
+        X.append(dbg["feats"])
+        Y.append(dbg["modes"].to(torch.int32))
+        del g
+    X, Y = torch.cat(X), torch.cat(Y)
+    t0 = time.perf_counter()
+    w0 = cpt.selector_init(11)
+    _, l0 = cpt.selector_grad(w0, X, Y)
+    _, wb, loss = cpt.selector_train(X, Y, w=w0, epochs=30, batch=512, lr=2e-3, seed=5)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log("trained on %d blocks in %.2f s: loss %.4f -> %.4f" % (Y.numel(), train_s, l0, loss))
+
+    log("generating the 1024x1024x128 evaluation field on cuda:0")
+    f, meta = synthfields.workload(4, device="cuda")
+    f = f.contiguous()
+    _, T, H, W = f.shape
+    raw = f.numel() * 4
+    dt = meta["dt_dx"]
+    out = torch.empty(cpt.compress_bound(H, W, T), dtype=torch.uint8, device="cuda")
+    dec = torch.empty_like(f)
+    k, eb_abs, _ = cpt.field_params(f, eb)
+    res = {}
+    for name, kw in (("exhaustive", dict(predictor=3)), ("learned", dict(predictor=4, selector_w=wb))):
+        opts = dict(mode_bt=bt, dt_dx=dt, dt_dy=dt, schedule="launch", outs=[out], **kw)
+        for _ in range(max(args.warmup, 1)):
+            (st,), _ = cpt.compress_batch([f], eb, **opts)
+            cpt.decompress(st, out=dec)
+        torch.cuda.synchronize()
+        v = cpt.verify(f, dec, k)
+        if not (v["fc_t"] == 0 and v["fc_s"] == 0 and v["max_err"] <= eb_abs):
+            raise SystemExit("guarantee violated (%s): %s" % (name, v))
+        cpt.timing_enable(True, period=TIMING_PERIOD)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record()
+            (st,), _ = cpt.compress_batch([f], eb, **opts)
+            ev[i][1].record()
+            cpt.decompress(st, out=dec)
+            ev[i][2].record()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t1
+        fam = {nm: cpt.timing_read(nm) for nm in cpt.TIMING_FAMILIES}
+        cpt.timing_enable(False)
+        res[name] = {"GBps": round(args.steps * raw / elapsed / 1e9, 4), "CR": round(raw / st.numel(), 4),
+                     "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+                     "compress_ms": round(sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps, 3),
+                     "decompress_ms": round(sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps, 3),
+                     "choice_us_per_launch": round(fam["modes"][0] / max(fam["modes"][1], 1) * 1e3, 3),
+                     "max_err": v["max_err"], "fc_t": v["fc_t"], "fc_s": v["fc_s"],
+                     "roofline": phase_roofline(fam, "k_phase_b<false>")}
+        log("%s: %s" % (name, res[name]))
+    _, de = cpt.compress_debug(f, eb, predictor=3, mode_bt=bt, dt_dx=dt, dt_dy=dt)
+    _, dl = cpt.compress_debug(f, eb, predictor=4, mode_bt=bt, dt_dx=dt, dt_dy=dt, selector_w=wb)
+    agree = float((de["modes"] == dl["modes"]).float().mean())
+    L, E = res["learned"], res["exhaustive"]
+    result = {
+        "metric": METRIC, "value": L["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": L["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i32+f64(exact); selector bf16 weights, fp32 accumulation",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["selector"]["name"], "shape_T_H_W": [T, H, W], "raw_bytes": raw,
+                   "eb_rel": eb, "eb_abs": eb_abs, "mode_bt": bt, "schedule": "launch",
+                   "training": {"blocks": int(Y.numel()), "loss_before": round(l0, 4), "loss_after": round(loss, 4),
+                                "seconds": round(train_s, 3), "epochs": 30, "batch": 512, "lr": 2e-3},
+                   "agreement_with_exhaustive": round(agree, 4), "learned": L, "exhaustive": E,
+                   "CR_change_pct": round(100 * (L["CR"] / E["CR"] - 1), 3),
+                   "GBps_change_pct": round(100 * (L["GBps"] / E["GBps"] - 1), 3)},
+        "roofline": L["roofline"],
     }
     print(json.dumps(result), flush=True)
 
@@ -203,6 +293,8 @@ def main():
     cpt.lib()
     if args.workload == "batch":
         return bench_batch(args, cpt, torch, synthfields)
+    if args.workload == "selector":
+        return bench_selector(args, cpt, torch, synthfields)
     wl = WORKLOADS[args.workload]
     log("generating workload %s on cuda:0" % args.workload)
     f, meta = synthfields.workload(wl["cfg"], device="cuda")

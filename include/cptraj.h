@@ -181,6 +181,20 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
                               const cpt_options* opt, uint8_t* const* outs, const size_t* caps, int reps,
                               cpt_exec_options* best, double* ms, void* stream);
 
+/*
+ * Decompress n streams (1 <= n <= 65536) in one device pipeline, as
+ * cpt_decompress does for each: streams (host array of device pointers,
+ * 4-byte aligned) of lens[i] bytes (host) into fields (host array of device
+ * pointers, each (2,T,H,W) float32 as its header says).  Streams may differ
+ * in size, predictor and block height.  status (host, n, may be NULL)
+ * receives each stream's outcome; a corrupt stream (CPT_ECORRUPT) leaves the
+ * others unaffected and its own output undefined.  Returns CPT_OK when every
+ * stream succeeded, else the first failure.  Synchronises `stream` twice
+ * (after reading the headers, and at the end).
+ */
+cpt_status cpt_decompress_batch(int n, const uint8_t* const* streams, const size_t* lens, float* const* fields,
+                                int32_t* status, void* stream);
+
 /* Parse a stream header (host bytes, at least 256). */
 cpt_status cpt_stream_info(const uint8_t* bytes, size_t len, cpt_info* info);
 

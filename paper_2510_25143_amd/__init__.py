@@ -62,7 +62,7 @@ class VerifyResult(ctypes.Structure):
 EXPORTS = ["cpt_compress_bound", "cpt_compress", "cpt_compress_debug", "cpt_stream_info",
            "cpt_decompress", "cpt_extract_trajectories", "cpt_verify", "cpt_field_params",
            "cpt_selector_grad", "cpt_selector_train", "cpt_timing_enable", "cpt_timing_read",
-           "cpt_compress_batch", "cpt_autotune_batch", "cpt_last_error"]
+           "cpt_compress_batch", "cpt_autotune_batch", "cpt_decompress_batch", "cpt_last_error"]
 
 _lib = None
 
@@ -91,6 +91,7 @@ def lib():
         "cpt_timing_read": [i32, P, P, P],
         "cpt_compress_batch": [i32, P, P, dbl, P, P, P, P, P, P, P],
         "cpt_autotune_batch": [i32, P, P, dbl, P, P, P, i32, P, P, P],
+        "cpt_decompress_batch": [i32, P, P, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -231,6 +232,28 @@ def autotune_batch(fields, eb, reps=2, predictor=PRED_MIX2, mode_bt=1, eb_mode=0
                                     _stream()))
     name = {v: k for k, v in SCHEDULES.items()}[best.schedule]
     return (name, bool(best.use_graph)), list(ms)
+
+
+def decompress_batch(streams, outs=None, raise_on_error=True):
+    """Decompress a list of streams (uint8 CUDA tensors) in one device
+    pipeline.  Returns (fields, status)."""
+    n = len(streams)
+    if n == 0:
+        raise ValueError("empty batch")
+    ss = [s.contiguous() for s in streams]
+    if outs is None:
+        outs = []
+        for st in ss:
+            info = stream_info(st)
+            outs.append(torch.empty((2, info["T"], info["H"], info["W"]), dtype=torch.float32, device=st.device))
+    sp = (ctypes.c_void_p * n)(*[st.data_ptr() for st in ss])
+    lens = (ctypes.c_size_t * n)(*[st.numel() for st in ss])
+    fp = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    status = (ctypes.c_int32 * n)()
+    r = lib().cpt_decompress_batch(n, sp, lens, fp, status, _stream())
+    if r != OK and (raise_on_error or r != ECORRUPT):
+        _check(r)
+    return outs, [status[i] for i in range(n)]
 
 
 def stream_info(stream_bytes):

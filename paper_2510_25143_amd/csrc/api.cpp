@@ -271,18 +271,6 @@ cpt_status field_range(const float* f, size_t n, Bufs& b, Arena& A, hipStream_t 
 }
 
 // ------------------------------------------------------- small kernels
-__global__ void k_unpack_modes(const uint32_t* in, size_t nblk, int mb, int K, uint8_t* modes, uint32_t* err) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nblk) return;
-  uint32_t v = 0;
-  for (int k = 0; k < mb; k++) {
-    size_t bit = i * mb + k;
-    v |= ((in[bit / 32] >> (bit % 32)) & 1u) << k;
-  }
-  if ((int)v >= K) atomicOr(err, 256u);
-  modes[i] = (uint8_t)v;
-}
-
 unsigned nb256(size_t n) { return (unsigned)((n + 255) / 256); }
 
 int mode_bits(int K) { return K == 4 ? 2 : (K == 2 ? 1 : 0); }
@@ -933,101 +921,285 @@ cpt_status parse_header(const uint8_t* h, size_t len, Parsed* P) {
 }
 
 // ---------------------------------------------------------- decompress
-cpt_status decompress_impl(const uint8_t* bytes, size_t len, float* field, hipStream_t s) {
-  if (!bytes || !field) return fail(CPT_EINVAL, "null pointer");
-  if ((uintptr_t)bytes & 3) return fail(CPT_EINVAL, "stream must be 4-byte aligned");
-  if (len < HDR_BYTES) return fail(CPT_ECORRUPT, "stream shorter than its header");
+__global__ void k_gather_headers(const uint8_t* const* __restrict__ ptrs, int n, uint32_t* __restrict__ out) {
+  const int f = blockIdx.x, i = threadIdx.x;
+  if (f < n && i < (int)(HDR_BYTES / 4)) out[(size_t)f * (HDR_BYTES / 4) + i] = ((const uint32_t*)ptrs[f])[i];
+}
+
+// Host plan of a batched decompression, from the parsed headers of the
+// streams that pass the header checks.
+struct DPlan {
+  int n = 0, maxT = 0;
+  std::vector<DecDesc> D;
+  std::vector<int> ord;
+  std::vector<long long> mpre, cxpre, cqpre, dxpre, dqpre, vpre, rpre, mtab;
+  std::vector<int> m_at;
+  long long Ntot = 0, CX = 0, CQ = 0, QS = 0, NB = 0;
+};
+
+struct DBufs {
+  DecDesc* D;
+  int* ord;
+  long long *mpre, *cxpre, *cqpre, *dxpre, *dqpre, *vpre, *rpre, *mtab;
+  size_t tables_bytes;
+  DecodeBufs B;
+};
+
+cpt_status carve_dec(Arena& A, const DPlan& P, DBufs& b) {
+  A.used = 0;
+  const int n = P.n;
+  const size_t N = (size_t)P.Ntot, CX = (size_t)P.CX, CQ = (size_t)P.CQ;
+  struct Item {
+    void** p;
+    size_t bytes;
+  };
+  std::vector<Item> tables = {
+      {(void**)&b.D, sizeof(DecDesc) * n},  {(void**)&b.ord, 4 * (size_t)n},
+      {(void**)&b.mpre, vec_bytes(P.mpre)}, {(void**)&b.cxpre, vec_bytes(P.cxpre)},
+      {(void**)&b.cqpre, vec_bytes(P.cqpre)}, {(void**)&b.dxpre, vec_bytes(P.dxpre)},
+      {(void**)&b.dqpre, vec_bytes(P.dqpre)}, {(void**)&b.vpre, vec_bytes(P.vpre)},
+      {(void**)&b.rpre, vec_bytes(P.rpre)}, {(void**)&b.mtab, vec_bytes(P.mtab)},
+  };
+  std::vector<Item> rest = {
+      {(void**)&b.B.lut, 8 * (size_t)n * (1u << MAXLEN)}, {(void**)&b.B.xw, 4 * CX + 16},
+      {(void**)&b.B.xwofs, 4 * CX + 16},                  {(void**)&b.B.qw, 4 * CQ + 16},
+      {(void**)&b.B.qwofs, 4 * CQ + 16},                  {(void**)&b.B.xs, 2 * N},
+      {(void**)&b.B.qs, 2 * (size_t)P.QS + 16},           {(void**)&b.B.nonll, 4 * N},
+      {(void**)&b.B.qofs, 4 * N},                         {(void**)&b.B.rcnt, 4 * N},
+      {(void**)&b.B.rofs, 4 * N},                         {(void**)&b.B.modes, (size_t)P.NB + 16},
+      {(void**)&b.B.cur, 8 * N},
+      {(void**)&b.B.part, 4 * (scan_partials_size(std::max(N, std::max(CX, CQ))) + 16)},
+  };
+  std::vector<size_t> offs;
+  size_t t0 = 0;
+  for (size_t i = 0; i < tables.size(); i++) {
+    size_t o = A.off(tables[i].bytes);
+    if (i == 0) t0 = o;
+    offs.push_back(o);
+  }
+  b.tables_bytes = A.used - t0;
+  for (auto& it : rest) offs.push_back(A.off(it.bytes));
+  cpt_status st = reserve(A);
+  if (st) return st;
+  size_t k = 0;
+  for (auto& it : tables) *it.p = A.base + offs[k++];
+  for (auto& it : rest) *it.p = A.base + offs[k++];
+  return CPT_OK;
+}
+
+// Decompress n streams; status (host, n) receives each stream's outcome.
+cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const size_t* lens, float* const* fields,
+                                 int32_t* status, hipStream_t s) {
+  if (n < 1 || n > 65536) return fail(CPT_EINVAL, "batch size must be in 1..65536");
+  if (!streams || !lens || !fields) return fail(CPT_EINVAL, "null pointer");
+  std::vector<int32_t> st_f(n, CPT_OK);
+  std::vector<std::string> why(n);
+  for (int i = 0; i < n; i++) {
+    if (!streams[i] || !fields[i]) return fail(CPT_EINVAL, "stream " + std::to_string(i) + ": null pointer");
+    if ((uintptr_t)streams[i] & 3) return fail(CPT_EINVAL, "stream must be 4-byte aligned");
+    if (lens[i] < HDR_BYTES) {
+      st_f[i] = CPT_ECORRUPT;
+      why[i] = "stream shorter than its header";
+    }
+  }
   cpt_status st;
   Arena* Ap = arena_for_device(&st);
   if (!Ap) return st;
   Arena& A = *Ap;
   std::lock_guard<std::mutex> lk(A.mu);
-  HIPCHK(hipMemcpyAsync(A.host, bytes, HDR_BYTES, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  Parsed P;
-  st = parse_header((const uint8_t*)A.host, len, &P);
-  if (st) return st;
-  const cpt_info& I = P.info;
-  const int H = I.H, W = I.W, T = I.T;
-  const size_t N = (size_t)H * W * T;
-  const int tx = (W + TILE - 1) / TILE, ty = (H + TILE - 1) / TILE;
-  const int bt = I.mode_bt, K = I.K;
-  const int G = (T + bt - 1) / bt;
-  const size_t ndec = K > 1 ? (size_t)decided_before(G, bt, T) : 0;
-  const size_t nblk = ndec * (size_t)tx * ty;
-  const int mb = mode_bits(K);
-  const size_t nq = I.n_q, n_raw = I.n_raw;
-  const size_t nchx = (N + CHUNK - 1) / CHUNK, nchq = (nq + CHUNK - 1) / CHUNK;
-  if (P.sec[0] != 4 * ((nblk * mb + 31) / 32)) return fail(CPT_ECORRUPT, "mode section size");
-  if (nq > 2 * N || n_raw > 2 * N || (nq & 1)) return fail(CPT_ECORRUPT, "symbol counts");
-  if (P.sec[7] != 4 * n_raw) return fail(CPT_ECORRUPT, "raw section size");
-  if (P.sec[2] != 4 * nchx || P.sec[5] != 4 * nchq) return fail(CPT_ECORRUPT, "chunk table size");
-  if (P.sec[1] < 4 || P.sec[4] < 4) return fail(CPT_ECORRUPT, "codebook size");
-  Bufs b;
-  st = carve(A, N, nblk, b);
-  if (st) return st;
-  size_t off[8], o = HDR_BYTES;
-  for (int i = 0; i < 8; i++) {
-    off[i] = o;
-    o += P.sec[i];
+  // ---- headers: one gather, one copy (streams too short for a header read
+  // the header of one that is not; their status is already set)
+  int safe = -1;
+  for (int i = 0; i < n && safe < 0; i++)
+    if (!st_f[i]) safe = i;
+  if (safe >= 0) {
+    A.used = 0;
+    const size_t po = A.off(8 * (size_t)n), ho = A.off(HDR_BYTES * (size_t)n);
+    st = reserve(A);
+    if (st) return st;
+    st = reserve_stage(A, HDR_BYTES * (size_t)n + 8 * (size_t)n + 256);
+    if (st) return st;
+    std::vector<const uint8_t*> ptrs(n);
+    for (int i = 0; i < n; i++) ptrs[i] = st_f[i] ? streams[safe] : streams[i];
+    std::memcpy(A.stage, ptrs.data(), 8 * (size_t)n);
+    HIPCHK(hipMemcpyAsync(A.base + po, A.stage, 8 * (size_t)n, hipMemcpyHostToDevice, s));
+    k_gather_headers<<<n, 64, 0, s>>>((const uint8_t* const*)(A.base + po), n, (uint32_t*)(A.base + ho));
+    HIPCHK(hipMemcpyAsync(A.stage, A.base + ho, HDR_BYTES * (size_t)n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
   }
-  const uint32_t* w = (const uint32_t*)bytes;
-  auto sec32 = [&](int i) { return w + off[i] / 4; };
-  launch_zero_u32(b.err, 4, s);
-  if (nblk) k_unpack_modes<<<nb256(nblk), 256, 0, s>>>(sec32(0), nblk, mb, K, b.modes, b.err);
-  launch_build_lut(sec32(1), P.sec[1] / 4, XSYM, b.xlut, b.err, s);
-  launch_build_lut(sec32(4), P.sec[4] / 4, QSYM, b.qlut, b.err, s);
-  launch_words_from_bits(sec32(2), nchx, b.xwords, s);
-  launch_scan(b.xwords, nchx, b.xwofs, b.part, b.tot + 0, s);
-  {
-    TimeScope ts(FAM_DECODE, N, s);
-    launch_decode(b.xlut, sec32(2), b.xwofs, sec32(3), P.sec[3] / 4, N, XSYM, b.xs, b.err, s);
+  std::vector<uint8_t> hdr((const uint8_t*)A.stage, (const uint8_t*)A.stage + HDR_BYTES * (size_t)n);
+  // ---- plan
+  DPlan P;
+  std::vector<int> live;
+  for (int i = 0; i < n; i++) {
+    if (st_f[i]) continue;
+    Parsed Q;
+    cpt_status ps = parse_header(hdr.data() + HDR_BYTES * (size_t)i, lens[i], &Q);
+    if (ps) {
+      st_f[i] = ps;
+      why[i] = g_err;
+      continue;
+    }
+    const cpt_info& I = Q.info;
+    const int H = I.H, W = I.W, T = I.T, bt = I.mode_bt, K = I.K;
+    const long long N = (long long)H * W * T;
+    const int tx = (W + TILE - 1) / TILE, ty = (H + TILE - 1) / TILE;
+    const int G = (T + bt - 1) / bt;
+    const long long ndec = K > 1 ? decided_before(G, bt, T) : 0;
+    const long long nblk = ndec * tx * ty;
+    const int mb = mode_bits(K);
+    const long long nq = (long long)I.n_q, nraw = (long long)I.n_raw;
+    const long long nchx = (N + CHUNK - 1) / CHUNK, nchq = (nq + CHUNK - 1) / CHUNK;
+    std::string bad;
+    if ((long long)Q.sec[0] != 4 * ((nblk * mb + 31) / 32)) bad = "mode section size";
+    else if (nq > 2 * N || nraw > 2 * N || (nq & 1)) bad = "symbol counts";
+    else if ((long long)Q.sec[7] != 4 * nraw) bad = "raw section size";
+    else if ((long long)Q.sec[2] != 4 * nchx || (long long)Q.sec[5] != 4 * nchq) bad = "chunk table size";
+    else if (Q.sec[1] < 4 || Q.sec[4] < 4) bad = "codebook size";
+    if (!bad.empty()) {
+      st_f[i] = CPT_ECORRUPT;
+      why[i] = bad;
+      continue;
+    }
+    DecDesc d{};
+    d.p.H = H;
+    d.p.W = W;
+    d.p.T = T;
+    d.p.k = I.k;
+    d.p.eps = (int)I.eps;
+    d.p.tx = tx;
+    d.p.ty = ty;
+    d.p.predictor = I.predictor;
+    d.p.K = K;
+    d.p.bt = bt;
+    d.p.cx = Q.cx;
+    d.p.sx = Q.sx;
+    d.p.cy = Q.cy;
+    d.p.sy = Q.sy;
+    d.N = N;
+    d.nq = nq;
+    d.nraw = nraw;
+    d.nchx = nchx;
+    d.nchq = nchq;
+    d.nblk = nblk;
+    d.mb = mb;
+    size_t o = HDR_BYTES;
+    for (int k = 0; k < 8; k++) {
+      d.sec[k] = (const uint32_t*)(streams[i] + o);
+      d.secw[k] = (long long)(Q.sec[k] / 4);
+      o += Q.sec[k];
+    }
+    d.out = fields[i];
+    d.voff = P.Ntot;
+    d.cxb = P.CX;
+    d.cqb = P.CQ;
+    d.qsb = P.QS;
+    d.mbase = P.NB;
+    d.mtb = (long long)P.mtab.size();
+    for (int t = 0; t < T; t++) {
+      long long mo = -1;
+      if (K > 1 && t >= 1) {
+        const int g = t / bt;
+        if (group_decided(g, bt, T)) mo = (long long)decided_before(g, bt, T) * tx * ty;
+      }
+      P.mtab.push_back(mo);
+    }
+    P.Ntot += N;
+    P.CX += nchx;
+    P.CQ += nchq;
+    P.QS += nq;
+    P.NB += nblk;
+    P.maxT = std::max(P.maxT, T);
+    P.D.push_back(d);
+    live.push_back(i);
   }
-  launch_dec_nonll(b.xs, N, b.nonll, s);
-  launch_scan(b.nonll, N, b.qofs, b.part, b.tot + 1, s);
-  launch_words_from_bits(sec32(5), nchq, b.qwords, s);
-  launch_scan(b.qwords, nchq, b.qwofs, b.part, b.tot + 2, s);
-  {
-    TimeScope ts(FAM_DECODE, nq, s);
-    launch_decode(b.qlut, sec32(5), b.qwofs, sec32(6), P.sec[6] / 4, nq, QSYM, b.qs, b.err, s);
+  const int m = (int)P.D.size();
+  P.n = m;
+  if (m > 0) {
+    for (auto* v : {&P.mpre, &P.cxpre, &P.cqpre, &P.dxpre, &P.dqpre, &P.vpre, &P.rpre}) v->assign(m + 1, 0);
+    for (int j = 0; j < m; j++) {
+      const DecDesc& d = P.D[j];
+      P.mpre[j + 1] = P.mpre[j] + (d.nblk + 255) / 256;
+      P.cxpre[j + 1] = P.cxpre[j] + d.nchx;
+      P.cqpre[j + 1] = P.cqpre[j] + d.nchq;
+      P.dxpre[j + 1] = P.dxpre[j] + (d.nchx + 255) / 256;
+      P.dqpre[j + 1] = P.dqpre[j] + (d.nchq + 255) / 256;
+      P.vpre[j + 1] = P.vpre[j] + (d.N + 255) / 256;
+    }
+    P.ord.resize(m);
+    for (int j = 0; j < m; j++) P.ord[j] = j;
+    std::stable_sort(P.ord.begin(), P.ord.end(), [&](int a, int b) { return P.D[a].p.T > P.D[b].p.T; });
+    for (int j = 0; j < m; j++) {
+      const DecDesc& d = P.D[P.ord[j]];
+      P.rpre[j + 1] = P.rpre[j] + (long long)d.p.tx * d.p.ty;
+    }
+    P.m_at.assign(P.maxT, 0);
+    int mm = m;
+    for (int t = 0; t < P.maxT; t++) {
+      while (mm > 0 && P.D[P.ord[mm - 1]].p.T <= t) mm--;
+      P.m_at[t] = mm;
+    }
+    for (auto v : {P.mpre.back(), P.dxpre.back(), P.dqpre.back(), P.vpre.back(), P.rpre.back()})
+      if (v >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
+    DBufs b;
+    st = carve_dec(A, P, b);
+    if (st) return st;
+    const size_t rb_off = (b.tables_bytes + 255) & ~(size_t)255;
+    st = reserve_stage(A, rb_off + sizeof(DecDesc) * m + 64);
+    if (st) return st;
+    {
+      const char* base = (const char*)b.D;
+      auto put = [&](const void* dev, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(A.stage + ((const char*)dev - base), src, bytes);
+      };
+      put(b.D, P.D.data(), sizeof(DecDesc) * m);
+      put(b.ord, P.ord.data(), 4 * (size_t)m);
+      put(b.mpre, P.mpre.data(), vec_bytes(P.mpre));
+      put(b.cxpre, P.cxpre.data(), vec_bytes(P.cxpre));
+      put(b.cqpre, P.cqpre.data(), vec_bytes(P.cqpre));
+      put(b.dxpre, P.dxpre.data(), vec_bytes(P.dxpre));
+      put(b.dqpre, P.dqpre.data(), vec_bytes(P.dqpre));
+      put(b.vpre, P.vpre.data(), vec_bytes(P.vpre));
+      put(b.rpre, P.rpre.data(), vec_bytes(P.rpre));
+      put(b.mtab, P.mtab.data(), vec_bytes(P.mtab));
+    }
+    HIPCHK(hipMemcpyAsync(b.D, A.stage, b.tables_bytes, hipMemcpyHostToDevice, s));
+    launch_decode_front_b(b.D, m, b.B, b.mpre, P.mpre.back(), b.cxpre, P.CX, b.cqpre, P.CQ, s);
+    {
+      TimeScope ts(FAM_DECODE, (uint64_t)(P.Ntot + P.QS), s);
+      launch_decode_b(b.D, m, b.B, b.dxpre, P.dxpre.back(), b.dqpre, P.dqpre.back(), b.vpre, P.vpre.back(), P.Ntot,
+                      P.CX, P.CQ, s);
+    }
+    for (int t = 0; t < P.maxT; t++) {
+      const int mt = P.m_at[t];
+      uint64_t units = 0;
+      for (int j = 0; j < mt; j++) units += (uint64_t)P.D[P.ord[j]].p.H * P.D[P.ord[j]].p.W;
+      TimeScope ts(FAM_RECON, units, s);
+      launch_reconstruct_b(b.D, b.ord, b.rpre, mt, P.rpre[mt], t, b.mtab, b.B, s);
+    }
+    char* rb = A.stage + rb_off;
+    HIPCHK(hipMemcpyAsync(rb, b.D, sizeof(DecDesc) * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    harvest_timing();
+    const DecDesc* Dh = (const DecDesc*)rb;
+    for (int j = 0; j < m; j++) {
+      const int i = live[j];
+      if (Dh[j].status || Dh[j].err) {
+        st_f[i] = CPT_ECORRUPT;
+        why[i] = "stream failed a device check (code " + std::to_string(Dh[j].err) + ")";
+      }
+    }
   }
-  launch_dec_counts(b.xs, b.qs, b.qofs, N, nq, (int)I.eps, b.rcnt, b.err, s);
-  launch_scan(b.rcnt, N, b.rofs, b.part, b.tot + 3, s);
-  HIPCHK(hipMemcpyAsync(A.host, b.tot, 16, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(A.host + 2, b.err, 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const uint32_t* h32 = (const uint32_t*)A.host;
-  if (h32[4]) return fail(CPT_ECORRUPT, "stream failed a device check (code " + std::to_string(h32[4]) + ")");
-  if (h32[0] != P.sec[3] / 4 || h32[2] != P.sec[6] / 4) return fail(CPT_ECORRUPT, "bitstream sizes");
-  if (2 * (size_t)h32[1] != nq || h32[3] != n_raw) return fail(CPT_ECORRUPT, "symbol counts do not match");
-  FieldParams p;
-  p.H = H;
-  p.W = W;
-  p.T = T;
-  p.k = I.k;
-  p.eps = (int)I.eps;
-  p.tx = tx;
-  p.ty = ty;
-  p.predictor = I.predictor;
-  p.K = K;
-  p.bt = bt;
-  p.cx = P.cx;
-  p.sx = P.sx;
-  p.cy = P.cy;
-  p.sy = P.sy;
-  for (int t = 0; t < T; t++) {
-    int g = t / bt;
-    bool dec = K > 1 && group_decided(g, bt, T);
-    long long mbase = (dec && t >= 1) ? (long long)decided_before(g, bt, T) * tx * ty : -1;
-    TimeScope ts(FAM_RECON, (uint64_t)H * W, s);
-    launch_reconstruct(b.cur, field, b.xs, b.qs, b.qofs, sec32(7), b.rofs, b.modes, mbase, p, t, b.err, s);
+  cpt_status first = CPT_OK;
+  for (int i = 0; i < n; i++) {
+    if (status) status[i] = st_f[i];
+    if (st_f[i] && first == CPT_OK) {
+      first = (cpt_status)st_f[i];
+      g_err = n > 1 ? "stream " + std::to_string(i) + ": " + why[i] : why[i];
+    }
   }
-  HIPCHK(hipMemcpyAsync(A.host, b.err, 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(s));
-  harvest_timing();
-  if (h32[0]) return fail(CPT_ECORRUPT, "reconstruction failed a check (code " + std::to_string(h32[0]) + ")");
-  return CPT_OK;
+  return first;
 }
 
 }  // namespace
@@ -1299,7 +1471,17 @@ cpt_status cpt_stream_info(const uint8_t* bytes, size_t len, cpt_info* info) {
 
 cpt_status cpt_decompress(const uint8_t* bytes, size_t len, float* field, void* stream) {
   try {
-    return decompress_impl(bytes, len, field, (hipStream_t)stream);
+    if (!bytes || !field) return fail(CPT_EINVAL, "null pointer");
+    return decompress_batch_impl(1, &bytes, &len, &field, nullptr, (hipStream_t)stream);
+  } catch (...) {
+    return fail(CPT_EHIP, "unexpected exception");
+  }
+}
+
+cpt_status cpt_decompress_batch(int n, const uint8_t* const* streams, const size_t* lens, float* const* fields,
+                                int32_t* status, void* stream) {
+  try {
+    return decompress_batch_impl(n, streams, lens, fields, status, (hipStream_t)stream);
   } catch (...) {
     return fail(CPT_EHIP, "unexpected exception");
   }

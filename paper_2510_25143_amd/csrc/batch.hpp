@@ -121,6 +121,51 @@ void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBuf
                        long long cxtot, const long long* cqpre, long long cqtot, const long long* vpre,
                        long long vblocks, hipStream_t s);
 
+// ------------------------------------------------------- batched decoding
+// Per-stream descriptor of a batched decompression: header values and
+// section pointers (host), scratch offsets, and the device's verdict.
+struct DecDesc {
+  FieldParams p;            // dimensions and predictor parameters from the header
+  long long N;              // vertices
+  long long voff;           // first vertex in the concatenated per-vertex arrays
+  long long nq, nraw;       // residual symbols and raw values (header)
+  long long nchx, nchq;     // chunks of both code streams
+  long long cxb, cqb;       // first chunk in the concatenated chunk arrays
+  long long qsb;            // first residual symbol in the concatenated symbol array
+  long long mbase, nblk;    // predictor classes: first and count
+  long long mtb;            // first entry of the stream in the per-frame class-offset table
+  int mb;                   // bits per predictor class
+  const uint32_t* sec[8];   // the stream's sections (device)
+  long long secw[8];        // their lengths in words
+  float* out;               // decompressed field (2, T, H, W)
+  uint32_t err;             // device error bits
+  int status;               // 0 ok, else a cpt_status
+};
+
+struct DecodeBufs {
+  uint32_t* lut;            // two 4096-entry tables per stream
+  uint32_t *xw, *xwofs, *qw, *qwofs;  // chunk words and their prefix sums
+  uint16_t *xs, *qs;        // decoded symbols
+  uint32_t *nonll, *qofs, *rcnt, *rofs;
+  uint8_t* modes;
+  int2* cur;
+  uint32_t* part;
+};
+
+// k_entropy.hip: headers and tables (before decoding), decoding, offsets
+void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long long* mpre, long long mblocks,
+                           const long long* cxpre, long long cxtot, const long long* cqpre, long long cqtot,
+                           hipStream_t s);
+void launch_decode_b(DecDesc* D, int n, const DecodeBufs& B, const long long* dxpre, long long dxblocks,
+                     const long long* dqpre, long long dqblocks, const long long* vpre, long long vblocks,
+                     long long Ntot, long long CX, long long CQ, hipStream_t s);
+// k_decompress.hip: reconstruction of frame t of the first m streams of the
+// launch order (pre: blocks per stream)
+// mtab[mtb + t]: offset of frame t's predictor classes in the stream's
+// class array, or -1 when frame t has none
+void launch_reconstruct_b(DecDesc* D, const int* ord, const long long* pre, int m, long long nblocks, int t,
+                          const long long* mtab, const DecodeBufs& B, hipStream_t s);
+
 // launchers (k_compress.hip)
 void launch_modes_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int gidx,
                     hipStream_t s);

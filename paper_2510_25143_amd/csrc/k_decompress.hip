@@ -6,67 +6,52 @@
 // vertex is lossless or the component was unpredictable.  Predictions only
 // read the block's own frame (Lorenzo) or the previous frame (semi-
 // Lagrangian), so every block of a frame is reconstructed independently.
+#include "batch.hpp"
 #include "cpt_device.hpp"
 #include "launch.hpp"
 #include "predict.hpp"
 
 namespace cpt {
 
-__global__ __launch_bounds__(256) void k_dec_nonll(const uint16_t* __restrict__ xs, size_t N,
-                                                   uint32_t* __restrict__ nonll) {
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < N) nonll[i] = xs[i] != XLOSSLESS ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(256) void k_dec_counts(const uint16_t* __restrict__ xs, const uint16_t* __restrict__ qs,
-                                                    const uint32_t* __restrict__ qofs, size_t N, size_t nq, int eps,
-                                                    uint32_t* __restrict__ rcnt, uint32_t* __restrict__ err) {
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  uint32_t c = xs[i];
-  uint32_t r = 0;
-  if (c > XLOSSLESS) {
-    atomicOr(err, 16u);
-  } else if (c == XLOSSLESS) {
-    r = 2;
-  } else {
-    size_t o = 2 * (size_t)qofs[i];
-    if ((eps >> c) < 1 || o + 2 > nq) {
-      atomicOr(err, 32u);
-    } else {
-      r = (qs[o] == 0) + (qs[o + 1] == 0);
-    }
-  }
-  rcnt[i] = r;
-}
-
 // One wave per block: each lane prepares four vertices (v = lane + 64 k),
 // lanes 0-31 then sweep the Lorenzo anti-diagonals, and each lane writes its
 // four vertices.  With one wave per block every block of a frame is
-// resident at once.
+// resident at once.  Streams that failed a check are skipped.
 __device__ __forceinline__ void rc_wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-__global__ __launch_bounds__(64) void k_reconstruct(int2* __restrict__ cur, float* __restrict__ field,
-                                                    const uint16_t* __restrict__ xs, const uint16_t* __restrict__ qs,
-                                                    const uint32_t* __restrict__ qofs, const uint32_t* __restrict__ raw,
-                                                    const uint32_t* __restrict__ rofs,
-                                                    const uint8_t* __restrict__ modes, long long mode_base,
-                                                    FieldParams p, int t, uint32_t* __restrict__ err) {
+__global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, const int* __restrict__ ord,
+                                                      const long long* __restrict__ pre, int m, int t,
+                                                      const long long* __restrict__ mtab, DecodeBufs B) {
   __shared__ int C[2][TILE][TILE];     // reconstructed fixed-point values (u, v)
   __shared__ int P[2][TILE][TILE];     // previous frame, for the Lorenzo predictor
   __shared__ int DQ[2][TILE][TILE];    // q (2 xi~ + 1) of components still to predict
   __shared__ uint8_t KN[2][TILE][TILE];  // component already known (raw or semi-Lagrangian)
+  const int j = find_field(pre, m, blockIdx.x);
+  DecDesc& d = D[ord[j]];
+  if (d.status) return;
+  const FieldParams p = d.p;
   const int lane = threadIdx.x;
-  const int bx = blockIdx.x, by = blockIdx.y;
+  const long long li = (long long)blockIdx.x - pre[j];
+  const int by = (int)(li / p.tx), bx = (int)(li - (long long)by * p.tx);
   const int H = p.H, W = p.W;
   const size_t HW = (size_t)H * W, N = HW * (size_t)p.T;
+  int2* cur = B.cur + d.voff;
+  float* field = d.out;
+  const uint16_t* xs = B.xs + d.voff;
+  const uint16_t* qs = B.qs + d.qsb;
+  const uint32_t* qofs = B.qofs + d.voff;
+  const uint32_t* rofs = B.rofs + d.voff;
+  const uint32_t qbase = qofs[0], rbase = rofs[0];
+  const uint32_t* raw = d.sec[7];
+  uint32_t* err = &d.err;
+  const long long mode_base = mtab[d.mtb + t];
   int cls = 0;
   if (t >= 1) {
     if (p.predictor == 1) cls = 1;
-    else if (mode_base >= 0) cls = modes[(size_t)mode_base + (size_t)by * p.tx + bx];
+    else if (mode_base >= 0) cls = B.modes[d.mbase + mode_base + (long long)by * p.tx + bx];
   }
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
   int vcode[4], vq[4];
@@ -103,11 +88,11 @@ __global__ __launch_bounds__(64) void k_reconstruct(int2* __restrict__ cur, floa
     vr[k] = 0;
     if (!valid) continue;
     const int code = xs[gv];
-    uint32_t r = rofs[gv];
+    uint32_t r = rofs[gv] - rbase;
     int q[2] = {0, 0}, pr[2] = {0, 0};
     int64_t w = 0;
     if (code != XLOSSLESS) {
-      size_t o = 2 * (size_t)qofs[gv];
+      size_t o = 2 * (size_t)(qofs[gv] - qbase);
       q[0] = qs[o];
       q[1] = qs[o + 1];
       w = 2 * (int64_t)(p.eps >> code) + 1;
@@ -151,18 +136,18 @@ __global__ __launch_bounds__(64) void k_reconstruct(int2* __restrict__ cur, floa
     const bool mine = lane < 2 * TILE;
     const bool has_prev = t > 0;
     int last = 0, upl = 0;
-    for (int d = 0; d < 2 * TILE - 1; d++) {
-      const int col = d - row;
+    for (int dd = 0; dd < 2 * TILE - 1; dd++) {
+      const int col = dd - row;
       const int up = __builtin_amdgcn_update_dpp(0, last, 0x111, 0xF, 0xF, true);  // row_shr:1
-      if (mine && col >= 0 && col < TILE && bx * TILE + col < W && by * TILE + row < H) {
+      if (mine && col >= 0 && col < TILE && x0 + col < W && y0 + row < H) {
         if (KN[c][row][col]) {
           last = C[c][row][col];
         } else {
-          int s = (col > 0 ? last : 0) + (row > 0 ? up : 0) - (col > 0 && row > 0 ? upl : 0);
+          int sm = (col > 0 ? last : 0) + (row > 0 ? up : 0) - (col > 0 && row > 0 ? upl : 0);
           if (has_prev)
-            s += P[c][row][col] - (col > 0 ? P[c][row][col - 1] : 0) - (row > 0 ? P[c][row - 1][col] : 0) +
-                 (col > 0 && row > 0 ? P[c][row - 1][col - 1] : 0);
-          int64_t rv = (int64_t)s + DQ[c][row][col];
+            sm += P[c][row][col] - (col > 0 ? P[c][row][col - 1] : 0) - (row > 0 ? P[c][row - 1][col] : 0) +
+                  (col > 0 && row > 0 ? P[c][row - 1][col - 1] : 0);
+          int64_t rv = (int64_t)sm + DQ[c][row][col];
           if (rv >= (1 << 25) || rv <= -(1 << 25)) {
             atomicOr(err, 128u);
             rv = 0;
@@ -180,7 +165,7 @@ __global__ __launch_bounds__(64) void k_reconstruct(int2* __restrict__ cur, floa
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
-    const int x = bx * TILE + lx, y = by * TILE + ly;
+    const int x = x0 + lx, y = y0 + ly;
     if (!(x < W && y < H)) continue;
     const size_t gv = (size_t)t * HW + (size_t)y * W + x;
     const int u = C[0][ly][lx], vv = C[1][ly][lx];
@@ -201,20 +186,9 @@ __global__ __launch_bounds__(64) void k_reconstruct(int2* __restrict__ cur, floa
 }
 
 // ============================================================ launchers
-static inline unsigned nblk(size_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
-
-void launch_dec_nonll(const uint16_t* xs, size_t N, uint32_t* nonll, hipStream_t s) {
-  if (N) k_dec_nonll<<<nblk(N), 256, 0, s>>>(xs, N, nonll);
-}
-void launch_dec_counts(const uint16_t* xs, const uint16_t* qs, const uint32_t* qofs, size_t N, size_t nq, int eps,
-                       uint32_t* rcnt, uint32_t* err, hipStream_t s) {
-  if (N) k_dec_counts<<<nblk(N), 256, 0, s>>>(xs, qs, qofs, N, nq, eps, rcnt, err);
-}
-void launch_reconstruct(int2* cur, float* field, const uint16_t* xs, const uint16_t* qs, const uint32_t* qofs,
-                        const uint32_t* raw, const uint32_t* rofs, const uint8_t* modes, long long mode_base,
-                        const FieldParams& p, int t, uint32_t* err, hipStream_t s) {
-  dim3 grid(p.tx, p.ty);
-  k_reconstruct<<<grid, 64, 0, s>>>(cur, field, xs, qs, qofs, raw, rofs, modes, mode_base, p, t, err);
+void launch_reconstruct_b(DecDesc* D, const int* ord, const long long* pre, int m, long long nblocks, int t,
+                          const long long* mtab, const DecodeBufs& B, hipStream_t s) {
+  if (nblocks > 0) k_reconstruct_b<<<(unsigned)nblocks, 64, 0, s>>>(D, ord, pre, m, t, mtab, B);
 }
 
 }  // namespace cpt

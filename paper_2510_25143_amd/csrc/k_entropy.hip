@@ -581,8 +581,8 @@ __global__ __launch_bounds__(256) void k_raw_b(const FieldDesc* __restrict__ D, 
 // ------------------------------------------------------------- decoding
 // LUT entry for every 12-bit prefix: symbol | length << 16; 0xFFFFFFFF when
 // no codeword matches.
-__global__ __launch_bounds__(1024) void k_build_lut(const uint32_t* __restrict__ cb, size_t cb_words, int nsym,
-                                                    uint32_t* __restrict__ lut, uint32_t* __restrict__ err) {
+__device__ void build_lut(const uint32_t* __restrict__ cb, size_t cb_words, int nsym, uint32_t* __restrict__ lut,
+                          uint32_t* __restrict__ err) {
   __shared__ uint8_t len[1024];
   __shared__ int lcount[MAXLEN + 2];
   __shared__ uint32_t first[MAXLEN + 2];
@@ -636,27 +636,22 @@ __global__ __launch_bounds__(1024) void k_build_lut(const uint32_t* __restrict__
   }
 }
 
-__global__ __launch_bounds__(256) void k_words_from_bits(const uint32_t* __restrict__ bits, size_t n,
-                                                         uint32_t* __restrict__ words) {
-  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) words[i] = (bits[i] + 31) / 32;
-}
-
 // One lane per chunk.  Lanes decode DEC_STEP symbols at a time into a
 // per-wave staging buffer, then the wave writes the 64 chunks' pieces as
 // 32-bit words, each piece contiguous (16 lanes per 64-byte piece).
 constexpr int DEC_STEP = 32;
-__global__ __launch_bounds__(256) void k_decode(const uint32_t* __restrict__ lut_g, const uint32_t* __restrict__ cbits,
-                                                const uint32_t* __restrict__ wofs, const uint32_t* __restrict__ bs,
-                                                size_t bs_words, size_t nsym_total, int alphabet,
-                                                uint16_t* __restrict__ out, uint32_t* __restrict__ err) {
+// chunks cfirst .. cfirst + 255 of one stream (the workgroup's share)
+__device__ void decode_chunks(const uint32_t* __restrict__ lut_g, const uint32_t* __restrict__ cbits,
+                              const uint32_t* __restrict__ wofs, uint32_t wbase, const uint32_t* __restrict__ bs,
+                              size_t bs_words, size_t nsym_total, int alphabet, uint16_t* __restrict__ out,
+                              uint32_t* __restrict__ err, size_t cfirst) {
   __shared__ uint32_t lut[1 << MAXLEN];
   __shared__ uint32_t stage[4][64][DEC_STEP / 2 + 1];  // per wave, per lane: DEC_STEP symbols
   for (int i = threadIdx.x; i < (1 << MAXLEN); i += 256) lut[i] = lut_g[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const size_t nch = (nsym_total + CHUNK - 1) / CHUNK;
-  const size_t c0 = (size_t)blockIdx.x * 256 + (size_t)wv * 64;  // first chunk of this wave
+  const size_t c0 = cfirst + (size_t)wv * 64;  // first chunk of this wave
   if (c0 >= nch) return;  // whole wave past the end
   const size_t c = c0 + lane;
   bool live = c < nch;
@@ -664,7 +659,7 @@ __global__ __launch_bounds__(256) void k_decode(const uint32_t* __restrict__ lut
   size_t w0 = 0, nw = 0;
   if (live) {
     nbits = cbits[c];
-    w0 = wofs[c];
+    w0 = wofs[c] - wbase;
     nw = (nbits + 31) / 32;
     if (w0 + nw > bs_words || nbits > (uint32_t)CHUNK * MAXLEN) {
       atomicOr(err, 2u);
@@ -737,6 +732,138 @@ __global__ __launch_bounds__(256) void k_decode(const uint32_t* __restrict__ lut
   if (live && !bad && consumed != nbits) atomicOr(err, 8u);
 }
 
+// ===================================================== batched decoding
+// Every kernel covers all streams of a batch; a workgroup finds its stream
+// from a prefix table; error bits are recorded per stream.
+__global__ __launch_bounds__(256) void k_unpack_modes_b(DecDesc* __restrict__ D, const long long* __restrict__ mpre,
+                                                        int n, uint8_t* __restrict__ modes) {
+  const int f = find_field(mpre, n, blockIdx.x);
+  DecDesc& d = D[f];
+  const size_t i = (size_t)((long long)blockIdx.x - mpre[f]) * 256 + threadIdx.x;
+  if (i >= (size_t)d.nblk) return;
+  const uint32_t* in = d.sec[0];
+  uint32_t v = 0;
+  for (int k = 0; k < d.mb; k++) {
+    const size_t bit = i * d.mb + k;
+    v |= ((in[bit / 32] >> (bit % 32)) & 1u) << k;
+  }
+  if ((int)v >= d.p.K) atomicOr(&d.err, 256u);
+  modes[d.mbase + i] = (uint8_t)v;
+}
+
+__global__ __launch_bounds__(1024) void k_build_lut_b(DecDesc* __restrict__ D, uint32_t* __restrict__ luts) {
+  const int f = blockIdx.x >> 1, a = blockIdx.x & 1;
+  DecDesc& d = D[f];
+  build_lut(d.sec[a ? 4 : 1], (size_t)d.secw[a ? 4 : 1], a ? QSYM : XSYM, luts + (size_t)blockIdx.x * (1 << MAXLEN),
+            &d.err);
+}
+
+// words of every chunk from its bit count (chunk table of the stream)
+template <bool RESID>
+__global__ __launch_bounds__(256) void k_words_from_bits_b(const DecDesc* __restrict__ D,
+                                                           const long long* __restrict__ cpre, int n, long long tot,
+                                                           uint32_t* __restrict__ words) {
+  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (c >= tot) return;
+  const int f = find_field(cpre, n, c);
+  const DecDesc& d = D[f];
+  const long long lc = c - cpre[f];
+  words[c] = (d.sec[RESID ? 5 : 2][lc] + 31) / 32;
+}
+
+// dpre[f]: decoding workgroups (256 chunks each) of the streams before f
+template <bool RESID>
+__global__ __launch_bounds__(256) void k_decode_b(DecDesc* __restrict__ D, const long long* __restrict__ dpre, int n,
+                                                  const uint32_t* __restrict__ luts,
+                                                  const uint32_t* __restrict__ wofs, uint16_t* __restrict__ out) {
+  const int f = find_field(dpre, n, blockIdx.x);
+  DecDesc& d = D[f];
+  const size_t cb = (size_t)(RESID ? d.cqb : d.cxb);
+  const size_t cfirst = (size_t)((long long)blockIdx.x - dpre[f]) * 256;
+  decode_chunks(luts + (size_t)(2 * f + (RESID ? 1 : 0)) * (1 << MAXLEN), d.sec[RESID ? 5 : 2], wofs + cb, wofs[cb],
+                d.sec[RESID ? 6 : 3], (size_t)d.secw[RESID ? 6 : 3], (size_t)(RESID ? d.nq : d.N),
+                RESID ? QSYM : XSYM, out + (RESID ? (size_t)d.qsb : (size_t)d.voff), &d.err, cfirst);
+}
+
+struct VPosD {
+  int f;
+  size_t i;
+  bool valid;
+};
+__device__ __forceinline__ VPosD vpos_d(const DecDesc* __restrict__ D, const long long* __restrict__ vpre, int n) {
+  VPosD v;
+  v.f = find_field(vpre, n, blockIdx.x);
+  v.i = (size_t)((long long)blockIdx.x - vpre[v.f]) * 256 + threadIdx.x;
+  v.valid = v.i < (size_t)D[v.f].N;
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_dec_nonll_b(const DecDesc* __restrict__ D, const long long* __restrict__ vpre,
+                                                     int n, const uint16_t* __restrict__ xs,
+                                                     uint32_t* __restrict__ nonll) {
+  const VPosD v = vpos_d(D, vpre, n);
+  if (!v.valid) return;
+  const size_t g = (size_t)D[v.f].voff + v.i;
+  nonll[g] = xs[g] != XLOSSLESS ? 1u : 0u;
+}
+
+// raw values per vertex; a bound code above 24, a residual position past
+// the stream's symbols or a bound too small for a code is an error
+__global__ __launch_bounds__(256) void k_dec_counts_b(DecDesc* __restrict__ D, const long long* __restrict__ vpre,
+                                                      int n, const uint16_t* __restrict__ xs,
+                                                      const uint16_t* __restrict__ qs,
+                                                      const uint32_t* __restrict__ qofs, uint32_t* __restrict__ rcnt) {
+  const VPosD v = vpos_d(D, vpre, n);
+  if (!v.valid) return;
+  DecDesc& d = D[v.f];
+  const size_t g = (size_t)d.voff + v.i;
+  const uint32_t c = xs[g];
+  uint32_t r = 0;
+  if (c > XLOSSLESS) {
+    atomicOr(&d.err, 16u);
+  } else if (c == XLOSSLESS) {
+    r = 2;
+  } else {
+    const size_t o = 2 * (size_t)(qofs[g] - qofs[d.voff]);
+    if ((d.p.eps >> c) < 1 || o + 2 > (size_t)d.nq) {
+      atomicOr(&d.err, 32u);
+    } else {
+      const uint16_t* q = qs + d.qsb;
+      r = (q[o] == 0) + (q[o + 1] == 0);
+    }
+  }
+  rcnt[g] = r;
+}
+
+// the stream's totals against its header: bitstream words, residual
+// symbols, raw values; no error bit.  Reconstruction runs only for streams
+// that pass, so that every offset it follows stays inside the stream.
+__global__ void k_dec_check_b(DecDesc* __restrict__ D, int n, const uint32_t* __restrict__ xw,
+                              const uint32_t* __restrict__ xwofs, const uint32_t* __restrict__ qw,
+                              const uint32_t* __restrict__ qwofs, const uint32_t* __restrict__ nonll,
+                              const uint32_t* __restrict__ qofs, const uint32_t* __restrict__ rcnt,
+                              const uint32_t* __restrict__ rofs) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  DecDesc& d = D[f];
+  if (d.status) return;
+  uint32_t e = d.err;
+  const size_t xa = d.cxb, xz = d.cxb + d.nchx - 1;
+  const uint32_t words_x = d.nchx > 0 ? xwofs[xz] + xw[xz] - xwofs[xa] : 0;
+  uint32_t words_q = 0;
+  if (d.nchq > 0) {
+    const size_t qa = d.cqb, qz = d.cqb + d.nchq - 1;
+    words_q = qwofs[qz] + qw[qz] - qwofs[qa];
+  }
+  const size_t a = d.voff, z = d.voff + d.N - 1;
+  const uint32_t nl = qofs[z] + nonll[z] - qofs[a];
+  const uint32_t nr = rofs[z] + rcnt[z] - rofs[a];
+  if ((long long)words_x != d.secw[3] || (long long)words_q != d.secw[6]) e |= 512u;
+  if (2 * (long long)nl != d.nq || (long long)nr != d.nraw) e |= 1024u;
+  d.err = e;
+  if (e) d.status = -3;  // CPT_ECORRUPT
+}
+
 // ============================================================ launchers
 static inline unsigned nblk(size_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
@@ -780,16 +907,33 @@ void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBuf
   if (cqtot > 0) k_encode_b<true><<<(unsigned)cqtot, 256, 0, s>>>(D, cqpre, n, B.xcode, E.qsym, E.qt, E.qwofs);
   if (vblocks > 0) k_raw_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.rofs);
 }
-void launch_build_lut(const uint32_t* cb, size_t cb_words, int nsym, uint32_t* lut, uint32_t* err, hipStream_t s) {
-  k_build_lut<<<1, 1024, 0, s>>>(cb, cb_words, nsym, lut, err);
+void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long long* mpre, long long mblocks,
+                           const long long* cxpre, long long cxtot, const long long* cqpre, long long cqtot,
+                           hipStream_t s) {
+  if (mblocks > 0) k_unpack_modes_b<<<(unsigned)mblocks, 256, 0, s>>>(D, mpre, n, B.modes);
+  k_build_lut_b<<<2 * n, 1024, 0, s>>>(D, B.lut);
+  if (cxtot > 0) {
+    k_words_from_bits_b<false><<<nblk((size_t)cxtot), 256, 0, s>>>(D, cxpre, n, cxtot, B.xw);
+    launch_scan(B.xw, (size_t)cxtot, B.xwofs, B.part + 4, B.part, s);
+  }
+  if (cqtot > 0) {
+    k_words_from_bits_b<true><<<nblk((size_t)cqtot), 256, 0, s>>>(D, cqpre, n, cqtot, B.qw);
+    launch_scan(B.qw, (size_t)cqtot, B.qwofs, B.part + 4, B.part + 1, s);
+  }
 }
-void launch_words_from_bits(const uint32_t* bits, size_t n, uint32_t* words, hipStream_t s) {
-  if (n) k_words_from_bits<<<nblk(n), 256, 0, s>>>(bits, n, words);
-}
-void launch_decode(const uint32_t* lut, const uint32_t* chunk_bits, const uint32_t* wofs, const uint32_t* bs,
-                   size_t bs_words, size_t nsym_total, int alphabet, uint16_t* out, uint32_t* err, hipStream_t s) {
-  size_t nch = (nsym_total + CHUNK - 1) / CHUNK;
-  if (nch) k_decode<<<nblk(nch), 256, 0, s>>>(lut, chunk_bits, wofs, bs, bs_words, nsym_total, alphabet, out, err);
+
+void launch_decode_b(DecDesc* D, int n, const DecodeBufs& B, const long long* dxpre, long long dxblocks,
+                     const long long* dqpre, long long dqblocks, const long long* vpre, long long vblocks,
+                     long long Ntot, long long CX, long long CQ, hipStream_t s) {
+  if (dxblocks > 0) k_decode_b<false><<<(unsigned)dxblocks, 256, 0, s>>>(D, dxpre, n, B.lut, B.xwofs, B.xs);
+  if (dqblocks > 0) k_decode_b<true><<<(unsigned)dqblocks, 256, 0, s>>>(D, dqpre, n, B.lut, B.qwofs, B.qs);
+  if (vblocks <= 0) return;
+  k_dec_nonll_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xs, B.nonll);
+  launch_scan(B.nonll, (size_t)Ntot, B.qofs, B.part + 4, B.part + 2, s);
+  k_dec_counts_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xs, B.qs, B.qofs, B.rcnt);
+  launch_scan(B.rcnt, (size_t)Ntot, B.rofs, B.part + 4, B.part + 3, s);
+  k_dec_check_b<<<nblk((size_t)n, 64), 64, 0, s>>>(D, n, B.xw, B.xwofs, B.qw, B.qwofs, B.nonll, B.qofs, B.rcnt,
+                                                   B.rofs);
 }
 
 }  // namespace cpt

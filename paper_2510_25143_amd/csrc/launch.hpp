@@ -38,22 +38,6 @@ struct HuffTables {
   uint8_t len[1024];
 };
 void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
-// decoding: build the lookup tables from a codebook section; err receives a
-// nonzero code on any inconsistency
-void launch_build_lut(const uint32_t* cb, size_t cb_words, int nsym, uint32_t* lut, uint32_t* err,
-                      hipStream_t s);
-void launch_decode(const uint32_t* lut, const uint32_t* chunk_bits, const uint32_t* wofs, const uint32_t* bs,
-                   size_t bs_words, size_t nsym_total, int alphabet, uint16_t* out, uint32_t* err, hipStream_t s);
-void launch_words_from_bits(const uint32_t* bits, size_t n, uint32_t* words, hipStream_t s);
-
-// k_decompress.hip
-void launch_dec_counts(const uint16_t* xs, const uint16_t* qs, const uint32_t* qofs, size_t N, size_t nq,
-                       int eps, uint32_t* rcnt, uint32_t* err, hipStream_t s);
-void launch_dec_nonll(const uint16_t* xs, size_t N, uint32_t* nonll, hipStream_t s);
-void launch_reconstruct(int2* cur, float* field, const uint16_t* xs, const uint16_t* qs, const uint32_t* qofs,
-                        const uint32_t* raw, const uint32_t* rofs, const uint8_t* modes, long long mode_base,
-                        const FieldParams& p, int t, uint32_t* err, hipStream_t s);
-
 // k_selector.hip
 int selector_parts(int nbatch, int per_block);
 void launch_mlp_grad(const float* w, const float* feats, const int32_t* labels, const int32_t* idx, int nbatch,

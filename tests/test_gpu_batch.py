@@ -178,3 +178,51 @@ def test_persistent_schedule_reports_unsupported(cpt, small):
     with pytest.raises(cpt.CptError) as e:
         cpt.compress_batch(small[1][:2], 1e-2, schedule="persistent")
     assert e.value.status == cpt.EUNSUPPORTED
+
+
+# ------------------------------------------------------------ decompression
+def test_decompress_batch_matches_oracle(cpt, small):
+    """Streams of several predictors and block heights in one batch."""
+    kws = [dict(), dict(predictor=3, mode_bt=4), dict(predictor=0), dict(predictor=1), dict(predictor=2, mode_bt=3)]
+    streams, want = [], []
+    for i, f in enumerate(small[0]):
+        w = oracle.compress(f.numpy(), 1e-2, **kws[i % len(kws)])
+        streams.append(torch.from_numpy(w).cuda())
+        want.append(oracle.decompress(w))
+    got, st = cpt.decompress_batch(streams)
+    assert st == [0] * len(streams)
+    for i, (g, w) in enumerate(zip(got, want)):
+        assert np.array_equal(g.cpu().numpy().view(np.uint32), w.view(np.uint32)), "stream %d %s" % (i, SMALL[i])
+
+
+def test_decompress_batch_isolates_corrupt_streams(cpt, small, want_mix2):
+    streams = [torch.from_numpy(w.copy()).cuda() for w in want_mix2[:4]]
+    bad = streams[1].clone()
+    info = cpt.stream_info(bad)
+    # flip bits inside the residual bitstream (after header and small sections)
+    bad[info["total_len"] - 8 * int(info["n_raw"]) // 2 - 40:][:4] ^= 0x5A
+    streams[1] = bad
+    streams[3] = streams[3][:200].contiguous()  # shorter than a header
+    outs = [torch.empty((2, T, H, W), dtype=torch.float32, device="cuda") for (H, W, T) in SMALL[:4]]
+    got, st = cpt.decompress_batch(streams, outs=outs, raise_on_error=False)
+    assert st[0] == cpt.OK and st[2] == cpt.OK and st[3] == cpt.ECORRUPT
+    for i in (0, 2):
+        assert np.array_equal(got[i].cpu().numpy().view(np.uint32),
+                              oracle.decompress(want_mix2[i]).view(np.uint32))
+    with pytest.raises(cpt.CptError):
+        cpt.decompress_batch(streams, outs=outs)
+
+
+def test_batch_round_trip_on_uneven_batch(cpt):
+    shapes = [(max(h // 4, 2), max(w // 4, 2), t) for h, w, t in synthfields.batch_shapes(16, seed=3001)]
+    fields = [synthfields.batch_field(i, s, device="cuda")[0].float() for i, s in enumerate(shapes)]
+    streams, st = cpt.compress_batch(fields, 1e-2, schedule="launch")
+    assert st == [0] * len(fields)
+    dec, st = cpt.decompress_batch(streams)
+    assert st == [0] * len(fields)
+    for f, s, d in zip(fields, streams, dec):
+        single = cpt.decompress(s)
+        assert np.array_equal(single.cpu().numpy().view(np.uint32), d.cpu().numpy().view(np.uint32))
+        k, ea, _ = cpt.field_params(f, 1e-2)
+        v = cpt.verify(f, d, k)
+        assert v["fc_t"] == 0 and v["fc_s"] == 0 and v["max_err"] <= ea
