@@ -86,12 +86,14 @@ __device__ __forceinline__ double det2(int2 a, int2 b) {
 }
 
 // Minimum over each row of 16 lanes (DPP row rotations; every lane of the
-// row receives the result).
+// row receives the result).  Called with every lane of the wave enabled, so
+// no lane reads outside the row's live values; bound_ctrl lets the compiler
+// fold each rotation into the min itself.
 __device__ __forceinline__ int row16_min(int v) {
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false));  // row_ror:8
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, false));  // row_ror:4
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x122, 0xF, 0xF, false));  // row_ror:2
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x121, 0xF, 0xF, false));  // row_ror:1
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true));  // row_ror:8
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, true));  // row_ror:4
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x122, 0xF, 0xF, true));  // row_ror:2
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x121, 0xF, 0xF, true));  // row_ror:1
   return v;
 }
 
@@ -113,19 +115,19 @@ __device__ __forceinline__ int xi_code(int eps, int xi) {
 
 // Residual quantization with bin 2 xt + 1; returns the code (0 when the
 // component is unpredictable) and writes the reconstruction.  The quotient
-// (|q| < 512) is estimated in fp32 and corrected exactly.
+// q = floor((x - pred + xt) / w) is estimated in fp32 and corrected to the
+// exact value; the component is predictable when 1 - QR <= q <= QR - 1.
+// With eps' < 2^23 and |x|, |pred| < 2^28 every step fits in 32 bits, and
+// an estimate more than one off only happens far outside that range.
 __device__ __forceinline__ int quantize(int x, int pred, int xt, int* recon) {
-  int num = x - pred + xt;
-  int w = 2 * xt + 1;
-  int64_t hi = (int64_t)QR * w, lo = (int64_t)(1 - QR) * w;
-  if ((int64_t)num >= hi || (int64_t)num < lo) {
+  const int num = x - pred + xt, w = 2 * xt + 1;
+  int q = (int)floorf((float)num * __builtin_amdgcn_rcpf((float)w));
+  const int r = num - q * w;
+  q += (r >= w ? 1 : 0) - (r < 0 ? 1 : 0);
+  if (q < 1 - QR || q > QR - 1) {
     *recon = x;
     return 0;
   }
-  int q = (int)floorf((float)num * __builtin_amdgcn_rcpf((float)w));
-  int r = num - q * w;
-  if (r < 0) q--;
-  else if (r >= w) q++;
   *recon = pred + q * w;
   return q + QR;
 }

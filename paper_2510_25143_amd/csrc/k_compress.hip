@@ -398,18 +398,23 @@ static_assert(make_pairs().a[0] >= 0 && make_dyn_pairs().a[13] >= 0 && make_dyn_
 // share a strict sign.  A face whose raise already reaches the running
 // minimum xi cannot lower it, so its quotients are skipped; a quotient is
 // only evaluated when it beats the current value (N - 1 < e D, exact).
+// N is a non-negative integer; for N = 0 the estimate ends at -1 and the
+// final max gives the 0 of Alg. 2.  The one-step correction of the fp64
+// reciprocal estimate is a select, not a branch.
 __device__ __forceinline__ void lower_to(int& e, double N, int D) {
-  if (N == 0.0) {
-    e = 0;
-    return;
-  }
   double Dd = (double)D, n1 = N - 1.0;
   if (n1 >= (double)e * Dd) return;
   int q = (int)(n1 * __builtin_amdgcn_rcp(Dd));
   double r = n1 - (double)q * Dd;
-  if (r < 0.0) q--;
-  else if (r >= Dd) q++;
-  e = q;
+  q += (r >= Dd ? 1 : 0) - (r < 0.0 ? 1 : 0);
+  e = max(q, 0);
+}
+
+// the raise of Alg. 2 for one component: |c| - 1 when the three values share
+// a strict sign, else -1
+__device__ __forceinline__ int relax_of(int c, int c0, int c1) {
+  const int lo = min(min(c0, c1), c), hi = max(max(c0, c1), c);
+  return ((lo > 0) | (hi < 0)) ? iabs(c) - 1 : -1;
 }
 
 __device__ __forceinline__ void face_update(int& xi, int2 me, int2 n0, int2 n1, double d0, double d1) {
@@ -419,9 +424,7 @@ __device__ __forceinline__ void face_update(int& xi, int2 me, int2 n0, int2 n1, 
     xi = 0;
     return;
   }
-  int relax = -1;
-  if ((n0.x > 0 && n1.x > 0 && me.x > 0) || (n0.x < 0 && n1.x < 0 && me.x < 0)) relax = iabs(me.x) - 1;
-  if ((n0.y > 0 && n1.y > 0 && me.y > 0) || (n0.y < 0 && n1.y < 0 && me.y < 0)) relax = max(relax, iabs(me.y) - 1);
+  const int relax = max(relax_of(me.x, n0.x, n1.x), relax_of(me.y, n0.y, n1.y));
   if (relax >= xi) return;
   int e = xi;
   lower_to(e, fabs(M), iabs(n1.x - n0.x) + iabs(n0.y - n1.y));
@@ -462,6 +465,10 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
   const size_t HW = (size_t)H * W;
   const int x0 = bx * TILE, y0 = by * TILE;
   const int eps = p.eps;
+  // this thread's vertex and its lossless flag, fetched along with the frames
+  const int vx = tid & 15, vy = tid >> 4;
+  const bool vin = x0 + vx < W && y0 + vy < H;
+  const bool lossless = vin ? flags[(size_t)t * HW + (size_t)(y0 + vy) * W + x0 + vx] != 0 : true;
 
   // ---- stage frames t-1, t, t+1 (block plus halo); the two corner cells
   // that belong to blocks of the same colour are never read and not loaded
@@ -480,11 +487,10 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
 
   // ---- faces whose other vertices stay fixed during the sweep
   {
-    const int lx = tid & 15, ly = tid >> 4, x = x0 + lx, y = y0 + ly;
+    const int lx = vx, ly = vy, x = x0 + lx, y = y0 + ly;
     int xi = -1;
-    if (x < W && y < H) {
-      const size_t gv = (size_t)t * HW + (size_t)y * W + x;
-      if (!flags[gv]) {
+    if (vin) {
+      if (!lossless) {
         xi = eps;
         const int2 me = V[1][ly + 1][lx + 1];
         // Faces through a raster predecessor (left, up, up-left) are all
@@ -539,44 +545,53 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
   const int axo = fa >= 0 ? c_nbr_dx(fa) : 0, ayo = fa >= 0 ? c_nbr_dy(fa) : 0, ato = fa >= 0 ? c_nbr_dt(fa) : 0;
   const int bxo = fb >= 0 ? c_nbr_dx(fb) : 0, byo = fb >= 0 ? c_nbr_dy(fb) : 0, bto = fb >= 0 ? c_nbr_dt(fb) : 0;
   const int comp = j & 1;
-  // this lane's face exists for x in [xlo, xhi) (both neighbours inside the
-  // domain); y and t do not change during the sweep
+  // y and t of this lane's face do not change during the sweep
   const bool face_yt = fa >= 0 && y + ayo >= 0 && y + ayo < H && t + ato >= 0 && t + ato < T && y + byo >= 0 &&
                        y + byo < H && t + bto >= 0 && t + bto < T;
-  const int xlo = max(-min(axo, bxo), 0), xhi = W - max(max(axo, bxo), 0);
+  // columns of the block with a vertex [0, aend), and those where this
+  // lane's face has both neighbours inside the domain [flo, fhi)
+  const int aend = y < H ? min(TILE, W - x0) : 0;
+  const int flo = max(max(-min(axo, bxo), 0) - x0, 0);
+  const int fhi = face_yt ? max(min(W - max(max(axo, bxo), 0) - x0, TILE), flo) : flo;
   const int2* Vme = &V[1][g + 1][1];
   const int2* Va = &V[1 + ato][g + 1 + ayo][1 + axo];
   const int2* Vb = &V[1 + bto][g + 1 + byo][1 + bxo];
-  for (int d = 0; d < 2 * TILE - 1; d++) {
-    const int lx = d - g, x = x0 + lx;
-    const bool active = lx >= 0 && lx < TILE && x < W && y < H;
-    int e = eps, xs = -1, lorenzo = 0;
+  // component comp of the left, upper and upper-left neighbours and of the
+  // fixed prediction term, at index lx (int2 rows: stride 2)
+  const int* Ql = (const int*)&V[1][g + 1][0] + comp;
+  const int* Qu = (const int*)&V[1][g][1] + comp;
+  const int* Qlu = (const int*)&V[1][g][0] + comp;
+  const int* Qp = (const int*)&SLP[g][0] + comp;
+  // wave wv holds rows 4 wv .. 4 wv + 3, which have vertices on the
+  // anti-diagonals 4 wv .. 4 wv + 18; on the others it only keeps the
+  // workgroup's barrier count
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int dlo = 4 * wv, dhi = 4 * wv + 19;
+  for (int d = 0; d < dlo; d++) __syncthreads();
+  for (int d = dlo; d < dhi; d++) {
+    const int lx = d - g;
+    const bool active = (unsigned)lx < (unsigned)aend;
+    // every value the step reads is final after the last barrier: read them
+    // all at once (at a clamped column for the idle lanes)
+    const int lc = min(max(lx, 0), TILE - 1);
+    const int xs = XS[g][lc];
+    const int2 me = Vme[lc], pa = Va[lc], pb = Vb[lc];
+    const int l = Ql[2 * lc], u = Qu[2 * lc], lu = Qlu[2 * lc], pt = Qp[2 * lc];
+    int e = eps;
     if (active) {
-      xs = XS[g][lx];
       e = xs >= 0 ? xs : eps;
-      if (xs >= 0 && face_yt && x >= xlo && x < xhi) {
-        const int2 me = Vme[lx], pa = Va[lx], pb = Vb[lx];
-        face_update(e, me, pa, pb, det2(me, pa), det2(me, pb));
-      }
-      if (j < 2 && cls == 0) {
-        // Lorenzo neighbours of this step's vertex (final after the last
-        // barrier) plus the frame t-1 part computed before the sweep
-        auto cmp = [&](int2 v) { return comp ? v.y : v.x; };
-        const int l = lx > 0 ? cmp(V[1][g + 1][lx]) : 0;
-        const int u = g > 0 ? cmp(V[1][g][lx + 1]) : 0;
-        const int lu = (lx > 0 && g > 0) ? cmp(V[1][g][lx]) : 0;
-        lorenzo = l + u - lu + cmp(SLP[g][lx]);
-      }
+      if (xs >= 0 && (unsigned)(lx - flo) < (unsigned)(fhi - flo)) face_update(e, me, pa, pb, det2(me, pa), det2(me, pb));
     }
     e = row16_min(e);
     if (active && j < 2) {
-      int xi = xs < 0 ? 0 : min(xs, e);
-      int code = xi_code(eps, xi);
+      const int xi = xs < 0 ? 0 : min(xs, e);
+      const int code = xi_code(eps, xi);
       int qc = 0;
       if (code != XLOSSLESS) {
         const int xt = eps >> code;
-        const int2 me = V[1][g + 1][lx + 1];
-        const int pred = cls == 0 ? lorenzo : (comp ? SLP[g][lx].y : SLP[g][lx].x);
+        // 3-D Lorenzo (the halo cells at the block's edges count as 0) or
+        // the semi-Lagrangian prediction
+        const int pred = cls == 0 ? (lx > 0 ? l : 0) + (g > 0 ? u : 0) - (lx > 0 && g > 0 ? lu : 0) + pt : pt;
         int rec;
         qc = quantize(comp ? me.y : me.x, pred, xt, &rec);
         ((int*)&V[1][g + 1][lx + 1])[comp] = rec;
@@ -584,11 +599,12 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
       ((uint16_t*)&OQ[g][lx])[comp] = (uint16_t)qc;
       if (!comp) {
         OC[g][lx] = (uint8_t)code;
-        OX[g][lx] = xi;
+        if (xi_dbg) OX[g][lx] = xi;
       }
     }
     __syncthreads();
   }
+  for (int d = dhi; d < 2 * TILE - 1; d++) __syncthreads();
 
   // ---- results of the block, one coalesced write per array
   {
@@ -614,6 +630,17 @@ __device__ __forceinline__ bool phase_block(long long li, int tx, int c, int* bx
   *bx = b0 + 3 * xi;
   *by = y;
   return *bx < tx;
+}
+
+// Workgroups are dealt to the chip's eight XCDs in turn (workgroup i to XCD
+// i mod 8), each with its own L2.  The n workgroups of one field take the
+// field's blocks so that those dealt to one XCD form one contiguous run of
+// the row-major block order: every XCD keeps a band of block rows in every
+// colour phase and frame, and finds the halo and the neighbouring frames in
+// its own L2.  A bijection of [0, n).
+__device__ __forceinline__ long long xcd_band(long long li, long long n) {
+  const long long k = li & 7, q = li >> 3, base = n >> 3, rem = n & 7;
+  return k * base + (k < rem ? k : rem) + q;
 }
 
 // Class of block (bx, by) of frame t, then its phase.  mstate says whether
@@ -660,7 +687,7 @@ __global__ __launch_bounds__(64) void k_modes_b(BatchView B, const long long* __
   const FieldDesc& d = B.D[B.ord[j]];
   if (d.status) return;
   const FieldParams p = d.p;
-  const long long li = (long long)blockIdx.x - pre[j];
+  const long long li = xcd_band((long long)blockIdx.x - pre[j], pre[j + 1] - pre[j]);
   const int by = (int)(li / p.tx), bx = (int)(li - (long long)by * p.tx);
   uint8_t* mrow = B.modes + d.mbase + (size_t)gidx * p.tx * p.ty;
   float* feats = d.feats_dbg ? d.feats_dbg + (size_t)gidx * p.tx * p.ty * 10 : nullptr;
@@ -679,7 +706,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   if (d.status) return;
   const FieldParams p = d.p;
   int bx, by;
-  if (!phase_block((long long)blockIdx.x - pre[j], p.tx, c, &bx, &by)) return;
+  if (!phase_block(xcd_band((long long)blockIdx.x - pre[j], pre[j + 1] - pre[j]), p.tx, c, &bx, &by)) return;
   run_block<DECIDE>(S, B, d, p, t, bx, by, mstate, gidx);
 }
 
