@@ -398,46 +398,65 @@ static_assert(make_pairs().a[0] >= 0 && make_dyn_pairs().a[13] >= 0 && make_dyn_
 // share a strict sign.  A face whose raise already reaches the running
 // minimum xi cannot lower it, so its quotients are skipped; a quotient is
 // only evaluated when it beats the current value (N - 1 < e D, exact).
-// N is a non-negative integer; for N = 0 the estimate ends at -1 and the
-// final max gives the 0 of Alg. 2.  The one-step correction of the fp64
-// reciprocal estimate is a select, not a branch.
-__device__ __forceinline__ void lower_to(int& e, double N, int D) {
-  double Dd = (double)D, n1 = N - 1.0;
-  if (n1 >= (double)e * Dd) return;
-  int q = (int)(n1 * __builtin_amdgcn_rcp(Dd));
-  double r = n1 - (double)q * Dd;
-  q += (r >= Dd ? 1 : 0) - (r < 0.0 ? 1 : 0);
+// The operands are fixed-point integers below 2^25 held as fp64 values, so
+// every sum, difference, absolute value and product below is exact and the
+// comparisons decide exactly as in integers.  N is a non-negative integer;
+// for N = 0 the estimate ends at -1 and the final max gives the 0 of
+// Alg. 2.  The one-step correction of the fp64 reciprocal estimate is a
+// select, not a branch.
+__device__ __forceinline__ void lower_to(int& e, double N, double D) {
+  const double n1 = N - 1.0;
+  if (n1 >= (double)e * D) return;
+  int q = (int)(n1 * __builtin_amdgcn_rcp(D));
+  const double r = n1 - (double)q * D;
+  q += (r >= D ? 1 : 0) - (r < 0.0 ? 1 : 0);
   e = max(q, 0);
 }
 
-// the raise of Alg. 2 for one component: |c| - 1 when the three values share
-// a strict sign, else -1
-__device__ __forceinline__ int relax_of(int c, int c0, int c1) {
-  const int lo = min(min(c0, c1), c), hi = max(max(c0, c1), c);
-  return ((lo > 0) | (hi < 0)) ? iabs(c) - 1 : -1;
+__device__ __forceinline__ double det2d(double2 a, double2 b) { return fma(a.x, b.y, -(a.y * b.x)); }
+
+// What the raise of Alg. 2 needs of the vertex itself: the sign of each
+// component (+1, -1 or 0) and |component| - 1.
+struct MeSign {
+  double sx, sy;
+  int rx, ry;
+};
+__device__ __forceinline__ MeSign me_sign(double2 me) {
+  MeSign m;
+  m.sx = me.x > 0.0 ? 1.0 : (me.x < 0.0 ? -1.0 : 0.0);
+  m.sy = me.y > 0.0 ? 1.0 : (me.y < 0.0 ? -1.0 : 0.0);
+  m.rx = (int)fabs(me.x) - 1;
+  m.ry = (int)fabs(me.y) - 1;
+  return m;
 }
 
-__device__ __forceinline__ void face_update(int& xi, int2 me, int2 n0, int2 n1, double d0, double d1) {
-  double M = (d0 - d1) + det2(n0, n1);
-  int a0 = iabs(n0.x) + iabs(n0.y), a1 = iabs(n1.x) + iabs(n1.y);
-  if (M == 0.0 || a0 == 0 || a1 == 0) {
+// Running minimum with the Alg. 2 bound of the face (me, n0, n1).  A
+// component's raise applies when n0 and n1 share the strict sign of the
+// vertex's own component: min(n0 s, n1 s) > 0 for that sign s.
+__device__ __forceinline__ void face_update(int& xi, double2 me, const MeSign& ms, double2 n0, double2 n1) {
+  const double d0 = det2d(me, n0), d1 = det2d(me, n1);
+  const double M = (d0 - d1) + det2d(n0, n1);
+  const double a0 = fabs(n0.x) + fabs(n0.y), a1 = fabs(n1.x) + fabs(n1.y);
+  if (M == 0.0 || a0 == 0.0 || a1 == 0.0) {
     xi = 0;
     return;
   }
-  const int relax = max(relax_of(me.x, n0.x, n1.x), relax_of(me.y, n0.y, n1.y));
+  const bool sx = fmin(n0.x * ms.sx, n1.x * ms.sx) > 0.0;
+  const bool sy = fmin(n0.y * ms.sy, n1.y * ms.sy) > 0.0;
+  const int relax = max(sx ? ms.rx : -1, sy ? ms.ry : -1);
   if (relax >= xi) return;
   int e = xi;
-  lower_to(e, fabs(M), iabs(n1.x - n0.x) + iabs(n0.y - n1.y));
+  lower_to(e, fabs(M), fabs(n1.x - n0.x) + fabs(n0.y - n1.y));
   lower_to(e, fabs(d1), a1);
   lower_to(e, fabs(d0), a0);
   xi = min(xi, max(e, relax));
 }
 
 struct PhaseSmem {
-  int2 V[3][HALO][HALO];  // frames t-1, t, t+1 around the block
-  int XS[TILE][TILE];     // bound from the faces fixed for the whole sweep; -1 = lossless
-  int2 SLP[TILE][TILE];   // semi-Lagrangian predictions, or the frame t-1 part of the Lorenzo prediction
-  uint32_t OQ[TILE][TILE];  // outputs, written once after the sweep
+  double2 V[3][HALO][HALO];  // frames t-1, t, t+1 around the block (exact fp64 integers)
+  int XS[TILE][TILE];        // bound from the faces fixed for the whole sweep; -1 = lossless
+  int2 SLP[TILE][TILE];      // semi-Lagrangian predictions, or the frame t-1 part of the Lorenzo prediction
+  uint32_t OQ[TILE][TILE];   // outputs, written once after the sweep
   int OX[TILE][TILE];
   uint8_t OC[TILE][TILE];
 };
@@ -480,7 +499,7 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
     bool corner = (hx == HALO - 1 && hy == 0) || (hx == 0 && hy == HALO - 1);
     if (!corner && gx >= 0 && gx < W && gy >= 0 && gy < H && tt >= 0 && tt < T)
       v = cur[(size_t)tt * HW + (size_t)gy * W + gx];
-    V[f][hy][hx] = v;
+    V[f][hy][hx] = make_double2((double)v.x, (double)v.y);
   }
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
   __syncthreads();
@@ -492,7 +511,8 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
     if (vin) {
       if (!lossless) {
         xi = eps;
-        const int2 me = V[1][ly + 1][lx + 1];
+        const double2 me = V[1][ly + 1][lx + 1];
+        const MeSign ms = me_sign(me);
         // Faces through a raster predecessor (left, up, up-left) are all
         // evaluated in the sweep, also where that neighbour lies outside the
         // block; the other 22 are evaluated here for every vertex alike.
@@ -506,18 +526,19 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
         for (int f = 0; f < 22; f++) {
           const int a = SPAIRS.a[f], b = SPAIRS.b[f];
           if (((ok >> a) & (ok >> b) & 1u) == 0) continue;
-          int2 na = V[1 + NBR.dt[a]][ly + 1 + NBR.dy[a]][lx + 1 + NBR.dx[a]];
-          int2 nb = V[1 + NBR.dt[b]][ly + 1 + NBR.dy[b]][lx + 1 + NBR.dx[b]];
-          face_update(xi, me, na, nb, det2(me, na), det2(me, nb));
+          const double2 na = V[1 + NBR.dt[a]][ly + 1 + NBR.dy[a]][lx + 1 + NBR.dx[a]];
+          const double2 nb = V[1 + NBR.dt[b]][ly + 1 + NBR.dy[b]][lx + 1 + NBR.dx[b]];
+          face_update(xi, me, ms, na, nb);
         }
       }
       if (cls == 0) {
         // the frame t-1 part of the 3-D Lorenzo prediction (fixed during the sweep)
-        const int2 pc = V[0][ly + 1][lx + 1];
-        const int2 pl = lx > 0 ? V[0][ly + 1][lx] : make_int2(0, 0);
-        const int2 pu = ly > 0 ? V[0][ly][lx + 1] : make_int2(0, 0);
-        const int2 plu = (lx > 0 && ly > 0) ? V[0][ly][lx] : make_int2(0, 0);
-        SLP[ly][lx] = make_int2(pc.x - pl.x - pu.x + plu.x, pc.y - pl.y - pu.y + plu.y);
+        const double2 z = make_double2(0.0, 0.0);
+        const double2 pc = V[0][ly + 1][lx + 1];
+        const double2 pl = lx > 0 ? V[0][ly + 1][lx] : z;
+        const double2 pu = ly > 0 ? V[0][ly][lx + 1] : z;
+        const double2 plu = (lx > 0 && ly > 0) ? V[0][ly][lx] : z;
+        SLP[ly][lx] = make_int2((int)(pc.x - pl.x - pu.x + plu.x), (int)(pc.y - pl.y - pu.y + plu.y));
       } else {
         // frame t-1 from the staged halo where it covers the sample (all of
         // it but the two unstaged corners), else from global memory
@@ -526,7 +547,9 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
           const int hx = xx - x0 + 1, hy = yy - y0 + 1;
           const bool staged = hx >= 0 && hx < HALO && hy >= 0 && hy < HALO && !(hx == HALO - 1 && hy == 0) &&
                               !(hx == 0 && hy == HALO - 1);
-          return staged ? V[0][hy][hx] : prev[(size_t)yy * W + xx];
+          if (!staged) return prev[(size_t)yy * W + xx];
+          const double2 q = V[0][hy][hx];
+          return make_int2((int)q.x, (int)q.y);
         };
         int pu, pv;
         sl_predict_f(F, H, W, x, y, SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pu, &pv);
@@ -553,14 +576,14 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
   const int aend = y < H ? min(TILE, W - x0) : 0;
   const int flo = max(max(-min(axo, bxo), 0) - x0, 0);
   const int fhi = face_yt ? max(min(W - max(max(axo, bxo), 0) - x0, TILE), flo) : flo;
-  const int2* Vme = &V[1][g + 1][1];
-  const int2* Va = &V[1 + ato][g + 1 + ayo][1 + axo];
-  const int2* Vb = &V[1 + bto][g + 1 + byo][1 + bxo];
+  const double2* Vme = &V[1][g + 1][1];
+  const double2* Va = &V[1 + ato][g + 1 + ayo][1 + axo];
+  const double2* Vb = &V[1 + bto][g + 1 + byo][1 + bxo];
   // component comp of the left, upper and upper-left neighbours and of the
-  // fixed prediction term, at index lx (int2 rows: stride 2)
-  const int* Ql = (const int*)&V[1][g + 1][0] + comp;
-  const int* Qu = (const int*)&V[1][g][1] + comp;
-  const int* Qlu = (const int*)&V[1][g][0] + comp;
+  // fixed prediction term, at index lx (rows of pairs: stride 2)
+  const double* Ql = &V[1][g + 1][0].x + comp;
+  const double* Qu = &V[1][g][1].x + comp;
+  const double* Qlu = &V[1][g][0].x + comp;
   const int* Qp = (const int*)&SLP[g][0] + comp;
   // wave wv holds rows 4 wv .. 4 wv + 3, which have vertices on the
   // anti-diagonals 4 wv .. 4 wv + 18; on the others it only keeps the
@@ -575,12 +598,13 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
     // all at once (at a clamped column for the idle lanes)
     const int lc = min(max(lx, 0), TILE - 1);
     const int xs = XS[g][lc];
-    const int2 me = Vme[lc], pa = Va[lc], pb = Vb[lc];
-    const int l = Ql[2 * lc], u = Qu[2 * lc], lu = Qlu[2 * lc], pt = Qp[2 * lc];
+    const double2 me = Vme[lc], pa = Va[lc], pb = Vb[lc];
+    const double l = Ql[2 * lc], u = Qu[2 * lc], lu = Qlu[2 * lc];
+    const int pt = Qp[2 * lc];
     int e = eps;
     if (active) {
       e = xs >= 0 ? xs : eps;
-      if (xs >= 0 && (unsigned)(lx - flo) < (unsigned)(fhi - flo)) face_update(e, me, pa, pb, det2(me, pa), det2(me, pb));
+      if (xs >= 0 && (unsigned)(lx - flo) < (unsigned)(fhi - flo)) face_update(e, me, me_sign(me), pa, pb);
     }
     e = row16_min(e);
     if (active && j < 2) {
@@ -591,10 +615,11 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
         const int xt = eps >> code;
         // 3-D Lorenzo (the halo cells at the block's edges count as 0) or
         // the semi-Lagrangian prediction
-        const int pred = cls == 0 ? (lx > 0 ? l : 0) + (g > 0 ? u : 0) - (lx > 0 && g > 0 ? lu : 0) + pt : pt;
+        const int pred =
+            cls == 0 ? (int)((lx > 0 ? l : 0.0) + (g > 0 ? u : 0.0) - (lx > 0 && g > 0 ? lu : 0.0)) + pt : pt;
         int rec;
-        qc = quantize(comp ? me.y : me.x, pred, xt, &rec);
-        ((int*)&V[1][g + 1][lx + 1])[comp] = rec;
+        qc = quantize((int)(comp ? me.y : me.x), pred, xt, &rec);
+        ((double*)&V[1][g + 1][lx + 1])[comp] = (double)rec;
       }
       ((uint16_t*)&OQ[g][lx])[comp] = (uint16_t)qc;
       if (!comp) {
@@ -611,7 +636,8 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
     const int lx = tid & 15, ly = tid >> 4, x = x0 + lx, yy = y0 + ly;
     if (x < W && yy < H) {
       const size_t gv = (size_t)t * HW + (size_t)yy * W + x;
-      cur[gv] = V[1][ly + 1][lx + 1];
+      const double2 r = V[1][ly + 1][lx + 1];
+      cur[gv] = make_int2((int)r.x, (int)r.y);
       xcode[gv] = OC[ly][lx];
       qcode[gv] = OQ[ly][lx];
       if (xi_dbg) xi_dbg[gv] = OX[ly][lx];
