@@ -415,24 +415,17 @@ __device__ __forceinline__ void lower_to(int& e, double N, double D) {
 
 __device__ __forceinline__ double det2d(double2 a, double2 b) { return fma(a.x, b.y, -(a.y * b.x)); }
 
-// What the raise of Alg. 2 needs of the vertex itself: the sign of each
-// component (+1, -1 or 0) and |component| - 1.
+// What the raise of Alg. 2 needs of the vertex itself besides its value:
+// |component| - 1.
 struct MeSign {
-  double sx, sy;
   int rx, ry;
 };
-__device__ __forceinline__ MeSign me_sign(double2 me) {
-  MeSign m;
-  m.sx = me.x > 0.0 ? 1.0 : (me.x < 0.0 ? -1.0 : 0.0);
-  m.sy = me.y > 0.0 ? 1.0 : (me.y < 0.0 ? -1.0 : 0.0);
-  m.rx = (int)fabs(me.x) - 1;
-  m.ry = (int)fabs(me.y) - 1;
-  return m;
-}
+__device__ __forceinline__ MeSign me_sign(double2 me) { return MeSign{(int)fabs(me.x) - 1, (int)fabs(me.y) - 1}; }
 
 // Running minimum with the Alg. 2 bound of the face (me, n0, n1).  A
 // component's raise applies when n0 and n1 share the strict sign of the
-// vertex's own component: min(n0 s, n1 s) > 0 for that sign s.
+// vertex's own component, i.e. both products with it are positive (exact:
+// the products stay below 2^50).
 __device__ __forceinline__ void face_update(int& xi, double2 me, const MeSign& ms, double2 n0, double2 n1) {
   const double d0 = det2d(me, n0), d1 = det2d(me, n1);
   const double M = (d0 - d1) + det2d(n0, n1);
@@ -441,8 +434,8 @@ __device__ __forceinline__ void face_update(int& xi, double2 me, const MeSign& m
     xi = 0;
     return;
   }
-  const bool sx = fmin(n0.x * ms.sx, n1.x * ms.sx) > 0.0;
-  const bool sy = fmin(n0.y * ms.sy, n1.y * ms.sy) > 0.0;
+  const bool sx = fmin(n0.x * me.x, n1.x * me.x) > 0.0;
+  const bool sy = fmin(n0.y * me.y, n1.y * me.y) > 0.0;
   const int relax = max(sx ? ms.rx : -1, sy ? ms.ry : -1);
   if (relax >= xi) return;
   int e = xi;
@@ -466,11 +459,13 @@ union TileSmem {
   PhaseSmem p;
 };
 
-// One block (bx, by) of frame t with predictor class cls; cur, flags, xcode,
-// qcode and xi_dbg point at the field's own arrays.  Called by all 256
-// threads; ends with a barrier, so the shared memory may be reused at once.
+// One block (bx, by) of frame t with predictor class *clsp, or cls0 when
+// clsp is null; cur, flags, xcode, qcode and xi_dbg point at the field's
+// own arrays.  Called by all 256 threads; ends with a barrier, so the shared
+// memory may be reused at once.
 __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur, const uint8_t* __restrict__ flags,
-                                           const FieldParams& p, int t, int bx, int by, int cls,
+                                           const FieldParams& p, int t, int bx, int by, int cls0,
+                                           const uint8_t* __restrict__ clsp,
                                            uint8_t* __restrict__ xcode, uint32_t* __restrict__ qcode,
                                            int32_t* __restrict__ xi_dbg) {
   auto& V = S.V;
@@ -484,22 +479,37 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
   const size_t HW = (size_t)H * W;
   const int x0 = bx * TILE, y0 = by * TILE;
   const int eps = p.eps;
-  // this thread's vertex and its lossless flag, fetched along with the frames
   const int vx = tid & 15, vy = tid >> 4;
   const bool vin = x0 + vx < W && y0 + vy < H;
-  const bool lossless = vin ? flags[(size_t)t * HW + (size_t)(y0 + vy) * W + x0 + vx] != 0 : true;
 
   // ---- stage frames t-1, t, t+1 (block plus halo); the two corner cells
-  // that belong to blocks of the same colour are never read and not loaded
-  for (int i = tid; i < 3 * HALO * HALO; i += 256) {
-    int f = i / (HALO * HALO), r = i - f * HALO * HALO;
-    int hy = r / HALO, hx = r - hy * HALO;
-    int gx = x0 - 1 + hx, gy = y0 - 1 + hy, tt = t - 1 + f;
-    int2 v = make_int2(0, 0);
-    bool corner = (hx == HALO - 1 && hy == 0) || (hx == 0 && hy == HALO - 1);
-    if (!corner && gx >= 0 && gx < W && gy >= 0 && gy < H && tt >= 0 && tt < T)
-      v = cur[(size_t)tt * HW + (size_t)gy * W + gx];
-    V[f][hy][hx] = make_double2((double)v.x, (double)v.y);
+  // that belong to blocks of the same colour are never read and not loaded.
+  // All loads of a thread are issued before the first one is waited for.
+  constexpr int NSTAGE = 3 * HALO * HALO, KSTAGE = (NSTAGE + 255) / 256;
+  int2 sv[KSTAGE];
+  uint32_t ldm = 0;
+#pragma unroll
+  for (int k = 0; k < KSTAGE; k++) {
+    const int i = tid + 256 * k;
+    const int f = i / (HALO * HALO), r = i - f * HALO * HALO;
+    const int hy = r / HALO, hx = r - hy * HALO;
+    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, tt = t - 1 + f;
+    const bool corner = (hx == HALO - 1 && hy == 0) | (hx == 0 && hy == HALO - 1);
+    const bool ld = (i < NSTAGE) & !corner & (gx >= 0) & (gx < W) & (gy >= 0) & (gy < H) & (tt >= 0) & (tt < T);
+    ldm |= ld ? 1u << k : 0u;
+    // element 0 of the field stands in for the cells that are not loaded
+    sv[k] = cur[ld ? (size_t)tt * HW + (size_t)gy * W + gx : 0];
+  }
+  // this thread's lossless flag and the block's class (when read here), with
+  // the frame loads in flight
+  const uint8_t fl = flags[vin ? (size_t)t * HW + (size_t)(y0 + vy) * W + x0 + vx : 0];
+  const int cls = clsp ? (int)*clsp : cls0;
+  const bool lossless = !vin || fl != 0;
+#pragma unroll
+  for (int k = 0; k < KSTAGE; k++) {
+    const int i = tid + 256 * k;
+    const int2 v = (ldm >> k) & 1u ? sv[k] : make_int2(0, 0);
+    if (i < NSTAGE) (&V[0][0][0])[i] = make_double2((double)v.x, (double)v.y);
   }
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
   __syncthreads();
@@ -676,7 +686,10 @@ __device__ __forceinline__ void run_block(Smem& S, const BatchView& B, const Fie
                                           int t, int bx, int by, int mstate, int gidx) {
   int2* cur = B.cur + d.voff;
   const uint8_t* flags = B.flags + d.voff;
+  // the class is either known here or read from clsp inside the phase,
+  // after the frame loads are under way
   int cls = 0;
+  const uint8_t* clsp = nullptr;
   if (t >= 1) {
     if (p.predictor == 1) {
       cls = 1;
@@ -693,15 +706,17 @@ __device__ __forceinline__ void run_block(Smem& S, const BatchView& B, const Fie
           cls = S.m.cls;
           __syncthreads();
         } else {
-          cls = mrow[(size_t)by * p.tx + bx];
+          clsp = mrow + (size_t)by * p.tx + bx;
         }
       } else {
-        cls = mrow[(size_t)by * p.tx + bx];
+        clsp = mrow + (size_t)by * p.tx + bx;
       }
     }
   }
-  if constexpr (DECIDE) phase_tile(S.p, cur, flags, p, t, bx, by, cls, B.xcode + d.voff, B.qcode + d.voff, d.xi_dbg);
-  else phase_tile(S, cur, flags, p, t, bx, by, cls, B.xcode + d.voff, B.qcode + d.voff, d.xi_dbg);
+  if constexpr (DECIDE)
+    phase_tile(S.p, cur, flags, p, t, bx, by, cls, clsp, B.xcode + d.voff, B.qcode + d.voff, d.xi_dbg);
+  else
+    phase_tile(S, cur, flags, p, t, bx, by, cls, clsp, B.xcode + d.voff, B.qcode + d.voff, d.xi_dbg);
 }
 
 // predictor classes of frame t for every block of the first m fields of the
