@@ -83,12 +83,13 @@ struct ModesSmem {
   int64_t R[4];
   float fin[10];
   float h1[64], h2[64], lg[4];
-  int SAMP[4][128];
-  uint32_t hist[4][256];  // per class: 1024 codes, one byte each
-  int64_t T[129];         // T[h] = floor(h log2 h 2^16) for h <= 128
+  int16_t SAMP[4][128];
+  alignas(16) uint32_t hist[256];  // one class at a time: 1024 codes, one byte each
+  int T[129];          // T[h] = floor(h log2 h 2^16) for h <= 128 (< 2^26)
   int cls;
 };
 static_assert(QSYM == 4 * 256, "one histogram byte per residual code");
+static_assert(sizeof(ModesSmem) <= 9216, "sixteen one-wave blocks share a compute unit's LDS");
 
 // LDS writes of one lane become visible to the other lanes of its wave
 // (the wave's LDS operations complete in order; this keeps the compiler from
@@ -96,6 +97,17 @@ static_assert(QSYM == 4 * 256, "one histogram byte per residual code");
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Sum over the wave, every lane enabled: DPP row rotations give each lane
+// its 16-lane row's sum, then the four rows are added.
+__device__ __forceinline__ int wave_sum(int v) {
+  v += __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);  // row_ror:8
+  v += __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, true);  // row_ror:4
+  v += __builtin_amdgcn_mov_dpp(v, 0x122, 0xF, 0xF, true);  // row_ror:2
+  v += __builtin_amdgcn_mov_dpp(v, 0x121, 0xF, 0xF, true);  // row_ror:1
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+         __builtin_amdgcn_readlane(v, 48);
 }
 
 template <typename T, typename Op>
@@ -122,18 +134,32 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
   const int2* pf = cur + (size_t)(t - 1) * HW;
   const SLConst slc{p.cx, p.sx, p.cy, p.sy};
   const int eps = p.eps;
+  // all loads of the block and the table are issued before the first wait
+  int2 cv[4], pv[4];
+  uint32_t vm = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    const int v = lane + 64 * k, lx = v & 15, ly = v >> 4, x = x0 + lx, y = y0 + ly;
-    const bool valid = x < W && y < H;
-    const size_t gi = (size_t)y * W + x;
-    const int2 X = valid ? cf[gi] : make_int2(0, 0);
-    C[ly][lx] = X;
-    P[ly][lx] = valid ? pf[gi] : make_int2(0, 0);
+    const int v = lane + 64 * k, x = x0 + (v & 15), y = y0 + (v >> 4);
+    const bool valid = (x < W) & (y < H);
+    vm |= valid ? 1u << k : 0u;
+    const size_t gi = valid ? (size_t)y * W + x : 0;
+    cv[k] = cf[gi];
+    pv[k] = pf[gi];
   }
-  for (int i = lane; i < 4 * 128; i += 64) (&SAMP[0][0])[i] = -1;
-  for (int i = lane; i < 4 * 256; i += 64) (&S.hist[0][0])[i] = 0u;
-  for (int i = lane; i <= 128; i += 64) S.T[i] = tlog[i];
+  int64_t tv[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) tv[k] = tlog[min(lane + 64 * k, 128)];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int v = lane + 64 * k;
+    const bool valid = (vm >> k) & 1u;
+    C[v >> 4][v & 15] = valid ? cv[k] : make_int2(0, 0);
+    P[v >> 4][v & 15] = valid ? pv[k] : make_int2(0, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; k++)
+    if (lane + 64 * k <= 128) S.T[lane + 64 * k] = (int)tv[k];
+  for (int i = lane; i < p.K * 128; i += 64) (&SAMP[0][0])[i] = -1;
   wave_sync();
 
   // ---------------- block features (also the selector's input)
@@ -278,30 +304,32 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
   wave_sync();
   // rate score per candidate: a byte histogram of the class's 128 codes
   // (counts <= 128); the lane whose atomic add finds a code's count still 0
-  // holds its first occurrence and adds T[final count] for it
+  // holds its first occurrence and adds T[final count] for it.  Sums fit in
+  // 32 bits: T[h] < 2^26 and the first occurrences add up to at most T[128].
   for (int cls = 0; cls < p.K; cls++) {
+    reinterpret_cast<uint4*>(S.hist)[lane] = make_uint4(0u, 0u, 0u, 0u);
+    wave_sync();
     const int a0 = SAMP[cls][lane], a1 = SAMP[cls][lane + 64];
     const int s0 = 8 * (a0 & 3), s1 = 8 * (a1 & 3);
     bool f0 = false, f1 = false;
-    if (a0 > 0) f0 = ((atomicAdd(&S.hist[cls][a0 >> 2], 1u << s0) >> s0) & 0xFFu) == 0u;
-    if (a1 > 0) f1 = ((atomicAdd(&S.hist[cls][a1 >> 2], 1u << s1) >> s1) & 0xFFu) == 0u;
+    if (a0 > 0) f0 = ((atomicAdd(&S.hist[a0 >> 2], 1u << s0) >> s0) & 0xFFu) == 0u;
+    if (a1 > 0) f1 = ((atomicAdd(&S.hist[a1 >> 2], 1u << s1) >> s1) & 0xFFu) == 0u;
     wave_sync();
-    int64_t tsum = 0;
-    if (f0) tsum += S.T[(S.hist[cls][a0 >> 2] >> s0) & 0xFFu];
-    if (f1) tsum += S.T[(S.hist[cls][a1 >> 2] >> s1) & 0xFFu];
-    int64_t nvalid = (a0 > 0) + (a1 > 0), nover = (a0 == 0) + (a1 == 0);
-    auto add = [](int64_t a, int64_t b) { return a + b; };
-    tsum = wave_reduce(tsum, add);
-    nvalid = wave_reduce(nvalid, add);
-    nover = wave_reduce(nover, add);
+    int tsum = 0;
+    if (f0) tsum += S.T[(S.hist[a0 >> 2] >> s0) & 0xFFu];
+    if (f1) tsum += S.T[(S.hist[a1 >> 2] >> s1) & 0xFFu];
+    tsum = wave_sum(tsum);
+    // valid codes in the low half, unpredictable ones in the high half
+    const int cnt = wave_sum((a0 > 0) + (a1 > 0) + (((a0 == 0) + (a1 == 0)) << 16));
     if (lane == 0) {
-      const int64_t n = nvalid, L = nover;
-      const int64_t h0 = n > 0 ? floor_div64(S.T[n] - tsum, n) : 0;
-      const int64_t pen = (n + L) > 0 ? floor_div64((int64_t)16 * 65536 * L, n + L) : 0;
-      const int64_t lgK = p.K == 4 ? 2 : 1;
-      const int64_t meta = floor_div64(65536 * lgK, (int64_t)512 * p.bt);
-      S.R[cls] = h0 + pen + meta;
+      const int n = cnt & 0xFFFF, L = cnt >> 16;
+      const int h0 = n > 0 ? floor_div32(S.T[n] - tsum, n) : 0;
+      const int pen = (n + L) > 0 ? floor_div32(16 * 65536 * L, n + L) : 0;
+      const int lgK = p.K == 4 ? 2 : 1;
+      const int meta = floor_div32(65536 * lgK, 512 * p.bt);
+      S.R[cls] = (int64_t)h0 + pen + meta;
     }
+    wave_sync();
   }
   if (lane == 0) {
     int best = 1;
@@ -721,7 +749,7 @@ __device__ __forceinline__ void run_block(Smem& S, const BatchView& B, const Fie
 
 // predictor classes of frame t for every block of the first m fields of the
 // launch order; pre[j] = blocks of the fields before j
-__global__ __launch_bounds__(64) void k_modes_b(BatchView B, const long long* __restrict__ pre, int m, int t,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_modes_b(BatchView B, const long long* __restrict__ pre, int m, int t,
                                                 int gidx) {
   __shared__ ModesSmem S;
   const int j = find_field(pre, m, blockIdx.x);
