@@ -16,7 +16,10 @@ namespace cpt {
 // One wave per block: each lane prepares four vertices (v = lane + 64 k),
 // lanes 0-31 then sweep the Lorenzo anti-diagonals, and each lane writes its
 // four vertices.  With one wave per block every block of a frame is
-// resident at once.  Streams that failed a check are skipped.
+// resident at once.  Global reads come in two rounds, each with all its
+// loads in flight: the per-vertex codes and offsets with the previous frame,
+// then the residual symbols and raw words they point at.  Streams that
+// failed a check are skipped.
 __device__ __forceinline__ void rc_wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -25,9 +28,9 @@ __device__ __forceinline__ void rc_wave_sync() {
 __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, const int* __restrict__ ord,
                                                       const long long* __restrict__ pre, int m, int t,
                                                       const long long* __restrict__ mtab, DecodeBufs B) {
-  __shared__ int C[2][TILE][TILE];     // reconstructed fixed-point values (u, v)
-  __shared__ int P[2][TILE][TILE];     // previous frame, for the Lorenzo predictor
-  __shared__ int DQ[2][TILE][TILE];    // q (2 xi~ + 1) of components still to predict
+  __shared__ int C[2][TILE][TILE];       // reconstructed fixed-point values (u, v)
+  __shared__ int P[2][HALO][HALO];       // previous frame around the block
+  __shared__ int A[2][TILE][TILE];       // known value, or frame t-1 Lorenzo term plus q (2 xi~ + 1)
   __shared__ uint8_t KN[2][TILE][TILE];  // component already known (raw or semi-Lagrangian)
   const int j = find_field(pre, m, blockIdx.x);
   DecDesc& d = D[ord[j]];
@@ -44,36 +47,71 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
   const uint16_t* qs = B.qs + d.qsb;
   const uint32_t* qofs = B.qofs + d.voff;
   const uint32_t* rofs = B.rofs + d.voff;
-  const uint32_t qbase = qofs[0], rbase = rofs[0];
   const uint32_t* raw = d.sec[7];
+  const long long nq = d.nq, nraw = d.nraw;
   uint32_t* err = &d.err;
   const long long mode_base = mtab[d.mtb + t];
+  const int x0 = bx * TILE, y0 = by * TILE;
+  const int2* prevf = t > 0 ? cur + (size_t)(t - 1) * HW : cur;
+
+  // ---- round 1: codes, offsets, previous frame with a one-vertex halo
+  constexpr int NH = HALO * HALO, KH = (NH + 63) / 64;
+  uint32_t vcode[4], vqo[4], vro[4], vm = 0, hm = 0;
+  int2 hp[KH];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int v = lane + 64 * k, x = x0 + (v & 15), y = y0 + (v >> 4);
+    const bool valid = (x < W) & (y < H);
+    vm |= valid ? 1u << k : 0u;
+    const size_t gv = valid ? (size_t)t * HW + (size_t)y * W + x : 0;
+    vcode[k] = xs[gv];
+    vqo[k] = qofs[gv];
+    vro[k] = rofs[gv];
+  }
+#pragma unroll
+  for (int k = 0; k < KH; k++) {
+    const int i = lane + 64 * k, hy = i / HALO, hx = i - hy * HALO, x = x0 - 1 + hx, y = y0 - 1 + hy;
+    const bool valid = (i < NH) & (t > 0) & (x >= 0) & (x < W) & (y >= 0) & (y < H);
+    hm |= valid ? 1u << k : 0u;
+    hp[k] = prevf[valid ? (size_t)y * W + x : 0];
+  }
+  const uint32_t qbase = qofs[0], rbase = rofs[0];
   int cls = 0;
   if (t >= 1) {
     if (p.predictor == 1) cls = 1;
     else if (mode_base >= 0) cls = B.modes[d.mbase + mode_base + (long long)by * p.tx + bx];
   }
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
-  int vcode[4], vq[4];
-  uint32_t vr[4];
-  const int x0 = bx * TILE, y0 = by * TILE;
+#pragma unroll
+  for (int k = 0; k < KH; k++) {
+    const int i = lane + 64 * k;
+    if (i < NH) {
+      const int2 v = (hm >> k) & 1u ? hp[k] : make_int2(0, 0);
+      (&P[0][0][0])[i] = v.x;
+      (&P[1][0][0])[i] = v.y;
+    }
+  }
+
+  // ---- round 2: the vertex's two residual symbols and the two raw words it
+  // may use (indices clamped into the sections; unused values are ignored)
+  int vq[4];
+  uint32_t rw0[4], rw1[4];
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
-    const int x = x0 + lx, y = y0 + ly;
-    const bool valid = x < W && y < H;
-    const size_t gv = (size_t)t * HW + (size_t)y * W + x;
-    const int2 pv2 = (valid && t > 0) ? cur[gv - HW] : make_int2(0, 0);
-    P[0][ly][lx] = pv2.x;
-    P[1][ly][lx] = pv2.y;
+    const long long o = 2 * (long long)(vqo[k] - qbase), r = (long long)(vro[k] - rbase);
+    const long long oc = nq >= 2 ? min(o, nq - 2) : 0, rc = nraw >= 1 ? min(r, nraw - 1) : 0;
+    const long long rc1 = nraw >= 1 ? min(r + 1, nraw - 1) : 0;
+    const uint32_t q0 = nq >= 2 ? qs[oc] : 0u, q1 = nq >= 2 ? qs[oc + 1] : 0u;
+    rw0[k] = nraw >= 1 ? raw[rc] : 0u;
+    rw1[k] = nraw >= 1 ? raw[rc1] : 0u;
+    vq[k] = (int)(q0 | (q1 << 16));
   }
   rc_wave_sync();
-  // frame t-1 from the staged block where it covers the sample
-  const int2* prevf = t > 0 ? cur + (size_t)(t - 1) * HW : cur;
+  // frame t-1 from the staged halo where it covers the sample
   auto F = [&](int xx, int yy) {
-    const int tx_ = xx - x0, ty_ = yy - y0;
-    return (tx_ >= 0 && tx_ < TILE && ty_ >= 0 && ty_ < TILE) ? make_int2(P[0][ty_][tx_], P[1][ty_][tx_])
-                                                               : prevf[(size_t)yy * W + xx];
+    const int hx = xx - x0 + 1, hy = yy - y0 + 1;
+    return (hx >= 0 && hx < HALO && hy >= 0 && hy < HALO) ? make_int2(P[0][hy][hx], P[1][hy][hx])
+                                                          : prevf[(size_t)yy * W + xx];
   };
 
   // everything that does not depend on the block's own reconstruction
@@ -81,31 +119,28 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
   for (int k = 0; k < 4; k++) {
     const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
     const int x = x0 + lx, y = y0 + ly;
-    const bool valid = x < W && y < H;
-    const size_t gv = (size_t)t * HW + (size_t)y * W + x;
-    vcode[k] = XLOSSLESS;
-    vq[k] = 0;
-    vr[k] = 0;
-    if (!valid) continue;
-    const int code = xs[gv];
-    uint32_t r = rofs[gv] - rbase;
-    int q[2] = {0, 0}, pr[2] = {0, 0};
+    if (!((vm >> k) & 1u)) {
+      vcode[k] = XLOSSLESS;
+      continue;
+    }
+    const int code = (int)vcode[k];
+    if (code == XLOSSLESS) vq[k] = 0;
+    const int q[2] = {vq[k] & 0xFFFF, (int)((uint32_t)vq[k] >> 16)};
+    int pr[2] = {0, 0};
     int64_t w = 0;
     if (code != XLOSSLESS) {
-      size_t o = 2 * (size_t)(qofs[gv] - qbase);
-      q[0] = qs[o];
-      q[1] = qs[o + 1];
       w = 2 * (int64_t)(p.eps >> code) + 1;
       if (cls != 0) sl_predict_f(F, H, W, x, y, SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pr[0], &pr[1]);
     }
-    vcode[k] = code;
-    vq[k] = q[0] | (q[1] << 16);
-    vr[k] = r;
+    int used = 0;  // raw words taken so far by this vertex
     for (int c = 0; c < 2; c++) {
       if (code == XLOSSLESS || q[c] == 0) {
-        uint32_t b = raw[r++];
+        const uint32_t b = used ? rw1[k] : rw0[k];
+        used++;
         if (((b >> 23) & 0xFFu) == 0xFFu) atomicOr(err, 64u);
-        C[c][ly][lx] = to_fixed(__uint_as_float(b), p.k);
+        const int val = to_fixed(__uint_as_float(b), p.k);
+        C[c][ly][lx] = val;
+        A[c][ly][lx] = val;
         KN[c][ly][lx] = 1;
       } else {
         int64_t dq = (int64_t)(q[c] - QR) * w;
@@ -116,9 +151,17 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
             rv = 0;
           }
           C[c][ly][lx] = (int)rv;
+          A[c][ly][lx] = (int)rv;
           KN[c][ly][lx] = 1;
         } else {
-          DQ[c][ly][lx] = (int)dq;
+          // the part of the Lorenzo value that does not depend on this
+          // frame's reconstruction; a magnitude of 2^30 or more (corrupt
+          // stream) is saturated there, which still fails the range test
+          int64_t a = (int)dq;
+          if (t > 0)
+            a += P[c][ly + 1][lx + 1] - (lx > 0 ? P[c][ly + 1][lx] : 0) - (ly > 0 ? P[c][ly][lx + 1] : 0) +
+                 (lx > 0 && ly > 0 ? P[c][ly][lx] : 0);
+          A[c][ly][lx] = (int)max(min(a, (int64_t)1 << 30), -((int64_t)1 << 30));
           KN[c][ly][lx] = 0;
         }
       }
@@ -133,21 +176,21 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
   // together (DPP reads need active source lanes).
   if (cls == 0) {
     const int c = (lane >> 4) & 1, row = lane & 15;
-    const bool mine = lane < 2 * TILE;
-    const bool has_prev = t > 0;
+    const bool rowok = lane < 2 * TILE && y0 + row < H;
+    const int cend = min(TILE, W - x0);
     int last = 0, upl = 0;
     for (int dd = 0; dd < 2 * TILE - 1; dd++) {
       const int col = dd - row;
+      const int cc = min(max(col, 0), TILE - 1);
+      const int a = A[c][row][cc];
+      const bool kn = KN[c][row][cc] != 0;
       const int up = __builtin_amdgcn_update_dpp(0, last, 0x111, 0xF, 0xF, true);  // row_shr:1
-      if (mine && col >= 0 && col < TILE && x0 + col < W && y0 + row < H) {
-        if (KN[c][row][col]) {
-          last = C[c][row][col];
+      if (rowok && (unsigned)col < (unsigned)cend) {
+        if (kn) {
+          last = a;
         } else {
-          int sm = (col > 0 ? last : 0) + (row > 0 ? up : 0) - (col > 0 && row > 0 ? upl : 0);
-          if (has_prev)
-            sm += P[c][row][col] - (col > 0 ? P[c][row][col - 1] : 0) - (row > 0 ? P[c][row - 1][col] : 0) +
-                  (col > 0 && row > 0 ? P[c][row - 1][col - 1] : 0);
-          int64_t rv = (int64_t)sm + DQ[c][row][col];
+          const int64_t rv0 = (int64_t)(col > 0 ? last : 0) + (row > 0 ? up : 0) - (col > 0 && row > 0 ? upl : 0) + a;
+          int64_t rv = rv0;
           if (rv >= (1 << 25) || rv <= -(1 << 25)) {
             atomicOr(err, 128u);
             rv = 0;
@@ -166,19 +209,18 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
   for (int k = 0; k < 4; k++) {
     const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
     const int x = x0 + lx, y = y0 + ly;
-    if (!(x < W && y < H)) continue;
+    if (!((vm >> k) & 1u)) continue;
     const size_t gv = (size_t)t * HW + (size_t)y * W + x;
     const int u = C[0][ly][lx], vv = C[1][ly][lx];
     cur[gv] = make_int2(u, vv);
-    const uint32_t r0 = vr[k];
     float fu, fv;
     if (vcode[k] == XLOSSLESS) {
-      fu = __uint_as_float(raw[r0]);
-      fv = __uint_as_float(raw[r0 + 1]);
+      fu = __uint_as_float(rw0[k]);
+      fv = __uint_as_float(rw1[k]);
     } else {
-      uint32_t r = r0;
-      fu = (vq[k] & 0xFFFF) == 0 ? __uint_as_float(raw[r++]) : from_fixed(u, p.k);
-      fv = (vq[k] >> 16) == 0 ? __uint_as_float(raw[r]) : from_fixed(vv, p.k);
+      const bool ru = (vq[k] & 0xFFFF) == 0;
+      fu = ru ? __uint_as_float(rw0[k]) : from_fixed(u, p.k);
+      fv = ((uint32_t)vq[k] >> 16) == 0 ? __uint_as_float(ru ? rw1[k] : rw0[k]) : from_fixed(vv, p.k);
     }
     field[gv] = fu;
     field[N + gv] = fv;

@@ -638,16 +638,31 @@ __device__ void build_lut(const uint32_t* __restrict__ cb, size_t cb_words, int 
 
 // One lane per chunk.  Lanes decode DEC_STEP symbols at a time into a
 // per-wave staging buffer, then the wave writes the 64 chunks' pieces as
-// 32-bit words, each piece contiguous (16 lanes per 64-byte piece).
+// 32-bit words, each piece contiguous (16 lanes per 64-byte piece).  A
+// piece of DEC_STEP symbols consumes at most DEC_STEP * MAXLEN bits, which
+// takes at most DEC_WIN refills of the 64-bit bit buffer (one more than the
+// bits' word count covers a buffer that starts the piece empty), so before
+// each piece every lane fetches the next DEC_WIN words of its chunk into its
+// window in LDS, all loads in flight together and one wait, and the buffer
+// refills from there.
 constexpr int DEC_STEP = 32;
+constexpr int DEC_WIN = (DEC_STEP * MAXLEN + 31) / 32 + 1;
 // chunks cfirst .. cfirst + 255 of one stream (the workgroup's share)
-__device__ void decode_chunks(const uint32_t* __restrict__ lut_g, const uint32_t* __restrict__ cbits,
+__device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g, const uint32_t* __restrict__ cbits,
                               const uint32_t* __restrict__ wofs, uint32_t wbase, const uint32_t* __restrict__ bs,
                               size_t bs_words, size_t nsym_total, int alphabet, uint16_t* __restrict__ out,
                               uint32_t* __restrict__ err, size_t cfirst) {
   __shared__ uint32_t lut[1 << MAXLEN];
   __shared__ uint32_t stage[4][64][DEC_STEP / 2 + 1];  // per wave, per lane: DEC_STEP symbols
-  for (int i = threadIdx.x; i < (1 << MAXLEN); i += 256) lut[i] = lut_g[i];
+  __shared__ uint32_t win[4][64][DEC_WIN];             // per wave, per lane: the piece's words
+  {
+    constexpr int NL = (1 << MAXLEN) / 4 / 256;
+    uint4 lv[NL];
+#pragma unroll
+    for (int k = 0; k < NL; k++) lv[k] = reinterpret_cast<const uint4*>(lut_g)[threadIdx.x + 256 * k];
+#pragma unroll
+    for (int k = 0; k < NL; k++) reinterpret_cast<uint4*>(lut)[threadIdx.x + 256 * k] = lv[k];
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const size_t nch = (nsym_total + CHUNK - 1) / CHUNK;
@@ -666,33 +681,34 @@ __device__ void decode_chunks(const uint32_t* __restrict__ lut_g, const uint32_t
       live = false;
     }
   }
+  if (!live) nw = 0;
   const size_t lo = c * CHUNK;
   const size_t hi = live ? (lo + CHUNK < nsym_total ? lo + CHUNK : nsym_total) : lo;
-  // the chunk's words reach the 64-bit bit buffer through a queue of four
-  // words loaded ahead of use (only words inside the chunk are loaded)
-  uint32_t ahead[4];
-#pragma unroll
-  for (int k = 0; k < 4; k++) ahead[k] = (size_t)k < nw ? bs[w0 + k] : 0u;
+  const uint32_t* cw = bs + w0;  // the chunk's words (only the first nw are read)
+  uint32_t* mywin = win[wv][lane];
   uint64_t buf = 0;
   int have = 0;
-  size_t wi = 0;
+  uint32_t wi = 0;  // next word of the chunk to enter the bit buffer
   uint32_t consumed = 0;
   bool bad = false;
   for (int base = 0; base < CHUNK; base += DEC_STEP) {
+    // the words wi .. wi + DEC_WIN - 1 that this piece may need (0 past the
+    // chunk's end)
+    uint32_t wl[DEC_WIN];
+#pragma unroll
+    for (int k = 0; k < DEC_WIN; k++) wl[k] = nw > 0 ? cw[wi + k < nw ? wi + k : 0] : 0u;
+#pragma unroll
+    for (int k = 0; k < DEC_WIN; k++) mywin[k] = wi + k < nw ? wl[k] : 0u;
+    const uint32_t wbeg = wi;
     // decode this lane's next DEC_STEP symbols into the staging buffer
     uint32_t pair = 0;
     for (int k = 0; k < DEC_STEP; k++) {
       const size_t i = lo + base + k;
       uint32_t sym = 0;
       if (!bad && i < hi) {
-        while (have <= 32) {
-          const uint64_t nxt = ahead[0];
-          ahead[0] = ahead[1];
-          ahead[1] = ahead[2];
-          ahead[2] = ahead[3];
-          ahead[3] = wi + 4 < nw ? bs[w0 + wi + 4] : 0u;
+        if (have <= 32) {
+          buf |= (uint64_t)mywin[wi - wbeg] << (32 - have);
           wi++;
-          buf |= nxt << (32 - have);
           have += 32;
         }
         const uint32_t e = lut[(uint32_t)(buf >> (64 - MAXLEN))];
