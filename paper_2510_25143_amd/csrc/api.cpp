@@ -302,8 +302,10 @@ struct Timing {
       pool.pop_back();
       return e;
     }
+    // timing only: no system-scope fence, so a bracketed launch costs no
+    // cache writeback and invalidation of its own
     hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
+    (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     return e;
   }
   void harvest() {

@@ -466,7 +466,7 @@ __device__ __forceinline__ uint32_t fp_mask(const uint8_t (*E0)[FP_EW], const ui
 }
 
 // fpre[f]: tiles of the fields before f
-__global__ __launch_bounds__(256) void k_fieldpass_b(const FieldDesc* __restrict__ D,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fieldpass_b(const FieldDesc* __restrict__ D,
                                                      const long long* __restrict__ fpre, int n,
                                                      int2* __restrict__ cur_all, uint8_t* __restrict__ flags_all) {
   __shared__ FieldPassSmem S;
