@@ -934,15 +934,15 @@ struct DPlan {
   int n = 0, maxT = 0;
   std::vector<DecDesc> D;
   std::vector<int> ord;
-  std::vector<long long> mpre, cxpre, cqpre, dxpre, dqpre, vpre, rpre, mtab;
+  std::vector<long long> mpre, cxpre, cqpre, dxpre, dqpre, spre, rpre, mtab;
   std::vector<int> m_at;
-  long long Ntot = 0, CX = 0, CQ = 0, QS = 0, NB = 0;
+  long long Ntot = 0, CX = 0, CQ = 0, QS = 0, NB = 0, Stot = 0;
 };
 
 struct DBufs {
   DecDesc* D;
   int* ord;
-  long long *mpre, *cxpre, *cqpre, *dxpre, *dqpre, *vpre, *rpre, *mtab;
+  long long *mpre, *cxpre, *cqpre, *dxpre, *dqpre, *spre, *rpre, *mtab;
   size_t tables_bytes;
   DecodeBufs B;
 };
@@ -950,7 +950,7 @@ struct DBufs {
 cpt_status carve_dec(Arena& A, const DPlan& P, DBufs& b) {
   A.used = 0;
   const int n = P.n;
-  const size_t N = (size_t)P.Ntot, CX = (size_t)P.CX, CQ = (size_t)P.CQ;
+  const size_t N = (size_t)P.Ntot, CX = (size_t)P.CX, CQ = (size_t)P.CQ, S = (size_t)P.Stot;
   struct Item {
     void** p;
     size_t bytes;
@@ -959,18 +959,18 @@ cpt_status carve_dec(Arena& A, const DPlan& P, DBufs& b) {
       {(void**)&b.D, sizeof(DecDesc) * n},  {(void**)&b.ord, 4 * (size_t)n},
       {(void**)&b.mpre, vec_bytes(P.mpre)}, {(void**)&b.cxpre, vec_bytes(P.cxpre)},
       {(void**)&b.cqpre, vec_bytes(P.cqpre)}, {(void**)&b.dxpre, vec_bytes(P.dxpre)},
-      {(void**)&b.dqpre, vec_bytes(P.dqpre)}, {(void**)&b.vpre, vec_bytes(P.vpre)},
+      {(void**)&b.dqpre, vec_bytes(P.dqpre)}, {(void**)&b.spre, vec_bytes(P.spre)},
       {(void**)&b.rpre, vec_bytes(P.rpre)}, {(void**)&b.mtab, vec_bytes(P.mtab)},
   };
   std::vector<Item> rest = {
       {(void**)&b.B.lut, 8 * (size_t)n * (1u << MAXLEN)}, {(void**)&b.B.xw, 4 * CX + 16},
       {(void**)&b.B.xwofs, 4 * CX + 16},                  {(void**)&b.B.qw, 4 * CQ + 16},
       {(void**)&b.B.qwofs, 4 * CQ + 16},                  {(void**)&b.B.xs, 2 * N},
-      {(void**)&b.B.qs, 2 * (size_t)P.QS + 16},           {(void**)&b.B.nonll, 4 * N},
-      {(void**)&b.B.qofs, 4 * N},                         {(void**)&b.B.rcnt, 4 * N},
-      {(void**)&b.B.rofs, 4 * N},                         {(void**)&b.B.modes, (size_t)P.NB + 16},
+      {(void**)&b.B.qs, 2 * (size_t)P.QS + 16},           {(void**)&b.B.sn, 4 * S + 16},
+      {(void**)&b.B.sq, 4 * S + 16},                      {(void**)&b.B.sr, 4 * S + 16},
+      {(void**)&b.B.sro, 4 * S + 16},                     {(void**)&b.B.modes, (size_t)P.NB + 16},
       {(void**)&b.B.cur, 8 * N},
-      {(void**)&b.B.part, 4 * (scan_partials_size(std::max(N, std::max(CX, CQ))) + 16)},
+      {(void**)&b.B.part, 4 * (scan_partials_size(std::max(S, std::max(CX, CQ))) + 16)},
   };
   std::vector<size_t> offs;
   size_t t0 = 0;
@@ -1093,6 +1093,8 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
     }
     d.out = fields[i];
     d.voff = P.Ntot;
+    d.soff = P.Stot;
+    d.nseg = (long long)T * H * tx;
     d.cxb = P.CX;
     d.cqb = P.CQ;
     d.qsb = P.QS;
@@ -1107,6 +1109,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
       P.mtab.push_back(mo);
     }
     P.Ntot += N;
+    P.Stot += d.nseg;
     P.CX += nchx;
     P.CQ += nchq;
     P.QS += nq;
@@ -1118,7 +1121,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
   const int m = (int)P.D.size();
   P.n = m;
   if (m > 0) {
-    for (auto* v : {&P.mpre, &P.cxpre, &P.cqpre, &P.dxpre, &P.dqpre, &P.vpre, &P.rpre}) v->assign(m + 1, 0);
+    for (auto* v : {&P.mpre, &P.cxpre, &P.cqpre, &P.dxpre, &P.dqpre, &P.spre, &P.rpre}) v->assign(m + 1, 0);
     for (int j = 0; j < m; j++) {
       const DecDesc& d = P.D[j];
       P.mpre[j + 1] = P.mpre[j] + (d.nblk + 255) / 256;
@@ -1126,7 +1129,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
       P.cqpre[j + 1] = P.cqpre[j] + d.nchq;
       P.dxpre[j + 1] = P.dxpre[j] + (d.nchx + 255) / 256;
       P.dqpre[j + 1] = P.dqpre[j] + (d.nchq + 255) / 256;
-      P.vpre[j + 1] = P.vpre[j] + (d.N + 255) / 256;
+      P.spre[j + 1] = P.spre[j] + (d.nseg + 15) / 16;
     }
     P.ord.resize(m);
     for (int j = 0; j < m; j++) P.ord[j] = j;
@@ -1141,7 +1144,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
       while (mm > 0 && P.D[P.ord[mm - 1]].p.T <= t) mm--;
       P.m_at[t] = mm;
     }
-    for (auto v : {P.mpre.back(), P.dxpre.back(), P.dqpre.back(), P.vpre.back(), P.rpre.back()})
+    for (auto v : {P.mpre.back(), P.dxpre.back(), P.dqpre.back(), P.spre.back(), P.rpre.back()})
       if (v >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
     DBufs b;
     st = carve_dec(A, P, b);
@@ -1161,7 +1164,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
       put(b.cqpre, P.cqpre.data(), vec_bytes(P.cqpre));
       put(b.dxpre, P.dxpre.data(), vec_bytes(P.dxpre));
       put(b.dqpre, P.dqpre.data(), vec_bytes(P.dqpre));
-      put(b.vpre, P.vpre.data(), vec_bytes(P.vpre));
+      put(b.spre, P.spre.data(), vec_bytes(P.spre));
       put(b.rpre, P.rpre.data(), vec_bytes(P.rpre));
       put(b.mtab, P.mtab.data(), vec_bytes(P.mtab));
     }
@@ -1169,7 +1172,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
     launch_decode_front_b(b.D, m, b.B, b.mpre, P.mpre.back(), b.cxpre, P.CX, b.cqpre, P.CQ, s);
     {
       TimeScope ts(FAM_DECODE, (uint64_t)(P.Ntot + P.QS), s);
-      launch_decode_b(b.D, m, b.B, b.dxpre, P.dxpre.back(), b.dqpre, P.dqpre.back(), b.vpre, P.vpre.back(), P.Ntot,
+      launch_decode_b(b.D, m, b.B, b.dxpre, P.dxpre.back(), b.dqpre, P.dqpre.back(), b.spre, P.spre.back(), P.Stot,
                       P.CX, P.CQ, s);
     }
     for (int t = 0; t < P.maxT; t++) {

@@ -134,6 +134,7 @@ struct DecDesc {
   long long qsb;            // first residual symbol in the concatenated symbol array
   long long mbase, nblk;    // predictor classes: first and count
   long long mtb;            // first entry of the stream in the per-frame class-offset table
+  long long soff, nseg;     // block rows (segments): first in the concatenated segment arrays, count
   int mb;                   // bits per predictor class
   const uint32_t* sec[8];   // the stream's sections (device)
   long long secw[8];        // their lengths in words
@@ -142,11 +143,16 @@ struct DecDesc {
   int status;               // 0 ok, else a cpt_status
 };
 
+// A segment is one block row: the vertices x in [16 bx, min(16 bx + 16, W))
+// of row y of frame t, segment index (t H + y) tx + bx.  Segments follow
+// the vertex order, so per-segment prefix sums of residual-coded vertices
+// and raw words locate every vertex's symbols and raw words.
 struct DecodeBufs {
   uint32_t* lut;            // two 4096-entry tables per stream
   uint32_t *xw, *xwofs, *qw, *qwofs;  // chunk words and their prefix sums
   uint16_t *xs, *qs;        // decoded symbols
-  uint32_t *nonll, *qofs, *rcnt, *rofs;
+  uint32_t *sn, *sq;        // per segment: residual-coded vertices, their exclusive prefix
+  uint32_t *sr, *sro;       // per segment: raw words, their exclusive prefix
   uint8_t* modes;
   int2* cur;
   uint32_t* part;
@@ -156,9 +162,10 @@ struct DecodeBufs {
 void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long long* mpre, long long mblocks,
                            const long long* cxpre, long long cxtot, const long long* cqpre, long long cqtot,
                            hipStream_t s);
+// spre: workgroups of 16 segments per stream; Stot: all segments
 void launch_decode_b(DecDesc* D, int n, const DecodeBufs& B, const long long* dxpre, long long dxblocks,
-                     const long long* dqpre, long long dqblocks, const long long* vpre, long long vblocks,
-                     long long Ntot, long long CX, long long CQ, hipStream_t s);
+                     const long long* dqpre, long long dqblocks, const long long* spre, long long sblocks,
+                     long long Stot, long long CX, long long CQ, hipStream_t s);
 // k_decompress.hip: reconstruction of frame t of the first m streams of the
 // launch order (pre: blocks per stream)
 // mtab[mtb + t]: offset of frame t's predictor classes in the stream's

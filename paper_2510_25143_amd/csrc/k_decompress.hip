@@ -45,8 +45,6 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
   float* field = d.out;
   const uint16_t* xs = B.xs + d.voff;
   const uint16_t* qs = B.qs + d.qsb;
-  const uint32_t* qofs = B.qofs + d.voff;
-  const uint32_t* rofs = B.rofs + d.voff;
   const uint32_t* raw = d.sec[7];
   const long long nq = d.nq, nraw = d.nraw;
   uint32_t* err = &d.err;
@@ -54,19 +52,20 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
   const int x0 = bx * TILE, y0 = by * TILE;
   const int2* prevf = t > 0 ? cur + (size_t)(t - 1) * HW : cur;
 
-  // ---- round 1: codes, offsets, previous frame with a one-vertex halo
+  // ---- round 1: codes, the offsets of the block's rows (segments), the
+  // previous frame with a one-vertex halo
   constexpr int NH = HALO * HALO, KH = (NH + 63) / 64;
-  uint32_t vcode[4], vqo[4], vro[4], vm = 0, hm = 0;
+  uint32_t vcode[4], sqv[4], srv[4], vm = 0, hm = 0;
   int2 hp[KH];
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const int v = lane + 64 * k, x = x0 + (v & 15), y = y0 + (v >> 4);
     const bool valid = (x < W) & (y < H);
     vm |= valid ? 1u << k : 0u;
-    const size_t gv = valid ? (size_t)t * HW + (size_t)y * W + x : 0;
-    vcode[k] = xs[gv];
-    vqo[k] = qofs[gv];
-    vro[k] = rofs[gv];
+    vcode[k] = xs[valid ? (size_t)t * HW + (size_t)y * W + x : 0];
+    const long long sg = d.soff + (y < H ? ((long long)t * H + y) * p.tx + bx : 0);
+    sqv[k] = B.sq[sg];
+    srv[k] = B.sro[sg];
   }
 #pragma unroll
   for (int k = 0; k < KH; k++) {
@@ -75,7 +74,7 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
     hm |= valid ? 1u << k : 0u;
     hp[k] = prevf[valid ? (size_t)y * W + x : 0];
   }
-  const uint32_t qbase = qofs[0], rbase = rofs[0];
+  const uint32_t qbase = B.sq[d.soff], rbase = B.sro[d.soff];
   int cls = 0;
   if (t >= 1) {
     if (p.predictor == 1) cls = 1;
@@ -92,19 +91,36 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
     }
   }
 
-  // ---- round 2: the vertex's two residual symbols and the two raw words it
-  // may use (indices clamped into the sections; unused values are ignored)
+  // ---- round 2: the two residual symbols of every coded vertex, at its
+  // segment's offset plus the coded vertices before it in the row (each
+  // 16-lane DPP row holds one block row; index clamped into the stream)
   int vq[4];
-  uint32_t rw0[4], rw1[4];
+  uint32_t ridx[4], rneed = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    const long long o = 2 * (long long)(vqo[k] - qbase), r = (long long)(vro[k] - rbase);
-    const long long oc = nq >= 2 ? min(o, nq - 2) : 0, rc = nraw >= 1 ? min(r, nraw - 1) : 0;
-    const long long rc1 = nraw >= 1 ? min(r + 1, nraw - 1) : 0;
+    if (!((vm >> k) & 1u)) vcode[k] = XLOSSLESS;
+    const bool coded = ((vm >> k) & 1u) && vcode[k] != XLOSSLESS;
+    const long long o = 2 * ((long long)(sqv[k] - qbase) + row16_exclusive(coded ? 1u : 0u));
+    const long long oc = nq >= 2 ? min(max(o, 0LL), nq - 2) : 0;
     const uint32_t q0 = nq >= 2 ? qs[oc] : 0u, q1 = nq >= 2 ? qs[oc + 1] : 0u;
-    rw0[k] = nraw >= 1 ? raw[rc] : 0u;
-    rw1[k] = nraw >= 1 ? raw[rc1] : 0u;
-    vq[k] = (int)(q0 | (q1 << 16));
+    vq[k] = coded ? (int)(q0 | (q1 << 16)) : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const bool valid = (vm >> k) & 1u;
+    const uint32_t r = !valid ? 0u : vcode[k] == XLOSSLESS ? 2u : ((vq[k] & 0xFFFF) == 0) + (((uint32_t)vq[k] >> 16) == 0);
+    ridx[k] = (srv[k] - rbase) + row16_exclusive(r);
+    rneed |= r;
+  }
+  // ---- round 3 (only where the block has raw words): the two raw words a
+  // vertex may use
+  uint32_t rw0[4] = {0u, 0u, 0u, 0u}, rw1[4] = {0u, 0u, 0u, 0u};
+  if (__builtin_amdgcn_readfirstlane(__ballot(rneed != 0) != 0ull ? 1 : 0) && nraw >= 1) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      rw0[k] = raw[min((long long)ridx[k], nraw - 1)];
+      rw1[k] = raw[min((long long)ridx[k] + 1, nraw - 1)];
+    }
   }
   rc_wave_sync();
   // frame t-1 from the staged halo where it covers the sample

@@ -801,54 +801,66 @@ __global__ __launch_bounds__(256) void k_decode_b(DecDesc* __restrict__ D, const
                 RESID ? QSYM : XSYM, out + (RESID ? (size_t)d.qsb : (size_t)d.voff), &d.err, cfirst);
 }
 
-struct VPosD {
+// Lane (segment, column) of a segment workgroup: 16 segments of 256 threads;
+// g is the lane's vertex, valid when it exists.
+struct SegPos {
   int f;
-  size_t i;
-  bool valid;
+  long long ls;  // segment within the stream
+  size_t g;
+  bool live, valid;
 };
-__device__ __forceinline__ VPosD vpos_d(const DecDesc* __restrict__ D, const long long* __restrict__ vpre, int n) {
-  VPosD v;
-  v.f = find_field(vpre, n, blockIdx.x);
-  v.i = (size_t)((long long)blockIdx.x - vpre[v.f]) * 256 + threadIdx.x;
-  v.valid = v.i < (size_t)D[v.f].N;
-  return v;
+__device__ __forceinline__ SegPos seg_pos(const DecDesc* __restrict__ D, const long long* __restrict__ spre, int n) {
+  SegPos q;
+  q.f = find_field(spre, n, blockIdx.x);
+  const DecDesc& d = D[q.f];
+  q.ls = ((long long)blockIdx.x - spre[q.f]) * 16 + (threadIdx.x >> 4);
+  q.live = q.ls < d.nseg;
+  const int tx = d.p.tx, H = d.p.H, W = d.p.W;
+  const long long ls = q.live ? q.ls : 0;
+  const long long ty = ls / tx;
+  const int bx = (int)(ls - ty * tx), y = (int)(ty % H), t = (int)(ty / H);
+  const int x = 16 * bx + (int)(threadIdx.x & 15);
+  q.valid = q.live && x < W;
+  q.g = q.valid ? ((size_t)t * H + y) * W + x : 0;
+  return q;
 }
 
-__global__ __launch_bounds__(256) void k_dec_nonll_b(const DecDesc* __restrict__ D, const long long* __restrict__ vpre,
+// residual-coded vertices per segment; a bound code above 24 is an error
+__global__ __launch_bounds__(256) void k_seg_nonll_b(DecDesc* __restrict__ D, const long long* __restrict__ spre,
                                                      int n, const uint16_t* __restrict__ xs,
-                                                     uint32_t* __restrict__ nonll) {
-  const VPosD v = vpos_d(D, vpre, n);
-  if (!v.valid) return;
-  const size_t g = (size_t)D[v.f].voff + v.i;
-  nonll[g] = xs[g] != XLOSSLESS ? 1u : 0u;
+                                                     uint32_t* __restrict__ sn) {
+  const SegPos q = seg_pos(D, spre, n);
+  DecDesc& d = D[q.f];
+  const uint32_t c = xs[d.voff + q.g];
+  if (q.valid && c > XLOSSLESS) atomicOr(&d.err, 16u);
+  const uint32_t tot = row16_sum(q.valid && c < XLOSSLESS ? 1u : 0u);
+  if (q.live && (threadIdx.x & 15) == 0) sn[d.soff + q.ls] = tot;
 }
 
-// raw values per vertex; a bound code above 24, a residual position past
-// the stream's symbols or a bound too small for a code is an error
-__global__ __launch_bounds__(256) void k_dec_counts_b(DecDesc* __restrict__ D, const long long* __restrict__ vpre,
-                                                      int n, const uint16_t* __restrict__ xs,
-                                                      const uint16_t* __restrict__ qs,
-                                                      const uint32_t* __restrict__ qofs, uint32_t* __restrict__ rcnt) {
-  const VPosD v = vpos_d(D, vpre, n);
-  if (!v.valid) return;
-  DecDesc& d = D[v.f];
-  const size_t g = (size_t)d.voff + v.i;
-  const uint32_t c = xs[g];
+// raw words per segment (two for a lossless vertex, one per unpredictable
+// component); a residual position past the stream's symbols or a bound too
+// small for its code is an error
+__global__ __launch_bounds__(256) void k_seg_raw_b(DecDesc* __restrict__ D, const long long* __restrict__ spre, int n,
+                                                   const uint16_t* __restrict__ xs, const uint16_t* __restrict__ qs,
+                                                   const uint32_t* __restrict__ sq, uint32_t* __restrict__ sr) {
+  const SegPos q = seg_pos(D, spre, n);
+  DecDesc& d = D[q.f];
+  const uint32_t c = xs[d.voff + q.g];
+  const bool coded = q.valid && c < XLOSSLESS;
+  const uint32_t before = row16_exclusive(coded ? 1u : 0u);
+  const long long o = 2 * ((long long)(sq[d.soff + (q.live ? q.ls : 0)] - sq[d.soff]) + before);
   uint32_t r = 0;
-  if (c > XLOSSLESS) {
-    atomicOr(&d.err, 16u);
-  } else if (c == XLOSSLESS) {
-    r = 2;
-  } else {
-    const size_t o = 2 * (size_t)(qofs[g] - qofs[d.voff]);
-    if ((d.p.eps >> c) < 1 || o + 2 > (size_t)d.nq) {
+  if (q.valid && c == XLOSSLESS) r = 2;
+  if (coded) {
+    if ((d.p.eps >> c) < 1 || o + 2 > d.nq) {
       atomicOr(&d.err, 32u);
     } else {
-      const uint16_t* q = qs + d.qsb;
-      r = (q[o] == 0) + (q[o + 1] == 0);
+      const uint16_t* qq = qs + d.qsb;
+      r = (qq[o] == 0) + (qq[o + 1] == 0);
     }
   }
-  rcnt[g] = r;
+  const uint32_t tot = row16_sum(r);
+  if (q.live && (threadIdx.x & 15) == 0) sr[d.soff + q.ls] = tot;
 }
 
 // the stream's totals against its header: bitstream words, residual
@@ -856,9 +868,9 @@ __global__ __launch_bounds__(256) void k_dec_counts_b(DecDesc* __restrict__ D, c
 // that pass, so that every offset it follows stays inside the stream.
 __global__ void k_dec_check_b(DecDesc* __restrict__ D, int n, const uint32_t* __restrict__ xw,
                               const uint32_t* __restrict__ xwofs, const uint32_t* __restrict__ qw,
-                              const uint32_t* __restrict__ qwofs, const uint32_t* __restrict__ nonll,
-                              const uint32_t* __restrict__ qofs, const uint32_t* __restrict__ rcnt,
-                              const uint32_t* __restrict__ rofs) {
+                              const uint32_t* __restrict__ qwofs, const uint32_t* __restrict__ sn,
+                              const uint32_t* __restrict__ sq, const uint32_t* __restrict__ sr,
+                              const uint32_t* __restrict__ sro) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= n) return;
   DecDesc& d = D[f];
@@ -871,9 +883,9 @@ __global__ void k_dec_check_b(DecDesc* __restrict__ D, int n, const uint32_t* __
     const size_t qa = d.cqb, qz = d.cqb + d.nchq - 1;
     words_q = qwofs[qz] + qw[qz] - qwofs[qa];
   }
-  const size_t a = d.voff, z = d.voff + d.N - 1;
-  const uint32_t nl = qofs[z] + nonll[z] - qofs[a];
-  const uint32_t nr = rofs[z] + rcnt[z] - rofs[a];
+  const size_t a = d.soff, z = d.soff + d.nseg - 1;
+  const uint32_t nl = sq[z] + sn[z] - sq[a];
+  const uint32_t nr = sro[z] + sr[z] - sro[a];
   if ((long long)words_x != d.secw[3] || (long long)words_q != d.secw[6]) e |= 512u;
   if (2 * (long long)nl != d.nq || (long long)nr != d.nraw) e |= 1024u;
   d.err = e;
@@ -939,17 +951,16 @@ void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long lo
 }
 
 void launch_decode_b(DecDesc* D, int n, const DecodeBufs& B, const long long* dxpre, long long dxblocks,
-                     const long long* dqpre, long long dqblocks, const long long* vpre, long long vblocks,
-                     long long Ntot, long long CX, long long CQ, hipStream_t s) {
+                     const long long* dqpre, long long dqblocks, const long long* spre, long long sblocks,
+                     long long Stot, long long CX, long long CQ, hipStream_t s) {
   if (dxblocks > 0) k_decode_b<false><<<(unsigned)dxblocks, 256, 0, s>>>(D, dxpre, n, B.lut, B.xwofs, B.xs);
   if (dqblocks > 0) k_decode_b<true><<<(unsigned)dqblocks, 256, 0, s>>>(D, dqpre, n, B.lut, B.qwofs, B.qs);
-  if (vblocks <= 0) return;
-  k_dec_nonll_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xs, B.nonll);
-  launch_scan(B.nonll, (size_t)Ntot, B.qofs, B.part + 4, B.part + 2, s);
-  k_dec_counts_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xs, B.qs, B.qofs, B.rcnt);
-  launch_scan(B.rcnt, (size_t)Ntot, B.rofs, B.part + 4, B.part + 3, s);
-  k_dec_check_b<<<nblk((size_t)n, 64), 64, 0, s>>>(D, n, B.xw, B.xwofs, B.qw, B.qwofs, B.nonll, B.qofs, B.rcnt,
-                                                   B.rofs);
+  if (sblocks <= 0) return;
+  k_seg_nonll_b<<<(unsigned)sblocks, 256, 0, s>>>(D, spre, n, B.xs, B.sn);
+  launch_scan(B.sn, (size_t)Stot, B.sq, B.part + 4, B.part + 2, s);
+  k_seg_raw_b<<<(unsigned)sblocks, 256, 0, s>>>(D, spre, n, B.xs, B.qs, B.sq, B.sr);
+  launch_scan(B.sr, (size_t)Stot, B.sro, B.part + 4, B.part + 3, s);
+  k_dec_check_b<<<nblk((size_t)n, 64), 64, 0, s>>>(D, n, B.xw, B.xwofs, B.qw, B.qwofs, B.sn, B.sq, B.sr, B.sro);
 }
 
 }  // namespace cpt
