@@ -375,7 +375,7 @@ struct Plan {
   std::vector<long long> mpre, ppre;                      // launch order
   std::vector<int> m_at, mstate_at, gidx_at;              // per frame
   std::vector<uint64_t> hw_at, cv_at;                     // vertices per frame / per phase
-  long long Ntot = 0, CX = 0, CQ = 0, NB = 0;
+  long long Ntot = 0, CX = 0, CQ = 0, NB = 0, Rtot = 0;
   std::string key;
   // persistent schedule
   int group = 0;
@@ -431,6 +431,7 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
     d.ndec = K > 1 ? decided_before(G, bt, T) : 0;
     d.N = N;
     d.voff = P.Ntot;
+    d.ro = P.Rtot;
     d.cxb = P.CX;
     d.cqb = P.CQ;
     d.mbase = P.NB;
@@ -446,6 +447,7 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
     d.dt_dy = opt.dt_dy;
     const long long ncq = (2 * N + CHUNK - 1) / CHUNK;
     P.Ntot += N;
+    P.Rtot += (N + 15) / 16;
     P.CX += d.nchx;
     P.CQ += ncq;
     P.NB += nblk;
@@ -559,7 +561,7 @@ size_t vec_bytes(const std::vector<T>& v) {
 cpt_status carve_batch(Arena& A, const Plan& P, BatchBufs& b) {
   A.used = 0;
   const int n = P.n;
-  const size_t N = (size_t)P.Ntot, CX = (size_t)P.CX, CQ = (size_t)P.CQ;
+  const size_t N = (size_t)P.Ntot, CX = (size_t)P.CX, CQ = (size_t)P.CQ, R = (size_t)P.Rtot;
   struct Item {
     void** p;
     size_t bytes;
@@ -578,8 +580,8 @@ cpt_status carve_batch(Arena& A, const Plan& P, BatchBufs& b) {
       {(void**)&b.range, 16 * (size_t)n},       {(void**)&b.cur, 8 * N},
       {(void**)&b.flags, N},                    {(void**)&b.xcode, N},
       {(void**)&b.modes, (size_t)P.NB + 1},     {(void**)&b.qcode, 4 * N},
-      {(void**)&b.E.nonll, 4 * N},              {(void**)&b.E.qofs, 4 * N},
-      {(void**)&b.E.rcnt, 4 * N},               {(void**)&b.E.rofs, 4 * N},
+      {(void**)&b.E.sn, 4 * R + 16},            {(void**)&b.E.sq, 4 * R + 16},
+      {(void**)&b.E.sr, 4 * R + 16},            {(void**)&b.E.sro, 4 * R + 16},
       {(void**)&b.E.qsym, 2 * CQ * CHUNK},      {(void**)&b.E.xbits, 4 * CX},
       {(void**)&b.E.xwords, 4 * CX},            {(void**)&b.E.xwofs, 4 * CX},
       {(void**)&b.E.qbits, 4 * CQ},             {(void**)&b.E.qwords, 4 * CQ},
@@ -679,7 +681,7 @@ void enqueue_compress(const Plan& P, const BatchBufs& b, const ExecChoice& ex, c
     }
   }
   // lossless_comp of Alg. 3: Huffman codes of both code streams, raw values
-  launch_codes_b(b.D, n, B, b.E, b.hpre, P.hpre.back(), b.vpre, P.vpre.back(), P.Ntot, s);
+  launch_codes_b(b.D, n, B, b.E, b.hpre, P.hpre.back(), b.vpre, P.vpre.back(), P.Rtot, s);
   launch_chunks_b(b.D, n, B, b.E, b.cxpre, P.CX, b.cqpre, P.CQ, s);
   {
     TimeScope ts(FAM_ENCODE, (uint64_t)P.Ntot, s);

@@ -31,6 +31,7 @@ struct FieldDesc {
   int ndec;              // decided predictor groups
   long long N;           // vertices
   long long voff;        // first vertex in the concatenated vertex arrays
+  long long ro;          // first run of 16 vertices in the concatenated run arrays
   long long cxb;         // first bound-code chunk in the concatenated chunk arrays
   long long cqb;         // first residual-code chunk (room for 2N symbols)
   long long mbase;       // first predictor block in the concatenated mode array
@@ -108,13 +109,15 @@ constexpr long long HIST_SPAN_VERTICES = 256 * 16;
 struct EntropyBufs {
   uint32_t *xhist, *qhist, *xcb, *qcb, *used;
   HuffTables *xt, *qt;
-  uint32_t *nonll, *qofs, *rcnt, *rofs;
+  // per run of 16 consecutive vertices of a field: residual-coded vertices
+  // and their exclusive prefix, raw words and their exclusive prefix
+  uint32_t *sn, *sq, *sr, *sro;
   uint16_t* qsym;
   uint32_t *xbits, *xwords, *xwofs, *qbits, *qwords, *qwofs;
   uint32_t* part;
 };
 void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* hpre,
-                    long long hblocks, const long long* vpre, long long vblocks, long long Ntot, hipStream_t s);
+                    long long hblocks, const long long* vpre, long long vblocks, long long Rtot, hipStream_t s);
 void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
                      long long cxtot, const long long* cqpre, long long cqtot, hipStream_t s);
 void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,

@@ -215,8 +215,8 @@ struct RunAdd {
 __global__ __launch_bounds__(256) void k_hist_b(const FieldDesc* __restrict__ D, const long long* __restrict__ hpre,
                                                 int n, const uint8_t* __restrict__ xcode,
                                                 const uint32_t* __restrict__ qcode, uint32_t* __restrict__ xhist,
-                                                uint32_t* __restrict__ qhist, uint32_t* __restrict__ rcnt,
-                                                uint32_t* __restrict__ nonll) {
+                                                uint32_t* __restrict__ qhist, uint32_t* __restrict__ sr,
+                                                uint32_t* __restrict__ sn) {
   __shared__ uint32_t hx[32];
   __shared__ uint32_t hq[QSYM];
   const int f = find_field(hpre, n, blockIdx.x);
@@ -225,9 +225,9 @@ __global__ __launch_bounds__(256) void k_hist_b(const FieldDesc* __restrict__ D,
   const size_t N = (size_t)d.N, hi = lo + HIST_SPAN < N ? lo + HIST_SPAN : N;
   const size_t base = (size_t)d.voff;
   if (d.status) {
-    for (size_t i = lo + threadIdx.x; i < hi; i += 256) {
-      rcnt[base + i] = 0;
-      nonll[base + i] = 0;
+    for (size_t i = lo + 16 * threadIdx.x; i < hi; i += 16 * 256) {
+      sr[d.ro + i / 16] = 0;
+      sn[d.ro + i / 16] = 0;
     }
     return;
   }
@@ -261,42 +261,28 @@ __global__ __launch_bounds__(256) void k_hist_b(const FieldDesc* __restrict__ D,
       qc[j] = in ? qcode[base + i0 + j] : 0u;
     }
   }
-  uint32_t rc[16], nl[16];
+  uint32_t rsum = 0, nsum = 0;
 #pragma unroll
   for (int j = 0; j < 16; j++) {
     const uint32_t c = xc[j];
-    rc[j] = 0;
-    nl[j] = 0;
     if (c == 0xFF) continue;  // past the end
     rx.add(hx, c);
     if (c == XLOSSLESS) {
-      rc[j] = 2;
+      rsum += 2;
     } else {
       const uint32_t u = qc[j] & 0xFFFFu, v = qc[j] >> 16;
       ru.add(hq, u);
       rv.add(hq, v);
-      rc[j] = (u == 0) + (v == 0);
-      nl[j] = 1;
+      rsum += (u == 0) + (v == 0);
+      nsum += 1;
     }
   }
   rx.flush(hx);
   ru.flush(hq);
   rv.flush(hq);
-  if (full) {
-    uint4* r4 = (uint4*)(rcnt + base + i0);
-    uint4* n4 = (uint4*)(nonll + base + i0);
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      r4[j] = make_uint4(rc[4 * j], rc[4 * j + 1], rc[4 * j + 2], rc[4 * j + 3]);
-      n4[j] = make_uint4(nl[4 * j], nl[4 * j + 1], nl[4 * j + 2], nl[4 * j + 3]);
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 16; j++)
-      if (i0 + j < hi) {
-        rcnt[base + i0 + j] = rc[j];
-        nonll[base + i0 + j] = nl[j];
-      }
+  if (i0 < hi) {
+    sr[d.ro + i0 / 16] = rsum;
+    sn[d.ro + i0 / 16] = nsum;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < QSYM; i += 256)
@@ -329,26 +315,30 @@ __device__ __forceinline__ VPos vpos(const FieldDesc* __restrict__ D, const long
   return v;
 }
 
+// Every residual-coded vertex puts its two symbols at its run's offset
+// plus the coded vertices before it in the run (a run of 16 vertices is one
+// 16-lane DPP row of the workgroup).
 __global__ __launch_bounds__(256) void k_gather_q_b(const FieldDesc* __restrict__ D,
                                                     const long long* __restrict__ vpre, int n,
                                                     const uint8_t* __restrict__ xcode,
                                                     const uint32_t* __restrict__ qcode,
-                                                    const uint32_t* __restrict__ qofs, uint16_t* __restrict__ qsym) {
+                                                    const uint32_t* __restrict__ sq, uint16_t* __restrict__ qsym) {
   const VPos v = vpos(D, vpre, n);
-  if (!v.valid) return;
   const FieldDesc& d = D[v.f];
-  const size_t g = d.voff + v.i;
-  if (d.status || xcode[g] == XLOSSLESS) return;
+  const size_t g = d.voff + (v.valid ? v.i : 0);
+  const bool coded = v.valid && !d.status && xcode[g] != XLOSSLESS;
+  const uint32_t before = row16_exclusive(coded ? 1u : 0u);
+  if (!coded) return;
   const uint32_t q = qcode[g];
-  const size_t o = (size_t)d.cqb * CHUNK + 2 * (size_t)(qofs[g] - qofs[d.voff]);
+  const size_t o = (size_t)d.cqb * CHUNK + 2 * ((size_t)(sq[d.ro + v.i / 16] - sq[d.ro]) + before);
   qsym[o] = (uint16_t)(q & 0xFFFFu);
   qsym[o + 1] = (uint16_t)(q >> 16);
 }
 
 // residual symbols and raw values per field, from the prefix sums
-__global__ void k_totals_b(FieldDesc* __restrict__ D, int n, const uint32_t* __restrict__ nonll,
-                           const uint32_t* __restrict__ qofs, const uint32_t* __restrict__ rcnt,
-                           const uint32_t* __restrict__ rofs) {
+__global__ void k_totals_b(FieldDesc* __restrict__ D, int n, const uint32_t* __restrict__ sn,
+                           const uint32_t* __restrict__ sq, const uint32_t* __restrict__ sr,
+                           const uint32_t* __restrict__ sro) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= n) return;
   FieldDesc& d = D[f];
@@ -356,9 +346,9 @@ __global__ void k_totals_b(FieldDesc* __restrict__ D, int n, const uint32_t* __r
     d.nq = d.nraw = d.nchq = 0;
     return;
   }
-  const size_t a = d.voff, z = d.voff + d.N - 1;
-  const uint32_t nl = qofs[z] + nonll[z] - qofs[a];
-  const uint32_t nr = rofs[z] + rcnt[z] - rofs[a];
+  const size_t a = d.ro, z = d.ro + (d.N + 15) / 16 - 1;
+  const uint32_t nl = sq[z] + sn[z] - sq[a];
+  const uint32_t nr = sro[z] + sr[z] - sro[a];
   d.nq = 2 * (long long)nl;
   d.nraw = nr;
   d.nchq = (d.nq + CHUNK - 1) / CHUNK;
@@ -557,22 +547,27 @@ __global__ __launch_bounds__(256) void k_sections_b(const FieldDesc* __restrict_
   for (size_t w = first; w < (size_t)d.nchq; w += step) out[d.off[5] / 4 + w] = qbits[d.cqb + w];
 }
 
+// raw words: two per lossless vertex, one per unpredictable component, at
+// the run's offset plus the raw words of the vertices before it in the run
 __global__ __launch_bounds__(256) void k_raw_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
                                                int n, const uint8_t* __restrict__ xcode,
-                                               const uint32_t* __restrict__ qcode, const uint32_t* __restrict__ rofs) {
+                                               const uint32_t* __restrict__ qcode, const uint32_t* __restrict__ sro) {
   const VPos v = vpos(D, vpre, n);
-  if (!v.valid) return;
   const FieldDesc& d = D[v.f];
-  if (d.status) return;
-  const size_t g = d.voff + v.i, N = (size_t)d.N;
-  uint32_t o = rofs[g] - rofs[d.voff];
+  const bool live = v.valid && !d.status;
+  const size_t i = live ? v.i : 0, g = d.voff + i, N = (size_t)d.N;
+  const bool ll = xcode[g] == XLOSSLESS;
+  const uint32_t q = qcode[g];
+  const uint32_t cnt = !live ? 0u : ll ? 2u : ((q & 0xFFFFu) == 0) + ((q >> 16) == 0);
+  const uint32_t before = row16_exclusive(cnt);
+  if (cnt == 0) return;
+  uint32_t o = (sro[d.ro + i / 16] - sro[d.ro]) + before;
   uint32_t* out = (uint32_t*)(d.out + d.off[7]);
-  const uint32_t bu = __float_as_uint(d.field[v.i]), bv = __float_as_uint(d.field[N + v.i]);
-  if (xcode[g] == XLOSSLESS) {
+  const uint32_t bu = __float_as_uint(d.field[i]), bv = __float_as_uint(d.field[N + i]);
+  if (ll) {
     out[o] = bu;
     out[o + 1] = bv;
   } else {
-    const uint32_t q = qcode[g];
     if ((q & 0xFFFFu) == 0) out[o++] = bu;
     if ((q >> 16) == 0) out[o] = bv;
   }
@@ -899,18 +894,18 @@ void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
   if (n) k_zero<<<nblk(n), 256, 0, s>>>(p, n);
 }
 void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* hpre,
-                    long long hblocks, const long long* vpre, long long vblocks, long long Ntot, hipStream_t s) {
+                    long long hblocks, const long long* vpre, long long vblocks, long long Rtot, hipStream_t s) {
   launch_zero_u32(E.xhist, 32 * (size_t)n, s);
   launch_zero_u32(E.qhist, QSYM * (size_t)n, s);
   if (hblocks > 0)
-    k_hist_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.xhist, E.qhist, E.rcnt, E.nonll);
+    k_hist_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.xhist, E.qhist, E.sr, E.sn);
   k_codebooks_b<<<2 * n, CB_THREADS, 0, s>>>(D, E.xhist, E.qhist, E.xt, E.qt, E.xcb, E.qcb, E.used);
   if (vblocks <= 0) return;
   uint32_t* tot = E.part;  // two scratch words ahead of the scan partials
-  launch_scan(E.nonll, (size_t)Ntot, E.qofs, E.part + 4, tot, s);
-  launch_scan(E.rcnt, (size_t)Ntot, E.rofs, E.part + 4, tot + 1, s);
-  k_totals_b<<<nblk(n, 64), 64, 0, s>>>(D, n, E.nonll, E.qofs, E.rcnt, E.rofs);
-  k_gather_q_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.qofs, E.qsym);
+  launch_scan(E.sn, (size_t)Rtot, E.sq, E.part + 4, tot, s);
+  launch_scan(E.sr, (size_t)Rtot, E.sro, E.part + 4, tot + 1, s);
+  k_totals_b<<<nblk(n, 64), 64, 0, s>>>(D, n, E.sn, E.sq, E.sr, E.sro);
+  k_gather_q_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.sq, E.qsym);
 }
 
 void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
@@ -933,7 +928,7 @@ void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBuf
   k_sections_b<<<dim3(n, 16), 256, 0, s>>>(D, B.modes, E.xcb, E.qcb, E.used, E.xbits, E.qbits);
   if (cxtot > 0) k_encode_b<false><<<(unsigned)cxtot, 256, 0, s>>>(D, cxpre, n, B.xcode, E.qsym, E.xt, E.xwofs);
   if (cqtot > 0) k_encode_b<true><<<(unsigned)cqtot, 256, 0, s>>>(D, cqpre, n, B.xcode, E.qsym, E.qt, E.qwofs);
-  if (vblocks > 0) k_raw_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.rofs);
+  if (vblocks > 0) k_raw_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.sro);
 }
 void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long long* mpre, long long mblocks,
                            const long long* cxpre, long long cxtot, const long long* cqpre, long long cqtot,
