@@ -81,11 +81,16 @@ struct ModesSmem {
   int2 C[TILE][TILE];
   int2 P[TILE][TILE];
   int64_t R[4];
-  float fin[10];
-  float h1[64], h2[64], lg[4];
+  union {
+    struct {  // features and selector activations
+      float fin[10];
+      float h1[64], h2[64], lg[4];
+    };
+    int2 PT[TILE][TILE];             // Lorenzo trial: frame t-1 part of each prediction
+    alignas(16) uint32_t hist[256];  // rate: one class at a time, 1024 codes, one byte each
+  };
   int16_t SAMP[4][128];
-  alignas(16) uint32_t hist[256];  // one class at a time: 1024 codes, one byte each
-  int T[129];          // T[h] = floor(h log2 h 2^16) for h <= 128 (< 2^26)
+  int T[129];  // T[h] = floor(h log2 h 2^16) for h <= 128 (< 2^26)
   int cls;
 };
 static_assert(QSYM == 4 * 256, "one histogram byte per residual code");
@@ -259,27 +264,35 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
   // stride-2 subgrid go to SAMP[class][0..127] (slot 2 i + component of
   // subgrid point i; -1 when absent).
   {
+    // the frame t-1 part of every vertex's prediction first (tile-local)
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
+      const int2 z = make_int2(0, 0);
+      const int2 pc = P[ly][lx], pl = lx > 0 ? P[ly][lx - 1] : z, pu = ly > 0 ? P[ly - 1][lx] : z;
+      const int2 plu = (lx > 0 && ly > 0) ? P[ly - 1][lx - 1] : z;
+      S.PT[ly][lx] = make_int2(pc.x - pl.x - pu.x + plu.x, pc.y - pl.y - pu.y + plu.y);
+    }
+    wave_sync();
     // A lane keeps its own last reconstruction (the left neighbour of its
     // next vertex); the row above arrives from the previous lane of the same
     // 16-lane DPP row by a row shift of that lane's last value.  All 64 lanes
     // step together (DPP reads need active source lanes); lanes 32-63 have
     // no vertices.
     const int c = (lane >> 4) & 1, row = lane & 15;
-    const bool mine = lane < 2 * TILE;
+    const bool rowok = lane < 2 * TILE && y0 + row < H;
+    const int cend = min(TILE, W - x0);
+    const int* PTc = &S.PT[row][0].x + c;
+    const int* Cc = &C[row][0].x + c;
     int last = 0, upl = 0;
     for (int d = 0; d < 2 * TILE - 1; d++) {
-      const int col = d - row;
+      const int col = d - row, cc = min(max(col, 0), TILE - 1);
+      const int pt = PTc[2 * cc], xv = Cc[2 * cc];
       const int up = __builtin_amdgcn_update_dpp(0, last, 0x111, 0xF, 0xF, true);  // row_shr:1
-      if (mine && col >= 0 && col < TILE && x0 + col < W && y0 + row < H) {
-        int sm = (col > 0 ? last : 0) + (row > 0 ? up : 0) - (col > 0 && row > 0 ? upl : 0);
-        const int2 pc = P[row][col];
-        const int2 pl = col > 0 ? P[row][col - 1] : make_int2(0, 0);
-        const int2 pu = row > 0 ? P[row - 1][col] : make_int2(0, 0);
-        const int2 plu = (col > 0 && row > 0) ? P[row - 1][col - 1] : make_int2(0, 0);
-        sm += c ? (pc.y - pl.y - pu.y + plu.y) : (pc.x - pl.x - pu.x + plu.x);
-        const int2 xv = C[row][col];
+      if (rowok && (unsigned)col < (unsigned)cend) {
+        const int sm = (col > 0 ? last : 0) + (row > 0 ? up : 0) - (col > 0 && row > 0 ? upl : 0) + pt;
         int rec;
-        const int q = quantize(c ? xv.y : xv.x, sm, eps, &rec);
+        const int q = quantize(xv, sm, eps, &rec);
         last = rec;
         if (((row | col) & 1) == 0) SAMP[0][2 * ((row >> 1) * 8 + (col >> 1)) + c] = q;
       }
