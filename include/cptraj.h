@@ -63,8 +63,9 @@ typedef struct {
   int32_t mode_bt;        /* frames per predictor block (>= 1, default 1) */
   double dt_dx, dt_dy;    /* time step over grid spacing for the
                              semi-Lagrangian backtrace (default 1.0) */
-  const uint16_t* selector_w; /* device, bf16 selector weights (5124 values)
-                                 when predictor == CPT_PRED_LEARNED */
+  const uint16_t* selector_w; /* device, bf16 selector weights (5124 values,
+                                 16-byte aligned, else CPT_EINVAL) when
+                                 predictor == CPT_PRED_LEARNED */
 } cpt_options;
 
 /* Parameters stored in a stream's header. */

@@ -131,6 +131,8 @@ def _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w):
             raise TypeError("selector_w must be a CUDA bf16/int16 tensor of %d values" % SELECTOR_PARAMS)
         if selector_w.numel() != SELECTOR_PARAMS:
             raise ValueError("selector_w must hold %d values" % SELECTOR_PARAMS)
+        if not selector_w.is_contiguous() or selector_w.data_ptr() % 16:
+            raise ValueError("selector_w must be a contiguous, 16-byte aligned tensor")
         o.selector_w = selector_w.data_ptr()
     return o
 

@@ -394,6 +394,8 @@ cpt_status check_options(const cpt_options* opt_in, double eb, cpt_options* opt)
   if (opt->mode_bt < 1 || opt->mode_bt > 1024) return fail(CPT_EINVAL, "mode_bt must be in 1..1024");
   if (opt->predictor == CPT_PRED_LEARNED && !opt->selector_w)
     return fail(CPT_EINVAL, "learned predictor needs selector_w");
+  if (opt->predictor == CPT_PRED_LEARNED && ((uintptr_t)opt->selector_w & 15))
+    return fail(CPT_EINVAL, "selector_w must be 16-byte aligned");
   if (!(opt->dt_dx >= 0.0) || !(opt->dt_dy >= 0.0) || !std::isfinite(opt->dt_dx) || !std::isfinite(opt->dt_dy))
     return fail(CPT_EINVAL, "dt_dx and dt_dy must be finite and non-negative");
   if (opt->eb_mode == 0) {

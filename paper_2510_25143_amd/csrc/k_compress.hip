@@ -115,6 +115,35 @@ __device__ __forceinline__ int wave_sum(int v) {
          __builtin_amdgcn_readlane(v, 48);
 }
 
+// The same for fp64 values (both halves through DPP): exact for integers
+// whose partial sums stay below 2^53.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v += dpp_f64<0x128>(v);
+  v += dpp_f64<0x124>(v);
+  v += dpp_f64<0x122>(v);
+  v += dpp_f64<0x121>(v);
+  return readlane_f64(v, 0) + readlane_f64(v, 16) + readlane_f64(v, 32) + readlane_f64(v, 48);
+}
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0x128>(v));
+  v = fmax(v, dpp_f64<0x124>(v));
+  v = fmax(v, dpp_f64<0x122>(v));
+  v = fmax(v, dpp_f64<0x121>(v));
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
 template <typename T, typename Op>
 __device__ __forceinline__ T wave_reduce(T v, Op op) {
   for (int o = 32; o > 0; o >>= 1) v = op(v, (T)__shfl_xor(v, o));
@@ -154,6 +183,16 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
   int64_t tv[3];
 #pragma unroll
   for (int k = 0; k < 3; k++) tv[k] = tlog[min(lane + 64 * k, 128)];
+  // lossless flags of the block, for the features
+  const bool need_feats = feats != nullptr || p.predictor == 4;
+  uint32_t fv = 0;
+  if (need_feats) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int v = lane + 64 * k, x = x0 + (v & 15), y = y0 + (v >> 4);
+      fv |= (flags[(size_t)t * HW + (((x < W) & (y < H)) ? (size_t)y * W + x : 0)] ? 1u : 0u) << k;
+    }
+  }
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const int v = lane + 64 * k;
@@ -166,16 +205,20 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
     if (lane + 64 * k <= 128) S.T[lane + 64 * k] = (int)tv[k];
   for (int i = lane; i < p.K * 128; i += 64) (&SAMP[0][0])[i] = -1;
   wave_sync();
+  // frame t-1 at a domain vertex: from the staged block where it covers it
+  auto Fprev = [&](int xx, int yy) {
+    const int tx_ = xx - x0, ty_ = yy - y0;
+    return (tx_ >= 0 && tx_ < TILE && ty_ >= 0 && ty_ < TILE) ? P[ty_][tx_] : pf[(size_t)yy * W + xx];
+  };
 
   // ---------------- block features (also the selector's input)
   int cls_learned = -1;
-  if (feats != nullptr || p.predictor == 4) {
+  if (need_feats) {
     const int64_t s = eps > 1 ? eps : 1;
     int64_t S0 = 0, S1 = 0, S2 = 0, Dm = 0, Ds = 0, Sx = 0, Sy = 0, nf = 0, S6 = 0, S7 = 0, n = 0, m = 0;
     for (int k = 0; k < 4; k++) {
       const int v = lane + 64 * k, lx = v & 15, ly = v >> 4, x = x0 + lx, y = y0 + ly;
       if (!(x < W && y < H)) continue;
-      const size_t gi = (size_t)y * W + x;
       const int2 X = C[ly][lx], Pv = P[ly][lx];
       n += 1;
       S0 += (int64_t)iabs(X.x - Pv.x) + iabs(X.y - Pv.y);
@@ -193,58 +236,88 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
       Ds += d;
       Sx += dx;
       Sy += dy;
-      nf += flags[(size_t)t * HW + gi] ? 1 : 0;
+      nf += (fv >> k) & 1u;
       if ((lx & 3) == 0 && (ly & 3) == 0) {
         int pu, pv;
-        sl_predict(pf, H, W, x, y, slc, 2, &pu, &pv);
+        sl_predict_f(Fprev, H, W, x, y, slc, 2, &pu, &pv);
         S6 += (int64_t)iabs(X.x - pu) + iabs(X.y - pv);
         S7 += r3;
         m += 1;
       }
     }
-    auto add = [](int64_t a, int64_t b) { return a + b; };
-    auto mx = [](int64_t a, int64_t b) { return a > b ? a : b; };
-    S0 = wave_reduce(S0, add);
-    S1 = wave_reduce(S1, add);
-    S2 = wave_reduce(S2, add);
-    Dm = wave_reduce(Dm, mx);
-    Ds = wave_reduce(Ds, add);
-    Sx = wave_reduce(Sx, add);
-    Sy = wave_reduce(Sy, add);
-    nf = wave_reduce(nf, add);
-    S6 = wave_reduce(S6, add);
-    S7 = wave_reduce(S7, add);
-    n = wave_reduce(n, add);
-    m = wave_reduce(m, add);
-    if (lane == 0) {
-      int64_t q[10] = {featq_num(S0, 2 * n * s), featq_num(S1, 2 * n * s), featq_num(S2, 2 * n * s),
-                       featq_num(Dm, 65536),     featq_num(Ds, n * 65536),  featq_num(nf, n),
-                       featq_num(S6, 2 * m * s), featq_num(S7, 2 * m * s),  featq_num(Sx, n * 65536),
-                       featq_num(Sy, n * 65536)};
-      for (int i = 0; i < 10; i++) S.fin[i] = (float)q[i] / 256.0f;
+    // wave sums and the maximum, exact in fp64: every partial sum is an
+    // integer below 2^49
+    auto sum = [](int64_t v) { return (int64_t)wave_sum_f64((double)v); };
+    S0 = sum(S0);
+    S1 = sum(S1);
+    S2 = sum(S2);
+    Dm = (int64_t)wave_max_f64((double)Dm);
+    Ds = sum(Ds);
+    Sx = sum(Sx);
+    Sy = sum(Sy);
+    nf = sum(nf);
+    S6 = sum(S6);
+    S7 = sum(S7);
+    n = sum(n);
+    m = sum(m);
+    // lane i < 10 forms feature i (one exact division each, side by side)
+    if (lane < 10) {
+      const int64_t num[10] = {S0, S1, S2, Dm, Ds, nf, S6, S7, Sx, Sy};
+      const int64_t den[10] = {2 * n * s, 2 * n * s, 2 * n * s, 65536,     n * 65536,
+                               n,         2 * m * s, 2 * m * s, n * 65536, n * 65536};
+      int64_t a = 0, b = 1;
+#pragma unroll
+      for (int i = 0; i < 10; i++)
+        if (lane == i) {
+          a = num[i];
+          b = den[i];
+        }
+      S.fin[lane] = (float)featq_num(a, b) / 256.0f;
     }
     wave_sync();
     const size_t bi = (size_t)by * p.tx + bx;
     if (feats != nullptr && lane < 10) feats[bi * 10 + lane] = S.fin[lane];
     if (p.predictor == 4) {
-      // 10-64-64-4 MLP, bf16 weights, fp32 fused multiply-add in input order
+      // 10-64-64-4 MLP, bf16 weights, fp32 fused multiply-add in input order;
+      // a unit's weight row is read in 32-bit (layer 1) or 128-bit pieces
+      // (the weights are 16-byte aligned, every row offset a multiple of 4
+      // or 16 bytes), low half first
       {
+        const uint32_t* w1 = reinterpret_cast<const uint32_t*>(selw + lane * 10);
+        uint32_t wr[5];
+#pragma unroll
+        for (int i = 0; i < 5; i++) wr[i] = w1[i];
         float a = bf16f(selw[640 + lane]);
-        for (int i = 0; i < 10; i++) a = fmaf(bf16f(selw[lane * 10 + i]), S.fin[i], a);
+#pragma unroll
+        for (int i = 0; i < 5; i++) {
+          a = fmaf(bf16f((uint16_t)(wr[i] & 0xFFFFu)), S.fin[2 * i], a);
+          a = fmaf(bf16f((uint16_t)(wr[i] >> 16)), S.fin[2 * i + 1], a);
+        }
         S.h1[lane] = a > 0.0f ? a : 0.0f;
       }
       wave_sync();
+      auto dense64 = [&](const uint16_t* row, const float* in, float a) {
+        const uint4* w = reinterpret_cast<const uint4*>(row);
+        uint4 wr[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) wr[i] = w[i];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          const uint32_t h[4] = {wr[i].x, wr[i].y, wr[i].z, wr[i].w};
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            a = fmaf(bf16f((uint16_t)(h[k] & 0xFFFFu)), in[8 * i + 2 * k], a);
+            a = fmaf(bf16f((uint16_t)(h[k] >> 16)), in[8 * i + 2 * k + 1], a);
+          }
+        }
+        return a;
+      };
       {
-        float a = bf16f(selw[4800 + lane]);
-        for (int i = 0; i < 64; i++) a = fmaf(bf16f(selw[704 + lane * 64 + i]), S.h1[i], a);
+        const float a = dense64(selw + 704 + lane * 64, S.h1, bf16f(selw[4800 + lane]));
         S.h2[lane] = a > 0.0f ? a : 0.0f;
       }
       wave_sync();
-      if (lane < 4) {
-        float a = bf16f(selw[5120 + lane]);
-        for (int i = 0; i < 64; i++) a = fmaf(bf16f(selw[4864 + lane * 64 + i]), S.h2[i], a);
-        S.lg[lane] = a;
-      }
+      if (lane < 4) S.lg[lane] = dense64(selw + 4864 + lane * 64, S.h2, bf16f(selw[5120 + lane]));
       wave_sync();
       int best = 0;
       for (int c = 1; c < 4; c++)
@@ -304,12 +377,8 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
     const int sx = 2 * (pt & 7), sy = 2 * (pt >> 3);
     if (x0 + sx < W && y0 + sy < H) {
       const int2 Xs = C[sy][sx];
-      auto F = [&](int xx, int yy) {
-        const int tx_ = xx - x0, ty_ = yy - y0;
-        return (tx_ >= 0 && tx_ < TILE && ty_ >= 0 && ty_ < TILE) ? P[ty_][tx_] : pf[(size_t)yy * W + xx];
-      };
       int pu, pv, ru, rv;
-      sl_predict_f(F, H, W, x0 + sx, y0 + sy, slc, class_dmax(p.K, cls), &pu, &pv);
+      sl_predict_f(Fprev, H, W, x0 + sx, y0 + sy, slc, class_dmax(p.K, cls), &pu, &pv);
       SAMP[cls][2 * pt] = quantize(Xs.x, pu, eps, &ru);
       SAMP[cls][2 * pt + 1] = quantize(Xs.y, pv, eps, &rv);
     }
