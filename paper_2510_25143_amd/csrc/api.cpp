@@ -1148,7 +1148,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
       while (mm > 0 && P.D[P.ord[mm - 1]].p.T <= t) mm--;
       P.m_at[t] = mm;
     }
-    for (auto v : {P.mpre.back(), P.dxpre.back(), P.dqpre.back(), P.spre.back(), P.rpre.back()})
+    for (auto v : {P.mpre.back(), P.dxpre.back() + P.dqpre.back(), P.spre.back(), P.rpre.back()})
       if (v >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
     DBufs b;
     st = carve_dec(A, P, b);

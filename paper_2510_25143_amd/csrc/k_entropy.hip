@@ -782,18 +782,27 @@ __global__ __launch_bounds__(256) void k_words_from_bits_b(const DecDesc* __rest
   words[c] = (d.sec[RESID ? 5 : 2][lc] + 31) / 32;
 }
 
-// dpre[f]: decoding workgroups (256 chunks each) of the streams before f
-template <bool RESID>
-__global__ __launch_bounds__(256) void k_decode_b(DecDesc* __restrict__ D, const long long* __restrict__ dpre, int n,
+// Both code streams of every stream in one launch: the first dxblocks
+// workgroups decode bound codes, the rest residual codes (256 chunks each;
+// dxpre / dqpre: workgroups of the streams before f).  Either alone leaves
+// the chip with one or two waves per SIMD; together they overlap.
+__global__ __launch_bounds__(256) void k_decode_b(DecDesc* __restrict__ D, const long long* __restrict__ dxpre,
+                                                  long long dxblocks, const long long* __restrict__ dqpre, int n,
                                                   const uint32_t* __restrict__ luts,
-                                                  const uint32_t* __restrict__ wofs, uint16_t* __restrict__ out) {
-  const int f = find_field(dpre, n, blockIdx.x);
+                                                  const uint32_t* __restrict__ xwofs,
+                                                  const uint32_t* __restrict__ qwofs, uint16_t* __restrict__ xs,
+                                                  uint16_t* __restrict__ qs) {
+  const bool resid = (long long)blockIdx.x >= dxblocks;
+  const long long b = resid ? (long long)blockIdx.x - dxblocks : (long long)blockIdx.x;
+  const long long* pre = resid ? dqpre : dxpre;
+  const int f = find_field(pre, n, b);
   DecDesc& d = D[f];
-  const size_t cb = (size_t)(RESID ? d.cqb : d.cxb);
-  const size_t cfirst = (size_t)((long long)blockIdx.x - dpre[f]) * 256;
-  decode_chunks(luts + (size_t)(2 * f + (RESID ? 1 : 0)) * (1 << MAXLEN), d.sec[RESID ? 5 : 2], wofs + cb, wofs[cb],
-                d.sec[RESID ? 6 : 3], (size_t)d.secw[RESID ? 6 : 3], (size_t)(RESID ? d.nq : d.N),
-                RESID ? QSYM : XSYM, out + (RESID ? (size_t)d.qsb : (size_t)d.voff), &d.err, cfirst);
+  const uint32_t* wofs = resid ? qwofs : xwofs;
+  const size_t cb = (size_t)(resid ? d.cqb : d.cxb);
+  const size_t cfirst = (size_t)(b - pre[f]) * 256;
+  decode_chunks(luts + (size_t)(2 * f + (resid ? 1 : 0)) * (1 << MAXLEN), d.sec[resid ? 5 : 2], wofs + cb, wofs[cb],
+                d.sec[resid ? 6 : 3], (size_t)d.secw[resid ? 6 : 3], (size_t)(resid ? d.nq : d.N),
+                resid ? QSYM : XSYM, resid ? qs + (size_t)d.qsb : xs + (size_t)d.voff, &d.err, cfirst);
 }
 
 // Lane (segment, column) of a segment workgroup: 16 segments of 256 threads;
@@ -948,8 +957,9 @@ void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long lo
 void launch_decode_b(DecDesc* D, int n, const DecodeBufs& B, const long long* dxpre, long long dxblocks,
                      const long long* dqpre, long long dqblocks, const long long* spre, long long sblocks,
                      long long Stot, long long CX, long long CQ, hipStream_t s) {
-  if (dxblocks > 0) k_decode_b<false><<<(unsigned)dxblocks, 256, 0, s>>>(D, dxpre, n, B.lut, B.xwofs, B.xs);
-  if (dqblocks > 0) k_decode_b<true><<<(unsigned)dqblocks, 256, 0, s>>>(D, dqpre, n, B.lut, B.qwofs, B.qs);
+  if (dxblocks + dqblocks > 0)
+    k_decode_b<<<(unsigned)(dxblocks + dqblocks), 256, 0, s>>>(D, dxpre, dxblocks, dqpre, n, B.lut, B.xwofs, B.qwofs,
+                                                                B.xs, B.qs);
   if (sblocks <= 0) return;
   k_seg_nonll_b<<<(unsigned)sblocks, 256, 0, s>>>(D, spre, n, B.xs, B.sn);
   launch_scan(B.sn, (size_t)Stot, B.sq, B.part + 4, B.part + 2, s);
