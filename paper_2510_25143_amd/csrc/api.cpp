@@ -687,7 +687,7 @@ void enqueue_compress(const Plan& P, const BatchBufs& b, const ExecChoice& ex, c
   launch_chunks_b(b.D, n, B, b.E, b.cxpre, P.CX, b.cqpre, P.CQ, s);
   {
     TimeScope ts(FAM_ENCODE, (uint64_t)P.Ntot, s);
-    launch_assemble_b(b.D, n, B, b.E, b.cxpre, P.CX, b.cqpre, P.CQ, b.vpre, P.vpre.back(), s);
+    launch_assemble_b(b.D, n, B, b.E, b.cxpre, P.CX, b.cqpre, P.CQ, b.hpre, P.hpre.back(), s);
   }
 }
 
@@ -1133,7 +1133,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
       P.cqpre[j + 1] = P.cqpre[j] + d.nchq;
       P.dxpre[j + 1] = P.dxpre[j] + (d.nchx + 255) / 256;
       P.dqpre[j + 1] = P.dqpre[j] + (d.nchq + 255) / 256;
-      P.spre[j + 1] = P.spre[j] + (d.nseg + 15) / 16;
+      P.spre[j + 1] = P.spre[j] + (d.nseg + 255) / 256;
     }
     P.ord.resize(m);
     for (int j = 0; j < m; j++) P.ord[j] = j;

@@ -121,8 +121,8 @@ void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& 
 void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
                      long long cxtot, const long long* cqpre, long long cqtot, hipStream_t s);
 void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
-                       long long cxtot, const long long* cqpre, long long cqtot, const long long* vpre,
-                       long long vblocks, hipStream_t s);
+                       long long cxtot, const long long* cqpre, long long cqtot, const long long* hpre,
+                       long long hblocks, hipStream_t s);
 
 // ------------------------------------------------------- batched decoding
 // Per-stream descriptor of a batched decompression: header values and
@@ -165,7 +165,7 @@ struct DecodeBufs {
 void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long long* mpre, long long mblocks,
                            const long long* cxpre, long long cxtot, const long long* cqpre, long long cqtot,
                            hipStream_t s);
-// spre: workgroups of 16 segments per stream; Stot: all segments
+// spre: workgroups of 256 segments per stream; Stot: all segments
 void launch_decode_b(DecDesc* D, int n, const DecodeBufs& B, const long long* dxpre, long long dxblocks,
                      const long long* dqpre, long long dqblocks, const long long* spre, long long sblocks,
                      long long Stot, long long CX, long long CQ, hipStream_t s);

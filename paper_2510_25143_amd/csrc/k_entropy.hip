@@ -212,6 +212,35 @@ struct RunAdd {
   }
 };
 
+// The bound and residual codes of the run of 16 vertices starting at field
+// vertex i0 (16-byte loads where aligned); 0xFF / 0 past the field's end hi.
+__device__ __forceinline__ void load_run(const uint8_t* __restrict__ xcode, const uint32_t* __restrict__ qcode,
+                                         size_t base, size_t i0, size_t hi, uint8_t xc[16], uint32_t qc[16]) {
+  const bool full = i0 + 16 <= hi && ((base + i0) & 15) == 0;
+  if (full) {
+    const uint4 xa = *(const uint4*)(xcode + base + i0);
+    const uint32_t xw[4] = {xa.x, xa.y, xa.z, xa.w};
+#pragma unroll
+    for (int j = 0; j < 16; j++) xc[j] = (uint8_t)(xw[j >> 2] >> (8 * (j & 3)));
+    const uint4* q4 = (const uint4*)(qcode + base + i0);
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const uint4 w = q4[j];
+      qc[4 * j] = w.x;
+      qc[4 * j + 1] = w.y;
+      qc[4 * j + 2] = w.z;
+      qc[4 * j + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      const bool in = i0 + j < hi;
+      xc[j] = in ? xcode[base + i0 + j] : (uint8_t)0xFF;
+      qc[j] = in ? qcode[base + i0 + j] : 0u;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_hist_b(const FieldDesc* __restrict__ D, const long long* __restrict__ hpre,
                                                 int n, const uint8_t* __restrict__ xcode,
                                                 const uint32_t* __restrict__ qcode, uint32_t* __restrict__ xhist,
@@ -238,29 +267,7 @@ __global__ __launch_bounds__(256) void k_hist_b(const FieldDesc* __restrict__ D,
   RunAdd rx, ru, rv;
   uint8_t xc[16];
   uint32_t qc[16];
-  const bool full = i0 + 16 <= hi && ((base + i0) & 15) == 0;
-  if (full) {
-    const uint4 xa = *(const uint4*)(xcode + base + i0);
-    const uint32_t xw[4] = {xa.x, xa.y, xa.z, xa.w};
-#pragma unroll
-    for (int j = 0; j < 16; j++) xc[j] = (uint8_t)(xw[j >> 2] >> (8 * (j & 3)));
-    const uint4* q4 = (const uint4*)(qcode + base + i0);
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const uint4 w = q4[j];
-      qc[4 * j] = w.x;
-      qc[4 * j + 1] = w.y;
-      qc[4 * j + 2] = w.z;
-      qc[4 * j + 3] = w.w;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 16; j++) {
-      const bool in = i0 + j < hi;
-      xc[j] = in ? xcode[base + i0 + j] : (uint8_t)0xFF;
-      qc[j] = in ? qcode[base + i0 + j] : 0u;
-    }
-  }
+  load_run(xcode, qcode, base, i0, hi, xc, qc);
   uint32_t rsum = 0, nsum = 0;
 #pragma unroll
   for (int j = 0; j < 16; j++) {
@@ -302,37 +309,30 @@ __global__ __launch_bounds__(CB_THREADS) void k_codebooks_b(const FieldDesc* __r
   else build_code(qhist + (size_t)f * QSYM, QSYM, qt + f, qcb + (size_t)f * (QSYM + 4), &used[2 * f + 1]);
 }
 
-struct VPos {
-  int f;
-  size_t i;
-  bool valid;
-};
-__device__ __forceinline__ VPos vpos(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre, int n) {
-  VPos v;
-  v.f = find_field(vpre, n, blockIdx.x);
-  v.i = (size_t)((long long)blockIdx.x - vpre[v.f]) * 256 + threadIdx.x;
-  v.valid = v.i < (size_t)D[v.f].N;
-  return v;
-}
-
-// Every residual-coded vertex puts its two symbols at its run's offset
-// plus the coded vertices before it in the run (a run of 16 vertices is one
-// 16-lane DPP row of the workgroup).
+// One thread per run of 16 vertices (the histogram's grid): every
+// residual-coded vertex puts its two symbols, its 32-bit residual code, at
+// the run's offset plus the coded vertices before it (pairs start at even
+// positions of the chunk-aligned symbol array).
 __global__ __launch_bounds__(256) void k_gather_q_b(const FieldDesc* __restrict__ D,
-                                                    const long long* __restrict__ vpre, int n,
+                                                    const long long* __restrict__ hpre, int n,
                                                     const uint8_t* __restrict__ xcode,
                                                     const uint32_t* __restrict__ qcode,
                                                     const uint32_t* __restrict__ sq, uint16_t* __restrict__ qsym) {
-  const VPos v = vpos(D, vpre, n);
-  const FieldDesc& d = D[v.f];
-  const size_t g = d.voff + (v.valid ? v.i : 0);
-  const bool coded = v.valid && !d.status && xcode[g] != XLOSSLESS;
-  const uint32_t before = row16_exclusive(coded ? 1u : 0u);
-  if (!coded) return;
-  const uint32_t q = qcode[g];
-  const size_t o = (size_t)d.cqb * CHUNK + 2 * ((size_t)(sq[d.ro + v.i / 16] - sq[d.ro]) + before);
-  qsym[o] = (uint16_t)(q & 0xFFFFu);
-  qsym[o + 1] = (uint16_t)(q >> 16);
+  const int f = find_field(hpre, n, blockIdx.x);
+  const FieldDesc& d = D[f];
+  if (d.status) return;
+  const size_t lo = (size_t)((long long)blockIdx.x - hpre[f]) * HIST_SPAN;
+  const size_t N = (size_t)d.N, hi = lo + HIST_SPAN < N ? lo + HIST_SPAN : N;
+  const size_t i0 = lo + (size_t)threadIdx.x * 16;
+  if (i0 >= hi) return;
+  uint8_t xc[16];
+  uint32_t qc[16];
+  load_run(xcode, qcode, (size_t)d.voff, i0, hi, xc, qc);
+  uint32_t* out = reinterpret_cast<uint32_t*>(qsym + (size_t)d.cqb * CHUNK);
+  size_t o = (size_t)(sq[d.ro + i0 / 16] - sq[d.ro]);
+#pragma unroll
+  for (int j = 0; j < 16; j++)
+    if (xc[j] < XLOSSLESS) out[o++] = qc[j];
 }
 
 // residual symbols and raw values per field, from the prefix sums
@@ -547,87 +547,126 @@ __global__ __launch_bounds__(256) void k_sections_b(const FieldDesc* __restrict_
   for (size_t w = first; w < (size_t)d.nchq; w += step) out[d.off[5] / 4 + w] = qbits[d.cqb + w];
 }
 
-// raw words: two per lossless vertex, one per unpredictable component, at
-// the run's offset plus the raw words of the vertices before it in the run
-__global__ __launch_bounds__(256) void k_raw_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
+// raw words, one thread per run of 16 vertices: two per lossless vertex,
+// one per unpredictable component, from the run's offset on in vertex order
+__global__ __launch_bounds__(256) void k_raw_b(const FieldDesc* __restrict__ D, const long long* __restrict__ hpre,
                                                int n, const uint8_t* __restrict__ xcode,
                                                const uint32_t* __restrict__ qcode, const uint32_t* __restrict__ sro) {
-  const VPos v = vpos(D, vpre, n);
-  const FieldDesc& d = D[v.f];
-  const bool live = v.valid && !d.status;
-  const size_t i = live ? v.i : 0, g = d.voff + i, N = (size_t)d.N;
-  const bool ll = xcode[g] == XLOSSLESS;
-  const uint32_t q = qcode[g];
-  const uint32_t cnt = !live ? 0u : ll ? 2u : ((q & 0xFFFFu) == 0) + ((q >> 16) == 0);
-  const uint32_t before = row16_exclusive(cnt);
-  if (cnt == 0) return;
-  uint32_t o = (sro[d.ro + i / 16] - sro[d.ro]) + before;
+  const int f = find_field(hpre, n, blockIdx.x);
+  const FieldDesc& d = D[f];
+  if (d.status) return;
+  const size_t lo = (size_t)((long long)blockIdx.x - hpre[f]) * HIST_SPAN;
+  const size_t N = (size_t)d.N, hi = lo + HIST_SPAN < N ? lo + HIST_SPAN : N;
+  const size_t i0 = lo + (size_t)threadIdx.x * 16;
+  if (i0 >= hi) return;
+  uint8_t xc[16];
+  uint32_t qc[16];
+  load_run(xcode, qcode, (size_t)d.voff, i0, hi, xc, qc);
   uint32_t* out = (uint32_t*)(d.out + d.off[7]);
-  const uint32_t bu = __float_as_uint(d.field[i]), bv = __float_as_uint(d.field[N + i]);
-  if (ll) {
-    out[o] = bu;
-    out[o + 1] = bv;
-  } else {
-    if ((q & 0xFFFFu) == 0) out[o++] = bu;
-    if ((q >> 16) == 0) out[o] = bv;
+  uint32_t o = sro[d.ro + i0 / 16] - sro[d.ro];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const size_t i = i0 + j;
+    if (xc[j] == XLOSSLESS) {
+      out[o] = __float_as_uint(d.field[i]);
+      out[o + 1] = __float_as_uint(d.field[N + i]);
+      o += 2;
+    } else if (xc[j] < XLOSSLESS) {
+      if ((qc[j] & 0xFFFFu) == 0) out[o++] = __float_as_uint(d.field[i]);
+      if ((qc[j] >> 16) == 0) out[o++] = __float_as_uint(d.field[N + i]);
+    }
   }
 }
 
 // ------------------------------------------------------------- decoding
 // LUT entry for every 12-bit prefix: symbol | length << 16; 0xFFFFFFFF when
 // no codeword matches.
+// Called by 1024 threads.  The codebook lists (symbol, length) in
+// increasing symbol order; a symbol's canonical code is first[l] plus its
+// rank among the symbols of length l.  Ranks come from wave ballots, the
+// codes are laid out in canonical order (their 12-bit left-aligned starts
+// then increase), and every table entry finds its code by binary search.
 __device__ void build_lut(const uint32_t* __restrict__ cb, size_t cb_words, int nsym, uint32_t* __restrict__ lut,
                           uint32_t* __restrict__ err) {
-  __shared__ uint8_t len[1024];
   __shared__ int lcount[MAXLEN + 2];
-  __shared__ uint32_t first[MAXLEN + 2];
+  __shared__ uint32_t first[MAXLEN + 2], lbase[MAXLEN + 2];
+  __shared__ uint32_t wcnt[16][MAXLEN + 1];
+  __shared__ uint32_t sstart[1024], sval[1024];
   __shared__ int bad;
   __shared__ uint32_t kraft;
-  const int tid = threadIdx.x;
-  len[tid] = 0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (tid <= MAXLEN + 1) lcount[tid] = 0;
   if (tid == 0) {
     bad = 0;
     kraft = 0;
   }
-  for (int i = tid; i < (1 << MAXLEN); i += 1024) lut[i] = 0xFFFFFFFFu;
   __syncthreads();
-  uint32_t used = cb_words >= 1 ? cb[0] : 0;
+  const uint32_t used = cb_words >= 1 ? cb[0] : 0;
   if (cb_words < 1 || (size_t)used + 1 != cb_words || used > (uint32_t)nsym) {
+    for (int i = tid; i < (1 << MAXLEN); i += 1024) lut[i] = 0xFFFFFFFFu;
     if (tid == 0) atomicOr(err, 1u);
     return;
   }
+  uint32_t s = 0, l = 0;
   if ((uint32_t)tid < used) {
-    uint32_t e = cb[1 + tid];
-    uint32_t s = e & 0xFFFFu, l = e >> 16;
-    uint32_t prev = tid > 0 ? (cb[tid] & 0xFFFFu) : 0;
-    if (s >= (uint32_t)nsym || l < 1 || l > MAXLEN || (tid > 0 && s <= prev)) atomicOr((uint32_t*)&bad, 1u);
-    else {
-      len[s] = (uint8_t)l;
+    const uint32_t e = cb[1 + tid];
+    s = e & 0xFFFFu;
+    l = e >> 16;
+    const uint32_t prev = tid > 0 ? (cb[tid] & 0xFFFFu) : 0;
+    if (s >= (uint32_t)nsym || l < 1 || l > MAXLEN || (tid > 0 && s <= prev)) {
+      atomicOr((uint32_t*)&bad, 1u);
+      l = 0;
+    } else {
       atomicAdd(&lcount[l], 1);
       atomicAdd(&kraft, 1u << (MAXLEN - l));
     }
   }
+  // rank within the wave among entries of the same length
+  uint32_t rank = 0;
+  for (int L = 1; L <= MAXLEN; L++) {
+    const unsigned long long m = __ballot(l == (uint32_t)L);
+    if (l == (uint32_t)L) rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[wv][L] = (uint32_t)__popcll(m);
+  }
   __syncthreads();
   if (bad || kraft > (1u << MAXLEN)) {
+    for (int i = tid; i < (1 << MAXLEN); i += 1024) lut[i] = 0xFFFFFFFFu;
     if (tid == 0) atomicOr(err, 1u);
     return;
   }
   if (tid == 0) {
-    uint32_t code = 0;
+    uint32_t code = 0, base = 0;
     lcount[0] = 0;
-    for (int l = 1; l <= MAXLEN; l++) {
-      code = (code + (uint32_t)lcount[l - 1]) << 1;
-      first[l] = code;
+    for (int L = 1; L <= MAXLEN; L++) {
+      code = (code + (uint32_t)lcount[L - 1]) << 1;
+      first[L] = code;
+      lbase[L] = base;
+      base += (uint32_t)lcount[L];
     }
   }
+  if (l) {
+    for (int w = 0; w < wv; w++) rank += wcnt[w][l];
+  }
   __syncthreads();
-  if (tid < nsym && len[tid]) {
-    uint32_t l = len[tid], r = 0;
-    for (int s = 0; s < tid; s++) r += len[s] == l ? 1u : 0u;
-    uint32_t code = first[l] + r;
-    uint32_t lo = code << (MAXLEN - l), hi = (code + 1) << (MAXLEN - l);
-    for (uint32_t i = lo; i < hi && i < (1u << MAXLEN); i++) lut[i] = (uint32_t)tid | (l << 16);
+  if (l) {
+    const uint32_t ci = lbase[l] + rank;
+    sstart[ci] = (first[l] + rank) << (MAXLEN - l);
+    sval[ci] = s | (l << 16);
+  }
+  __syncthreads();
+  for (int i = tid; i < (1 << MAXLEN); i += 1024) {
+    uint32_t v = 0xFFFFFFFFu;
+    if (used > 0 && sstart[0] <= (uint32_t)i) {
+      int lo = 0, hi = (int)used - 1;  // the last code starting at or before i
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sstart[mid] <= (uint32_t)i) lo = mid;
+        else hi = mid - 1;
+      }
+      const uint32_t cl = sval[lo] >> 16;
+      if ((uint32_t)i < sstart[lo] + (1u << (MAXLEN - cl))) v = sval[lo];
+    }
+    lut[i] = v;
   }
 }
 
@@ -805,66 +844,97 @@ __global__ __launch_bounds__(256) void k_decode_b(DecDesc* __restrict__ D, const
                 resid ? QSYM : XSYM, resid ? qs + (size_t)d.qsb : xs + (size_t)d.voff, &d.err, cfirst);
 }
 
-// Lane (segment, column) of a segment workgroup: 16 segments of 256 threads;
-// g is the lane's vertex, valid when it exists.
-struct SegPos {
+// One thread per segment (block row): its stream, the segment within the
+// stream, the segment's first vertex g0 and its length (16, or less at the
+// right edge).  A stream has fewer than 2^31 segments: 32-bit divisions.
+struct SegRow {
   int f;
-  long long ls;  // segment within the stream
-  size_t g;
-  bool live, valid;
+  unsigned ls, len;
+  size_t g0;
+  bool live;
 };
-__device__ __forceinline__ SegPos seg_pos(const DecDesc* __restrict__ D, const long long* __restrict__ spre, int n) {
-  SegPos q;
+__device__ __forceinline__ SegRow seg_row(const DecDesc* __restrict__ D, const long long* __restrict__ spre, int n) {
+  SegRow q;
   q.f = find_field(spre, n, blockIdx.x);
   const DecDesc& d = D[q.f];
-  q.ls = ((long long)blockIdx.x - spre[q.f]) * 16 + (threadIdx.x >> 4);
-  q.live = q.ls < d.nseg;
-  const int tx = d.p.tx, H = d.p.H, W = d.p.W;
-  const long long ls = q.live ? q.ls : 0;
-  const long long ty = ls / tx;
-  const int bx = (int)(ls - ty * tx), y = (int)(ty % H), t = (int)(ty / H);
-  const int x = 16 * bx + (int)(threadIdx.x & 15);
-  q.valid = q.live && x < W;
-  q.g = q.valid ? ((size_t)t * H + y) * W + x : 0;
+  const long long ls = ((long long)blockIdx.x - spre[q.f]) * 256 + threadIdx.x;
+  q.live = ls < d.nseg;
+  q.ls = q.live ? (unsigned)ls : 0u;
+  const unsigned tx = (unsigned)d.p.tx, H = (unsigned)d.p.H, W = (unsigned)d.p.W;
+  const unsigned ty = q.ls / tx, t = ty / H;
+  const unsigned bx = q.ls - ty * tx, y = ty - t * H;
+  q.len = min(16u, W - 16 * bx);
+  q.g0 = ((size_t)t * H + y) * W + 16 * bx;
   return q;
+}
+
+// the segment's bound codes (16-byte loads where the row is aligned)
+__device__ __forceinline__ void seg_codes(const uint16_t* __restrict__ p, unsigned len, uint32_t c[16]) {
+  if (len == 16 && ((uintptr_t)p & 15) == 0) {
+    const uint4 a = reinterpret_cast<const uint4*>(p)[0], b = reinterpret_cast<const uint4*>(p)[1];
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      c[2 * j] = w[j] & 0xFFFFu;
+      c[2 * j + 1] = w[j] >> 16;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; j++) c[j] = (unsigned)j < len ? p[j] : (uint32_t)XLOSSLESS;
+  }
 }
 
 // residual-coded vertices per segment; a bound code above 24 is an error
 __global__ __launch_bounds__(256) void k_seg_nonll_b(DecDesc* __restrict__ D, const long long* __restrict__ spre,
                                                      int n, const uint16_t* __restrict__ xs,
                                                      uint32_t* __restrict__ sn) {
-  const SegPos q = seg_pos(D, spre, n);
+  const SegRow q = seg_row(D, spre, n);
+  if (!q.live) return;
   DecDesc& d = D[q.f];
-  const uint32_t c = xs[d.voff + q.g];
-  if (q.valid && c > XLOSSLESS) atomicOr(&d.err, 16u);
-  const uint32_t tot = row16_sum(q.valid && c < XLOSSLESS ? 1u : 0u);
-  if (q.live && (threadIdx.x & 15) == 0) sn[d.soff + q.ls] = tot;
+  uint32_t c[16];
+  seg_codes(xs + d.voff + q.g0, q.len, c);
+  uint32_t cnt = 0;
+  bool over = false;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    over |= c[j] > XLOSSLESS;
+    cnt += c[j] < XLOSSLESS ? 1u : 0u;
+  }
+  if (over) atomicOr(&d.err, 16u);
+  sn[d.soff + q.ls] = cnt;
 }
 
 // raw words per segment (two for a lossless vertex, one per unpredictable
 // component); a residual position past the stream's symbols or a bound too
-// small for its code is an error
+// small for its code is an error.  Symbol pairs start at even positions of
+// an even-aligned array, so each pair is one 32-bit load.
 __global__ __launch_bounds__(256) void k_seg_raw_b(DecDesc* __restrict__ D, const long long* __restrict__ spre, int n,
                                                    const uint16_t* __restrict__ xs, const uint16_t* __restrict__ qs,
                                                    const uint32_t* __restrict__ sq, uint32_t* __restrict__ sr) {
-  const SegPos q = seg_pos(D, spre, n);
+  const SegRow q = seg_row(D, spre, n);
+  if (!q.live) return;
   DecDesc& d = D[q.f];
-  const uint32_t c = xs[d.voff + q.g];
-  const bool coded = q.valid && c < XLOSSLESS;
-  const uint32_t before = row16_exclusive(coded ? 1u : 0u);
-  const long long o = 2 * ((long long)(sq[d.soff + (q.live ? q.ls : 0)] - sq[d.soff]) + before);
+  uint32_t c[16];
+  seg_codes(xs + d.voff + q.g0, q.len, c);
+  const uint32_t* qq = reinterpret_cast<const uint32_t*>(qs + d.qsb);
+  long long o = 2 * (long long)(uint32_t)(sq[d.soff + q.ls] - sq[d.soff]);
   uint32_t r = 0;
-  if (q.valid && c == XLOSSLESS) r = 2;
-  if (coded) {
-    if ((d.p.eps >> c) < 1 || o + 2 > d.nq) {
-      atomicOr(&d.err, 32u);
-    } else {
-      const uint16_t* qq = qs + d.qsb;
-      r = (qq[o] == 0) + (qq[o + 1] == 0);
+  bool bad = false;
+  for (unsigned j = 0; j < q.len; j++) {
+    if (c[j] == XLOSSLESS) {
+      r += 2;
+    } else if (c[j] < XLOSSLESS) {
+      if ((d.p.eps >> c[j]) < 1 || o + 2 > d.nq) {
+        bad = true;
+      } else {
+        const uint32_t pr = qq[o >> 1];
+        r += ((pr & 0xFFFFu) == 0) + ((pr >> 16) == 0);
+      }
+      o += 2;
     }
   }
-  const uint32_t tot = row16_sum(r);
-  if (q.live && (threadIdx.x & 15) == 0) sr[d.soff + q.ls] = tot;
+  if (bad) atomicOr(&d.err, 32u);
+  sr[d.soff + q.ls] = r;
 }
 
 // the stream's totals against its header: bitstream words, residual
@@ -914,7 +984,7 @@ void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& 
   launch_scan(E.sn, (size_t)Rtot, E.sq, E.part + 4, tot, s);
   launch_scan(E.sr, (size_t)Rtot, E.sro, E.part + 4, tot + 1, s);
   k_totals_b<<<nblk(n, 64), 64, 0, s>>>(D, n, E.sn, E.sq, E.sr, E.sro);
-  k_gather_q_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.sq, E.qsym);
+  if (hblocks > 0) k_gather_q_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.sq, E.qsym);
 }
 
 void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
@@ -932,12 +1002,12 @@ void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs&
 }
 
 void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
-                       long long cxtot, const long long* cqpre, long long cqtot, const long long* vpre,
-                       long long vblocks, hipStream_t s) {
+                       long long cxtot, const long long* cqpre, long long cqtot, const long long* hpre,
+                       long long hblocks, hipStream_t s) {
   k_sections_b<<<dim3(n, 16), 256, 0, s>>>(D, B.modes, E.xcb, E.qcb, E.used, E.xbits, E.qbits);
   if (cxtot > 0) k_encode_b<false><<<(unsigned)cxtot, 256, 0, s>>>(D, cxpre, n, B.xcode, E.qsym, E.xt, E.xwofs);
   if (cqtot > 0) k_encode_b<true><<<(unsigned)cqtot, 256, 0, s>>>(D, cqpre, n, B.xcode, E.qsym, E.qt, E.qwofs);
-  if (vblocks > 0) k_raw_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.sro);
+  if (hblocks > 0) k_raw_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.sro);
 }
 void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long long* mpre, long long mblocks,
                            const long long* cxpre, long long cxtot, const long long* cqpre, long long cqtot,
