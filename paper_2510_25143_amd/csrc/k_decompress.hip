@@ -13,19 +13,16 @@
 
 namespace cpt {
 
-// One wave per block: each lane prepares four vertices (v = lane + 64 k),
-// lanes 0-31 then sweep the Lorenzo anti-diagonals, and each lane writes its
-// four vertices.  With one wave per block every block of a frame is
-// resident at once.  Global reads come in two rounds, each with all its
-// loads in flight: the per-vertex codes and offsets with the previous frame,
-// then the residual symbols and raw words they point at.  Streams that
-// failed a check are skipped.
-__device__ __forceinline__ void rc_wave_sync() {
-  __builtin_amdgcn_wave_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
+// Two waves per block: each lane prepares two vertices (v = lane + 128 k),
+// lanes 0-31 of the first wave then sweep the Lorenzo anti-diagonals, and
+// each lane writes its two vertices.  Every block of a frame is resident at
+// once.  Global reads come in two rounds, each with all its loads in flight:
+// the per-vertex codes and the block rows' offsets with the previous frame,
+// then the residual symbols (and, where the wave has any, the raw words)
+// they point at.  Streams that failed a check are skipped.
+constexpr int RC_THREADS = 128, RC_VPL = TILE * TILE / RC_THREADS;
 
-__global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, const int* __restrict__ ord,
+__global__ __launch_bounds__(RC_THREADS) void k_reconstruct_b(DecDesc* __restrict__ D, const int* __restrict__ ord,
                                                       const long long* __restrict__ pre, int m, int t,
                                                       const long long* __restrict__ mtab, DecodeBufs B) {
   __shared__ int C[2][TILE][TILE];       // reconstructed fixed-point values (u, v)
@@ -54,12 +51,12 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
 
   // ---- round 1: codes, the offsets of the block's rows (segments), the
   // previous frame with a one-vertex halo
-  constexpr int NH = HALO * HALO, KH = (NH + 63) / 64;
-  uint32_t vcode[4], sqv[4], srv[4], vm = 0, hm = 0;
+  constexpr int NH = HALO * HALO, KH = (NH + RC_THREADS - 1) / RC_THREADS;
+  uint32_t vcode[RC_VPL], sqv[RC_VPL], srv[RC_VPL], vm = 0, hm = 0;
   int2 hp[KH];
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const int v = lane + 64 * k, x = x0 + (v & 15), y = y0 + (v >> 4);
+  for (int k = 0; k < RC_VPL; k++) {
+    const int v = lane + RC_THREADS * k, x = x0 + (v & 15), y = y0 + (v >> 4);
     const bool valid = (x < W) & (y < H);
     vm |= valid ? 1u << k : 0u;
     vcode[k] = xs[valid ? (size_t)t * HW + (size_t)y * W + x : 0];
@@ -69,7 +66,7 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
   }
 #pragma unroll
   for (int k = 0; k < KH; k++) {
-    const int i = lane + 64 * k, hy = i / HALO, hx = i - hy * HALO, x = x0 - 1 + hx, y = y0 - 1 + hy;
+    const int i = lane + RC_THREADS * k, hy = i / HALO, hx = i - hy * HALO, x = x0 - 1 + hx, y = y0 - 1 + hy;
     const bool valid = (i < NH) & (t > 0) & (x >= 0) & (x < W) & (y >= 0) & (y < H);
     hm |= valid ? 1u << k : 0u;
     hp[k] = prevf[valid ? (size_t)y * W + x : 0];
@@ -83,7 +80,7 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
 #pragma unroll
   for (int k = 0; k < KH; k++) {
-    const int i = lane + 64 * k;
+    const int i = lane + RC_THREADS * k;
     if (i < NH) {
       const int2 v = (hm >> k) & 1u ? hp[k] : make_int2(0, 0);
       (&P[0][0][0])[i] = v.x;
@@ -94,10 +91,10 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
   // ---- round 2: the two residual symbols of every coded vertex, at its
   // segment's offset plus the coded vertices before it in the row (each
   // 16-lane DPP row holds one block row; index clamped into the stream)
-  int vq[4];
-  uint32_t ridx[4], rneed = 0;
+  int vq[RC_VPL];
+  uint32_t ridx[RC_VPL], rneed = 0;
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < RC_VPL; k++) {
     if (!((vm >> k) & 1u)) vcode[k] = XLOSSLESS;
     const bool coded = ((vm >> k) & 1u) && vcode[k] != XLOSSLESS;
     const long long o = 2 * ((long long)(sqv[k] - qbase) + row16_exclusive(coded ? 1u : 0u));
@@ -106,7 +103,7 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
     vq[k] = coded ? (int)(q0 | (q1 << 16)) : 0;
   }
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < RC_VPL; k++) {
     const bool valid = (vm >> k) & 1u;
     const uint32_t r = !valid ? 0u : vcode[k] == XLOSSLESS ? 2u : ((vq[k] & 0xFFFF) == 0) + (((uint32_t)vq[k] >> 16) == 0);
     ridx[k] = (srv[k] - rbase) + row16_exclusive(r);
@@ -114,15 +111,15 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
   }
   // ---- round 3 (only where the block has raw words): the two raw words a
   // vertex may use
-  uint32_t rw0[4] = {0u, 0u, 0u, 0u}, rw1[4] = {0u, 0u, 0u, 0u};
+  uint32_t rw0[RC_VPL] = {}, rw1[RC_VPL] = {};
   if (__builtin_amdgcn_readfirstlane(__ballot(rneed != 0) != 0ull ? 1 : 0) && nraw >= 1) {
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
+    for (int k = 0; k < RC_VPL; k++) {
       rw0[k] = raw[min((long long)ridx[k], nraw - 1)];
       rw1[k] = raw[min((long long)ridx[k] + 1, nraw - 1)];
     }
   }
-  rc_wave_sync();
+  __syncthreads();
   // frame t-1 from the staged halo where it covers the sample
   auto F = [&](int xx, int yy) {
     const int hx = xx - x0 + 1, hy = yy - y0 + 1;
@@ -132,8 +129,8 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
 
   // everything that does not depend on the block's own reconstruction
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
+  for (int k = 0; k < RC_VPL; k++) {
+    const int v = lane + RC_THREADS * k, lx = v & 15, ly = v >> 4;
     const int x = x0 + lx, y = y0 + ly;
     if (!((vm >> k) & 1u)) {
       vcode[k] = XLOSSLESS;
@@ -183,14 +180,14 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
       }
     }
   }
-  rc_wave_sync();
+  __syncthreads();
 
   // Lorenzo blocks: lanes 0-15 sweep the rows of u and lanes 16-31 the rows
   // of v along the anti-diagonals.  A lane keeps its last value (the left
   // neighbour of its next vertex); the row above arrives from the previous
-  // lane of the same 16-lane DPP row by a row shift.  All 64 lanes step
-  // together (DPP reads need active source lanes).
-  if (cls == 0) {
+  // lane of the same 16-lane DPP row by a row shift.  All 64 lanes of the
+  // first wave step together (DPP reads need active source lanes).
+  if (cls == 0 && __builtin_amdgcn_readfirstlane(lane >> 6) == 0) {
     const int c = (lane >> 4) & 1, row = lane & 15;
     const bool rowok = lane < 2 * TILE && y0 + row < H;
     const int cend = min(TILE, W - x0);
@@ -217,13 +214,13 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
       }
       upl = up;
     }
-    rc_wave_sync();
   }
+  __syncthreads();
   // known raw components are restored bit-exactly; the rest are exact
   // multiples of 2^-k
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const int v = lane + 64 * k, lx = v & 15, ly = v >> 4;
+  for (int k = 0; k < RC_VPL; k++) {
+    const int v = lane + RC_THREADS * k, lx = v & 15, ly = v >> 4;
     const int x = x0 + lx, y = y0 + ly;
     if (!((vm >> k) & 1u)) continue;
     const size_t gv = (size_t)t * HW + (size_t)y * W + x;
@@ -246,7 +243,7 @@ __global__ __launch_bounds__(64) void k_reconstruct_b(DecDesc* __restrict__ D, c
 // ============================================================ launchers
 void launch_reconstruct_b(DecDesc* D, const int* ord, const long long* pre, int m, long long nblocks, int t,
                           const long long* mtab, const DecodeBufs& B, hipStream_t s) {
-  if (nblocks > 0) k_reconstruct_b<<<(unsigned)nblocks, 64, 0, s>>>(D, ord, pre, m, t, mtab, B);
+  if (nblocks > 0) k_reconstruct_b<<<(unsigned)nblocks, RC_THREADS, 0, s>>>(D, ord, pre, m, t, mtab, B);
 }
 
 }  // namespace cpt
