@@ -115,6 +115,21 @@ __device__ __forceinline__ uint32_t row16_exclusive(uint32_t v) {
   return x - v;
 }
 
+// Inclusive prefix sum over the wave, every lane enabled: DPP row prefixes,
+// then the totals of the rows before (lanes 15, 31, 47) added per row.
+__device__ __forceinline__ uint32_t wave_inclusive(uint32_t v) {
+  uint32_t x = v;
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
+  const uint32_t t0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 15);
+  const uint32_t t1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 31);
+  const uint32_t t2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 47);
+  const int row = (int)(threadIdx.x & 63) >> 4;
+  return x + (row > 0 ? t0 : 0u) + (row > 1 ? t1 : 0u) + (row > 2 ? t2 : 0u);
+}
+
 // Minimum over each quad of 4 lanes (DPP quad permutations).
 __device__ __forceinline__ int quad_min(int v) {
   v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]

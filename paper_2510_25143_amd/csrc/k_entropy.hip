@@ -362,7 +362,7 @@ __global__ __launch_bounds__(256) void k_chunk_bits_b(const FieldDesc* __restric
                                                       const uint16_t* __restrict__ qsym,
                                                       const HuffTables* __restrict__ tabs,
                                                       uint32_t* __restrict__ bits, uint32_t* __restrict__ words) {
-  __shared__ uint32_t red[256];
+  __shared__ uint32_t red[4];
   const int f = find_field(cpre, n, blockIdx.x);
   const FieldDesc& d = D[f];
   const long long lc = (long long)blockIdx.x - cpre[f];
@@ -377,15 +377,16 @@ __global__ __launch_bounds__(256) void k_chunk_bits_b(const FieldDesc* __restric
       if ((long long)k < nsym) b += RESID ? t->len[qsym[(size_t)d.cqb * CHUNK + k]] : t->len[xcode[d.voff + k]];
     }
   }
-  red[threadIdx.x] = b;
+  // wave sums (DPP rows, then the four rows), then the four waves
+  b = row16_sum(b);
+  b = (uint32_t)__builtin_amdgcn_readlane((int)b, 0) + (uint32_t)__builtin_amdgcn_readlane((int)b, 16) +
+      (uint32_t)__builtin_amdgcn_readlane((int)b, 32) + (uint32_t)__builtin_amdgcn_readlane((int)b, 48);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    bits[slot] = red[0];
-    words[slot] = (red[0] + 31) / 32;
+    const uint32_t tot = red[0] + red[1] + red[2] + red[3];
+    bits[slot] = tot;
+    words[slot] = (tot + 31) / 32;
   }
 }
 
@@ -425,12 +426,8 @@ __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ 
     mine += lens[i];
   }
   // exclusive prefix of bit counts over the workgroup
-  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t x = mine;
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = (uint32_t)__shfl_up((int)x, o);
-    if (lane >= o) x += y;
-  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t x = wave_inclusive(mine);
   if (lane == 63) wsum[wid] = x;
   __syncthreads();
   uint32_t off = x - mine;
