@@ -92,12 +92,10 @@ __device__ __forceinline__ int find_field(const long long* pre, int n, long long
 __host__ __device__ __forceinline__ int phase_cols(int tx) { return (tx + 2) / 3; }
 
 // launchers (k_field.hip)
-void launch_field_pass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* vpre,
-                         long long vblocks, int4* range, int2* cur, uint8_t* edges, uint32_t* masks, uint8_t* flags,
-                         hipStream_t s);
 constexpr long long RANGE_SPAN_FLOATS = 256 * 256;
-// the same with conversion, edges, faces and flags fused in one time-marching
-// kernel over 32x16 tiles (fpre: tiles per field)
+// range, parameters, then conversion, edges, faces and flags fused in one
+// time-marching kernel over 32x16 tiles (rpre: range workgroups per field,
+// fpre: tiles per field)
 void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* fpre,
                         long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s);
 constexpr int FIELDPASS_TW = 32, FIELDPASS_TH = 16;

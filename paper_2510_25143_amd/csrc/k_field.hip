@@ -209,21 +209,6 @@ __global__ __launch_bounds__(256) void k_flags(const uint32_t* __restrict__ mask
 }
 
 // ------------------------------------------------------- batched field pass
-// Workgroups of 256 vertices never straddle two fields: vpre[f] is the
-// number of such workgroups of the fields before f.
-struct VSeg {
-  int f;
-  size_t i;      // vertex of the field
-  bool valid;
-};
-__device__ __forceinline__ VSeg vseg(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre, int n) {
-  VSeg v;
-  v.f = find_field(vpre, n, blockIdx.x);
-  v.i = (size_t)((long long)blockIdx.x - vpre[v.f]) * 256 + threadIdx.x;
-  v.valid = v.i < (size_t)D[v.f].N;
-  return v;
-}
-
 // per-field range slots: min key, max key, max |x| bits, non-finite seen
 __global__ void k_range_init_b(int4* __restrict__ r, int n) {
   int f = blockIdx.x * blockDim.x + threadIdx.x;
@@ -353,42 +338,6 @@ __global__ void k_params_b(FieldDesc* __restrict__ D, const int4* __restrict__ r
   sl_factor_dev(d.dt_dy, kk, &p.cy, &p.sy);
   d.p = p;
   d.eb_abs = a;
-}
-
-// fixed point, SoS edge signs, face masks and lossless flags of every field
-__global__ __launch_bounds__(256) void k_convert_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
-                                                   int n, int2* __restrict__ cur) {
-  const VSeg v = vseg(D, vpre, n);
-  const FieldDesc& d = D[v.f];
-  if (!v.valid || d.status) return;
-  const size_t N = (size_t)d.N;
-  cur[d.voff + v.i] = make_int2(to_fixed(d.field[v.i], d.p.k), to_fixed(d.field[N + v.i], d.p.k));
-}
-
-__global__ __launch_bounds__(256) void k_edges_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
-                                                 int n, const int2* __restrict__ cur, uint8_t* __restrict__ edges) {
-  const VSeg v = vseg(D, vpre, n);
-  const FieldDesc& d = D[v.f];
-  if (!v.valid || d.status) return;
-  edges[d.voff + v.i] = edge_bits(cur + d.voff, d.H, d.W, d.T, v.i);
-}
-
-__global__ __launch_bounds__(256) void k_faces_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
-                                                 int n, const uint8_t* __restrict__ edges,
-                                                 uint32_t* __restrict__ masks) {
-  const VSeg v = vseg(D, vpre, n);
-  const FieldDesc& d = D[v.f];
-  if (!v.valid || d.status) return;
-  masks[d.voff + v.i] = face_mask(edges + d.voff, d.H, d.W, d.T, v.i);
-}
-
-__global__ __launch_bounds__(256) void k_flags_b(const FieldDesc* __restrict__ D, const long long* __restrict__ vpre,
-                                                 int n, const uint32_t* __restrict__ masks,
-                                                 uint8_t* __restrict__ flags) {
-  const VSeg v = vseg(D, vpre, n);
-  const FieldDesc& d = D[v.f];
-  if (!v.valid || d.status) return;
-  flags[d.voff + v.i] = lossless_flag(masks + d.voff, d.H, d.W, v.i, (size_t)d.H * d.W);
 }
 
 // ------------------------------------------------------ fused field pass
@@ -786,19 +735,6 @@ void launch_write_codes(const uint32_t* masks, const uint32_t* ofs, size_t N, ui
   k_write_codes<<<nblk(N), 256, 0, s>>>(masks, ofs, N, codes, cap);
 }
 size_t compare_partials(size_t N) { return nblk(N); }
-
-void launch_field_pass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* vpre,
-                         long long vblocks, int4* range, int2* cur, uint8_t* edges, uint32_t* masks, uint8_t* flags,
-                         hipStream_t s) {
-  k_range_init_b<<<nblk(n, 64), 64, 0, s>>>(range, n);
-  if (rblocks > 0) k_range_b<<<(unsigned)rblocks, 256, 0, s>>>(D, rpre, n, range);
-  k_params_b<<<nblk(n, 64), 64, 0, s>>>(D, range, n);
-  if (vblocks <= 0) return;
-  k_convert_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, cur);
-  k_edges_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, cur, edges);
-  k_faces_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, edges, masks);
-  k_flags_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, masks, flags);
-}
 
 void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* fpre,
                         long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s) {
