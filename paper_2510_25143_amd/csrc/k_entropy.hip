@@ -309,30 +309,26 @@ __global__ __launch_bounds__(CB_THREADS) void k_codebooks_b(const FieldDesc* __r
   else build_code(qhist + (size_t)f * QSYM, QSYM, qt + f, qcb + (size_t)f * (QSYM + 4), &used[2 * f + 1]);
 }
 
-// One thread per run of 16 vertices (the histogram's grid): every
-// residual-coded vertex puts its two symbols, its 32-bit residual code, at
-// the run's offset plus the coded vertices before it (pairs start at even
-// positions of the chunk-aligned symbol array).
+// One thread per vertex: every residual-coded vertex puts its two symbols,
+// its 32-bit residual code, at its run's offset plus the coded vertices
+// before it in the run (a run of 16 vertices is one 16-lane DPP row of the
+// workgroup; symbol pairs start at even positions of the chunk-aligned
+// symbol array, so consecutive coded vertices write consecutive words).
 __global__ __launch_bounds__(256) void k_gather_q_b(const FieldDesc* __restrict__ D,
-                                                    const long long* __restrict__ hpre, int n,
+                                                    const long long* __restrict__ vpre, int n,
                                                     const uint8_t* __restrict__ xcode,
                                                     const uint32_t* __restrict__ qcode,
                                                     const uint32_t* __restrict__ sq, uint16_t* __restrict__ qsym) {
-  const int f = find_field(hpre, n, blockIdx.x);
+  const int f = find_field(vpre, n, blockIdx.x);
   const FieldDesc& d = D[f];
-  if (d.status) return;
-  const size_t lo = (size_t)((long long)blockIdx.x - hpre[f]) * HIST_SPAN;
-  const size_t N = (size_t)d.N, hi = lo + HIST_SPAN < N ? lo + HIST_SPAN : N;
-  const size_t i0 = lo + (size_t)threadIdx.x * 16;
-  if (i0 >= hi) return;
-  uint8_t xc[16];
-  uint32_t qc[16];
-  load_run(xcode, qcode, (size_t)d.voff, i0, hi, xc, qc);
+  const size_t i = (size_t)((long long)blockIdx.x - vpre[f]) * 256 + threadIdx.x;
+  const bool valid = i < (size_t)d.N && !d.status;
+  const size_t g = d.voff + (valid ? i : 0);
+  const bool coded = valid && xcode[g] != XLOSSLESS;
+  const uint32_t before = row16_exclusive(coded ? 1u : 0u);
+  if (!coded) return;
   uint32_t* out = reinterpret_cast<uint32_t*>(qsym + (size_t)d.cqb * CHUNK);
-  size_t o = (size_t)(sq[d.ro + i0 / 16] - sq[d.ro]);
-#pragma unroll
-  for (int j = 0; j < 16; j++)
-    if (xc[j] < XLOSSLESS) out[o++] = qc[j];
+  out[(size_t)(sq[d.ro + i / 16] - sq[d.ro]) + before] = qcode[g];
 }
 
 // residual symbols and raw values per field, from the prefix sums
@@ -894,8 +890,9 @@ __global__ __launch_bounds__(256) void k_seg_nonll_b(DecDesc* __restrict__ D, co
   bool over = false;
 #pragma unroll
   for (int j = 0; j < 16; j++) {
-    over |= c[j] > XLOSSLESS;
-    cnt += c[j] < XLOSSLESS ? 1u : 0u;
+    const bool in = (unsigned)j < q.len;
+    over |= in && c[j] > XLOSSLESS;
+    cnt += in && c[j] < XLOSSLESS ? 1u : 0u;
   }
   if (over) atomicOr(&d.err, 16u);
   sn[d.soff + q.ls] = cnt;
@@ -914,22 +911,27 @@ __global__ __launch_bounds__(256) void k_seg_raw_b(DecDesc* __restrict__ D, cons
   uint32_t c[16];
   seg_codes(xs + d.voff + q.g0, q.len, c);
   const uint32_t* qq = reinterpret_cast<const uint32_t*>(qs + d.qsb);
-  long long o = 2 * (long long)(uint32_t)(sq[d.soff + q.ls] - sq[d.soff]);
-  uint32_t r = 0;
+  const long long o0 = 2 * (long long)(uint32_t)(sq[d.soff + q.ls] - sq[d.soff]);
+  // every coded vertex's symbol pair, all loads in flight together (an index
+  // past the stream's symbols is an error and reads nothing)
+  uint32_t pr[16];
+  uint32_t ok = 0, r = 0;
   bool bad = false;
-  for (unsigned j = 0; j < q.len; j++) {
-    if (c[j] == XLOSSLESS) {
-      r += 2;
-    } else if (c[j] < XLOSSLESS) {
-      if ((d.p.eps >> c[j]) < 1 || o + 2 > d.nq) {
-        bad = true;
-      } else {
-        const uint32_t pr = qq[o >> 1];
-        r += ((pr & 0xFFFFu) == 0) + ((pr >> 16) == 0);
-      }
-      o += 2;
-    }
+  long long o = o0;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const bool inrow = (unsigned)j < q.len;
+    const bool coded = inrow && c[j] < XLOSSLESS;
+    const bool in = coded && (d.p.eps >> c[j]) >= 1 && o + 2 <= d.nq;
+    bad |= coded && !in;
+    ok |= in ? 1u << j : 0u;
+    pr[j] = in ? qq[o >> 1] : 0xFFFFFFFFu;
+    o += coded ? 2 : 0;
+    r += inrow && c[j] == XLOSSLESS ? 2u : 0u;
   }
+#pragma unroll
+  for (int j = 0; j < 16; j++)
+    if ((ok >> j) & 1u) r += ((pr[j] & 0xFFFFu) == 0) + ((pr[j] >> 16) == 0);
   if (bad) atomicOr(&d.err, 32u);
   sr[d.soff + q.ls] = r;
 }
@@ -981,7 +983,7 @@ void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& 
   launch_scan(E.sn, (size_t)Rtot, E.sq, E.part + 4, tot, s);
   launch_scan(E.sr, (size_t)Rtot, E.sro, E.part + 4, tot + 1, s);
   k_totals_b<<<nblk(n, 64), 64, 0, s>>>(D, n, E.sn, E.sq, E.sr, E.sro);
-  if (hblocks > 0) k_gather_q_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.sq, E.qsym);
+  k_gather_q_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.sq, E.qsym);
 }
 
 void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
