@@ -656,7 +656,7 @@ std::map<std::string, ExecChoice> g_tuned;
 // synchronisation.
 void enqueue_compress(const Plan& P, const BatchBufs& b, const ExecChoice& ex, const Arena& A, hipStream_t s) {
   const int n = P.n;
-  BatchView B{b.D, b.ord, b.cur, b.flags, b.xcode, b.qcode, b.modes, A.tlog, P.opt.selector_w};
+  BatchView B{b.D, b.ord, P.ord[0], b.cur, b.flags, b.xcode, b.qcode, b.modes, A.tlog, P.opt.selector_w};
   // Alg. 3: fixed point, crossed faces of the original field, lossless flags
   {
     TimeScope ts(FAM_EXTRACT, (uint64_t)P.Ntot, s);
@@ -1184,7 +1184,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
       uint64_t units = 0;
       for (int j = 0; j < mt; j++) units += (uint64_t)P.D[P.ord[j]].p.H * P.D[P.ord[j]].p.W;
       TimeScope ts(FAM_RECON, units, s);
-      launch_reconstruct_b(b.D, b.ord, b.rpre, mt, P.rpre[mt], t, b.mtab, b.B, s);
+      launch_reconstruct_b(b.D, b.ord, P.ord[0], b.rpre, mt, P.rpre[mt], t, b.mtab, b.B, s);
     }
     char* rb = A.stage + rb_off;
     HIPCHK(hipMemcpyAsync(rb, b.D, sizeof(DecDesc) * m, hipMemcpyDeviceToHost, s));

@@ -59,6 +59,7 @@ struct FieldDesc {
 struct BatchView {
   FieldDesc* D;
   const int* ord;
+  int ord0;  // ord[0], so that a launch over one field reads no table first
   int2* cur;
   uint8_t* flags;
   uint8_t* xcode;
@@ -171,8 +172,8 @@ void launch_decode_b(DecDesc* D, int n, const DecodeBufs& B, const long long* dx
 // launch order (pre: blocks per stream)
 // mtab[mtb + t]: offset of frame t's predictor classes in the stream's
 // class array, or -1 when frame t has none
-void launch_reconstruct_b(DecDesc* D, const int* ord, const long long* pre, int m, long long nblocks, int t,
-                          const long long* mtab, const DecodeBufs& B, hipStream_t s);
+void launch_reconstruct_b(DecDesc* D, const int* ord, int ord0, const long long* pre, int m, long long nblocks,
+                          int t, const long long* mtab, const DecodeBufs& B, hipStream_t s);
 
 // launchers (k_compress.hip)
 void launch_modes_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int gidx,

@@ -835,7 +835,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                                                 int gidx) {
   __shared__ ModesSmem S;
   const int j = find_field(pre, m, blockIdx.x);
-  const FieldDesc& d = B.D[B.ord[j]];
+  const FieldDesc& d = B.D[j == 0 ? B.ord0 : B.ord[j]];
   if (d.status) return;
   const FieldParams p = d.p;
   const long long li = xcd_band((long long)blockIdx.x - pre[j], pre[j + 1] - pre[j]);
@@ -853,7 +853,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   using Smem = typename std::conditional<DECIDE, TileSmem, PhaseSmem>::type;
   __shared__ Smem S;
   const int j = find_field(pre, m, blockIdx.x);
-  const FieldDesc& d = B.D[B.ord[j]];
+  const FieldDesc& d = B.D[j == 0 ? B.ord0 : B.ord[j]];
   if (d.status) return;
   const FieldParams p = d.p;
   int bx, by;

@@ -23,14 +23,14 @@ namespace cpt {
 constexpr int RC_THREADS = 128, RC_VPL = TILE * TILE / RC_THREADS;
 
 __global__ __launch_bounds__(RC_THREADS) void k_reconstruct_b(DecDesc* __restrict__ D, const int* __restrict__ ord,
-                                                      const long long* __restrict__ pre, int m, int t,
-                                                      const long long* __restrict__ mtab, DecodeBufs B) {
+                                                              int ord0, const long long* __restrict__ pre, int m, int t,
+                                                              const long long* __restrict__ mtab, DecodeBufs B) {
   __shared__ int C[2][TILE][TILE];       // reconstructed fixed-point values (u, v)
   __shared__ int P[2][HALO][HALO];       // previous frame around the block
   __shared__ int A[2][TILE][TILE];       // known value, or frame t-1 Lorenzo term plus q (2 xi~ + 1)
   __shared__ uint8_t KN[2][TILE][TILE];  // component already known (raw or semi-Lagrangian)
   const int j = find_field(pre, m, blockIdx.x);
-  DecDesc& d = D[ord[j]];
+  DecDesc& d = D[j == 0 ? ord0 : ord[j]];  // ord0 = ord[0]: one stream reads no table first
   if (d.status) return;
   const FieldParams p = d.p;
   const int lane = threadIdx.x;
@@ -241,9 +241,9 @@ __global__ __launch_bounds__(RC_THREADS) void k_reconstruct_b(DecDesc* __restric
 }
 
 // ============================================================ launchers
-void launch_reconstruct_b(DecDesc* D, const int* ord, const long long* pre, int m, long long nblocks, int t,
-                          const long long* mtab, const DecodeBufs& B, hipStream_t s) {
-  if (nblocks > 0) k_reconstruct_b<<<(unsigned)nblocks, RC_THREADS, 0, s>>>(D, ord, pre, m, t, mtab, B);
+void launch_reconstruct_b(DecDesc* D, const int* ord, int ord0, const long long* pre, int m, long long nblocks,
+                          int t, const long long* mtab, const DecodeBufs& B, hipStream_t s) {
+  if (nblocks > 0) k_reconstruct_b<<<(unsigned)nblocks, RC_THREADS, 0, s>>>(D, ord, ord0, pre, m, t, mtab, B);
 }
 
 }  // namespace cpt
