@@ -351,103 +351,152 @@ __global__ void k_totals_b(FieldDesc* __restrict__ D, int n, const uint32_t* __r
 }
 
 // bits and 32-bit words of every chunk; chunks past a field's last get 0
+// One wave per chunk, four chunks per workgroup (chunk c = 4 blockIdx + wave
+// of the concatenated chunks; cpre: chunks of the fields before f).  A lane
+// sums the code lengths of symbols lane + 64 k: 16-byte loads of 8 residual
+// or 16 bound symbols where the chunk is aligned, single loads otherwise.
 template <bool RESID>
 __global__ __launch_bounds__(256) void k_chunk_bits_b(const FieldDesc* __restrict__ D,
-                                                      const long long* __restrict__ cpre, int n,
+                                                      const long long* __restrict__ cpre, int n, long long ctot,
                                                       const uint8_t* __restrict__ xcode,
                                                       const uint16_t* __restrict__ qsym,
                                                       const HuffTables* __restrict__ tabs,
                                                       uint32_t* __restrict__ bits, uint32_t* __restrict__ words) {
-  __shared__ uint32_t red[4];
-  const int f = find_field(cpre, n, blockIdx.x);
+  const long long c = 4 * (long long)blockIdx.x + (threadIdx.x >> 6);
+  if (c >= ctot) return;
+  const int lane = threadIdx.x & 63;
+  const int f = find_field(cpre, n, c);
   const FieldDesc& d = D[f];
-  const long long lc = (long long)blockIdx.x - cpre[f];
+  const long long lc = c - cpre[f];
   const size_t slot = (size_t)(RESID ? d.cqb : d.cxb) + lc;
   const long long nsym = d.status ? 0 : (RESID ? d.nq : d.N);
-  const size_t base = (size_t)lc * CHUNK;
+  const long long base = lc * CHUNK;
+  const long long cnt = nsym - base < CHUNK ? nsym - base : CHUNK;  // symbols in this chunk (<= 0: none)
+  const uint8_t* len = tabs[f].len;
   uint32_t b = 0;
-  if ((long long)base < nsym) {
-    const HuffTables* t = tabs + f;
-    for (int i = threadIdx.x; i < CHUNK; i += 256) {
-      const size_t k = base + i;
-      if ((long long)k < nsym) b += RESID ? t->len[qsym[(size_t)d.cqb * CHUNK + k]] : t->len[xcode[d.voff + k]];
+  if (cnt > 0) {
+    constexpr int PER = RESID ? 8 : 16;  // symbols per 16-byte load
+    const void* src = RESID ? (const void*)(qsym + (size_t)d.cqb * CHUNK + base) : (const void*)(xcode + d.voff + base);
+    if (cnt == CHUNK && ((uintptr_t)src & 15) == 0) {
+      const uint4* v = reinterpret_cast<const uint4*>(src);
+      uint4 w[CHUNK / PER / 64];
+#pragma unroll
+      for (int k = 0; k < CHUNK / PER / 64; k++) w[k] = v[lane + 64 * k];
+#pragma unroll
+      for (int k = 0; k < CHUNK / PER / 64; k++) {
+        const uint32_t q[4] = {w[k].x, w[k].y, w[k].z, w[k].w};
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+          if (RESID) {
+            b += len[q[h] & 0xFFFFu];
+            b += len[q[h] >> 16];
+          } else {
+            b += len[q[h] & 0xFFu];
+            b += len[(q[h] >> 8) & 0xFFu];
+            b += len[(q[h] >> 16) & 0xFFu];
+            b += len[q[h] >> 24];
+          }
+        }
+      }
+    } else {
+      for (long long i = lane; i < cnt; i += 64)
+        b += RESID ? len[qsym[(size_t)d.cqb * CHUNK + base + i]] : len[xcode[d.voff + base + i]];
     }
   }
-  // wave sums (DPP rows, then the four rows), then the four waves
   b = row16_sum(b);
   b = (uint32_t)__builtin_amdgcn_readlane((int)b, 0) + (uint32_t)__builtin_amdgcn_readlane((int)b, 16) +
       (uint32_t)__builtin_amdgcn_readlane((int)b, 32) + (uint32_t)__builtin_amdgcn_readlane((int)b, 48);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t tot = red[0] + red[1] + red[2] + red[3];
-    bits[slot] = tot;
-    words[slot] = (tot + 31) / 32;
+  if (lane == 0) {
+    bits[slot] = b;
+    words[slot] = (b + 31) / 32;
   }
 }
 
-// one workgroup per chunk, CHUNK / 256 consecutive symbols per thread; the
-// chunk's words go to the field's bitstream section
+// One wave per chunk as above, CHUNK / 64 = 16 consecutive symbols per lane
+// (16-byte loads where the chunk is aligned); the chunk's words go to the
+// field's bitstream section
 template <bool RESID>
 __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ D, const long long* __restrict__ cpre,
-                                                  int n, const uint8_t* __restrict__ xcode,
+                                                  int n, long long ctot, const uint8_t* __restrict__ xcode,
                                                   const uint16_t* __restrict__ qsym,
                                                   const HuffTables* __restrict__ tabs,
                                                   const uint32_t* __restrict__ wofs) {
-  __shared__ uint32_t w[CHUNK * MAXLEN / 32];
-  __shared__ uint32_t wsum[4];
-  const int f = find_field(cpre, n, blockIdx.x);
+  constexpr int NW = CHUNK * MAXLEN / 32, PER = CHUNK / 64;
+  __shared__ uint32_t wbuf[4][NW];
+  const long long c = 4 * (long long)blockIdx.x + (threadIdx.x >> 6);
+  if (c >= ctot) return;
+  const int lane = threadIdx.x & 63;
+  uint32_t* w = wbuf[threadIdx.x >> 6];
+  const int f = find_field(cpre, n, c);
   const FieldDesc& d = D[f];
-  const long long lc = (long long)blockIdx.x - cpre[f];
+  const long long lc = c - cpre[f];
   const long long nsym = RESID ? d.nq : d.N;
   if (d.status || lc * CHUNK >= nsym) return;
   const HuffTables* t = tabs + f;
   const size_t cb = (size_t)(RESID ? d.cqb : d.cxb);
-  const int per = CHUNK / 256;
-  const size_t base = (size_t)lc * CHUNK + (size_t)threadIdx.x * per;
-  for (int i = threadIdx.x; i < CHUNK * MAXLEN / 32; i += 256) w[i] = 0;
-  uint32_t codes[per];
-  uint8_t lens[per];
+  const long long base = lc * CHUNK + (long long)lane * PER;
+  const long long cnt = nsym - lc * CHUNK < CHUNK ? nsym - lc * CHUNK : CHUNK;
+  for (int i = lane; i < NW; i += 64) w[i] = 0;
+  uint32_t sym[PER];
+  const void* src = RESID ? (const void*)(qsym + cb * CHUNK + lc * CHUNK) : (const void*)(xcode + d.voff + lc * CHUNK);
+  if (cnt == CHUNK && ((uintptr_t)src & 15) == 0) {
+    if (RESID) {
+      const uint4* v = reinterpret_cast<const uint4*>(src) + 2 * lane;
+      const uint4 a = v[0], bq = v[1];
+      const uint32_t h[8] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w};
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        sym[2 * i] = h[i] & 0xFFFFu;
+        sym[2 * i + 1] = h[i] >> 16;
+      }
+    } else {
+      const uint4 a = reinterpret_cast<const uint4*>(src)[lane];
+      const uint32_t h[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+      for (int i = 0; i < 16; i++) sym[i] = (h[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < PER; i++)
+      sym[i] = base + i < nsym ? (RESID ? (uint32_t)qsym[cb * CHUNK + base + i] : (uint32_t)xcode[d.voff + base + i])
+                               : 0xFFFFFFFFu;
+  }
+  uint32_t codes[PER];
+  uint8_t lens[PER];
   uint32_t mine = 0;
 #pragma unroll
-  for (int i = 0; i < per; i++) {
-    if ((long long)(base + i) < nsym) {
-      const uint32_t s = RESID ? qsym[cb * CHUNK + base + i] : xcode[d.voff + base + i];
-      codes[i] = t->code[s];
-      lens[i] = t->len[s];
-    } else {
-      codes[i] = 0;
-      lens[i] = 0;
-    }
+  for (int i = 0; i < PER; i++) {
+    const bool in = sym[i] != 0xFFFFFFFFu;
+    codes[i] = in ? t->code[sym[i]] : 0u;
+    lens[i] = in ? t->len[sym[i]] : (uint8_t)0;
     mine += lens[i];
   }
-  // exclusive prefix of bit counts over the workgroup
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t x = wave_inclusive(mine);
-  if (lane == 63) wsum[wid] = x;
-  __syncthreads();
-  uint32_t off = x - mine;
-  for (int q = 0; q < wid; q++) off += wsum[q];
-  uint32_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  // exclusive prefix of bit counts over the wave
+  const uint32_t incl = wave_inclusive(mine);
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  uint32_t off = incl - mine;
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
-  for (int i = 0; i < per; i++) {
-    uint32_t l = lens[i];
+  for (int i = 0; i < PER; i++) {
+    const uint32_t l = lens[i];
     if (!l) continue;
-    uint32_t c = codes[i];
-    uint32_t wi = off >> 5, o = off & 31;
+    const uint32_t cw = codes[i];
+    const uint32_t wi = off >> 5, o = off & 31;
     if (o + l <= 32) {
-      atomicOr(&w[wi], c << (32 - o - l));
+      atomicOr(&w[wi], cw << (32 - o - l));
     } else {
-      uint32_t spill = o + l - 32;
-      atomicOr(&w[wi], c >> spill);
-      atomicOr(&w[wi + 1], c << (32 - spill));
+      const uint32_t spill = o + l - 32;
+      atomicOr(&w[wi], cw >> spill);
+      atomicOr(&w[wi + 1], cw << (32 - spill));
     }
     off += l;
   }
-  __syncthreads();
-  uint32_t nw = (total + 31) / 32;
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const uint32_t nw = (total + 31) / 32;
   uint32_t* dst = (uint32_t*)(d.out + d.off[RESID ? 6 : 3]) + (wofs[cb + lc] - wofs[cb]);
-  for (uint32_t i = threadIdx.x; i < nw; i += 256) dst[i] = w[i];
+  for (uint32_t i = lane; i < nw; i += 64) dst[i] = w[i];
 }
 
 // Stream layout of every field: section lengths and offsets, total length,
@@ -990,11 +1039,13 @@ void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs&
                      long long cxtot, const long long* cqpre, long long cqtot, hipStream_t s) {
   uint32_t* tot = E.part;
   if (cxtot > 0) {
-    k_chunk_bits_b<false><<<(unsigned)cxtot, 256, 0, s>>>(D, cxpre, n, B.xcode, E.qsym, E.xt, E.xbits, E.xwords);
+    k_chunk_bits_b<false><<<(unsigned)((cxtot + 3) / 4), 256, 0, s>>>(D, cxpre, n, cxtot, B.xcode, E.qsym, E.xt,
+                                                                        E.xbits, E.xwords);
     launch_scan(E.xwords, (size_t)cxtot, E.xwofs, E.part + 4, tot + 2, s);
   }
   if (cqtot > 0) {
-    k_chunk_bits_b<true><<<(unsigned)cqtot, 256, 0, s>>>(D, cqpre, n, B.xcode, E.qsym, E.qt, E.qbits, E.qwords);
+    k_chunk_bits_b<true><<<(unsigned)((cqtot + 3) / 4), 256, 0, s>>>(D, cqpre, n, cqtot, B.xcode, E.qsym, E.qt,
+                                                                       E.qbits, E.qwords);
     launch_scan(E.qwords, (size_t)cqtot, E.qwofs, E.part + 4, tot + 3, s);
   }
   k_layout_b<<<n, 64, 0, s>>>(D, E.used, E.xwords, E.xwofs, E.qwords, E.qwofs);
@@ -1004,8 +1055,10 @@ void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBuf
                        long long cxtot, const long long* cqpre, long long cqtot, const long long* hpre,
                        long long hblocks, hipStream_t s) {
   k_sections_b<<<dim3(n, 16), 256, 0, s>>>(D, B.modes, E.xcb, E.qcb, E.used, E.xbits, E.qbits);
-  if (cxtot > 0) k_encode_b<false><<<(unsigned)cxtot, 256, 0, s>>>(D, cxpre, n, B.xcode, E.qsym, E.xt, E.xwofs);
-  if (cqtot > 0) k_encode_b<true><<<(unsigned)cqtot, 256, 0, s>>>(D, cqpre, n, B.xcode, E.qsym, E.qt, E.qwofs);
+  if (cxtot > 0)
+    k_encode_b<false><<<(unsigned)((cxtot + 3) / 4), 256, 0, s>>>(D, cxpre, n, cxtot, B.xcode, E.qsym, E.xt, E.xwofs);
+  if (cqtot > 0)
+    k_encode_b<true><<<(unsigned)((cqtot + 3) / 4), 256, 0, s>>>(D, cqpre, n, cqtot, B.xcode, E.qsym, E.qt, E.qwofs);
   if (hblocks > 0) k_raw_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.sro);
 }
 void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long long* mpre, long long mblocks,
