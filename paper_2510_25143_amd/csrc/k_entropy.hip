@@ -309,26 +309,57 @@ __global__ __launch_bounds__(CB_THREADS) void k_codebooks_b(const FieldDesc* __r
   else build_code(qhist + (size_t)f * QSYM, QSYM, qt + f, qcb + (size_t)f * (QSYM + 4), &used[2 * f + 1]);
 }
 
-// One thread per vertex: every residual-coded vertex puts its two symbols,
-// its 32-bit residual code, at its run's offset plus the coded vertices
-// before it in the run (a run of 16 vertices is one 16-lane DPP row of the
-// workgroup; symbol pairs start at even positions of the chunk-aligned
-// symbol array, so consecutive coded vertices write consecutive words).
+// Four consecutive vertices per lane (1024 per workgroup), so a run of 16
+// vertices is one DPP quad: every residual-coded vertex puts its two
+// symbols, its 32-bit residual code, at its run's offset plus the coded
+// vertices before it in the run (symbol pairs start at even positions of
+// the chunk-aligned symbol array).  Four workgroups per histogram span of
+// hpre; those wholly past a field's end only take part in no store.
 __global__ __launch_bounds__(256) void k_gather_q_b(const FieldDesc* __restrict__ D,
-                                                    const long long* __restrict__ vpre, int n,
+                                                    const long long* __restrict__ hpre, int n,
                                                     const uint8_t* __restrict__ xcode,
                                                     const uint32_t* __restrict__ qcode,
                                                     const uint32_t* __restrict__ sq, uint16_t* __restrict__ qsym) {
-  const int f = find_field(vpre, n, blockIdx.x);
+  static_assert(HIST_SPAN_VERTICES == 4 * 1024, "four gather workgroups per histogram span");
+  const int f = find_field(hpre, n, blockIdx.x >> 2);
   const FieldDesc& d = D[f];
-  const size_t i = (size_t)((long long)blockIdx.x - vpre[f]) * 256 + threadIdx.x;
-  const bool valid = i < (size_t)d.N && !d.status;
-  const size_t g = d.voff + (valid ? i : 0);
-  const bool coded = valid && xcode[g] != XLOSSLESS;
-  const uint32_t before = row16_exclusive(coded ? 1u : 0u);
-  if (!coded) return;
+  const size_t i0 = (size_t)((long long)blockIdx.x - 4 * hpre[f]) * 1024 + 4 * (size_t)threadIdx.x;
+  const size_t N = (size_t)d.N;
+  const bool live = !d.status && i0 < N;
+  uint32_t xc[4], qc[4];
+  const size_t g = d.voff + (live ? i0 : 0);
+  if (live && i0 + 4 <= N && (g & 3) == 0) {
+    const uint32_t xw = *reinterpret_cast<const uint32_t*>(xcode + g);
+    const uint4 qw = *reinterpret_cast<const uint4*>(qcode + g);
+#pragma unroll
+    for (int k = 0; k < 4; k++) xc[k] = (xw >> (8 * k)) & 0xFFu;
+    qc[0] = qw.x;
+    qc[1] = qw.y;
+    qc[2] = qw.z;
+    qc[3] = qw.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const bool in = live && i0 + k < N;
+      xc[k] = in ? xcode[g + k] : (uint32_t)XLOSSLESS;
+      qc[k] = in ? qcode[g + k] : 0u;
+    }
+  }
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) cnt += xc[k] != XLOSSLESS ? 1u : 0u;
+  // coded vertices of the lanes before this one in its quad
+  const int qi = threadIdx.x & 3;
+  const uint32_t t1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)cnt, 0x90, 0xF, 0xF, true);  // quad_perm [0,0,1,2]
+  const uint32_t t2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)cnt, 0x40, 0xF, 0xF, true);  // quad_perm [0,0,0,1]
+  const uint32_t t3 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)cnt, 0x00, 0xF, 0xF, true);  // quad_perm [0,0,0,0]
+  const uint32_t before = (qi >= 1 ? t1 : 0u) + (qi >= 2 ? t2 : 0u) + (qi >= 3 ? t3 : 0u);
+  if (!live) return;
   uint32_t* out = reinterpret_cast<uint32_t*>(qsym + (size_t)d.cqb * CHUNK);
-  out[(size_t)(sq[d.ro + i / 16] - sq[d.ro]) + before] = qcode[g];
+  size_t o = (size_t)(sq[d.ro + i0 / 16] - sq[d.ro]) + before;
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+    if (xc[k] != XLOSSLESS) out[o++] = qc[k];
 }
 
 // residual symbols and raw values per field, from the prefix sums
@@ -1032,7 +1063,7 @@ void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& 
   launch_scan(E.sn, (size_t)Rtot, E.sq, E.part + 4, tot, s);
   launch_scan(E.sr, (size_t)Rtot, E.sro, E.part + 4, tot + 1, s);
   k_totals_b<<<nblk(n, 64), 64, 0, s>>>(D, n, E.sn, E.sq, E.sr, E.sro);
-  k_gather_q_b<<<(unsigned)vblocks, 256, 0, s>>>(D, vpre, n, B.xcode, B.qcode, E.sq, E.qsym);
+  k_gather_q_b<<<(unsigned)(4 * hblocks), 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.sq, E.qsym);
 }
 
 void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
