@@ -79,6 +79,8 @@ def lib():
             "cpo_lorenzo3": (i64, [P, P, i32, i32, i32, i32, i32]),
             "cpo_choose": (ctypes.c_int, [P, i32]),
             "cpo_xi_code": (i32, [i64, i64]),
+            "cpo_vertex_bound": (i64, [P, P, P, i32, i32, i32, i32, i32, i32, i64]),
+            "cpo_block_mode": (ctypes.c_int, [P, P, P, P, P, i32, i32, i32, i32, P, i32, i64, P]),
             "cpo_tlog": (i64, [i32]),
             "cpo_score": (i64, [P, i32, i32, i32, i32, i32]),
             "cpo_huffman_lengths": (ctypes.c_int, [P, i32, i32, P]),
@@ -228,6 +230,38 @@ def choose(R):
 
 def xi_code(eps, xi):
     return lib().cpo_xi_code(int(eps), int(xi))
+
+
+def vertex_bound(U, V, flags, x, y, t, eps):
+    """Alg. 4 bound of vertex (x, y, t) on the current values U, V
+    ((T, H, W) int32: reconstructed where already processed, original
+    elsewhere) and the lossless flags (T, H, W)."""
+    U = np.ascontiguousarray(U, dtype=np.int32)
+    V = np.ascontiguousarray(V, dtype=np.int32)
+    fl = np.ascontiguousarray(flags, dtype=np.uint8)
+    T, H, W = U.shape
+    assert V.shape == U.shape and fl.shape == U.shape
+    assert 0 <= x < W and 0 <= y < H and 0 <= t < T
+    return lib().cpo_vertex_bound(_p(U), _p(V), _p(fl), H, W, T, x, y, t, int(eps))
+
+
+def block_mode(Ut, Vt, Up, Vp, flags_t, bx, by, k, eps, predictor=2, mode_bt=1, dt_dx=1.0,
+               dt_dy=1.0, selector_w=None):
+    """Predictor class of block (bx, by) at a decision frame, from the
+    frame's original planes, the previous frame's reconstructed planes and
+    the frame's lossless flags ((H, W) each); returns (class, features)."""
+    planes = [np.ascontiguousarray(a, dtype=np.int32) for a in (Ut, Vt, Up, Vp)]
+    fl = np.ascontiguousarray(flags_t, dtype=np.uint8)
+    H, W = planes[0].shape
+    assert all(a.shape == (H, W) for a in planes) and fl.shape == (H, W)
+    o, keep = _opts(predictor, mode_bt, 0, dt_dx, dt_dy, selector_w)
+    feat = np.zeros(NFEAT, dtype=np.float32)
+    r = lib().cpo_block_mode(*[_p(a) for a in planes], _p(fl), H, W, bx, by, ctypes.byref(o), k,
+                             int(eps), _p(feat))
+    del keep
+    if r < 0:
+        raise ValueError("cpo_block_mode failed: %d" % r)
+    return r, feat
 
 
 def tlog(h):

@@ -305,8 +305,8 @@ int64_t cpo_alg2(int64_t u0, int64_t u1, int64_t u2, int64_t v0, int64_t v1,
 /* Alg. 4: zero when the vertex touches a face of C, else the minimum of eps'
    and Alg. 2 over every incident face, evaluated on the current values
    (reconstructed where already processed, original elsewhere). */
-static int64_t vertex_bound(const int32_t* U, const int32_t* V, const uint8_t* flags,
-                            int H, int W, int T, int x, int y, int t, int64_t eps) {
+int64_t cpo_vertex_bound(const int32_t* U, const int32_t* V, const uint8_t* flags,
+                         int H, int W, int T, int x, int y, int t, int64_t eps) {
   size_t v = vid(H, W, x, y, t);
   if (flags[v]) return 0;
   int32_t nb[72];
@@ -1018,6 +1018,69 @@ static int decide_mode(const ctx_t* c, int t, int x0, int y0, int x1, int y1,
   return cpo_choose(R, c->K);
 }
 
+/* The predictor class that the decision of Sec. VI-B gives block (bx, by)
+   of a decision frame, and the block's features, from that frame's original
+   values (Ut, Vt), the previous frame's current (reconstructed) values (Up,
+   Vp) and the frame's lossless flags: the steps of compression, run on a
+   two-frame copy.  Needs a predictor with a choice (2, 3 or 4); returns the
+   class, or CPO_EINVAL / CPO_ENOMEM. */
+int cpo_block_mode(const int32_t* Ut, const int32_t* Vt, const int32_t* Up, const int32_t* Vp,
+                   const uint8_t* flags_t, int H, int W, int bx, int by, const cpo_options* opt,
+                   int k, int64_t eps, float* feat) {
+  if (!opt || opt->predictor < 2 || opt->predictor > 4 || opt->mode_bt < 1) return CPO_EINVAL;
+  if (opt->predictor == 4 && !opt->selector_w) return CPO_EINVAL;
+  ctx_t c;
+  memset(&c, 0, sizeof(c));
+  c.H = H;
+  c.W = W;
+  c.T = 2;
+  c.k = k;
+  c.eps = eps;
+  c.predictor = opt->predictor;
+  c.bt = opt->mode_bt;
+  c.K = opt->predictor == 2 ? 2 : 4;
+  c.tx = (W + TILE - 1) / TILE;
+  c.ty = (H + TILE - 1) / TILE;
+  c.selw = opt->selector_w;
+  if (bx < 0 || by < 0 || bx >= c.tx || by >= c.ty) return CPO_EINVAL;
+  cpo_sl_factor(opt->dt_dx, k, &c.cx, &c.sx);
+  cpo_sl_factor(opt->dt_dy, k, &c.cy, &c.sy);
+  size_t HW = (size_t)H * W;
+  int32_t* F0 = (int32_t*)malloc(4 * HW * sizeof(int32_t));
+  int32_t* F = (int32_t*)malloc(4 * HW * sizeof(int32_t));
+  uint8_t* fl = (uint8_t*)calloc(2 * HW, 1);
+  int32_t* SU = (int32_t*)malloc(HW * sizeof(int32_t));
+  int32_t* SV = (int32_t*)malloc(HW * sizeof(int32_t));
+  int32_t* hist = (int32_t*)malloc(QSYM * sizeof(int32_t));
+  int r = CPO_ENOMEM;
+  if (F0 && F && fl && SU && SV && hist) {
+    /* frame 0 of the copy is the previous frame, frame 1 the decision frame */
+    memcpy(F0, Up, HW * sizeof(int32_t));
+    memcpy(F0 + HW, Ut, HW * sizeof(int32_t));
+    memcpy(F0 + 2 * HW, Vp, HW * sizeof(int32_t));
+    memcpy(F0 + 3 * HW, Vt, HW * sizeof(int32_t));
+    memcpy(F, F0, 4 * HW * sizeof(int32_t));
+    memcpy(fl + HW, flags_t, HW);
+    c.U0 = F0;
+    c.V0 = F0 + 2 * HW;
+    c.U = F;
+    c.V = F + 2 * HW;
+    c.flags = fl;
+    int x0 = bx * TILE, y0 = by * TILE;
+    int x1 = x0 + TILE < W ? x0 + TILE : W, y1 = y0 + TILE < H ? y0 + TILE : H;
+    float f[CPO_NFEAT];
+    r = decide_mode(&c, 1, x0, y0, x1, y1, SU, SV, hist, f);
+    if (feat) memcpy(feat, f, sizeof(f));
+  }
+  free(F0);
+  free(F);
+  free(fl);
+  free(SU);
+  free(SV);
+  free(hist);
+  return r;
+}
+
 size_t cpo_compress_bound(int H, int W, int T) {
   size_t N = (size_t)H * W * T;
   size_t nch = (N + CHUNK - 1) / CHUNK, nq = 2 * N, nqch = (nq + CHUNK - 1) / CHUNK;
@@ -1111,7 +1174,7 @@ int cpo_compress_ex(const float* field, int H, int W, int T, double eb,
           for (int y = y0; y < y1; y++)
             for (int x = x0; x < x1; x++) {
               size_t v = vid(H, W, x, y, t);
-              int64_t xi = vertex_bound(c.U, c.V, flags, H, W, T, x, y, t, c.eps);
+              int64_t xi = cpo_vertex_bound(c.U, c.V, flags, H, W, T, x, y, t, c.eps);
               int32_t code = cpo_xi_code(c.eps, xi);
               if (xi_out) xi_out[v] = (int32_t)xi;
               xcode[v] = (uint8_t)code;

@@ -94,6 +94,11 @@ int cpo_choose(const int64_t* R, int K);
 int32_t cpo_quantize(int64_t x, int64_t pred, int64_t xt, int64_t* recon);
 /* Error-bound code: smallest q with (eps>>q) <= xi, 24 for xi == 0. */
 int32_t cpo_xi_code(int64_t eps, int64_t xi);
+/* Alg. 4 bound of vertex (x,y,t) on the current values U, V ([T][H][W]:
+   reconstructed where already processed, original elsewhere) with the
+   lossless flags; 0 for a flagged vertex. */
+int64_t cpo_vertex_bound(const int32_t* U, const int32_t* V, const uint8_t* flags,
+                         int H, int W, int T, int x, int y, int t, int64_t eps);
 
 /* Entropy-score table entry floor(h log2 h 2^16) and block score. */
 int64_t cpo_tlog(int h);
@@ -126,6 +131,14 @@ int cpo_compress_ex(const float* field, int H, int W, int T, double eb,
 int cpo_compress(const float* field, int H, int W, int T, double eb,
                  const cpo_options* opt, uint8_t* out, size_t cap,
                  size_t* out_len);
+/* Predictor class of block (bx,by) at a decision frame (Sec. VI-B) from the
+   frame's original planes Ut, Vt, the previous frame's current planes Up, Vp
+   and the frame's lossless flags ([H][W] each); feat [10] may be NULL.
+   Returns the class or a negative status. */
+int cpo_block_mode(const int32_t* Ut, const int32_t* Vt, const int32_t* Up,
+                   const int32_t* Vp, const uint8_t* flags_t, int H, int W,
+                   int bx, int by, const cpo_options* opt, int k, int64_t eps,
+                   float* feat);
 size_t cpo_compress_bound(int H, int W, int T);
 int cpo_stream_info(const uint8_t* bytes, size_t len, cpo_info* info);
 int cpo_decompress(const uint8_t* bytes, size_t len, float* field);
