@@ -371,7 +371,7 @@ struct Plan {
   int K = 1, maxT = 0;
   std::vector<FieldDesc> D;
   std::vector<int> ord;
-  std::vector<long long> rpre, vpre, hpre, cxpre, cqpre, fpre;  // natural order
+  std::vector<long long> rpre, gpre, hpre, cxpre, cqpre, fpre;  // natural order
   std::vector<long long> mpre, ppre;                      // launch order
   std::vector<int> m_at, mstate_at, gidx_at;              // per frame
   std::vector<uint64_t> hw_at, cv_at;                     // vertices per frame / per phase
@@ -416,7 +416,7 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
   P.K = opt.predictor == 2 ? 2 : (opt.predictor >= 3 ? 4 : 1);
   const int K = P.K, bt = opt.mode_bt, mb = mode_bits(K);
   P.D.assign(n, FieldDesc{});
-  for (auto* v : {&P.rpre, &P.vpre, &P.hpre, &P.cxpre, &P.cqpre, &P.fpre, &P.mpre, &P.ppre}) v->assign(n + 1, 0);
+  for (auto* v : {&P.rpre, &P.gpre, &P.hpre, &P.cxpre, &P.cqpre, &P.fpre, &P.mpre, &P.ppre}) v->assign(n + 1, 0);
   P.key = std::to_string(n) + ":" + std::to_string(opt.predictor) + ":" + std::to_string(bt);
   for (int i = 0; i < n; i++) {
     const int H = HWT[3 * i], W = HWT[3 * i + 1], T = HWT[3 * i + 2];
@@ -454,7 +454,7 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
     P.CQ += ncq;
     P.NB += nblk;
     P.rpre[i + 1] = P.rpre[i] + (2 * N + RANGE_SPAN_FLOATS - 1) / RANGE_SPAN_FLOATS;
-    P.vpre[i + 1] = P.vpre[i] + (N + 255) / 256;
+    P.gpre[i + 1] = P.gpre[i] + (N + HIST_WG_VERTICES - 1) / HIST_WG_VERTICES;
     P.hpre[i + 1] = P.hpre[i] + (N + HIST_SPAN_VERTICES - 1) / HIST_SPAN_VERTICES;
     P.cxpre[i + 1] = P.cxpre[i] + d.nchx;
     P.cqpre[i + 1] = P.cqpre[i] + ncq;
@@ -462,7 +462,7 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
     P.maxT = std::max(P.maxT, T);
     P.key += ":" + std::to_string(H) + "x" + std::to_string(W) + "x" + std::to_string(T);
   }
-  for (auto v : {P.rpre.back(), P.vpre.back(), P.hpre.back(), P.cxpre.back(), P.cqpre.back(), P.fpre.back()})
+  for (auto v : {P.rpre.back(), P.gpre.back(), P.hpre.back(), P.cxpre.back(), P.cqpre.back(), P.fpre.back()})
     if (v >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
   P.ord.resize(n);
   for (int i = 0; i < n; i++) P.ord[i] = i;
@@ -544,7 +544,7 @@ cpt_status build_schedule(Plan& P, int group) {
 struct BatchBufs {
   FieldDesc* D;
   int* ord;
-  long long *rpre, *vpre, *hpre, *cxpre, *cqpre, *fpre, *mpre, *ppre, *sstart;
+  long long *rpre, *gpre, *hpre, *cxpre, *cqpre, *fpre, *mpre, *ppre, *sstart;
   SchedSeg* seg;
   size_t tables_bytes;
   unsigned *done, *ctl;
@@ -570,7 +570,7 @@ cpt_status carve_batch(Arena& A, const Plan& P, BatchBufs& b) {
   };
   std::vector<Item> tables = {
       {(void**)&b.D, sizeof(FieldDesc) * n}, {(void**)&b.ord, 4 * (size_t)n},
-      {(void**)&b.rpre, vec_bytes(P.rpre)},   {(void**)&b.vpre, vec_bytes(P.vpre)},
+      {(void**)&b.rpre, vec_bytes(P.rpre)},   {(void**)&b.gpre, vec_bytes(P.gpre)},
       {(void**)&b.hpre, vec_bytes(P.hpre)},   {(void**)&b.cxpre, vec_bytes(P.cxpre)},
       {(void**)&b.cqpre, vec_bytes(P.cqpre)}, {(void**)&b.fpre, vec_bytes(P.fpre)},
       {(void**)&b.mpre, vec_bytes(P.mpre)},
@@ -579,7 +579,7 @@ cpt_status carve_batch(Arena& A, const Plan& P, BatchBufs& b) {
   };
   std::vector<Item> rest = {
       {(void**)&b.done, 4 * (size_t)n + 64},   {(void**)&b.ctl, 64},
-      {(void**)&b.range, 16 * (size_t)n},       {(void**)&b.cur, 8 * N},
+      {(void**)&b.range, 16 * (size_t)RANGE_SLOTS * RANGE_SLOT_STRIDE * n},       {(void**)&b.cur, 8 * N},
       {(void**)&b.flags, N},                    {(void**)&b.xcode, N},
       {(void**)&b.modes, (size_t)P.NB + 1},     {(void**)&b.qcode, 4 * N},
       {(void**)&b.E.sn, 4 * R + 16},            {(void**)&b.E.sq, 4 * R + 16},
@@ -588,7 +588,7 @@ cpt_status carve_batch(Arena& A, const Plan& P, BatchBufs& b) {
       {(void**)&b.E.xwords, 4 * CX},            {(void**)&b.E.xwofs, 4 * CX},
       {(void**)&b.E.qbits, 4 * CQ},             {(void**)&b.E.qwords, 4 * CQ},
       {(void**)&b.E.qwofs, 4 * CQ},             {(void**)&b.E.part, 4 * (scan_partials_size(N) + 16)},
-      {(void**)&b.E.xhist, 128 * (size_t)n},    {(void**)&b.E.qhist, 4 * (size_t)QSYM * n},
+      {(void**)&b.E.xhist, 128 * (size_t)HIST_SLOTS * n},    {(void**)&b.E.qhist, 4 * (size_t)QSYM * HIST_SLOTS * n},
       {(void**)&b.E.xcb, 128 * (size_t)n},      {(void**)&b.E.qcb, 4 * (size_t)(QSYM + 4) * n},
       {(void**)&b.E.used, 8 * (size_t)n},       {(void**)&b.E.xt, sizeof(HuffTables) * n},
       {(void**)&b.E.qt, sizeof(HuffTables) * n},
@@ -633,7 +633,7 @@ void stage_tables(const Plan& P, const BatchBufs& b, char* stage) {
   put(b.D, P.D.data(), sizeof(FieldDesc) * P.n);
   put(b.ord, P.ord.data(), 4 * (size_t)P.n);
   put(b.rpre, P.rpre.data(), vec_bytes(P.rpre));
-  put(b.vpre, P.vpre.data(), vec_bytes(P.vpre));
+  put(b.gpre, P.gpre.data(), vec_bytes(P.gpre));
   put(b.hpre, P.hpre.data(), vec_bytes(P.hpre));
   put(b.cxpre, P.cxpre.data(), vec_bytes(P.cxpre));
   put(b.cqpre, P.cqpre.data(), vec_bytes(P.cqpre));
@@ -683,7 +683,7 @@ void enqueue_compress(const Plan& P, const BatchBufs& b, const ExecChoice& ex, c
     }
   }
   // lossless_comp of Alg. 3: Huffman codes of both code streams, raw values
-  launch_codes_b(b.D, n, B, b.E, b.hpre, P.hpre.back(), b.vpre, P.vpre.back(), P.Rtot, s);
+  launch_codes_b(b.D, n, B, b.E, b.hpre, P.hpre.back(), b.gpre, P.gpre.back(), P.Rtot, s);
   launch_chunks_b(b.D, n, B, b.E, b.cxpre, P.CX, b.cqpre, P.CQ, s);
   {
     TimeScope ts(FAM_ENCODE, (uint64_t)P.Ntot, s);

@@ -94,6 +94,8 @@ __host__ __device__ __forceinline__ int phase_cols(int tx) { return (tx + 2) / 3
 
 // launchers (k_field.hip)
 constexpr long long RANGE_SPAN_FLOATS = 256 * 256;
+// range slots per field (int4 each, RANGE_SLOT_STRIDE int4 apart)
+constexpr int RANGE_SLOTS = 32, RANGE_SLOT_STRIDE = 8;
 // range, parameters, then conversion, edges, faces and flags fused in one
 // time-marching kernel over 32x16 tiles (rpre: range workgroups per field,
 // fpre: tiles per field)
@@ -101,10 +103,12 @@ void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rb
                         long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s);
 constexpr int FIELDPASS_TW = 32, FIELDPASS_TH = 16;
 
-// launchers (k_entropy.hip); vpre: 256-vertex workgroups per field, hpre:
-// HIST_SPAN-vertex workgroups, cxpre / cqpre: bound-code / residual-code
-// chunk capacity per field
+// launchers (k_entropy.hip); gpre: HIST_WG-vertex histogram workgroups per
+// field, hpre: HIST_SPAN-vertex workgroups, cxpre / cqpre: bound-code /
+// residual-code chunk capacity per field
 constexpr long long HIST_SPAN_VERTICES = 256 * 16;
+constexpr long long HIST_WG_VERTICES = 4 * HIST_SPAN_VERTICES;
+constexpr int HIST_SLOTS = 8;  // partial histograms per field and alphabet
 struct EntropyBufs {
   uint32_t *xhist, *qhist, *xcb, *qcb, *used;
   HuffTables *xt, *qt;
@@ -116,7 +120,7 @@ struct EntropyBufs {
   uint32_t* part;
 };
 void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* hpre,
-                    long long hblocks, const long long* vpre, long long vblocks, long long Rtot, hipStream_t s);
+                    long long hblocks, const long long* gpre, long long gblocks, long long Rtot, hipStream_t s);
 void launch_chunks_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,
                      long long cxtot, const long long* cqpre, long long cqtot, hipStream_t s);
 void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* cxpre,

@@ -21,10 +21,11 @@ __global__ void k_zero(uint32_t* p, size_t n) {
 
 // ----------------------------------------------------------- codebook
 // One workgroup of 1024 threads builds the length-limited canonical code of
-// one alphabet (nsym <= 1024).
+// one alphabet (nsym <= 1024) from the sum of the HIST_SLOTS partial
+// histograms at hist + s * stride.
 constexpr int CB_THREADS = 1024;
 
-__device__ void build_code(const uint32_t* __restrict__ hist, int nsym, HuffTables* __restrict__ out,
+__device__ void build_code(const uint32_t* __restrict__ hist, int stride, int nsym, HuffTables* __restrict__ out,
                            uint32_t* __restrict__ cb, uint32_t* __restrict__ used_out) {
   __shared__ uint64_t key[1024];          // (count << 11) | symbol, sorted
   __shared__ uint64_t lw[2][2048];        // list weights, double-buffered
@@ -36,10 +37,13 @@ __device__ void build_code(const uint32_t* __restrict__ hist, int nsym, HuffTabl
   __shared__ int lcount[MAXLEN + 2];
   __shared__ uint32_t first[MAXLEN + 2];
   __shared__ uint32_t wsum[16];
+  __shared__ uint32_t wlen[CB_THREADS / 64][MAXLEN + 1];
   const int tid = threadIdx.x;
 
   // used symbols as sortable keys
-  uint32_t c = tid < nsym ? hist[tid] : 0;
+  uint32_t c = 0;
+  if (tid < nsym)
+    for (int sl = 0; sl < HIST_SLOTS; sl++) c += hist[(size_t)sl * stride + tid];
   key[tid] = c ? (((uint64_t)c << 11) | (uint64_t)tid) : ~0ull;
   clen[tid] = 0;
   if (tid == 0) nleaf = 0;
@@ -168,15 +172,24 @@ __device__ void build_code(const uint32_t* __restrict__ hist, int nsym, HuffTabl
     }
     __syncthreads();
   }
-  if (tid < nsym) {
-    uint32_t code = 0;
-    if (l) {
-      uint32_t r = 0;
-      for (int s = 0; s < tid; s++) r += clen[s] == l ? 1u : 0u;
-      code = first[l] + r;
+  // rank among the symbols of the same length before it: ballots inside
+  // the wave, per-wave counts for the waves before
+  {
+    const int lane = tid & 63, wid = tid >> 6;
+    const uint64_t below = (1ull << lane) - 1;
+    uint32_t r = 0;
+    for (int L = 1; L <= MAXLEN; L++) {
+      const uint64_t m = __ballot(l == (uint32_t)L);
+      if (l == (uint32_t)L) r = (uint32_t)__popcll(m & below);
+      if (lane == 0) wlen[wid][L] = (uint32_t)__popcll(m);
     }
-    out->code[tid] = code;
-    out->len[tid] = (uint8_t)l;
+    __syncthreads();
+    if (l)
+      for (int w = 0; w < wid; w++) r += wlen[w][l];
+    if (tid < nsym) {
+      out->code[tid] = l ? first[l] + r : 0u;
+      out->len[tid] = (uint8_t)l;
+    }
   }
 }
 
@@ -190,27 +203,39 @@ __device__ void build_code(const uint32_t* __restrict__ hist, int nsym, HuffTabl
 // Per-field histograms of the bound codes and residual codes, and per
 // vertex the raw-value count (both components of a lossless vertex, else
 // the components whose residual code is 0) and the non-lossless indicator.
-// hpre[f]: workgroups of HIST_SPAN vertices of the fields before f; each
-// thread takes 16 consecutive vertices and merges runs of equal codes in
-// registers before adding them to the shared histograms.
+// gpre[f]: workgroups of HIST_WG vertices of the fields before f; the
+// workgroup takes its spans of HIST_SPAN vertices in turn, each thread 16
+// consecutive vertices of a span.  The eight residual symbols around
+// QR (residuals -4 .. 3) and the bound codes 0 .. 7, which take most
+// vertices, are counted in packed 8-bit fields of a thread's registers and
+// summed per wave; only the other symbols are added to the shared
+// histograms, so few lanes of a wave add to one LDS word at once.
 constexpr int HIST_SPAN = (int)HIST_SPAN_VERTICES;
 static_assert(HIST_SPAN == 256 * 16, "16 consecutive vertices per thread");
+constexpr uint32_t HQ_LO = QR - 4;  // first residual symbol with a packed counter
+constexpr int HIST_WG = (int)HIST_WG_VERTICES;  // vertices per histogram workgroup: four spans
+static_assert(HIST_WG % HIST_SPAN == 0 && HIST_WG / HIST_SPAN <= 4, "packed counters hold four spans");
 
-struct RunAdd {
-  uint32_t v = 0xFFFFFFFFu, c = 0;
-  __device__ __forceinline__ void add(uint32_t* h, uint32_t x) {
-    if (x == v) {
-      c++;
-    } else {
-      if (c) atomicAdd(&h[v], c);
-      v = x;
-      c = 1;
+// Sum over the wave, every lane enabled (the same value in every lane).
+__device__ __forceinline__ uint32_t wave_total(uint32_t v) {
+  v = row16_sum(v);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+         (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
+// Adds the eight packed 8-bit counters of every lane to h[0..7] (each wave
+// total stays below 2^16: at most 64 lanes times 128 symbols).
+__device__ __forceinline__ void add_packed(uint32_t* h, uint64_t c) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const uint32_t w = (uint32_t)((c >> (16 * k)) & 0xFFu) | ((uint32_t)((c >> (16 * k + 8)) & 0xFFu) << 16);
+    const uint32_t tot = wave_total(w);
+    if ((threadIdx.x & 63) == 0) {
+      if (tot & 0xFFFFu) atomicAdd(&h[2 * k], tot & 0xFFFFu);
+      if (tot >> 16) atomicAdd(&h[2 * k + 1], tot >> 16);
     }
   }
-  __device__ __forceinline__ void flush(uint32_t* h) {
-    if (c) atomicAdd(&h[v], c);
-  }
-};
+}
 
 // The bound and residual codes of the run of 16 vertices starting at field
 // vertex i0 (16-byte loads where aligned); 0xFF / 0 past the field's end hi.
@@ -241,20 +266,20 @@ __device__ __forceinline__ void load_run(const uint8_t* __restrict__ xcode, cons
   }
 }
 
-__global__ __launch_bounds__(256) void k_hist_b(const FieldDesc* __restrict__ D, const long long* __restrict__ hpre,
+__global__ __launch_bounds__(256) void k_hist_b(const FieldDesc* __restrict__ D, const long long* __restrict__ gpre,
                                                 int n, const uint8_t* __restrict__ xcode,
                                                 const uint32_t* __restrict__ qcode, uint32_t* __restrict__ xhist,
                                                 uint32_t* __restrict__ qhist, uint32_t* __restrict__ sr,
                                                 uint32_t* __restrict__ sn) {
   __shared__ uint32_t hx[32];
   __shared__ uint32_t hq[QSYM];
-  const int f = find_field(hpre, n, blockIdx.x);
+  const int f = find_field(gpre, n, blockIdx.x);
   const FieldDesc& d = D[f];
-  const size_t lo = (size_t)((long long)blockIdx.x - hpre[f]) * HIST_SPAN;
-  const size_t N = (size_t)d.N, hi = lo + HIST_SPAN < N ? lo + HIST_SPAN : N;
+  const size_t wlo = (size_t)((long long)blockIdx.x - gpre[f]) * HIST_WG;
+  const size_t N = (size_t)d.N, whi = wlo + HIST_WG < N ? wlo + HIST_WG : N;
   const size_t base = (size_t)d.voff;
   if (d.status) {
-    for (size_t i = lo + 16 * threadIdx.x; i < hi; i += 16 * 256) {
+    for (size_t i = wlo + 16 * threadIdx.x; i < whi; i += 16 * 256) {
       sr[d.ro + i / 16] = 0;
       sn[d.ro + i / 16] = 0;
     }
@@ -263,38 +288,52 @@ __global__ __launch_bounds__(256) void k_hist_b(const FieldDesc* __restrict__ D,
   for (int i = threadIdx.x; i < QSYM; i += 256) hq[i] = 0;
   if (threadIdx.x < 32) hx[threadIdx.x] = 0;
   __syncthreads();
-  const size_t i0 = lo + (size_t)threadIdx.x * 16;
-  RunAdd rx, ru, rv;
-  uint8_t xc[16];
-  uint32_t qc[16];
-  load_run(xcode, qcode, base, i0, hi, xc, qc);
-  uint32_t rsum = 0, nsum = 0;
+  // packed counters over all spans of the workgroup: bound codes 0..7,
+  // residual symbols HQ_LO..HQ_LO+7 (at most 64 vertices per thread, so no
+  // 8-bit field passes 128)
+  uint64_t cx = 0, cq = 0;
+  for (int sp = 0; sp < HIST_WG / HIST_SPAN; sp++) {
+    const size_t lo = wlo + (size_t)sp * HIST_SPAN;
+    if (lo >= whi) break;
+    const size_t hi = lo + HIST_SPAN < whi ? lo + HIST_SPAN : whi;
+    const size_t i0 = lo + (size_t)threadIdx.x * 16;
+    uint8_t xc[16];
+    uint32_t qc[16];
+    load_run(xcode, qcode, base, i0, hi, xc, qc);
+    uint32_t rsum = 0, nsum = 0;
 #pragma unroll
-  for (int j = 0; j < 16; j++) {
-    const uint32_t c = xc[j];
-    if (c == 0xFF) continue;  // past the end
-    rx.add(hx, c);
-    if (c == XLOSSLESS) {
-      rsum += 2;
-    } else {
-      const uint32_t u = qc[j] & 0xFFFFu, v = qc[j] >> 16;
-      ru.add(hq, u);
-      rv.add(hq, v);
-      rsum += (u == 0) + (v == 0);
-      nsum += 1;
+    for (int j = 0; j < 16; j++) {
+      const uint32_t c = xc[j];
+      if (c == 0xFF) continue;  // past the end
+      if (c < 8) cx += 1ull << (8 * c);
+      else atomicAdd(&hx[c], 1u);
+      if (c == XLOSSLESS) {
+        rsum += 2;
+      } else {
+        const uint32_t u = qc[j] & 0xFFFFu, v = qc[j] >> 16;
+        const uint32_t du = u - HQ_LO, dv = v - HQ_LO;
+        if (du < 8) cq += 1ull << (8 * du);
+        else atomicAdd(&hq[u], 1u);
+        if (dv < 8) cq += 1ull << (8 * dv);
+        else atomicAdd(&hq[v], 1u);
+        rsum += (u == 0) + (v == 0);
+        nsum += 1;
+      }
+    }
+    if (i0 < hi) {
+      sr[d.ro + i0 / 16] = rsum;
+      sn[d.ro + i0 / 16] = nsum;
     }
   }
-  rx.flush(hx);
-  ru.flush(hq);
-  rv.flush(hq);
-  if (i0 < hi) {
-    sr[d.ro + i0 / 16] = rsum;
-    sn[d.ro + i0 / 16] = nsum;
-  }
+  add_packed(hx, cx);
+  add_packed(hq + HQ_LO, cq);
   __syncthreads();
+  // the field's histogram copy this workgroup adds to (HIST_SLOTS per field,
+  // summed by the codebook kernel), so that few workgroups queue on one word
+  const long long slot = (long long)f * HIST_SLOTS + ((long long)blockIdx.x - gpre[f]) % HIST_SLOTS;
   for (int i = threadIdx.x; i < QSYM; i += 256)
-    if (hq[i]) atomicAdd(&qhist[(size_t)f * QSYM + i], hq[i]);
-  if (threadIdx.x < XSYM && hx[threadIdx.x]) atomicAdd(&xhist[(size_t)f * 32 + threadIdx.x], hx[threadIdx.x]);
+    if (hq[i]) atomicAdd(&qhist[(size_t)slot * QSYM + i], hq[i]);
+  if (threadIdx.x < XSYM && hx[threadIdx.x]) atomicAdd(&xhist[(size_t)slot * 32 + threadIdx.x], hx[threadIdx.x]);
 }
 
 // two workgroups per field: the bound-code and the residual-code codebook
@@ -305,8 +344,11 @@ __global__ __launch_bounds__(CB_THREADS) void k_codebooks_b(const FieldDesc* __r
                                                             uint32_t* used) {
   const int f = blockIdx.x >> 1;
   if (D[f].status) return;
-  if ((blockIdx.x & 1) == 0) build_code(xhist + (size_t)f * 32, XSYM, xt + f, xcb + (size_t)f * 32, &used[2 * f]);
-  else build_code(qhist + (size_t)f * QSYM, QSYM, qt + f, qcb + (size_t)f * (QSYM + 4), &used[2 * f + 1]);
+  if ((blockIdx.x & 1) == 0)
+    build_code(xhist + (size_t)f * HIST_SLOTS * 32, 32, XSYM, xt + f, xcb + (size_t)f * 32, &used[2 * f]);
+  else
+    build_code(qhist + (size_t)f * HIST_SLOTS * QSYM, QSYM, QSYM, qt + f, qcb + (size_t)f * (QSYM + 4),
+               &used[2 * f + 1]);
 }
 
 // Four consecutive vertices per lane (1024 per workgroup), so a run of 16
@@ -1052,13 +1094,13 @@ void launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
   if (n) k_zero<<<nblk(n), 256, 0, s>>>(p, n);
 }
 void launch_codes_b(FieldDesc* D, int n, const BatchView& B, const EntropyBufs& E, const long long* hpre,
-                    long long hblocks, const long long* vpre, long long vblocks, long long Rtot, hipStream_t s) {
-  launch_zero_u32(E.xhist, 32 * (size_t)n, s);
-  launch_zero_u32(E.qhist, QSYM * (size_t)n, s);
-  if (hblocks > 0)
-    k_hist_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.xhist, E.qhist, E.sr, E.sn);
+                    long long hblocks, const long long* gpre, long long gblocks, long long Rtot, hipStream_t s) {
+  launch_zero_u32(E.xhist, 32 * (size_t)HIST_SLOTS * n, s);
+  launch_zero_u32(E.qhist, QSYM * (size_t)HIST_SLOTS * n, s);
+  if (gblocks > 0)
+    k_hist_b<<<(unsigned)gblocks, 256, 0, s>>>(D, gpre, n, B.xcode, B.qcode, E.xhist, E.qhist, E.sr, E.sn);
   k_codebooks_b<<<2 * n, CB_THREADS, 0, s>>>(D, E.xhist, E.qhist, E.xt, E.qt, E.xcb, E.qcb, E.used);
-  if (vblocks <= 0) return;
+  if (gblocks <= 0) return;
   uint32_t* tot = E.part;  // two scratch words ahead of the scan partials
   launch_scan(E.sn, (size_t)Rtot, E.sq, E.part + 4, tot, s);
   launch_scan(E.sr, (size_t)Rtot, E.sro, E.part + 4, tot + 1, s);

@@ -209,14 +209,21 @@ __global__ __launch_bounds__(256) void k_flags(const uint32_t* __restrict__ mask
 }
 
 // ------------------------------------------------------- batched field pass
-// per-field range slots: min key, max key, max |x| bits, non-finite seen
+// per-field range slots: min key, max key, max |x| bits, non-finite seen.
+// Each field has RANGE_SLOTS slots a cache line apart; workgroup w adds to
+// slot w mod RANGE_SLOTS, so the atomics of many workgroups do not queue on
+// one line.
+__device__ __forceinline__ int4* range_slot(int4* r, int f, long long s) {
+  return r + ((size_t)f * RANGE_SLOTS + (size_t)s) * RANGE_SLOT_STRIDE;
+}
 __global__ void k_range_init_b(int4* __restrict__ r, int n) {
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f < n) r[f] = make_int4(0x7FFFFFFF, (int)0x80000000, 0, 0);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * RANGE_SLOTS) *range_slot(r, i / RANGE_SLOTS, i % RANGE_SLOTS) = make_int4(0x7FFFFFFF, (int)0x80000000, 0, 0);
 }
 
 // rpre[f]: workgroups of the fields before f, each covering RANGE_SPAN
-// floats; one reduction per workgroup, then one atomic per quantity
+// floats; one reduction per workgroup, then one atomic per quantity into the
+// workgroup's slot
 constexpr int RANGE_SPAN = (int)RANGE_SPAN_FLOATS;
 __global__ __launch_bounds__(256) void k_range_b(const FieldDesc* __restrict__ D, const long long* __restrict__ rpre,
                                                  int n, int4* __restrict__ r) {
@@ -256,10 +263,11 @@ __global__ __launch_bounds__(256) void k_range_b(const FieldDesc* __restrict__ D
       ma = max(ma, (uint32_t)part[w].z);
       bad |= (uint32_t)part[w].w;
     }
-    atomicMin(&r[f].x, mn);
-    atomicMax(&r[f].y, mx);
-    atomicMax((unsigned int*)&r[f].z, ma);
-    if (bad) atomicOr(&r[f].w, 1);
+    int4* q = range_slot(r, f, ((long long)blockIdx.x - rpre[f]) % RANGE_SLOTS);
+    atomicMin(&q->x, mn);
+    atomicMax(&q->y, mx);
+    atomicMax((unsigned int*)&q->z, ma);
+    if (bad) atomicOr(&q->w, 1);
   }
 }
 
@@ -304,7 +312,14 @@ __global__ void k_params_b(FieldDesc* __restrict__ D, const int4* __restrict__ r
   FieldDesc& d = D[f];
   d.status = 0;
   d.reason = REASON_NONE;
-  const int4 R = r[f];
+  int4 R = *range_slot(const_cast<int4*>(r), f, 0);
+  for (int i = 1; i < RANGE_SLOTS; i++) {
+    const int4 q = *range_slot(const_cast<int4*>(r), f, i);
+    R.x = min(R.x, q.x);
+    R.y = max(R.y, q.y);
+    R.z = (int)max((uint32_t)R.z, (uint32_t)q.z);
+    R.w |= q.w;
+  }
   const double mn = key_value(R.x), mx = key_value(R.y), ma = (double)__int_as_float(R.z);
   int kk = 23;
   if (R.w) {
@@ -738,7 +753,7 @@ size_t compare_partials(size_t N) { return nblk(N); }
 
 void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* fpre,
                         long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s) {
-  k_range_init_b<<<nblk(n, 64), 64, 0, s>>>(range, n);
+  k_range_init_b<<<nblk((size_t)n * RANGE_SLOTS, 64), 64, 0, s>>>(range, n);
   if (rblocks > 0) k_range_b<<<(unsigned)rblocks, 256, 0, s>>>(D, rpre, n, range);
   k_params_b<<<nblk(n, 64), 64, 0, s>>>(D, range, n);
   if (fblocks > 0) k_fieldpass_b<<<(unsigned)fblocks, 256, 0, s>>>(D, fpre, n, cur, flags);
