@@ -785,28 +785,25 @@ __device__ void build_lut(const uint32_t* __restrict__ cb, size_t cb_words, int 
   }
 }
 
-// One lane per chunk, DEC_STEP symbols per piece.  A piece consumes at most
-// DEC_STEP * MAXLEN bits, so its refills of the 64-bit bit buffer take at
-// most DEC_WIN consecutive words of the chunk, starting at the first word
-// not yet in the buffer.  Each lane keeps its chunk's words in a ring of
-// DEC_RING words in LDS (word w at w mod DEC_RING): while a piece decodes
-// from the DEC_WIN words at its start, the next DEC_WIN words are in flight
-// from global memory and enter the ring after the piece, so the next piece
-// finds its window resident.  A refill takes the word read ahead from the
-// ring at the previous refill, so each symbol waits for one LDS read, its
-// table entry.  A decoding error stops the lane's consumption (its later
-// symbols are 0) and is reported once.  Symbols leave in 16-byte stores.
+// One lane per chunk.  Lanes decode DEC_STEP symbols at a time into a
+// per-wave staging buffer, then the wave writes the 64 chunks' pieces as
+// 32-bit words, each piece contiguous (16 lanes per 64-byte piece).  A
+// piece of DEC_STEP symbols consumes at most DEC_STEP * MAXLEN bits, which
+// takes at most DEC_WIN refills of the 64-bit bit buffer (one more than the
+// bits' word count covers a buffer that starts the piece empty), so before
+// each piece every lane fetches the next DEC_WIN words of its chunk into its
+// window in LDS, all loads in flight together and one wait, and the buffer
+// refills from there.
 constexpr int DEC_STEP = 32;
 constexpr int DEC_WIN = (DEC_STEP * MAXLEN + 31) / 32 + 1;
-constexpr int DEC_RING = 32, DEC_RSTRIDE = DEC_RING + 1;  // padded rows: lanes hit different banks
-static_assert(2 * DEC_WIN <= DEC_RING, "the ring holds a window and the next one");
 // chunks cfirst .. cfirst + 255 of one stream (the workgroup's share)
 __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g, const uint32_t* __restrict__ cbits,
                               const uint32_t* __restrict__ wofs, uint32_t wbase, const uint32_t* __restrict__ bs,
                               size_t bs_words, size_t nsym_total, int alphabet, uint16_t* __restrict__ out,
                               uint32_t* __restrict__ err, size_t cfirst) {
   __shared__ uint32_t lut[1 << MAXLEN];
-  __shared__ uint32_t ring[256 * DEC_RSTRIDE];
+  __shared__ uint32_t stage[4][64][DEC_STEP / 2 + 1];  // per wave, per lane: DEC_STEP symbols
+  __shared__ uint32_t win[4][64][DEC_WIN];             // per wave, per lane: the piece's words
   {
     constexpr int NL = (1 << MAXLEN) / 4 / 256;
     uint4 lv[NL];
@@ -822,8 +819,8 @@ __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g
   if (c0 >= nch) return;  // whole wave past the end
   const size_t c = c0 + lane;
   bool live = c < nch;
-  uint32_t nbits = 0, nw = 0;
-  size_t w0 = 0;
+  uint32_t nbits = 0;
+  size_t w0 = 0, nw = 0;
   if (live) {
     nbits = cbits[c];
     w0 = wofs[c] - wbase;
@@ -836,74 +833,67 @@ __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g
   if (!live) nw = 0;
   const size_t lo = c * CHUNK;
   const size_t hi = live ? (lo + CHUNK < nsym_total ? lo + CHUNK : nsym_total) : lo;
-  const uint32_t* cw = bs + w0;  // the chunk's words (only the first nw are read; later ones count as 0)
-  uint32_t* rg = ring + threadIdx.x * DEC_RSTRIDE;
-  {
-    uint32_t wl[DEC_WIN];
-#pragma unroll
-    for (int k = 0; k < DEC_WIN; k++) wl[k] = (uint32_t)k < nw ? cw[k] : 0u;
-#pragma unroll
-    for (int k = 0; k < DEC_WIN; k++) rg[k] = wl[k];
-  }
-  uint64_t buf = 0;  // the next `have` bits of the chunk, most significant first
+  const uint32_t* cw = bs + w0;  // the chunk's words (only the first nw are read)
+  uint32_t* mywin = win[wv][lane];
+  uint64_t buf = 0;
   int have = 0;
-  uint32_t wi = 0;        // next word of the chunk to enter the buffer
-  uint32_t nxt = rg[0];   // that word
+  uint32_t wi = 0;  // next word of the chunk to enter the bit buffer
   uint32_t consumed = 0;
   bool bad = false;
   for (int base = 0; base < CHUNK; base += DEC_STEP) {
+    // the words wi .. wi + DEC_WIN - 1 that this piece may need (0 past the
+    // chunk's end)
+    uint32_t wl[DEC_WIN];
+#pragma unroll
+    for (int k = 0; k < DEC_WIN; k++) wl[k] = nw > 0 ? cw[wi + k < nw ? wi + k : 0] : 0u;
+#pragma unroll
+    for (int k = 0; k < DEC_WIN; k++) mywin[k] = wi + k < nw ? wl[k] : 0u;
     const uint32_t wbeg = wi;
-    const size_t s0 = lo + base;
-    const int navail = s0 < hi ? (int)min((size_t)DEC_STEP, hi - s0) : 0;  // symbols of this piece
-    uint32_t pre[DEC_WIN];  // the next window's extension, in flight during the piece
-#pragma unroll
-    for (int k = 0; k < DEC_WIN; k++) {
-      const uint32_t w = wbeg + DEC_WIN + k;
-      pre[k] = w < nw ? cw[w] : 0u;
-    }
-    uint32_t pk[DEC_STEP / 2];
-#pragma unroll
+    // decode this lane's next DEC_STEP symbols into the staging buffer
+    uint32_t pair = 0;
     for (int k = 0; k < DEC_STEP; k++) {
-      // refill to more than 32 bits; read the word after it ahead (a read
-      // past the window only happens when no refill of this piece uses it)
-      const bool rf = have <= 32;
-      buf |= rf ? (uint64_t)nxt << (uint32_t)(32 - have) : 0ull;
-      have += rf ? 32 : 0;
-      wi += rf ? 1u : 0u;
-      const uint32_t ahead = rg[wi & (DEC_RING - 1)];
-      nxt = rf ? ahead : nxt;
-      const uint32_t e = lut[(uint32_t)(buf >> (64 - MAXLEN))];
-      const uint32_t l = e >> 16;
-      const bool in = k < navail;
-      const bool ok = !bad && in && e != 0xFFFFFFFFu && consumed + l <= nbits && (e & 0xFFFFu) < (uint32_t)alphabet;
-      bad = bad || (in && !ok);
-      const uint32_t ll = ok ? l : 0u;
-      buf <<= ll;
-      have -= (int)ll;
-      consumed += ll;
-      const uint32_t sym = ok ? (e & 0xFFFFu) : 0u;
-      if (k & 1) pk[k >> 1] |= sym << 16;
-      else pk[k >> 1] = sym;
+      const size_t i = lo + base + k;
+      uint32_t sym = 0;
+      if (!bad && i < hi) {
+        if (have <= 32) {
+          buf |= (uint64_t)mywin[wi - wbeg] << (32 - have);
+          wi++;
+          have += 32;
+        }
+        const uint32_t e = lut[(uint32_t)(buf >> (64 - MAXLEN))];
+        const uint32_t l = e >> 16;
+        if (e == 0xFFFFFFFFu || consumed + l > nbits || (int)(e & 0xFFFFu) >= alphabet) {
+          atomicOr(err, 4u);
+          bad = true;
+        } else {
+          sym = e & 0xFFFFu;
+          buf <<= l;
+          have -= (int)l;
+          consumed += l;
+        }
+      }
+      if (k & 1) stage[wv][lane][k >> 1] = pair | (sym << 16);
+      else pair = sym;
     }
-    if (navail > 0) {
-      uint16_t* o = out + s0;
-      if (navail == DEC_STEP && ((uintptr_t)o & 15) == 0) {
-#pragma unroll
-        for (int j = 0; j < DEC_STEP / 8; j++)
-          reinterpret_cast<uint4*>(o)[j] = make_uint4(pk[4 * j], pk[4 * j + 1], pk[4 * j + 2], pk[4 * j + 3]);
-      } else {
-#pragma unroll
-        for (int k = 0; k < DEC_STEP; k++)
-          if (k < navail) o[k] = (uint16_t)(pk[k >> 1] >> (16 * (k & 1)));
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    // write: piece (chunk c0 + q, symbols base .. base + DEC_STEP) as 16 words
+    for (int d = lane; d < 64 * (DEC_STEP / 2); d += 64) {
+      const int q = d / (DEC_STEP / 2), w = d - q * (DEC_STEP / 2);
+      const size_t cc = c0 + q;
+      if (cc >= nch) continue;
+      const size_t s0 = cc * CHUNK + base + 2 * w;
+      const size_t top = cc * CHUNK + CHUNK < nsym_total ? cc * CHUNK + CHUNK : nsym_total;
+      const uint32_t v = stage[wv][q][w];
+      if (s0 + 1 < top) {
+        *(uint32_t*)(out + s0) = v;
+      } else if (s0 < top) {
+        out[s0] = (uint16_t)(v & 0xFFFFu);
       }
     }
-    // the next piece starts at word wi <= wbeg + DEC_WIN and reads at most
-    // DEC_WIN words: all in [wbeg, wbeg + 2 DEC_WIN)
-#pragma unroll
-    for (int k = 0; k < DEC_WIN; k++) rg[(wbeg + DEC_WIN + k) & (DEC_RING - 1)] = pre[k];
-    nxt = rg[wi & (DEC_RING - 1)];
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
-  if (bad) atomicOr(err, 4u);
   if (live && !bad && consumed != nbits) atomicOr(err, 8u);
 }
 
