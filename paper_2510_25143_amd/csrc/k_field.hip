@@ -393,40 +393,40 @@ __device__ __forceinline__ uint32_t fp_edges(const int2 (*A)[FP_CW], const int2 
   return e;
 }
 
-__device__ __forceinline__ uint32_t fp_mask(const uint8_t (*E0)[FP_EW], const uint8_t (*E1)[FP_EW], int ex, int ey,
-                                            bool px, bool py, bool pt) {
-  if (!(px || py)) return 0;
-  const uint32_t ea = E0[ey][ex];
-  const uint32_t eb = px ? E0[ey][ex + 1] : 0;
-  const uint32_t ec = py ? E0[ey + 1][ex] : 0;
-  const uint32_t ed = (px && py) ? E0[ey + 1][ex + 1] : 0;
-  const uint32_t ea1 = pt ? E1[ey][ex] : 0;
-  const uint32_t eb1 = (pt && px) ? E1[ey][ex + 1] : 0;
-  const uint32_t ec1 = (pt && py) ? E1[ey + 1][ex] : 0;
-  uint32_t m = 0;
-#define B(e, k) (((e) >> (k)) & 1u)
-  if (px && py) {
-    m |= face_bits(B(ea, 0), B(eb, 1), B(ea, 2), 0);
-    m |= face_bits(B(ea, 1), B(ec, 0), B(ea, 2), 1);
-    if (pt) {
-      m |= face_bits(B(ea, 0), B(eb, 5), B(ea, 6), 2);
-      m |= face_bits(B(ea, 4), B(eb1, 1), B(ea, 6), 3);
-      m |= face_bits(B(ea, 1), B(ec, 4), B(ea, 6), 4);
-      m |= face_bits(B(ea, 5), B(ec1, 0), B(ea, 6), 5);
-      m |= face_bits(B(ea, 2), B(ed, 3), B(ea, 6), 10);
-      m |= face_bits(B(ea, 3), B(ea1, 2), B(ea, 6), 11);
-    }
+// The twelve face tests of a cell side by side.  Face f is crossed when
+// the signs of its edges ab and bc agree and differ from that of ac; bit f
+// of X, Y, Z holds the sign of ab, bc, ac.  X and Z come from the owner's
+// own seven edge bits (table xz: X in bits 0-11, Z in bits 16-27), Y from
+// the edges of the neighbouring cells.  Faces whose prism leaves the
+// domain are masked out; the sign of a crossed face is that of ab.
+__device__ __forceinline__ uint32_t fp_xz(uint32_t ea) {
+  constexpr int xb[12] = {0, 1, 0, 4, 1, 5, 0, 3, 1, 3, 2, 3};
+  constexpr int zb[12] = {2, 2, 6, 6, 6, 6, 4, 4, 5, 5, 6, 6};
+  uint32_t x = 0, z = 0;
+#pragma unroll
+  for (int f = 0; f < 12; f++) {
+    x |= ((ea >> xb[f]) & 1u) << f;
+    z |= ((ea >> zb[f]) & 1u) << f;
   }
-  if (px && pt) {
-    m |= face_bits(B(ea, 0), B(eb, 3), B(ea, 4), 6);
-    m |= face_bits(B(ea, 3), B(ea1, 0), B(ea, 4), 7);
-  }
-  if (py && pt) {
-    m |= face_bits(B(ea, 1), B(ec, 3), B(ea, 5), 8);
-    m |= face_bits(B(ea, 3), B(ea1, 1), B(ea, 5), 9);
-  }
+  return x | (z << 16);
+}
+
+__device__ __forceinline__ uint32_t fp_mask(const uint8_t (*E0)[FP_EW], const uint8_t (*E1)[FP_EW],
+                                            const uint32_t* __restrict__ xz, int ex, int ey, bool px, bool py,
+                                            bool pt) {
+  const uint32_t valid = (px && py ? 0x003u : 0u) | (px && py && pt ? 0xC3Cu : 0u) | (px && pt ? 0x0C0u : 0u) |
+                         (py && pt ? 0x300u : 0u);
+  if (!valid) return 0;
+  const uint32_t ea = E0[ey][ex], eb = E0[ey][ex + 1], ec = E0[ey + 1][ex], ed = E0[ey + 1][ex + 1];
+  const uint32_t ea1 = E1[ey][ex], eb1 = E1[ey][ex + 1], ec1 = E1[ey + 1][ex];
+  const uint32_t t = xz[ea & 127u];
+  const uint32_t X = t & 0xFFFu, Z = t >> 16;
+#define B(e, k, f) ((((e) >> (k)) & 1u) << (f))
+  const uint32_t Y = B(eb, 1, 0) | B(ec, 0, 1) | B(eb, 5, 2) | B(eb1, 1, 3) | B(ec, 4, 4) | B(ec1, 0, 5) |
+                     B(eb, 3, 6) | B(ea1, 0, 7) | B(ec, 3, 8) | B(ea1, 1, 9) | B(ed, 3, 10) | B(ea1, 2, 11);
 #undef B
-  return m;
+  const uint32_t crossed = ~(X ^ Y) & (Z ^ Y) & valid;
+  return crossed | ((X & crossed) << 12);
 }
 
 // fpre[f]: tiles of the fields before f
@@ -434,6 +434,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                                                      const long long* __restrict__ fpre, int n,
                                                      int2* __restrict__ cur_all, uint8_t* __restrict__ flags_all) {
   __shared__ FieldPassSmem S;
+  __shared__ uint32_t xz[128];  // the X and Z words of the face tests per edge byte of the owner
   const int f = find_field(fpre, n, blockIdx.x);
   const FieldDesc& d = D[f];
   if (d.status) return;
@@ -488,6 +489,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     }
   };
 
+  if (tid < 128) xz[tid] = fp_xz((uint32_t)tid);
   // prologue: frames 0 and 1, edges of frame 0
   fetch(0);
   store(0);
@@ -511,7 +513,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
       const int x = x0 + mx - 1, y = y0 + my - 1;
       uint32_t m = 0;
       if (x >= 0 && x < W && y >= 0 && y < H)
-        m = fp_mask(S.edg[s & 1], S.edg[(s + 1) & 1], mx, my, x + 1 < W, y + 1 < H, s + 1 < T);
+        m = fp_mask(S.edg[s & 1], S.edg[(s + 1) & 1], xz, mx, my, x + 1 < W, y + 1 < H, s + 1 < T);
       S.msk[s & 1][my][mx] = m;
     }
     __syncthreads();
