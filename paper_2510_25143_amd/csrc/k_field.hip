@@ -490,6 +490,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   };
 
   if (tid < 128) xz[tid] = fp_xz((uint32_t)tid);
+  // the masks of "frame -1" are empty, so the flags of frame 0 read zeros
+  // there (cells outside the domain hold zero masks as well)
+  for (int j = tid; j < FP_MW * FP_MH; j += 256) (&S.msk[1][0][0])[j] = 0u;
   // prologue: frames 0 and 1, edges of frame 0
   fetch(0);
   store(0);
@@ -526,7 +529,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 #pragma unroll
       for (int o = 0; o < 8; o++) {
         const int ox = o & 1, oy = (o >> 1) & 1, ot = (o >> 2) & 1;
-        if (x - ox < 0 || y - oy < 0 || s - ot < 0) continue;
         any |= S.msk[(s - ot) & 1][iy + 1 - oy][ix + 1 - ox] & c_inc.m[o];
       }
       flags[(size_t)s * HW + (size_t)y * W + x] = any ? 1 : 0;
