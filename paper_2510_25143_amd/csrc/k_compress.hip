@@ -493,6 +493,26 @@ constexpr int count_static() {
   return n;
 }
 static_assert(count_static() == 22, "22 faces avoid the raster predecessors");
+// The same 22 faces in four trails (each face oriented so that its first
+// neighbour is the previous face's second wherever the trail continues):
+// 18 faces reuse a neighbour's value, determinant with the vertex, norm and
+// sign tests.  The bound of a face is symmetric in its two neighbours and
+// the running minimum does not depend on the order of the faces.
+constexpr StaticPairs STRAIL = {{3, 5, 4, 13, 3, 11, 13, 12, 4, 6, 3, 8, 6, 5, 13, 10, 12, 9, 7, 6, 9, 7},
+                                {5, 4, 13, 3, 11, 13, 12, 4, 6, 3, 8, 6, 5, 13, 10, 11, 10, 8, 6, 9, 7, 4}};
+constexpr bool trail_covers_static() {
+  for (int f = 0; f < 22; f++) {
+    int hits = 0;
+    for (int k = 0; k < 22; k++)
+      hits += ((STRAIL.a[k] == SPAIRS.a[f] && STRAIL.b[k] == SPAIRS.b[f]) ||
+               (STRAIL.a[k] == SPAIRS.b[f] && STRAIL.b[k] == SPAIRS.a[f]))
+                  ? 1
+                  : 0;
+    if (hits != 1) return false;
+  }
+  return true;
+}
+static_assert(trail_covers_static(), "the trails hold every static face once");
 __constant__ NbrTable c_nbr = NBR;
 __device__ __forceinline__ int c_nbr_dx(int j) { return c_nbr.dx[j]; }
 __device__ __forceinline__ int c_nbr_dy(int j) { return c_nbr.dy[j]; }
@@ -552,6 +572,34 @@ __device__ __forceinline__ void face_update(int& xi, double2 me, const MeSign& m
   lower_to(e, fabs(M), fabs(n1.x - n0.x) + fabs(n0.y - n1.y));
   lower_to(e, fabs(d1), a1);
   lower_to(e, fabs(d0), a0);
+  xi = min(xi, max(e, relax));
+}
+
+// A neighbour of the vertex as the face bounds use it: its value, the
+// determinant with the vertex, |u| + |v|, and whether each component shares
+// the vertex's strict sign.
+struct NbrQ {
+  double2 n;
+  double d, a;
+  bool sx, sy;
+};
+__device__ __forceinline__ NbrQ nbr_q(double2 n, double2 me) {
+  return NbrQ{n, det2d(me, n), fabs(n.x) + fabs(n.y), n.x * me.x > 0.0, n.y * me.y > 0.0};
+}
+
+// face_update for neighbours given with their per-neighbour terms
+__device__ __forceinline__ void face_update_q(int& xi, const MeSign& ms, const NbrQ& A, const NbrQ& B) {
+  const double M = (A.d - B.d) + det2d(A.n, B.n);
+  if (M == 0.0 || A.a == 0.0 || B.a == 0.0) {
+    xi = 0;
+    return;
+  }
+  const int relax = max(A.sx && B.sx ? ms.rx : -1, A.sy && B.sy ? ms.ry : -1);
+  if (relax >= xi) return;
+  int e = xi;
+  lower_to(e, fabs(M), fabs(B.n.x - A.n.x) + fabs(A.n.y - B.n.y));
+  lower_to(e, fabs(B.d), B.a);
+  lower_to(e, fabs(A.d), A.a);
   xi = min(xi, max(e, relax));
 }
 
@@ -642,13 +690,21 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
           int xx = x + NBR.dx[j], yy = y + NBR.dy[j], tt = t + NBR.dt[j];
           ok |= (xx >= 0 && xx < W && yy >= 0 && yy < H && tt >= 0 && tt < T) ? (1u << j) : 0u;
         }
+        auto nv = [&](int j) { return V[1 + NBR.dt[j]][ly + 1 + NBR.dy[j]][lx + 1 + NBR.dx[j]]; };
+        NbrQ prev = nbr_q(nv(STRAIL.a[0]), me);
 #pragma unroll
-        for (int f = 0; f < 22; f++) {
-          const int a = SPAIRS.a[f], b = SPAIRS.b[f];
+        for (int k = 0; k < 22; k++) {
+          const int a = STRAIL.a[k], b = STRAIL.b[k];
+          // the shared neighbour's value is read again from LDS (no VALU
+          // work); its derived terms carry over in registers
+          NbrQ A = (k > 0 && a == STRAIL.b[k > 0 ? k - 1 : 0]) ? prev : nbr_q(nv(a), me);
+          A.n = nv(a);
+          const NbrQ B = nbr_q(nv(b), me);
+          prev = B;
           if (((ok >> a) & (ok >> b) & 1u) == 0) continue;
-          const double2 na = V[1 + NBR.dt[a]][ly + 1 + NBR.dy[a]][lx + 1 + NBR.dx[a]];
-          const double2 nb = V[1 + NBR.dt[b]][ly + 1 + NBR.dy[b]][lx + 1 + NBR.dx[b]];
-          face_update(xi, me, ms, na, nb);
+          face_update_q(xi, ms, A, B);
+          // keep each face's loads with the face (fewer live registers)
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
       }
       if (cls == 0) {
