@@ -606,6 +606,7 @@ __device__ __forceinline__ void face_update_q(int& xi, const MeSign& ms, const N
 struct PhaseSmem {
   double2 V[3][HALO][HALO];  // frames t-1, t, t+1 around the block (exact fp64 integers)
   int XS[TILE][TILE];        // bound from the faces fixed for the whole sweep; -1 = lossless
+  int2 MS[TILE][TILE];       // |u| - 1, |v| - 1 of each vertex (its raise terms), for the sweep
   int2 SLP[TILE][TILE];      // semi-Lagrangian predictions, or the frame t-1 part of the Lorenzo prediction
   uint32_t OQ[TILE][TILE];   // outputs, written once after the sweep
   int OX[TILE][TILE];
@@ -628,6 +629,7 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
                                            int32_t* __restrict__ xi_dbg) {
   auto& V = S.V;
   auto& XS = S.XS;
+  auto& MS = S.MS;
   auto& SLP = S.SLP;
   auto& OQ = S.OQ;
   auto& OX = S.OX;
@@ -676,11 +678,13 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
   {
     const int lx = vx, ly = vy, x = x0 + lx, y = y0 + ly;
     int xi = -1;
+    int2 msv = make_int2(0, 0);
     if (vin) {
       if (!lossless) {
         xi = eps;
         const double2 me = V[1][ly + 1][lx + 1];
         const MeSign ms = me_sign(me);
+        msv = make_int2(ms.rx, ms.ry);
         // Faces through a raster predecessor (left, up, up-left) are all
         // evaluated in the sweep, also where that neighbour lies outside the
         // block; the other 22 are evaluated here for every vertex alike.
@@ -733,6 +737,7 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
       }
     }
     XS[ly][lx] = xi;
+    MS[ly][lx] = msv;
   }
   __syncthreads();
 
@@ -774,13 +779,14 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
     // all at once (at a clamped column for the idle lanes)
     const int lc = min(max(lx, 0), TILE - 1);
     const int xs = XS[g][lc];
+    const int2 msw = MS[g][lc];
     const double2 me = Vme[lc], pa = Va[lc], pb = Vb[lc];
     const double l = Ql[2 * lc], u = Qu[2 * lc], lu = Qlu[2 * lc];
     const int pt = Qp[2 * lc];
     int e = eps;
     if (active) {
       e = xs >= 0 ? xs : eps;
-      if (xs >= 0 && (unsigned)(lx - flo) < (unsigned)(fhi - flo)) face_update(e, me, me_sign(me), pa, pb);
+      if (xs >= 0 && (unsigned)(lx - flo) < (unsigned)(fhi - flo)) face_update(e, me, MeSign{msw.x, msw.y}, pa, pb);
     }
     e = row16_min(e);
     if (active && j < 2) {
