@@ -107,42 +107,28 @@ Arena* arena_for_device(cpt_status* st) {
 }
 
 // Scratch layout for one field of N vertices.
-struct Bufs {
+struct Bufs {  // scratch of the extraction, verification and parameter calls
   int2* cur;
-  uint8_t *edges, *flags, *xcode, *modes;
-  uint32_t *masks, *qcode, *nonll, *qofs, *rcnt, *rofs;
-  uint16_t *qsym, *xs, *qs;
-  uint32_t *xbits, *xwords, *xwofs, *qbits, *qwords, *qwofs, *part;
-  uint32_t *tot, *xhist, *qhist, *used, *err, *xcb, *qcb, *xlut, *qlut;
+  uint8_t* edges;
+  uint32_t *masks, *masks2, *nonll, *qofs, *part, *tot;
   int* range;
-  HuffTables *xt, *qt;
   unsigned long long* fc;
   double* cpart;
 };
 
 cpt_status reserve(Arena& A);
 
-cpt_status carve(Arena& A, size_t N, size_t nblk, Bufs& b) {
+cpt_status carve(Arena& A, size_t N, Bufs& b) {
   A.used = 0;
-  size_t nchx = (N + CHUNK - 1) / CHUNK + 1, nchq = (2 * N + CHUNK - 1) / CHUNK + 1;
   struct Item {
     void** p;
     size_t bytes;
   };
   std::vector<Item> items = {
-      {(void**)&b.cur, 8 * N},        {(void**)&b.edges, N},          {(void**)&b.flags, N},
-      {(void**)&b.xcode, N},          {(void**)&b.modes, nblk + 1},   {(void**)&b.masks, 4 * N},
-      {(void**)&b.qcode, 4 * N},      {(void**)&b.nonll, 4 * N},      {(void**)&b.qofs, 4 * N},
-      {(void**)&b.rcnt, 4 * N},       {(void**)&b.rofs, 4 * N},       {(void**)&b.qsym, 4 * N},
-      {(void**)&b.xs, 2 * N},         {(void**)&b.qs, 4 * N},         {(void**)&b.xbits, 4 * nchx},
-      {(void**)&b.xwords, 4 * nchx},  {(void**)&b.xwofs, 4 * nchx},   {(void**)&b.qbits, 4 * nchq},
-      {(void**)&b.qwords, 4 * nchq},  {(void**)&b.qwofs, 4 * nchq},
-      {(void**)&b.part, 4 * (scan_partials_size(2 * N) + 16)},
-      {(void**)&b.tot, 64},           {(void**)&b.xhist, 4 * 32},     {(void**)&b.qhist, 4 * QSYM},
-      {(void**)&b.used, 16},          {(void**)&b.err, 16},           {(void**)&b.xcb, 4 * 32},
-      {(void**)&b.qcb, 4 * (QSYM + 4)}, {(void**)&b.xlut, 4 << MAXLEN}, {(void**)&b.qlut, 4 << MAXLEN},
-      {(void**)&b.range, 64},         {(void**)&b.xt, sizeof(HuffTables)}, {(void**)&b.qt, sizeof(HuffTables)},
-      {(void**)&b.fc, 16},            {(void**)&b.cpart, 16 * (compare_partials(N) + 1)},
+      {(void**)&b.cur, 8 * N},        {(void**)&b.edges, N},          {(void**)&b.masks, 4 * N},
+      {(void**)&b.masks2, 4 * N},     {(void**)&b.nonll, 4 * N},      {(void**)&b.qofs, 4 * N},
+      {(void**)&b.part, 4 * (scan_partials_size(N) + 16)},            {(void**)&b.tot, 64},
+      {(void**)&b.range, 64},         {(void**)&b.fc, 16},            {(void**)&b.cpart, 16 * (compare_partials(N) + 1)},
   };
   std::vector<size_t> offs;
   for (auto& it : items) offs.push_back(A.off(it.bytes));
@@ -1505,7 +1491,7 @@ cpt_status cpt_field_params(const float* field, int H, int W, int T, int eb_mode
   if (!Ap) return st;
   std::lock_guard<std::mutex> lk(Ap->mu);
   Bufs b;
-  st = carve(*Ap, 1, 0, b);
+  st = carve(*Ap, 1, b);
   if (st) return st;
   Range r;
   st = field_range(field, 2 * (size_t)H * W * T, b, *Ap, (hipStream_t)stream, &r);
@@ -1526,7 +1512,7 @@ cpt_status cpt_extract_trajectories(const float* field, int H, int W, int T, int
   std::lock_guard<std::mutex> lk(A.mu);
   const size_t N = (size_t)H * W * T;
   Bufs b;
-  st = carve(A, N, 0, b);
+  st = carve(A, N, b);
   if (st) return st;
   Range r;
   st = field_range(field, 2 * N, b, A, s, &r);
@@ -1560,7 +1546,7 @@ cpt_status cpt_verify(const float* a, const float* bf, int H, int W, int T, int 
   std::lock_guard<std::mutex> lk(A.mu);
   const size_t N = (size_t)H * W * T;
   Bufs b;
-  st = carve(A, N, 0, b);
+  st = carve(A, N, b);
   if (st) return st;
   Range ra, rb;
   st = field_range(a, 2 * N, b, A, s, &ra);
@@ -1571,8 +1557,8 @@ cpt_status cpt_verify(const float* a, const float* bf, int H, int W, int T, int 
   launch_convert(a, N, k, b.cur, s);
   launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
   launch_convert(bf, N, k, b.cur, s);
-  launch_masks(b.cur, H, W, T, b.edges, b.qcode, s);
-  launch_compare(b.masks, b.qcode, a, bf, N, b.fc, b.cpart, s);
+  launch_masks(b.cur, H, W, T, b.edges, b.masks2, s);
+  launch_compare(b.masks, b.masks2, a, bf, N, b.fc, b.cpart, s);
   size_t np = compare_partials(N);
   std::vector<double> part(2 * np);
   HIPCHK(hipMemcpyAsync(part.data(), b.cpart, 16 * np, hipMemcpyDeviceToHost, s));
