@@ -123,6 +123,23 @@ def test_tiny_degenerate_roundtrip(cpt, seed):
         assert np.array_equal(g.cpu().numpy().view(np.uint32), oracle.decompress(want).view(np.uint32))
 
 
+@pytest.mark.parametrize("eb,eb_mode", [(1e-12, 1), (0.5, 0), (5e-7, 0)])
+def test_extreme_bounds_match_oracle(cpt, eb, eb_mode):
+    """An absolute bound below one fixed-point unit (eps' = 0: every vertex
+    lossless), the largest relative bound, and a relative bound of a few
+    units."""
+    f, _ = synthfields.workload(0, shape=(33, 47, 3))
+    fn = f.numpy()
+    want = oracle.compress(fn, eb, eb_mode=eb_mode)
+    got = cpt.compress(dev(f), eb, eb_mode=eb_mode)
+    assert_bytes_equal(got.cpu().numpy(), want)
+    back = cpt.decompress(got).cpu().numpy()
+    assert np.array_equal(back.view(np.uint32), oracle.decompress(want).view(np.uint32))
+    k, _, eps = oracle.params(fn, eb, eb_mode)
+    if eps == 0:
+        assert np.array_equal(back.view(np.uint32), fn.view(np.uint32))
+
+
 def test_constant_field(cpt):
     f = torch.full((2, 3, 20, 18), 0.75)
     want = oracle.compress(f.numpy(), 0.1)
