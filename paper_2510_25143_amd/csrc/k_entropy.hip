@@ -799,7 +799,7 @@ constexpr int DEC_WIN = (DEC_STEP * MAXLEN + 31) / 32 + 1;
 // chunks cfirst .. cfirst + 255 of one stream (the workgroup's share)
 __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g, const uint32_t* __restrict__ cbits,
                               const uint32_t* __restrict__ wofs, uint32_t wbase, const uint32_t* __restrict__ bs,
-                              size_t bs_words, size_t nsym_total, int alphabet, uint16_t* __restrict__ out,
+                              size_t bs_words, size_t nsym_total, uint16_t* __restrict__ out,
                               uint32_t* __restrict__ err, size_t cfirst) {
   __shared__ uint32_t lut[1 << MAXLEN];
   __shared__ uint32_t stage[4][64][DEC_STEP / 2 + 1];  // per wave, per lane: DEC_STEP symbols
@@ -849,12 +849,14 @@ __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g
 #pragma unroll
     for (int k = 0; k < DEC_WIN; k++) mywin[k] = wi + k < nw ? wl[k] : 0u;
     const uint32_t wbeg = wi;
-    // decode this lane's next DEC_STEP symbols into the staging buffer
+    // symbols of this piece in the lane's chunk
+    const int navail = lo + base < hi ? (int)min((size_t)DEC_STEP, hi - (lo + base)) : 0;
+    // decode this lane's next DEC_STEP symbols into the staging buffer (the
+    // table holds only symbols of the alphabet: the codebook was checked)
     uint32_t pair = 0;
     for (int k = 0; k < DEC_STEP; k++) {
-      const size_t i = lo + base + k;
       uint32_t sym = 0;
-      if (!bad && i < hi) {
+      if (!bad && k < navail) {
         if (have <= 32) {
           buf |= (uint64_t)mywin[wi - wbeg] << (32 - have);
           wi++;
@@ -862,7 +864,7 @@ __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g
         }
         const uint32_t e = lut[(uint32_t)(buf >> (64 - MAXLEN))];
         const uint32_t l = e >> 16;
-        if (e == 0xFFFFFFFFu || consumed + l > nbits || (int)(e & 0xFFFFu) >= alphabet) {
+        if (e == 0xFFFFFFFFu || consumed + l > nbits) {
           atomicOr(err, 4u);
           bad = true;
         } else {
@@ -956,7 +958,7 @@ __global__ __launch_bounds__(256) void k_decode_b(DecDesc* __restrict__ D, const
   const size_t cfirst = (size_t)(b - pre[f]) * 256;
   decode_chunks(luts + (size_t)(2 * f + (resid ? 1 : 0)) * (1 << MAXLEN), d.sec[resid ? 5 : 2], wofs + cb, wofs[cb],
                 d.sec[resid ? 6 : 3], (size_t)d.secw[resid ? 6 : 3], (size_t)(resid ? d.nq : d.N),
-                resid ? QSYM : XSYM, resid ? qs + (size_t)d.qsb : xs + (size_t)d.voff, &d.err, cfirst);
+                resid ? qs + (size_t)d.qsb : xs + (size_t)d.voff, &d.err, cfirst);
 }
 
 // One thread per segment (block row): its stream, the segment within the
