@@ -879,18 +879,27 @@ __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g
     }
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    // write: piece (chunk c0 + q, symbols base .. base + DEC_STEP) as 16 words
-    for (int d = lane; d < 64 * (DEC_STEP / 2); d += 64) {
-      const int q = d / (DEC_STEP / 2), w = d - q * (DEC_STEP / 2);
-      const size_t cc = c0 + q;
-      if (cc >= nch) continue;
-      const size_t s0 = cc * CHUNK + base + 2 * w;
-      const size_t top = cc * CHUNK + CHUNK < nsym_total ? cc * CHUNK + CHUNK : nsym_total;
-      const uint32_t v = stage[wv][q][w];
-      if (s0 + 1 < top) {
-        *(uint32_t*)(out + s0) = v;
-      } else if (s0 < top) {
-        out[s0] = (uint16_t)(v & 0xFFFFu);
+    // write: piece (chunk c0 + q, symbols base .. base + DEC_STEP) as 16 words;
+    // when every chunk of the wave is whole, 32-bit offsets from one base
+    if ((c0 + 64) * CHUNK <= nsym_total) {
+      uint32_t* ow = reinterpret_cast<uint32_t*>(out + c0 * CHUNK + base);
+      for (int d = lane; d < 64 * (DEC_STEP / 2); d += 64) {
+        const int q = d / (DEC_STEP / 2), w = d - q * (DEC_STEP / 2);
+        ow[q * (CHUNK / 2) + w] = stage[wv][q][w];
+      }
+    } else {
+      for (int d = lane; d < 64 * (DEC_STEP / 2); d += 64) {
+        const int q = d / (DEC_STEP / 2), w = d - q * (DEC_STEP / 2);
+        const size_t cc = c0 + q;
+        if (cc >= nch) continue;
+        const size_t s0 = cc * CHUNK + base + 2 * w;
+        const size_t top = cc * CHUNK + CHUNK < nsym_total ? cc * CHUNK + CHUNK : nsym_total;
+        const uint32_t v = stage[wv][q][w];
+        if (s0 + 1 < top) {
+          *(uint32_t*)(out + s0) = v;
+        } else if (s0 < top) {
+          out[s0] = (uint16_t)(v & 0xFFFFu);
+        }
       }
     }
     __builtin_amdgcn_wave_barrier();
