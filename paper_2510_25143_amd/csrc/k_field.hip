@@ -377,18 +377,19 @@ struct FieldPassSmem {
   uint32_t msk[2][FP_MH][FP_MW];
 };
 
-__device__ __forceinline__ uint32_t fp_edges(const int2 (*A)[FP_CW], const int2 (*B)[FP_CW], int cx, int cy, bool px,
-                                             bool py, bool pt) {
-  const int2 a = A[cy][cx];
+// A, B: values of frames t and t + 1 as flat [FP_CH][FP_CW] arrays; c: the
+// owner's flat index
+__device__ __forceinline__ uint32_t fp_edges(const int2* A, const int2* B, int c, bool px, bool py, bool pt) {
+  const int2 a = A[c];
   uint32_t e = 0;
-  if (px) e |= (sos_sign(a.x, a.y, A[cy][cx + 1].x, A[cy][cx + 1].y) > 0) << 0;
-  if (py) e |= (sos_sign(a.x, a.y, A[cy + 1][cx].x, A[cy + 1][cx].y) > 0) << 1;
-  if (px && py) e |= (sos_sign(a.x, a.y, A[cy + 1][cx + 1].x, A[cy + 1][cx + 1].y) > 0) << 2;
+  if (px) e |= (sos_sign(a.x, a.y, A[c + 1].x, A[c + 1].y) > 0) << 0;
+  if (py) e |= (sos_sign(a.x, a.y, A[c + FP_CW].x, A[c + FP_CW].y) > 0) << 1;
+  if (px && py) e |= (sos_sign(a.x, a.y, A[c + FP_CW + 1].x, A[c + FP_CW + 1].y) > 0) << 2;
   if (pt) {
-    e |= (sos_sign(a.x, a.y, B[cy][cx].x, B[cy][cx].y) > 0) << 3;
-    if (px) e |= (sos_sign(a.x, a.y, B[cy][cx + 1].x, B[cy][cx + 1].y) > 0) << 4;
-    if (py) e |= (sos_sign(a.x, a.y, B[cy + 1][cx].x, B[cy + 1][cx].y) > 0) << 5;
-    if (px && py) e |= (sos_sign(a.x, a.y, B[cy + 1][cx + 1].x, B[cy + 1][cx + 1].y) > 0) << 6;
+    e |= (sos_sign(a.x, a.y, B[c].x, B[c].y) > 0) << 3;
+    if (px) e |= (sos_sign(a.x, a.y, B[c + 1].x, B[c + 1].y) > 0) << 4;
+    if (py) e |= (sos_sign(a.x, a.y, B[c + FP_CW].x, B[c + FP_CW].y) > 0) << 5;
+    if (px && py) e |= (sos_sign(a.x, a.y, B[c + FP_CW + 1].x, B[c + FP_CW + 1].y) > 0) << 6;
   }
   return e;
 }
@@ -411,14 +412,20 @@ __device__ __forceinline__ uint32_t fp_xz(uint32_t ea) {
   return x | (z << 16);
 }
 
-__device__ __forceinline__ uint32_t fp_mask(const uint8_t (*E0)[FP_EW], const uint8_t (*E1)[FP_EW],
-                                            const uint32_t* __restrict__ xz, int ex, int ey, bool px, bool py,
-                                            bool pt) {
-  const uint32_t valid = (px && py ? 0x003u : 0u) | (px && py && pt ? 0xC3Cu : 0u) | (px && pt ? 0x0C0u : 0u) |
-                         (py && pt ? 0x300u : 0u);
+// The faces of a cell that stay inside the domain: the two in the frame
+// need the cell's x and y successors, the others also the next frame.
+__device__ __forceinline__ uint32_t fp_valid(bool px, bool py, bool pt) {
+  return (px && py ? 0x003u : 0u) | (px && py && pt ? 0xC3Cu : 0u) | (px && pt ? 0x0C0u : 0u) |
+         (py && pt ? 0x300u : 0u);
+}
+
+// E0, E1: edge bytes of frames t and t + 1 as flat [FP_EH][FP_EW] arrays;
+// e: the owner's flat index; valid: fp_valid of the cell
+__device__ __forceinline__ uint32_t fp_mask(const uint8_t* E0, const uint8_t* E1, const uint32_t* __restrict__ xz,
+                                            int e, uint32_t valid) {
   if (!valid) return 0;
-  const uint32_t ea = E0[ey][ex], eb = E0[ey][ex + 1], ec = E0[ey + 1][ex], ed = E0[ey + 1][ex + 1];
-  const uint32_t ea1 = E1[ey][ex], eb1 = E1[ey][ex + 1], ec1 = E1[ey + 1][ex];
+  const uint32_t ea = E0[e], eb = E0[e + 1], ec = E0[e + FP_EW], ed = E0[e + FP_EW + 1];
+  const uint32_t ea1 = E1[e], eb1 = E1[e + 1], ec1 = E1[e + FP_EW];
   const uint32_t t = xz[ea & 127u];
   const uint32_t X = t & 0xFFFu, Z = t >> 16;
 #define B(e, k, f) ((((e) >> (k)) & 1u) << (f))
@@ -449,43 +456,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   uint8_t* flags = flags_all + d.voff;
   const int tid = threadIdx.x;
 
-  // halo value j of frame t: fixed-point pair (0 outside the domain)
+  // Per-thread offsets of halo values j = tid + 256 q (flat [FP_CH][FP_CW]
+  // index j) within a frame, fixed over the frames: -1 outside the domain
+  // (H W T < 2^31, so they fit 32 bits); bit q of tv: value j is a tile
+  // vertex, written out.  Edge and mask cells j = tid + 256 q, three bits
+  // each (cell in the domain, its x and y successors in the domain): edge
+  // cells in bits 3q of ecell, mask cells in bits 3q of mcell.
+  int hoff[3];
+  uint32_t tv = 0, ecell = 0, mcell = 0;
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    const int j = tid + 256 * q;
+    const int cy = j / FP_CW, cx = j - cy * FP_CW;
+    const int x = x0 + cx - 1, y = y0 + cy - 1;
+    const bool in = j < FP_NC && x >= 0 && x < W && y >= 0 && y < H;
+    hoff[q] = in ? y * W + x : -1;
+    if (in && cx >= 1 && cx <= FP_TW && cy >= 1 && cy <= FP_TH) tv |= 1u << q;
+    const int ey = j / FP_EW, ex = j - ey * FP_EW, ux = x0 + ex - 1, uy = y0 + ey - 1;
+    if (ux >= 0 && ux < W && uy >= 0 && uy < H)
+      ecell |= (1u | (ux + 1 < W ? 2u : 0u) | (uy + 1 < H ? 4u : 0u)) << (3 * q);
+    const int my = j / FP_MW, mx = j - my * FP_MW, vx = x0 + mx - 1, vy = y0 + my - 1;
+    if (vx >= 0 && vx < W && vy >= 0 && vy < H)
+      mcell |= (1u | (vx + 1 < W ? 2u : 0u) | (vy + 1 < H ? 4u : 0u)) << (3 * q);
+  }
+
+  // halo values of frame t: fixed-point pairs (0 outside the domain)
   float ru[3], rv[3];
   auto fetch = [&](int t) {
+    const float* pu = fu + (size_t)t * HW;
+    const float* pv = fv + (size_t)t * HW;
 #pragma unroll
     for (int q = 0; q < 3; q++) {
-      const int j = tid + 256 * q;
-      const int cy = j / FP_CW, cx = j - cy * FP_CW;
-      const int x = x0 + cx - 1, y = y0 + cy - 1;
       ru[q] = rv[q] = 0.f;
-      if (j < FP_NC && t < T && x >= 0 && x < W && y >= 0 && y < H) {
-        const size_t g = (size_t)t * HW + (size_t)y * W + x;
-        ru[q] = fu[g];
-        rv[q] = fv[g];
+      if (t < T && hoff[q] >= 0) {
+        ru[q] = pu[hoff[q]];
+        rv[q] = pv[hoff[q]];
       }
     }
   };
   auto store = [&](int t) {
+    int2* sc = &S.cur[t & 1][0][0];
+    int2* pc = cur + (size_t)t * HW;
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       const int j = tid + 256 * q;
       if (j >= FP_NC) continue;
-      const int cy = j / FP_CW, cx = j - cy * FP_CW;
-      const int x = x0 + cx - 1, y = y0 + cy - 1;
-      const bool in = t < T && x >= 0 && x < W && y >= 0 && y < H;
+      const bool in = t < T && hoff[q] >= 0;
       const int2 v = in ? make_int2(to_fixed(ru[q], k), to_fixed(rv[q], k)) : make_int2(0, 0);
-      S.cur[t & 1][cy][cx] = v;
-      if (in && cx >= 1 && cx <= FP_TW && cy >= 1 && cy <= FP_TH) cur[(size_t)t * HW + (size_t)y * W + x] = v;
+      sc[j] = v;
+      if (in && (tv >> q & 1u)) pc[hoff[q]] = v;
     }
   };
   auto edges_of = [&](int t) {  // edges of frame t (t + 1 < T uses frame t + 1)
-    for (int j = tid; j < FP_EW * FP_EH; j += 256) {
-      const int ey = j / FP_EW, ex = j - ey * FP_EW;
-      const int x = x0 + ex - 1, y = y0 + ey - 1;
+    const int2* A = &S.cur[t & 1][0][0];
+    const int2* B = &S.cur[(t + 1) & 1][0][0];
+    uint8_t* E = &S.edg[t & 1][0][0];
+    const bool pt = t + 1 < T;
+    uint32_t c = ecell;
+    for (int j = tid; j < FP_EW * FP_EH; j += 256, c >>= 3) {
       uint32_t e = 0;
-      if (x >= 0 && x < W && y >= 0 && y < H)
-        e = fp_edges(S.cur[t & 1], S.cur[(t + 1) & 1], ex, ey, x + 1 < W, y + 1 < H, t + 1 < T);
-      S.edg[t & 1][ey][ex] = (uint8_t)e;
+      if (c & 1u) e = fp_edges(A, B, j + j / FP_EW, c & 2u, c & 4u, pt);
+      E[j] = (uint8_t)e;
     }
   };
 
@@ -511,16 +542,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     if (s + 1 < T) edges_of(s + 1);
     __syncthreads();
     // masks of frame s
-    for (int j = tid; j < FP_MW * FP_MH; j += 256) {
-      const int my = j / FP_MW, mx = j - my * FP_MW;
-      const int x = x0 + mx - 1, y = y0 + my - 1;
-      uint32_t m = 0;
-      if (x >= 0 && x < W && y >= 0 && y < H)
-        m = fp_mask(S.edg[s & 1], S.edg[(s + 1) & 1], xz, mx, my, x + 1 < W, y + 1 < H, s + 1 < T);
-      S.msk[s & 1][my][mx] = m;
+    {
+      const uint8_t* E0 = &S.edg[s & 1][0][0];
+      const uint8_t* E1 = &S.edg[(s + 1) & 1][0][0];
+      uint32_t* M = &S.msk[s & 1][0][0];
+      const bool pt = s + 1 < T;
+      uint32_t c = mcell;
+      for (int j = tid; j < FP_MW * FP_MH; j += 256, c >>= 3) {
+        M[j] = fp_mask(E0, E1, xz, j + j / FP_MW, (c & 1u) ? fp_valid(c & 2u, c & 4u, pt) : 0u);
+      }
     }
     __syncthreads();
     // lossless flags of frame s: any crossed face through the vertex
+    uint8_t* pf = flags + (size_t)s * HW;
     for (int j = tid; j < FP_TW * FP_TH; j += 256) {
       const int iy = j / FP_TW, ix = j - iy * FP_TW;
       const int x = x0 + ix, y = y0 + iy;
@@ -531,7 +565,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         const int ox = o & 1, oy = (o >> 1) & 1, ot = (o >> 2) & 1;
         any |= S.msk[(s - ot) & 1][iy + 1 - oy][ix + 1 - ox] & c_inc.m[o];
       }
-      flags[(size_t)s * HW + (size_t)y * W + x] = any ? 1 : 0;
+      pf[y * W + x] = any ? 1 : 0;
     }
   }
 }
