@@ -1034,19 +1034,61 @@ __global__ __launch_bounds__(256) void k_seg_nonll_b(DecDesc* __restrict__ D, co
 // raw words per segment (two for a lossless vertex, one per unpredictable
 // component); a residual position past the stream's symbols or a bound too
 // small for its code is an error.  Symbol pairs start at even positions of
-// an even-aligned array, so each pair is one 32-bit load.
+// an even-aligned array, so each pair is one 32-bit word.  The 256
+// consecutive segments of a workgroup (one field) own one contiguous run of
+// pairs, at most 16 per segment; the workgroup first copies that run into
+// LDS with coalesced loads, and each thread then reads its pairs from there
+// (a pair outside the copied run, which consistent prefix sums never give,
+// is read from memory).
+constexpr int SEG_RAW_WORDS = 256 * 16;
 __global__ __launch_bounds__(256) void k_seg_raw_b(DecDesc* __restrict__ D, const long long* __restrict__ spre, int n,
                                                    const uint16_t* __restrict__ xs, const uint16_t* __restrict__ qs,
                                                    const uint32_t* __restrict__ sq, uint32_t* __restrict__ sr) {
+  __shared__ uint32_t run[SEG_RAW_WORDS];
+  __shared__ uint32_t wend[4];
   const SegRow q = seg_row(D, spre, n);
-  if (!q.live) return;
   DecDesc& d = D[q.f];
   uint32_t c[16];
-  seg_codes(xs + d.voff + q.g0, q.len, c);
+  if (q.live) {
+    seg_codes(xs + d.voff + q.g0, q.len, c);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; j++) c[j] = XLOSSLESS;
+  }
   const uint32_t* qq = reinterpret_cast<const uint32_t*>(qs + d.qsb);
-  const long long o0 = 2 * (long long)(uint32_t)(sq[d.soff + q.ls] - sq[d.soff]);
-  // every coded vertex's symbol pair, all loads in flight together (an index
-  // past the stream's symbols is an error and reads nothing)
+  const uint32_t o0 = q.live ? 2u * (sq[d.soff + q.ls] - sq[d.soff]) : 0u;
+  uint32_t coded = 0;
+#pragma unroll
+  for (int j = 0; j < 16; j++) coded += (unsigned)j < q.len && c[j] < XLOSSLESS ? 1u : 0u;
+  // the run: from the first segment's first pair to the furthest pair end
+  uint32_t e = q.live ? o0 + 2u * coded : 0u;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) e = max(e, (uint32_t)__shfl_xor((int)e, m));
+  if ((threadIdx.x & 63) == 0) wend[threadIdx.x >> 6] = e;
+  __shared__ uint32_t wlo;
+  if (threadIdx.x == 0) wlo = o0 >> 1;
+  __syncthreads();
+  const uint32_t w0 = wlo;
+  const uint32_t pend = max(max(wend[0], wend[1]), max(wend[2], wend[3]));
+  const uint32_t wlim = min(pend, (uint32_t)min(d.nq, (long long)0xFFFFFFFF)) >> 1;
+  const uint32_t nw = wlim > w0 ? min(wlim - w0, (uint32_t)SEG_RAW_WORDS) : 0u;
+  {  // all sixteen loads of a thread in flight together
+    uint32_t v[SEG_RAW_WORDS / 256];
+#pragma unroll
+    for (int k = 0; k < SEG_RAW_WORDS / 256; k++) {
+      const uint32_t w = threadIdx.x + 256u * k;
+      v[k] = w < nw ? qq[w0 + w] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < SEG_RAW_WORDS / 256; k++) {
+      const uint32_t w = threadIdx.x + 256u * k;
+      if (w < nw) run[w] = v[k];
+    }
+  }
+  __syncthreads();
+  if (!q.live) return;
+  // every coded vertex's symbol pair (an index past the stream's symbols is
+  // an error and reads nothing)
   uint32_t pr[16];
   uint32_t ok = 0, r = 0;
   bool bad = false;
@@ -1054,12 +1096,13 @@ __global__ __launch_bounds__(256) void k_seg_raw_b(DecDesc* __restrict__ D, cons
 #pragma unroll
   for (int j = 0; j < 16; j++) {
     const bool inrow = (unsigned)j < q.len;
-    const bool coded = inrow && c[j] < XLOSSLESS;
-    const bool in = coded && (d.p.eps >> c[j]) >= 1 && o + 2 <= d.nq;
-    bad |= coded && !in;
+    const bool cd = inrow && c[j] < XLOSSLESS;
+    const bool in = cd && (d.p.eps >> c[j]) >= 1 && o + 2 <= d.nq;
+    bad |= cd && !in;
     ok |= in ? 1u << j : 0u;
-    pr[j] = in ? qq[o >> 1] : 0xFFFFFFFFu;
-    o += coded ? 2 : 0;
+    const uint32_t i = (uint32_t)(o >> 1) - w0;
+    pr[j] = in ? (i < nw ? run[i] : qq[o >> 1]) : 0xFFFFFFFFu;
+    o += cd ? 2 : 0;
     r += inrow && c[j] == XLOSSLESS ? 2u : 0u;
   }
 #pragma unroll
