@@ -98,9 +98,11 @@ __global__ __launch_bounds__(RC_THREADS) void k_reconstruct_b(DecDesc* __restric
     if (!((vm >> k) & 1u)) vcode[k] = XLOSSLESS;
     const bool coded = ((vm >> k) & 1u) && vcode[k] != XLOSSLESS;
     const long long o = 2 * ((long long)(sqv[k] - qbase) + row16_exclusive(coded ? 1u : 0u));
+    // the pair starts at an even position of an even-aligned array (nq is
+    // even), so it is one 32-bit word
     const long long oc = nq >= 2 ? min(max(o, 0LL), nq - 2) : 0;
-    const uint32_t q0 = nq >= 2 ? qs[oc] : 0u, q1 = nq >= 2 ? qs[oc + 1] : 0u;
-    vq[k] = coded ? (int)(q0 | (q1 << 16)) : 0;
+    const uint32_t qw = nq >= 2 ? *reinterpret_cast<const uint32_t*>(qs + oc) : 0u;
+    vq[k] = coded ? (int)qw : 0;
   }
 #pragma unroll
   for (int k = 0; k < RC_VPL; k++) {
