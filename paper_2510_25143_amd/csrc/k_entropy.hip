@@ -663,10 +663,15 @@ __global__ __launch_bounds__(256) void k_sections_b(const FieldDesc* __restrict_
 }
 
 // raw words, one thread per run of 16 vertices: two per lossless vertex,
-// one per unpredictable component, from the run's offset on in vertex order
+// one per unpredictable component, from the run's offset on in vertex order.
+// The run's raw-word count sr (from the histogram pass) decides what is
+// read: nothing when it is zero, only the bound codes when it is twice the
+// lossless vertices (no unpredictable component), else the residual codes
+// as well.
 __global__ __launch_bounds__(256) void k_raw_b(const FieldDesc* __restrict__ D, const long long* __restrict__ hpre,
                                                int n, const uint8_t* __restrict__ xcode,
-                                               const uint32_t* __restrict__ qcode, const uint32_t* __restrict__ sro) {
+                                               const uint32_t* __restrict__ qcode, const uint32_t* __restrict__ sr,
+                                               const uint32_t* __restrict__ sro) {
   const int f = find_field(hpre, n, blockIdx.x);
   const FieldDesc& d = D[f];
   if (d.status) return;
@@ -674,9 +679,43 @@ __global__ __launch_bounds__(256) void k_raw_b(const FieldDesc* __restrict__ D, 
   const size_t N = (size_t)d.N, hi = lo + HIST_SPAN < N ? lo + HIST_SPAN : N;
   const size_t i0 = lo + (size_t)threadIdx.x * 16;
   if (i0 >= hi) return;
+  const uint32_t rw = sr[d.ro + i0 / 16];
+  if (rw == 0) return;
+  const size_t g = (size_t)d.voff + i0;
+  const bool full = i0 + 16 <= hi && (g & 15) == 0;
   uint8_t xc[16];
+  if (full) {
+    const uint4 xa = *(const uint4*)(xcode + g);
+    const uint32_t xw[4] = {xa.x, xa.y, xa.z, xa.w};
+#pragma unroll
+    for (int j = 0; j < 16; j++) xc[j] = (uint8_t)(xw[j >> 2] >> (8 * (j & 3)));
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; j++) xc[j] = i0 + j < hi ? xcode[g + j] : (uint8_t)0xFF;
+  }
+  uint32_t nll = 0;
+#pragma unroll
+  for (int j = 0; j < 16; j++) nll += xc[j] == XLOSSLESS ? 1u : 0u;
   uint32_t qc[16];
-  load_run(xcode, qcode, (size_t)d.voff, i0, hi, xc, qc);
+#pragma unroll
+  for (int j = 0; j < 16; j++) qc[j] = 0xFFFFFFFFu;  // no zero half: predictable
+  if (rw != 2 * nll) {
+    if (full) {
+      const uint4* q4 = (const uint4*)(qcode + g);
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const uint4 w = q4[j];
+        qc[4 * j] = w.x;
+        qc[4 * j + 1] = w.y;
+        qc[4 * j + 2] = w.z;
+        qc[4 * j + 3] = w.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; j++)
+        if (i0 + j < hi) qc[j] = qcode[g + j];
+    }
+  }
   uint32_t* out = (uint32_t*)(d.out + d.off[7]);
   uint32_t o = sro[d.ro + i0 / 16] - sro[d.ro];
 #pragma unroll
@@ -1186,7 +1225,7 @@ void launch_assemble_b(FieldDesc* D, int n, const BatchView& B, const EntropyBuf
     k_encode_b<false><<<(unsigned)((cxtot + 3) / 4), 256, 0, s>>>(D, cxpre, n, cxtot, B.xcode, E.qsym, E.xt, E.xwofs);
   if (cqtot > 0)
     k_encode_b<true><<<(unsigned)((cqtot + 3) / 4), 256, 0, s>>>(D, cqpre, n, cqtot, B.xcode, E.qsym, E.qt, E.qwofs);
-  if (hblocks > 0) k_raw_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.sro);
+  if (hblocks > 0) k_raw_b<<<(unsigned)hblocks, 256, 0, s>>>(D, hpre, n, B.xcode, B.qcode, E.sr, E.sro);
 }
 void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long long* mpre, long long mblocks,
                            const long long* cxpre, long long cxtot, const long long* cqpre, long long cqtot,
