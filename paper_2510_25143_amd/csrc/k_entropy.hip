@@ -428,6 +428,9 @@ __global__ void k_totals_b(FieldDesc* __restrict__ D, int n, const uint32_t* __r
 // of the concatenated chunks; cpre: chunks of the fields before f).  A lane
 // sums the code lengths of symbols lane + 64 k: 16-byte loads of 8 residual
 // or 16 bound symbols where the chunk is aligned, single loads otherwise.
+// Residual code lengths are looked up in a per-wave LDS copy of the field's
+// 1024-entry length table (lanes read it at scattered symbols; bound codes
+// touch only the table's first 32 bytes and read it in place).
 template <bool RESID>
 __global__ __launch_bounds__(256) void k_chunk_bits_b(const FieldDesc* __restrict__ D,
                                                       const long long* __restrict__ cpre, int n, long long ctot,
@@ -435,17 +438,24 @@ __global__ __launch_bounds__(256) void k_chunk_bits_b(const FieldDesc* __restric
                                                       const uint16_t* __restrict__ qsym,
                                                       const HuffTables* __restrict__ tabs,
                                                       uint32_t* __restrict__ bits, uint32_t* __restrict__ words) {
+  __shared__ __align__(16) uint8_t ltab[4][1024];
   const long long c = 4 * (long long)blockIdx.x + (threadIdx.x >> 6);
   if (c >= ctot) return;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int f = find_field(cpre, n, c);
   const FieldDesc& d = D[f];
   const long long lc = c - cpre[f];
   const size_t slot = (size_t)(RESID ? d.cqb : d.cxb) + lc;
+  if (RESID) {
+    reinterpret_cast<uint4*>(ltab[wv])[lane] = reinterpret_cast<const uint4*>(tabs[f].len)[lane];
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  }
   const long long nsym = d.status ? 0 : (RESID ? d.nq : d.N);
   const long long base = lc * CHUNK;
   const long long cnt = nsym - base < CHUNK ? nsym - base : CHUNK;  // symbols in this chunk (<= 0: none)
   const uint8_t* len = tabs[f].len;
+  const uint8_t* lw = ltab[wv];
   uint32_t b = 0;
   if (cnt > 0) {
     constexpr int PER = RESID ? 8 : 16;  // symbols per 16-byte load
@@ -461,8 +471,8 @@ __global__ __launch_bounds__(256) void k_chunk_bits_b(const FieldDesc* __restric
 #pragma unroll
         for (int h = 0; h < 4; h++) {
           if (RESID) {
-            b += len[q[h] & 0xFFFFu];
-            b += len[q[h] >> 16];
+            b += lw[q[h] & 0xFFFFu];
+            b += lw[q[h] >> 16];
           } else {
             b += len[q[h] & 0xFFu];
             b += len[(q[h] >> 8) & 0xFFu];
@@ -473,7 +483,7 @@ __global__ __launch_bounds__(256) void k_chunk_bits_b(const FieldDesc* __restric
       }
     } else {
       for (long long i = lane; i < cnt; i += 64)
-        b += RESID ? len[qsym[(size_t)d.cqb * CHUNK + base + i]] : len[xcode[d.voff + base + i]];
+        b += RESID ? lw[qsym[(size_t)d.cqb * CHUNK + base + i]] : len[xcode[d.voff + base + i]];
     }
   }
   b = row16_sum(b);
@@ -487,7 +497,9 @@ __global__ __launch_bounds__(256) void k_chunk_bits_b(const FieldDesc* __restric
 
 // One wave per chunk as above, CHUNK / 64 = 16 consecutive symbols per lane
 // (16-byte loads where the chunk is aligned); the chunk's words go to the
-// field's bitstream section
+// field's bitstream section.  Residual codes are looked up in a per-wave LDS
+// copy of the field's table, each entry code | length << 12 (a code of at
+// most MAXLEN = 12 bits).
 template <bool RESID>
 __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ D, const long long* __restrict__ cpre,
                                                   int n, long long ctot, const uint8_t* __restrict__ xcode,
@@ -495,7 +507,9 @@ __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ 
                                                   const HuffTables* __restrict__ tabs,
                                                   const uint32_t* __restrict__ wofs) {
   constexpr int NW = CHUNK * MAXLEN / 32, PER = CHUNK / 64;
+  static_assert(MAXLEN <= 12 && QSYM == 64 * PER, "16-bit table entries, 16 per lane");
   __shared__ uint32_t wbuf[4][NW];
+  __shared__ __align__(16) uint16_t ctab[4][QSYM];
   const long long c = 4 * (long long)blockIdx.x + (threadIdx.x >> 6);
   if (c >= ctot) return;
   const int lane = threadIdx.x & 63;
@@ -506,6 +520,25 @@ __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ 
   const long long nsym = RESID ? d.nq : d.N;
   if (d.status || lc * CHUNK >= nsym) return;
   const HuffTables* t = tabs + f;
+  uint16_t* ct = ctab[threadIdx.x >> 6];
+  if (RESID) {
+    const uint4* cq = reinterpret_cast<const uint4*>(t->code) + 4 * lane;
+    const uint4 c0 = cq[0], c1 = cq[1], c2 = cq[2], c3 = cq[3];
+    const uint4 l4 = reinterpret_cast<const uint4*>(t->len)[lane];
+    const uint32_t cv[16] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w,
+                             c2.x, c2.y, c2.z, c2.w, c3.x, c3.y, c3.z, c3.w};
+    const uint32_t lv[4] = {l4.x, l4.y, l4.z, l4.w};
+    uint32_t e[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      const uint32_t la = (lv[i >> 1] >> (16 * (i & 1))) & 0xFFu, lb = (lv[i >> 1] >> (16 * (i & 1) + 8)) & 0xFFu;
+      e[i] = (cv[2 * i] | (la << 12)) | ((cv[2 * i + 1] | (lb << 12)) << 16);
+    }
+    reinterpret_cast<uint4*>(ct)[2 * lane] = make_uint4(e[0], e[1], e[2], e[3]);
+    reinterpret_cast<uint4*>(ct)[2 * lane + 1] = make_uint4(e[4], e[5], e[6], e[7]);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  }
   const size_t cb = (size_t)(RESID ? d.cqb : d.cxb);
   const long long base = lc * CHUNK + (long long)lane * PER;
   const long long cnt = nsym - lc * CHUNK < CHUNK ? nsym - lc * CHUNK : CHUNK;
@@ -540,8 +573,14 @@ __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ 
 #pragma unroll
   for (int i = 0; i < PER; i++) {
     const bool in = sym[i] != 0xFFFFFFFFu;
-    codes[i] = in ? t->code[sym[i]] : 0u;
-    lens[i] = in ? t->len[sym[i]] : (uint8_t)0;
+    if (RESID) {
+      const uint32_t e = in ? ct[sym[i]] : 0u;
+      codes[i] = e & 0xFFFu;
+      lens[i] = (uint8_t)(e >> 12);
+    } else {
+      codes[i] = in ? t->code[sym[i]] : 0u;
+      lens[i] = in ? t->len[sym[i]] : (uint8_t)0;
+    }
     mine += lens[i];
   }
   // exclusive prefix of bit counts over the wave
