@@ -356,7 +356,11 @@ __global__ __launch_bounds__(CB_THREADS) void k_codebooks_b(const FieldDesc* __r
 // symbols, its 32-bit residual code, at its run's offset plus the coded
 // vertices before it in the run (symbol pairs start at even positions of
 // the chunk-aligned symbol array).  Four workgroups per histogram span of
-// hpre; those wholly past a field's end only take part in no store.
+// hpre; those wholly past a field's end only take part in no store.  The
+// workgroup's residual codes form one contiguous run of at most 1024 words:
+// they are placed in LDS first and written out with coalesced stores (a
+// word outside that window, which consistent prefix sums never give, is
+// stored directly).
 __global__ __launch_bounds__(256) void k_gather_q_b(const FieldDesc* __restrict__ D,
                                                     const long long* __restrict__ hpre, int n,
                                                     const uint8_t* __restrict__ xcode,
@@ -396,12 +400,31 @@ __global__ __launch_bounds__(256) void k_gather_q_b(const FieldDesc* __restrict_
   const uint32_t t2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)cnt, 0x40, 0xF, 0xF, true);  // quad_perm [0,0,0,1]
   const uint32_t t3 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)cnt, 0x00, 0xF, 0xF, true);  // quad_perm [0,0,0,0]
   const uint32_t before = (qi >= 1 ? t1 : 0u) + (qi >= 2 ? t2 : 0u) + (qi >= 3 ? t3 : 0u);
-  if (!live) return;
+  __shared__ uint32_t obuf[1024];
+  __shared__ uint32_t oend[4], ostart;
   uint32_t* out = reinterpret_cast<uint32_t*>(qsym + (size_t)d.cqb * CHUNK);
-  size_t o = (size_t)(sq[d.ro + i0 / 16] - sq[d.ro]) + before;
+  const uint32_t o = live ? (sq[d.ro + i0 / 16] - sq[d.ro]) + before : 0u;
+  uint32_t e = live ? o + cnt : 0u;
 #pragma unroll
-  for (int k = 0; k < 4; k++)
-    if (xc[k] != XLOSSLESS) out[o++] = qc[k];
+  for (int m = 1; m < 64; m <<= 1) e = max(e, (uint32_t)__shfl_xor((int)e, m));
+  if ((threadIdx.x & 63) == 0) oend[threadIdx.x >> 6] = e;
+  if (threadIdx.x == 0) ostart = o;
+  __syncthreads();
+  const uint32_t o0 = ostart, o1 = max(max(oend[0], oend[1]), max(oend[2], oend[3]));
+  const uint32_t nw = o1 > o0 ? min(o1 - o0, 1024u) : 0u;
+  if (live) {
+    uint32_t oo = o;
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (xc[k] != XLOSSLESS) {
+        const uint32_t i = oo - o0;
+        if (i < nw) obuf[i] = qc[k];
+        else out[oo] = qc[k];
+        oo++;
+      }
+  }
+  __syncthreads();
+  for (uint32_t w = threadIdx.x; w < nw; w += 256) out[o0 + w] = obuf[w];
 }
 
 // residual symbols and raw values per field, from the prefix sums
