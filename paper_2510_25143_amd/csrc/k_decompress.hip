@@ -16,7 +16,7 @@ namespace cpt {
 // Two waves per block: each lane prepares two vertices (v = lane + 128 k),
 // lanes 0-31 of the first wave then sweep the Lorenzo anti-diagonals, and
 // each lane writes its two vertices.  Every block of a frame is resident at
-// once.  Global reads come in two rounds, each with all its loads in flight:
+// once.  Global reads come in two batches, each with all its loads in flight:
 // the per-vertex codes and the block rows' offsets with the previous frame,
 // then the residual symbols (and, where the wave has any, the raw words)
 // they point at.  Streams that failed a check are skipped.
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(RC_THREADS) void k_reconstruct_b(DecDesc* __restric
   const int x0 = bx * TILE, y0 = by * TILE;
   const int2* prevf = t > 0 ? cur + (size_t)(t - 1) * HW : cur;
 
-  // ---- round 1: codes, the offsets of the block's rows (segments), the
+  // ---- read batch 1: codes, the offsets of the block's rows (segments), the
   // previous frame with a one-vertex halo
   constexpr int NH = HALO * HALO, KH = (NH + RC_THREADS - 1) / RC_THREADS;
   uint32_t vcode[RC_VPL], sqv[RC_VPL], srv[RC_VPL], vm = 0, hm = 0;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(RC_THREADS) void k_reconstruct_b(DecDesc* __restric
     }
   }
 
-  // ---- round 2: the two residual symbols of every coded vertex, at its
+  // ---- read batch 2: the two residual symbols of every coded vertex, at its
   // segment's offset plus the coded vertices before it in the row (each
   // 16-lane DPP row holds one block row; index clamped into the stream)
   int vq[RC_VPL];
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(RC_THREADS) void k_reconstruct_b(DecDesc* __restric
     ridx[k] = (srv[k] - rbase) + row16_exclusive(r);
     rneed |= r;
   }
-  // ---- round 3 (only where the block has raw words): the two raw words a
+  // ---- read batch 3 (only where the block has raw words): the two raw words a
   // vertex may use
   uint32_t rw0[RC_VPL] = {}, rw1[RC_VPL] = {};
   if (__builtin_amdgcn_readfirstlane(__ballot(rneed != 0) != 0ull ? 1 : 0) && nraw >= 1) {
