@@ -81,6 +81,8 @@ def lib():
             "cpo_xi_code": (i32, [i64, i64]),
             "cpo_vertex_bound": (i64, [P, P, P, i32, i32, i32, i32, i32, i32, i64]),
             "cpo_block_mode": (ctypes.c_int, [P, P, P, P, P, i32, i32, i32, i32, P, i32, i64, P]),
+            "cpo_block_scores": (ctypes.c_int, [P, P, P, P, P, i32, i32, i32, i32, P, i32, i64, P]),
+            "cpo_canonical_codes": (None, [P, i32, P]),
             "cpo_tlog": (i64, [i32]),
             "cpo_score": (i64, [P, i32, i32, i32, i32, i32]),
             "cpo_huffman_lengths": (ctypes.c_int, [P, i32, i32, P]),
@@ -264,6 +266,32 @@ def block_mode(Ut, Vt, Up, Vp, flags_t, bx, by, k, eps, predictor=2, mode_bt=1, 
     return r, feat
 
 
+def block_scores(Ut, Vt, Up, Vp, flags_t, bx, by, k, eps, predictor=2, mode_bt=1, dt_dx=1.0,
+                 dt_dy=1.0):
+    """Trial scores (Q16 bits per sample) of every class of the exhaustive
+    choice for block (bx, by), and the class chosen; planes as block_mode."""
+    planes = [np.ascontiguousarray(a, dtype=np.int32) for a in (Ut, Vt, Up, Vp)]
+    fl = np.ascontiguousarray(flags_t, dtype=np.uint8)
+    H, W = planes[0].shape
+    assert all(a.shape == (H, W) for a in planes) and fl.shape == (H, W)
+    o, keep = _opts(predictor, mode_bt, 0, dt_dx, dt_dy, None)
+    K = 2 if predictor == 2 else 4
+    R = np.zeros(K, dtype=np.int64)
+    r = lib().cpo_block_scores(*[_p(a) for a in planes], _p(fl), H, W, bx, by, ctypes.byref(o), k,
+                               int(eps), _p(R))
+    del keep
+    if r < 0:
+        raise ValueError("cpo_block_scores failed: %d" % r)
+    return R, r
+
+
+def canonical_codes(lengths):
+    ln = np.ascontiguousarray(lengths, dtype=np.uint8)
+    out = np.zeros(ln.size, dtype=np.uint32)
+    lib().cpo_canonical_codes(_p(ln), ln.size, _p(out))
+    return out
+
+
 def tlog(h):
     return lib().cpo_tlog(int(h))
 
@@ -377,8 +405,10 @@ def verify(a, b, k):
     _, T, H, W = a.shape
     ft, fs = ctypes.c_uint64(), ctypes.c_uint64()
     me, ps = ctypes.c_double(), ctypes.c_double()
-    lib().cpo_verify(_p(a), _p(b), H, W, T, k, ctypes.byref(ft), ctypes.byref(fs),
+    st = lib().cpo_verify(_p(a), _p(b), H, W, T, k, ctypes.byref(ft), ctypes.byref(fs),
                      ctypes.byref(me), ctypes.byref(ps))
+    if st:
+        raise ValueError("cpo_verify failed: %d" % st)
     return dict(fc_t=ft.value, fc_s=fs.value, max_err=me.value, psnr=ps.value)
 
 

@@ -99,8 +99,23 @@ int cpo_params(const float* field, int H, int W, int T, int eb_mode, double eb,
   return CPO_OK;
 }
 
+/* Values whose scaled magnitude leaves the int32 range (only a caller's k
+   that does not fit the field, or a corrupt stream, gives one) saturate, so
+   the conversion is defined for every finite input; callers reject such
+   values before using them. */
 void cpo_to_fixed(const float* x, size_t n, int k, int32_t* out) {
-  for (size_t i = 0; i < n; i++) out[i] = (int32_t)nearbyint(ldexp((double)x[i], k));
+  for (size_t i = 0; i < n; i++) {
+    double d = nearbyint(ldexp((double)x[i], k));
+    out[i] = d >= 2147483647.0 ? INT32_MAX : (d <= -2147483648.0 ? INT32_MIN : (int32_t)d);
+  }
+}
+
+/* 1 when every |x| 2^k stays below 2^24, the range the extraction needs
+   (Sec. III-F works on the exact fixed-point values). */
+static int fits_24(const float* x, size_t n, int k) {
+  for (size_t i = 0; i < n; i++)
+    if (!(fabs(ldexp((double)x[i], k)) < 16777216.0)) return 0;
+  return 1;
 }
 
 /* ======================================================================
@@ -214,6 +229,7 @@ int cpo_extract(const float* field, int H, int W, int T, int k, uint64_t* codes,
                 size_t cap, size_t* count) {
   if (H < 2 || W < 2 || T < 1) return CPO_EINVAL;
   size_t N = (size_t)H * W * T;
+  if (!fits_24(field, 2 * N, k)) return CPO_EINVAL;
   int32_t* F = (int32_t*)malloc(2 * N * sizeof(int32_t));
   if (!F) return CPO_ENOMEM;
   cpo_to_fixed(field, 2 * N, k, F);
@@ -558,6 +574,11 @@ int cpo_huffman_lengths(const uint64_t* counts, int nsym, int maxlen, uint8_t* l
 }
 
 /* canonical codewords: symbols ordered by (length, symbol) */
+static void canonical_codes(const uint8_t* lengths, int nsym, uint32_t* codes);
+void cpo_canonical_codes(const uint8_t* lengths, int nsym, uint32_t* codes) {
+  memset(codes, 0, sizeof(uint32_t) * (size_t)nsym);
+  canonical_codes(lengths, nsym, codes);
+}
 static void canonical_codes(const uint8_t* lengths, int nsym, uint32_t* codes) {
   uint32_t code = 0;
   int prev = 0, first = 1;
@@ -1006,8 +1027,9 @@ int cpo_choose(const int64_t* R, int K) {
   return 1000 * (R[0] - R[best]) > 3 * R[0] ? best : 0;
 }
 
+/* scores (may be NULL) receives the K trial scores of the exhaustive choice */
 static int decide_mode(const ctx_t* c, int t, int x0, int y0, int x1, int y1,
-                       int32_t* SU, int32_t* SV, int32_t* hist, float* feat) {
+                       int32_t* SU, int32_t* SV, int32_t* hist, float* feat, int64_t* scores) {
   block_features(c, t, x0, y0, x1, y1, feat);
   if (c->predictor == 4) {
     float lg[CPO_NCLS];
@@ -1015,6 +1037,7 @@ static int decide_mode(const ctx_t* c, int t, int x0, int y0, int x1, int y1,
   }
   int64_t R[4] = {0, 0, 0, 0};
   for (int k = 0; k < c->K; k++) R[k] = trial_score(c, t, x0, y0, x1, y1, k, SU, SV, hist);
+  if (scores) memcpy(scores, R, sizeof(int64_t) * (size_t)c->K);
   return cpo_choose(R, c->K);
 }
 
@@ -1024,9 +1047,30 @@ static int decide_mode(const ctx_t* c, int t, int x0, int y0, int x1, int y1,
    Vp) and the frame's lossless flags: the steps of compression, run on a
    two-frame copy.  Needs a predictor with a choice (2, 3 or 4); returns the
    class, or CPO_EINVAL / CPO_ENOMEM. */
+static int block_mode_impl(const int32_t* Ut, const int32_t* Vt, const int32_t* Up,
+                           const int32_t* Vp, const uint8_t* flags_t, int H, int W, int bx,
+                           int by, const cpo_options* opt, int k, int64_t eps, float* feat,
+                           int64_t* scores);
+
 int cpo_block_mode(const int32_t* Ut, const int32_t* Vt, const int32_t* Up, const int32_t* Vp,
                    const uint8_t* flags_t, int H, int W, int bx, int by, const cpo_options* opt,
                    int k, int64_t eps, float* feat) {
+  return block_mode_impl(Ut, Vt, Up, Vp, flags_t, H, W, bx, by, opt, k, eps, feat, NULL);
+}
+
+/* The same decision, also returning the K trial scores (Sec. VI-B rate
+   estimate, Q16 bits per sample) of the exhaustive choice; predictor 2 or 3. */
+int cpo_block_scores(const int32_t* Ut, const int32_t* Vt, const int32_t* Up, const int32_t* Vp,
+                     const uint8_t* flags_t, int H, int W, int bx, int by, const cpo_options* opt,
+                     int k, int64_t eps, int64_t* scores) {
+  if (!opt || !scores || opt->predictor < 2 || opt->predictor > 3) return CPO_EINVAL;
+  return block_mode_impl(Ut, Vt, Up, Vp, flags_t, H, W, bx, by, opt, k, eps, NULL, scores);
+}
+
+static int block_mode_impl(const int32_t* Ut, const int32_t* Vt, const int32_t* Up,
+                           const int32_t* Vp, const uint8_t* flags_t, int H, int W, int bx,
+                           int by, const cpo_options* opt, int k, int64_t eps, float* feat,
+                           int64_t* scores) {
   if (!opt || opt->predictor < 2 || opt->predictor > 4 || opt->mode_bt < 1) return CPO_EINVAL;
   if (opt->predictor == 4 && !opt->selector_w) return CPO_EINVAL;
   ctx_t c;
@@ -1069,7 +1113,7 @@ int cpo_block_mode(const int32_t* Ut, const int32_t* Vt, const int32_t* Up, cons
     int x0 = bx * TILE, y0 = by * TILE;
     int x1 = x0 + TILE < W ? x0 + TILE : W, y1 = y0 + TILE < H ? y0 + TILE : H;
     float f[CPO_NFEAT];
-    r = decide_mode(&c, 1, x0, y0, x1, y1, SU, SV, hist, f);
+    r = decide_mode(&c, 1, x0, y0, x1, y1, SU, SV, hist, f, scores);
     if (feat) memcpy(feat, f, sizeof(f));
   }
   free(F0);
@@ -1166,7 +1210,7 @@ int cpo_compress_ex(const float* field, int H, int W, int T, double eb,
             size_t bi = ((size_t)decided_before(g, c.bt, T) * c.ty + by) * c.tx + bx;
             if (t == td) {
               float feat[CPO_NFEAT];
-              modes[bi] = (uint8_t)decide_mode(&c, t, x0, y0, x1, y1, SU, SV, hist, feat);
+              modes[bi] = (uint8_t)decide_mode(&c, t, x0, y0, x1, y1, SU, SV, hist, feat, NULL);
               if (feats_out) memcpy(feats_out + bi * CPO_NFEAT, feat, sizeof(feat));
             }
             cls = modes[bi];
@@ -1317,6 +1361,10 @@ int cpo_stream_info(const uint8_t* b, size_t len, cpo_info* info) {
   return CPO_OK;
 }
 
+/* Every fixed-point value a valid stream yields, stored or reconstructed,
+   lies strictly inside (-2^25, 2^25); anything else marks a corrupt stream. */
+static int fits_25(int64_t v) { return v < (1 << 25) && v > -(1 << 25); }
+
 int cpo_decompress(const uint8_t* b, size_t len, float* field) {
   cpo_info in;
   int st = cpo_stream_info(b, len, &in);
@@ -1403,6 +1451,7 @@ int cpo_decompress(const uint8_t* b, size_t len, float* field) {
               if (!isfinite(fu) || !isfinite(fv)) { st = CPO_ECORRUPT; goto done; }
               cpo_to_fixed(&fu, 1, c.k, &c.U[v]);
               cpo_to_fixed(&fv, 1, c.k, &c.V[v]);
+              if (!fits_25(c.U[v]) || !fits_25(c.V[v])) { st = CPO_ECORRUPT; goto done; }
               field[v] = fu;
               field[N + v] = fv;
               continue;
@@ -1425,9 +1474,10 @@ int cpo_decompress(const uint8_t* b, size_t len, float* field) {
                 memcpy(&outv, &a, 4);
                 if (!isfinite(outv)) { st = CPO_ECORRUPT; goto done; }
                 cpo_to_fixed(&outv, 1, c.k, &plane[comp][v]);
+                if (!fits_25(plane[comp][v])) { st = CPO_ECORRUPT; goto done; }
               } else {
                 int64_t r = pred[comp] + (int64_t)((int)q - QR) * (2 * xt + 1);
-                if (r >= (1 << 25) || r <= -(1 << 25)) { st = CPO_ECORRUPT; goto done; }
+                if (!fits_25(r)) { st = CPO_ECORRUPT; goto done; }
                 plane[comp][v] = (int32_t)r;
                 outv = (float)ldexp((double)r, -c.k);
               }
@@ -1447,7 +1497,9 @@ done:
  * ==================================================================== */
 int cpo_verify(const float* a, const float* bfield, int H, int W, int T, int k,
                uint64_t* fc_t, uint64_t* fc_s, double* max_err, double* psnr) {
+  if (H < 2 || W < 2 || T < 1) return CPO_EINVAL;
   size_t N = (size_t)H * W * T;
+  if (!fits_24(a, 2 * N, k) || !fits_24(bfield, 2 * N, k)) return CPO_EINVAL;
   int32_t* A = (int32_t*)malloc(2 * N * sizeof(int32_t));
   int32_t* B = (int32_t*)malloc(2 * N * sizeof(int32_t));
   uint32_t* ma = (uint32_t*)malloc(N * sizeof(uint32_t));

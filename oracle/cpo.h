@@ -139,11 +139,22 @@ int cpo_block_mode(const int32_t* Ut, const int32_t* Vt, const int32_t* Up,
                    const int32_t* Vp, const uint8_t* flags_t, int H, int W,
                    int bx, int by, const cpo_options* opt, int k, int64_t eps,
                    float* feat);
+/* The same decision's K trial scores (Q16 bits per sample, Sec. VI-B) for
+   predictor 2 or 3, into scores [K]; returns the class or a negative status. */
+int cpo_block_scores(const int32_t* Ut, const int32_t* Vt, const int32_t* Up,
+                     const int32_t* Vp, const uint8_t* flags_t, int H, int W,
+                     int bx, int by, const cpo_options* opt, int k, int64_t eps,
+                     int64_t* scores);
+/* Canonical codewords of a code with the given lengths (0 = unused):
+   symbols ordered by (length, symbol), each codeword the previous one plus
+   one, shifted left by the length difference. */
+void cpo_canonical_codes(const uint8_t* lengths, int nsym, uint32_t* codes);
 size_t cpo_compress_bound(int H, int W, int T);
 int cpo_stream_info(const uint8_t* bytes, size_t len, cpo_info* info);
 int cpo_decompress(const uint8_t* bytes, size_t len, float* field);
 
-/* Comparison of two fields on the same fixed-point grid. */
+/* Comparison of two fields on the same fixed-point grid 2^k (both need
+   |x| 2^k < 2^24, else CPO_EINVAL). */
 int cpo_verify(const float* a, const float* b, int H, int W, int T, int k,
                uint64_t* fc_t, uint64_t* fc_s, double* max_err, double* psnr);
 /* Lemma-1 check and trajectory count over the tetrahedra. */
