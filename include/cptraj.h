@@ -186,25 +186,36 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
  * Decompress n streams (1 <= n <= 65536) in one device pipeline, as
  * cpt_decompress does for each: streams (host array of device pointers,
  * 4-byte aligned) of lens[i] bytes (host) into fields (host array of device
- * pointers, each (2,T,H,W) float32 as its header says).  Streams may differ
- * in size, predictor and block height.  status (host, n, may be NULL)
- * receives each stream's outcome; a corrupt stream (CPT_ECORRUPT) leaves the
- * others unaffected and its own output undefined.  Returns CPT_OK when every
- * stream succeeded, else the first failure.  Synchronises `stream` twice
- * (after reading the headers, and at the end).
+ * pointers, each (2,T,H,W) float32 as its header says, holding at least
+ * field_caps[i] floats (host array)).  Streams may differ in size, predictor
+ * and block height.  status (host, n, may be NULL) receives each stream's
+ * outcome: CPT_ECORRUPT for a corrupt stream, CPT_ECAPACITY when its field
+ * needs more than field_caps[i] floats (nothing is written to it); either
+ * leaves the others unaffected.  Returns CPT_OK when every stream succeeded,
+ * else the first failure.  Synchronises `stream` twice (after reading the
+ * headers, and at the end); when no stream is long enough for a header it
+ * returns CPT_ECORRUPT without any device work.
  */
 cpt_status cpt_decompress_batch(int n, const uint8_t* const* streams, const size_t* lens, float* const* fields,
-                                int32_t* status, void* stream);
+                                const size_t* field_caps, int32_t* status, void* stream);
 
 /* Parse a stream header (host bytes, at least 256). */
 cpt_status cpt_stream_info(const uint8_t* bytes, size_t len, cpt_info* info);
 
 /*
- * Decompress a stream (device, 4-byte aligned) into `field` (device,
- * (2,T,H,W) float32 as given by cpt_stream_info).  Any inconsistency gives
- * CPT_ECORRUPT without out-of-bounds access.  Synchronises `stream`.
+ * The decompressor D of Sec. IV-A: reverse the entropy coding and the
+ * predictions of Sec. VI (Lorenzo, semi-Lagrangian, in the processing order
+ * the compressor used) and return the reconstructed field, within eb_abs of
+ * the original at every vertex and with every space-time face's critical
+ * status and sign unchanged.
+ *   bytes      device, the stream (4-byte aligned), len bytes
+ *   field      device, (2,T,H,W) float32 as given by cpt_stream_info
+ *   field_cap  floats the caller allocated at `field`; CPT_ECAPACITY (and
+ *              nothing written) when it is below 2 T H W
+ * Any inconsistency gives CPT_ECORRUPT without out-of-bounds access, and the
+ * output is then undefined.  Synchronises `stream`.
  */
-cpt_status cpt_decompress(const uint8_t* bytes, size_t len, float* field, void* stream);
+cpt_status cpt_decompress(const uint8_t* bytes, size_t len, float* field, size_t field_cap, void* stream);
 
 /*
  * Critical-point trajectory pieces (Sec. III-E/F): the crossed space-time
@@ -218,8 +229,14 @@ cpt_status cpt_decompress(const uint8_t* bytes, size_t len, float* field, void* 
 cpt_status cpt_extract_trajectories(const float* field, int H, int W, int T, int k, uint64_t* codes, size_t cap,
                                     size_t* count, void* stream);
 
-/* Compare two fields (device) on the grid 2^k: false cases per slice and
- * per slab, max error and PSNR.  Synchronises `stream`. */
+/* The check of Sec. IV-A with the metrics of Sec. VII-A: both fields
+ * (device, (2,T,H,W) float32) converted to the grid 2^k, their crossed faces
+ * and signs extracted as cpt_extract_trajectories does, and every face whose
+ * crossed status or sign differs counted as a false case, in time slices
+ * (face types 0-1: FC_t) or across slabs (types 2-11: FC_s); also the
+ * largest |a - b| and PSNR = 20 log10(max a - min a) - 10 log10(MSE) over
+ * both components.  Requires max|x| 2^k < 2^24 for both fields, else
+ * CPT_EINVAL.  Synchronises `stream`. */
 cpt_status cpt_verify(const float* a, const float* b, int H, int W, int T, int k, cpt_verify_result* res,
                       void* stream);
 

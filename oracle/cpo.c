@@ -380,8 +380,9 @@ int64_t cpo_lorenzo3(const int32_t* cur_t, const int32_t* prev, int W, int x, in
 
 /* Semi-Lagrangian predictor (Sec. VI-A) in Q16 cell units.  READING: the
    displacement of a fixed-point velocity u is floor(u c / 2^s), where c/2^s
-   approximates dt/dx 2^(16-k); positions are clamped to the domain;
-   bilinear sampling rounds half up. */
+   approximates dt/dx 2^(16-k) with c in [2^30, 2^31) (s at most 62; a zero
+   factor is c = s = 0; 2^31 - 1 or more saturates to c = 2^31 - 1, s = 0);
+   positions are clamped to the domain; bilinear sampling rounds half up. */
 void cpo_sl_factor(double dt_dx, int k, int64_t* c, int64_t* s) {
   double f = ldexp(dt_dx, 16 - k);
   if (!(f > 0.0)) {
@@ -403,6 +404,7 @@ void cpo_sl_factor(double dt_dx, int k, int64_t* c, int64_t* s) {
     cc = 1073741824LL;
     sh -= 1;
   }
+  if (cc == 0) sh = 0; /* a factor too small for 62 fraction bits: no displacement */
   *c = cc;
   *s = sh;
 }

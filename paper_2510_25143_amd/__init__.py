@@ -81,7 +81,7 @@ def lib():
         "cpt_compress": [P, i32, i32, i32, dbl, P, P, sz, P, P],
         "cpt_compress_debug": [P, i32, i32, i32, dbl, P, P, sz, P, P, P, P, P, P, P, P],
         "cpt_stream_info": [P, sz, P],
-        "cpt_decompress": [P, sz, P, P],
+        "cpt_decompress": [P, sz, P, sz, P],
         "cpt_extract_trajectories": [P, i32, i32, i32, i32, P, sz, P, P],
         "cpt_verify": [P, P, i32, i32, i32, i32, P, P],
         "cpt_field_params": [P, i32, i32, i32, i32, dbl, P, P, P, P],
@@ -91,7 +91,7 @@ def lib():
         "cpt_timing_read": [i32, P, P, P],
         "cpt_compress_batch": [i32, P, P, dbl, P, P, P, P, P, P, P],
         "cpt_autotune_batch": [i32, P, P, dbl, P, P, P, i32, P, P, P],
-        "cpt_decompress_batch": [i32, P, P, P, P, P],
+        "cpt_decompress_batch": [i32, P, P, P, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -236,24 +236,42 @@ def autotune_batch(fields, eb, reps=2, predictor=PRED_MIX2, mode_bt=1, eb_mode=0
     return (name, bool(best.use_graph)), list(ms)
 
 
+def _out_field(out):
+    """An output field must be a contiguous float32 CUDA tensor; its element
+    count is passed to the library as the capacity."""
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float32):
+        raise TypeError("output field must be a float32 CUDA tensor")
+    if not out.is_contiguous():
+        raise ValueError("output field must be contiguous")
+    return out
+
+
 def decompress_batch(streams, outs=None, raise_on_error=True):
     """Decompress a list of streams (uint8 CUDA tensors) in one device
-    pipeline.  Returns (fields, status)."""
+    pipeline.  Returns (fields, status); with raise_on_error=False a corrupt
+    stream or an undersized output only sets its status."""
     n = len(streams)
     if n == 0:
         raise ValueError("empty batch")
     ss = [s.contiguous() for s in streams]
+    for st in ss:
+        if not (st.is_cuda and st.dtype == torch.uint8):
+            raise TypeError("streams must be uint8 CUDA tensors")
     if outs is None:
         outs = []
         for st in ss:
             info = stream_info(st)
             outs.append(torch.empty((2, info["T"], info["H"], info["W"]), dtype=torch.float32, device=st.device))
+    if len(outs) != n:
+        raise ValueError("need one output field per stream")
+    outs = [_out_field(o) for o in outs]
     sp = (ctypes.c_void_p * n)(*[st.data_ptr() for st in ss])
     lens = (ctypes.c_size_t * n)(*[st.numel() for st in ss])
     fp = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    caps = (ctypes.c_size_t * n)(*[o.numel() for o in outs])
     status = (ctypes.c_int32 * n)()
-    r = lib().cpt_decompress_batch(n, sp, lens, fp, status, _stream())
-    if r != OK and (raise_on_error or r != ECORRUPT):
+    r = lib().cpt_decompress_batch(n, sp, lens, fp, caps, status, _stream())
+    if r != OK and (raise_on_error or r not in (ECORRUPT, ECAPACITY)):
         _check(r)
     return outs, [status[i] for i in range(n)]
 
@@ -272,10 +290,11 @@ def decompress(stream_bytes, out=None):
     if not (stream_bytes.is_cuda and stream_bytes.dtype == torch.uint8):
         raise TypeError("stream must be a uint8 CUDA tensor")
     b = stream_bytes.contiguous()
-    info = stream_info(b)
     if out is None:
+        info = stream_info(b)
         out = torch.empty((2, info["T"], info["H"], info["W"]), dtype=torch.float32, device=b.device)
-    _check(lib().cpt_decompress(_ptr(b), b.numel(), _ptr(out), _stream()))
+    out = _out_field(out)
+    _check(lib().cpt_decompress(_ptr(b), b.numel(), _ptr(out), out.numel(), _stream()))
     return out
 
 

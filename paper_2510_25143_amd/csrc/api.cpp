@@ -158,61 +158,6 @@ cpt_status reserve(Arena& A) {
   return CPT_OK;
 }
 
-// ---------------------------------------------------- host-side derivations
-// Fixed point 2^k with k = 23 - e for max|x| = m 2^e, m in [0.5, 1), capped at
-// 120; eps' = floor(eb_abs 2^k - 1/2), at most 2^23 - 1.
-cpt_status derive_params(double mn, double mx, double ma, int eb_mode, double eb, int* k, double* ea,
-                         int64_t* eps) {
-  if (ma >= std::ldexp(1.0, 100)) return fail(CPT_EINVAL, "field magnitude of 2^100 or more is not supported");
-  int e = 0;
-  if (ma > 0) std::frexp(ma, &e);
-  int kk = 23 - e;
-  if (kk > 120) kk = 120;
-  double a;
-  if (eb_mode == 0) {
-    if (!(eb > 0.0 && eb <= 0.5)) return fail(CPT_EINVAL, "relative error bound must be in (0, 0.5]");
-    a = eb * (mx - mn);
-  } else if (eb_mode == 1) {
-    if (!(eb > 0.0) || !std::isfinite(eb)) return fail(CPT_EINVAL, "absolute error bound must be positive");
-    a = eb;
-  } else {
-    return fail(CPT_EINVAL, "eb_mode must be 0 or 1");
-  }
-  double s = std::floor(std::ldexp(a, kk) - 0.5);
-  int64_t ep = 0;
-  if (s > 0) ep = s >= 8388607.0 ? 8388607 : (int64_t)s;
-  *k = kk;
-  *ea = a;
-  *eps = ep;
-  return CPT_OK;
-}
-
-// displacement factor c / 2^s ~ dt_dx 2^(16-k), c < 2^31
-void sl_factor(double dt_dx, int k, int64_t* c, int64_t* s) {
-  double f = std::ldexp(dt_dx, 16 - k);
-  if (!(f > 0.0)) {
-    *c = 0;
-    *s = 0;
-    return;
-  }
-  if (f >= 2147483647.0) {
-    *c = 2147483647;
-    *s = 0;
-    return;
-  }
-  int e;
-  std::frexp(f, &e);
-  int sh = 31 - e;
-  if (sh > 62) sh = 62;
-  int64_t cc = (int64_t)std::nearbyint(std::ldexp(f, sh));
-  if (cc >= 2147483648LL) {
-    cc = 1073741824LL;
-    sh -= 1;
-  }
-  *c = cc;
-  *s = sh;
-}
-
 bool group_decided(int g, int bt, int T) {
   int td = g * bt > 1 ? g * bt : 1;
   int end = (g + 1) * bt < T ? (g + 1) * bt : T;
@@ -980,20 +925,40 @@ cpt_status carve_dec(Arena& A, const DPlan& P, DBufs& b) {
 }
 
 // Decompress n streams; status (host, n) receives each stream's outcome.
+// Every stream's outcome into status (host, may be NULL); the first failure,
+// if any, is returned with its message.
+cpt_status report_streams(int n, const std::vector<int32_t>& st_f, const std::vector<std::string>& why,
+                          int32_t* status) {
+  cpt_status first = CPT_OK;
+  for (int i = 0; i < n; i++) {
+    if (status) status[i] = st_f[i];
+    if (st_f[i] && first == CPT_OK) {
+      first = (cpt_status)st_f[i];
+      g_err = n > 1 ? "stream " + std::to_string(i) + ": " + why[i] : why[i];
+    }
+  }
+  return first;
+}
+
 cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const size_t* lens, float* const* fields,
-                                 int32_t* status, hipStream_t s) {
+                                 const size_t* caps, int32_t* status, hipStream_t s) {
   if (n < 1 || n > 65536) return fail(CPT_EINVAL, "batch size must be in 1..65536");
-  if (!streams || !lens || !fields) return fail(CPT_EINVAL, "null pointer");
+  if (!streams || !lens || !fields || !caps) return fail(CPT_EINVAL, "null pointer");
   std::vector<int32_t> st_f(n, CPT_OK);
   std::vector<std::string> why(n);
+  int safe = -1;  // first stream long enough for a header
   for (int i = 0; i < n; i++) {
     if (!streams[i] || !fields[i]) return fail(CPT_EINVAL, "stream " + std::to_string(i) + ": null pointer");
     if ((uintptr_t)streams[i] & 3) return fail(CPT_EINVAL, "stream must be 4-byte aligned");
     if (lens[i] < HDR_BYTES) {
       st_f[i] = CPT_ECORRUPT;
       why[i] = "stream shorter than its header";
+    } else if (safe < 0) {
+      safe = i;
     }
   }
+  // nothing to read: no device work and no staging at all
+  if (safe < 0) return report_streams(n, st_f, why, status);
   cpt_status st;
   Arena* Ap = arena_for_device(&st);
   if (!Ap) return st;
@@ -1001,10 +966,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
   std::lock_guard<std::mutex> lk(A.mu);
   // ---- headers: one gather, one copy (streams too short for a header read
   // the header of one that is not; their status is already set)
-  int safe = -1;
-  for (int i = 0; i < n && safe < 0; i++)
-    if (!st_f[i]) safe = i;
-  if (safe >= 0) {
+  {
     A.used = 0;
     const size_t po = A.off(8 * (size_t)n), ho = A.off(HDR_BYTES * (size_t)n);
     st = reserve(A);
@@ -1035,6 +997,11 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
     const cpt_info& I = Q.info;
     const int H = I.H, W = I.W, T = I.T, bt = I.mode_bt, K = I.K;
     const long long N = (long long)H * W * T;
+    if ((unsigned long long)(2 * N) > (unsigned long long)caps[i]) {
+      st_f[i] = CPT_ECAPACITY;
+      why[i] = "output holds " + std::to_string(caps[i]) + " floats, the stream needs " + std::to_string(2 * N);
+      continue;
+    }
     const int tx = (W + TILE - 1) / TILE, ty = (H + TILE - 1) / TILE;
     const int G = (T + bt - 1) / bt;
     const long long ndec = K > 1 ? decided_before(G, bt, T) : 0;
@@ -1186,15 +1153,7 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
       }
     }
   }
-  cpt_status first = CPT_OK;
-  for (int i = 0; i < n; i++) {
-    if (status) status[i] = st_f[i];
-    if (st_f[i] && first == CPT_OK) {
-      first = (cpt_status)st_f[i];
-      g_err = n > 1 ? "stream " + std::to_string(i) + ": " + why[i] : why[i];
-    }
-  }
-  return first;
+  return report_streams(n, st_f, why, status);
 }
 
 }  // namespace
@@ -1464,19 +1423,19 @@ cpt_status cpt_stream_info(const uint8_t* bytes, size_t len, cpt_info* info) {
   return CPT_OK;
 }
 
-cpt_status cpt_decompress(const uint8_t* bytes, size_t len, float* field, void* stream) {
+cpt_status cpt_decompress(const uint8_t* bytes, size_t len, float* field, size_t field_cap, void* stream) {
   try {
     if (!bytes || !field) return fail(CPT_EINVAL, "null pointer");
-    return decompress_batch_impl(1, &bytes, &len, &field, nullptr, (hipStream_t)stream);
+    return decompress_batch_impl(1, &bytes, &len, &field, &field_cap, nullptr, (hipStream_t)stream);
   } catch (...) {
     return fail(CPT_EHIP, "unexpected exception");
   }
 }
 
 cpt_status cpt_decompress_batch(int n, const uint8_t* const* streams, const size_t* lens, float* const* fields,
-                                int32_t* status, void* stream) {
+                                const size_t* field_caps, int32_t* status, void* stream) {
   try {
-    return decompress_batch_impl(n, streams, lens, fields, status, (hipStream_t)stream);
+    return decompress_batch_impl(n, streams, lens, fields, field_caps, status, (hipStream_t)stream);
   } catch (...) {
     return fail(CPT_EHIP, "unexpected exception");
   }
@@ -1484,19 +1443,49 @@ cpt_status cpt_decompress_batch(int n, const uint8_t* const* streams, const size
 
 cpt_status cpt_field_params(const float* field, int H, int W, int T, int eb_mode, double eb, int* k,
                             double* eb_abs, int64_t* eps, void* stream) {
-  if (!field || !k || !eb_abs || !eps) return fail(CPT_EINVAL, "null pointer");
-  cpt_status st = check_dims(H, W, T);
-  if (st) return st;
-  Arena* Ap = arena_for_device(&st);
-  if (!Ap) return st;
-  std::lock_guard<std::mutex> lk(Ap->mu);
-  Bufs b;
-  st = carve(*Ap, 1, b);
-  if (st) return st;
-  Range r;
-  st = field_range(field, 2 * (size_t)H * W * T, b, *Ap, (hipStream_t)stream, &r);
-  if (st) return st;
-  return derive_params(r.mn, r.mx, r.ma, eb_mode, eb, k, eb_abs, eps);
+  try {
+    if (!field || !k || !eb_abs || !eps) return fail(CPT_EINVAL, "null pointer");
+    const cpt_options o{sizeof(cpt_options), eb_mode, CPT_PRED_MIX2, 1, 1.0, 1.0, nullptr};
+    cpt_options opt;
+    cpt_status st = check_options(&o, eb, &opt);
+    if (st) return st;
+    const int32_t hwt[3] = {H, W, T};
+    Plan P;
+    st = make_plan(1, hwt, opt, eb, P);
+    if (st) return st;
+    P.D[0].field = field;
+    hipStream_t s = (hipStream_t)stream;
+    Arena* Ap = arena_for_device(&st);
+    if (!Ap) return st;
+    Arena& A = *Ap;
+    std::lock_guard<std::mutex> lk(A.mu);
+    // the compressor's own range and parameter kernels, on one field
+    A.used = 0;
+    const size_t od = A.off(sizeof(FieldDesc)), orp = A.off(vec_bytes(P.rpre)),
+                 org = A.off(16 * (size_t)RANGE_SLOTS * RANGE_SLOT_STRIDE);
+    st = reserve(A);
+    if (st) return st;
+    st = reserve_stage(A, sizeof(FieldDesc) + vec_bytes(P.rpre) + 64);
+    if (st) return st;
+    std::memcpy(A.stage, P.D.data(), sizeof(FieldDesc));
+    std::memcpy(A.stage + sizeof(FieldDesc), P.rpre.data(), vec_bytes(P.rpre));
+    FieldDesc* D = (FieldDesc*)(A.base + od);
+    const long long* rpre = (const long long*)(A.base + orp);
+    HIPCHK(hipMemcpyAsync(D, A.stage, sizeof(FieldDesc), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(A.base + orp, A.stage + sizeof(FieldDesc), vec_bytes(P.rpre), hipMemcpyHostToDevice, s));
+    launch_params_b(D, 1, rpre, P.rpre[1], (int4*)(A.base + org), s);
+    HIPCHK(hipMemcpyAsync(A.stage, D, sizeof(FieldDesc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    const FieldDesc* Dh = (const FieldDesc*)A.stage;
+    if (Dh->status) return fail(CPT_EINVAL, reason_text(Dh->reason));
+    *k = Dh->p.k;
+    *eb_abs = Dh->eb_abs;
+    *eps = Dh->p.eps;
+    return CPT_OK;
+  } catch (...) {
+    return fail(CPT_EHIP, "unexpected exception");
+  }
 }
 
 cpt_status cpt_extract_trajectories(const float* field, int H, int W, int T, int k, uint64_t* codes, size_t cap,

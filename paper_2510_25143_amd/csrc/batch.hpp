@@ -99,6 +99,8 @@ constexpr int RANGE_SLOTS = 32, RANGE_SLOT_STRIDE = 8;
 // range, parameters, then conversion, edges, faces and flags fused in one
 // time-marching kernel over 32x16 tiles (rpre: range workgroups per field,
 // fpre: tiles per field)
+// range and parameters only (k, eps', displacement factors into D[f].p)
+void launch_params_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, int4* range, hipStream_t s);
 void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* fpre,
                         long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s);
 constexpr int FIELDPASS_TW = 32, FIELDPASS_TH = 16;

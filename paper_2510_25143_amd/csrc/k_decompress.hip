@@ -154,6 +154,9 @@ __global__ __launch_bounds__(RC_THREADS) void k_reconstruct_b(DecDesc* __restric
         used++;
         if (((b >> 23) & 0xFFu) == 0xFFu) atomicOr(err, 64u);
         const int val = to_fixed(__uint_as_float(b), p.k);
+        // a stored original never reaches 2^24 on the field's grid; 2^25
+        // and beyond (saturated by the conversion) is a corrupt stream
+        if (val >= (1 << 25) || val <= -(1 << 25)) atomicOr(err, 128u);
         C[c][ly][lx] = val;
         A[c][ly][lx] = val;
         KN[c][ly][lx] = 1;

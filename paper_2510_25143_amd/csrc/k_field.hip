@@ -276,29 +276,57 @@ __device__ __forceinline__ double key_value(int key) {
   return (double)__int_as_float(s);
 }
 
-// displacement factor c / 2^s ~ dt_dx 2^(16-k), c < 2^31
-__device__ void sl_factor_dev(double dt_dx, int k, int64_t* c, int64_t* s) {
-  double f = ldexp(dt_dx, 16 - k);
-  if (!(f > 0.0)) {
+// Semi-Lagrangian displacement factor (Sec. VI-A in Q16 fixed point): the
+// displacement of a fixed-point velocity u is floor(u c / 2^s) cells in Q16,
+// where c / 2^s is r 2^(16-k) (r = dt/dx, the grid's time step over spacing)
+// rounded to 31 significant bits: c in [2^30, 2^31), round half to even.
+// Two limits: s is at most 62 (c then shorter, possibly 0, and a factor of 0
+// is stored as c = s = 0), and a factor of 2^31 - 1 or more saturates to
+// c = 2^31 - 1, s = 0.  Worked on the double's bits: r = m 2^ex with an
+// integer significand m normalised into [2^52, 2^53).
+__device__ void sl_factor_dev(double r, int k, int64_t* c, int64_t* s) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(r);
+  const int E = (int)((bits >> 52) & 0x7FF);
+  uint64_t m = bits & ((1ull << 52) - 1);
+  int ex;
+  if (E == 0) {
+    ex = -1074;
+  } else {
+    m |= 1ull << 52;
+    ex = E - 1075;
+  }
+  if (m == 0) {  // r = 0: no displacement
     *c = 0;
     *s = 0;
     return;
   }
-  if (f >= 2147483647.0) {
+  const int lz = __clzll((long long)m) - 11;
+  m <<= lz;
+  ex -= lz;
+  const int p = ex + 16 - k;  // r 2^(16-k) = m 2^p
+  int sh = -p - 22;  // c = m 2^-22 rounded, c 2^-sh = m 2^p
+  int rs = 22;
+  if (sh > 62) {
+    rs += sh - 62;
+    sh = 62;
+  }
+  uint64_t q = 0;
+  if (rs < 64) {
+    q = m >> rs;
+    const uint64_t rem = m & ((1ull << rs) - 1), half = 1ull << (rs - 1);
+    if (rem > half || (rem == half && (q & 1))) q++;
+  }
+  if (q == (1ull << 31)) {  // rounding carried into bit 31
+    q = 1ull << 30;
+    sh -= 1;
+  }
+  if (sh < 0) {  // the factor is 2^31 or more
     *c = 2147483647;
     *s = 0;
     return;
   }
-  int e;
-  frexp(f, &e);
-  int sh = 31 - e;
-  if (sh > 62) sh = 62;
-  int64_t cc = (int64_t)rint(ldexp(f, sh));
-  if (cc >= 2147483648LL) {
-    cc = 1073741824LL;
-    sh -= 1;
-  }
-  *c = cc;
+  if (q == 0) sh = 0;
+  *c = (int64_t)q;
   *s = sh;
 }
 
@@ -320,24 +348,27 @@ __global__ void k_params_b(FieldDesc* __restrict__ D, const int4* __restrict__ r
     R.z = (int)max((uint32_t)R.z, (uint32_t)q.z);
     R.w |= q.w;
   }
-  const double mn = key_value(R.x), mx = key_value(R.y), ma = (double)__int_as_float(R.z);
+  const double mn = key_value(R.x), mx = key_value(R.y);
+  // max|x| = 0.f 2^e with the leading fraction bit set: e from the float's
+  // exponent field (normal) or from the position of the leading significand
+  // bit (subnormal); k = 23 - e puts max|x| 2^k in [2^22, 2^23)
+  const uint32_t mab = (uint32_t)R.z, mexp = mab >> 23, mman = mab & 0x7FFFFFu;
   int kk = 23;
   if (R.w) {
     d.status = STATUS_EINVAL;
     d.reason = REASON_NONFINITE;
-  } else if (ma >= ldexp(1.0, 100)) {
+  } else if (mexp >= 127 + 100) {
     d.status = STATUS_EINVAL;
     d.reason = REASON_MAGNITUDE;
-  } else {
-    int e = 0;
-    if (ma > 0) frexp(ma, &e);
-    kk = 23 - e;
-    if (kk > 120) kk = 120;
+  } else if (mab != 0) {
+    const int e = mexp ? (int)mexp - 126 : (32 - __clz((int)mman)) - 149;
+    kk = min(23 - e, 120);
   }
+  // eps' = floor(eb_abs 2^k - 1/2) in [0, 2^23 - 1]: the half unit absorbs
+  // the rounding of the conversion, so |x - x'| <= eb_abs in field units
   const double a = d.eb_mode == 0 ? d.eb * (mx - mn) : d.eb;
   const double sc = floor(ldexp(a, kk) - 0.5);
-  int64_t ep = 0;
-  if (sc > 0) ep = sc >= 8388607.0 ? 8388607 : (int64_t)sc;
+  const int64_t ep = sc <= 0.0 ? 0 : (sc >= 8388607.0 ? 8388607 : (int64_t)sc);
   FieldParams p;
   p.H = d.H;
   p.W = d.W;
@@ -789,11 +820,14 @@ void launch_write_codes(const uint32_t* masks, const uint32_t* ofs, size_t N, ui
 }
 size_t compare_partials(size_t N) { return nblk(N); }
 
-void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* fpre,
-                        long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s) {
+void launch_params_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, int4* range, hipStream_t s) {
   k_range_init_b<<<nblk((size_t)n * RANGE_SLOTS, 64), 64, 0, s>>>(range, n);
   if (rblocks > 0) k_range_b<<<(unsigned)rblocks, 256, 0, s>>>(D, rpre, n, range);
   k_params_b<<<nblk(n, 64), 64, 0, s>>>(D, range, n);
+}
+void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* fpre,
+                        long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s) {
+  launch_params_b(D, n, rpre, rblocks, range, s);
   if (fblocks > 0) k_fieldpass_b<<<(unsigned)fblocks, 256, 0, s>>>(D, fpre, n, cur, flags);
 }
 void launch_compare(const uint32_t* ma, const uint32_t* mb, const float* a, const float* b, size_t N,

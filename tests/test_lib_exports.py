@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -70,3 +71,36 @@ def test_stream_info_rejects_garbage_on_host(built):
         cpt.stream_info(torch.from_numpy(bad))
     with pytest.raises(cpt.CptError):
         cpt.stream_info(torch.from_numpy(b[:100].copy()))
+
+
+SHORT_STREAMS = r'''
+import ctypes, sys
+L = ctypes.CDLL(sys.argv[1])
+L.cpt_last_error.restype = ctypes.c_char_p
+buf = (ctypes.c_uint32 * 64)()          # host memory: never read, every stream is too short
+out = (ctypes.c_float * 16)()
+P = ctypes.c_void_p
+L.cpt_decompress.argtypes = [P, ctypes.c_size_t, P, ctypes.c_size_t, P]
+st = L.cpt_decompress(ctypes.addressof(buf), 100, ctypes.addressof(out), 16, None)
+msg = L.cpt_last_error().decode()
+streams = (P * 2)(ctypes.addressof(buf), ctypes.addressof(buf))
+lens = (ctypes.c_size_t * 2)(0, 255)
+fields = (P * 2)(ctypes.addressof(out), ctypes.addressof(out))
+caps = (ctypes.c_size_t * 2)(16, 16)
+status = (ctypes.c_int32 * 2)(7, 7)
+L.cpt_decompress_batch.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+sb = L.cpt_decompress_batch(2, streams, lens, fields, caps, status, None)
+print(st, sb, status[0], status[1], msg)
+'''
+
+
+def test_streams_shorter_than_a_header_touch_no_device(built):
+    """As the first calls of a fresh process, decompressing streams that are
+    all shorter than the 256-byte header reports a corrupt stream without
+    staging, device work or any read of the stream."""
+    r = subprocess.run([sys.executable, "-c", SHORT_STREAMS, built], capture_output=True, text=True,
+                       env=dict(os.environ, HIP_VISIBLE_DEVICES=""), timeout=120)
+    assert r.returncode == 0, r.stderr
+    st, sb, s0, s1, *msg = r.stdout.split()
+    assert (int(st), int(sb), int(s0), int(s1)) == (-3, -3, -3, -3)
+    assert "shorter than its header" in " ".join(msg)

@@ -26,11 +26,12 @@ from test_oracle_mesh import brute_faces, generic_crossed
 # ------------------------------------------------------------- SL factor
 def test_sl_factor_non_power_of_two(ora):
     """c / 2^s is dt/dx 2^(16-k) rounded to the nearest integer multiple of
-    2^-s, with c normalised into [2^30, 2^31) unless s hits its cap of 62 or
-    the factor itself reaches 2^31 - 1 (then c = 2^31 - 1, s = 0)."""
+    2^-s, with c normalised into [2^30, 2^31) unless s hits its cap of 62 (a
+    factor that rounds to 0 there is stored as c = s = 0) or the factor
+    itself reaches 2^31 - 1 (then c = 2^31 - 1, s = 0)."""
     rng = np.random.default_rng(11)
     vals = list(rng.uniform(1e-4, 50.0, 300)) + list(np.exp(rng.uniform(-40, 25, 300)))
-    vals += [0.5 / 29.7, 0.016835, 1.0 / 3.0, 0.1, 7.0, 1e-30, 3e8]
+    vals += [0.5 / 29.7, 0.016835, 1.0 / 3.0, 0.1, 7.0, 1e-30, 3e8, 5e-324, 1e-300, 2.0 ** -47]
     ks = rng.integers(-60, 121, len(vals))
     for dt, k in zip(vals, ks):
         dt, k = float(dt), int(k)
@@ -40,6 +41,9 @@ def test_sl_factor_non_power_of_two(ora):
             assert (c, s) == (2 ** 31 - 1, 0), (dt, k)
             continue
         assert 0 <= c < 2 ** 31 and 0 <= s <= 62, (dt, k, c, s)
+        if c == 0:   # too small for 62 fraction bits: stored as no displacement
+            assert s == 0 and f * 2 ** 62 <= Fraction(1, 2), (dt, k)
+            continue
         assert abs(c - f * 2 ** s) <= Fraction(1, 2), (dt, k, c, s)
         assert c >= 2 ** 30 or s == 62, (dt, k, c, s)
     assert ora.sl_factor(0.0, 13) == (0, 0)
