@@ -240,6 +240,23 @@ cpt_status cpt_extract_trajectories(const float* field, int H, int W, int T, int
 cpt_status cpt_verify(const float* a, const float* b, int H, int W, int T, int k, cpt_verify_result* res,
                       void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the check
+ * of cpt_verify, same arguments and results bit for bit, without any device
+ * or pinned allocation.  Its intermediate arrays (fixed-point values, edge
+ * signs, both face masks, error partials: about 17.1 bytes per vertex) live
+ * in one fixed array of CPT_VERIFY_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on from load until the process ends, so fields
+ * of more than CPT_VERIFY_NOALLOC_MAX_VERTICES vertices (H W T) are refused
+ * with CPT_EUNSUPPORTED before any device work.  Every call on one GPU
+ * shares that array: overlapping calls would race, so the library runs one
+ * call at a time per process (a lock held until the call has synchronised
+ * its stream).  Synchronises `stream` twice. */
+#define CPT_VERIFY_NOALLOC_SCRATCH_BYTES (128u << 20)
+#define CPT_VERIFY_NOALLOC_MAX_VERTICES 7866176u
+cpt_status cpt_verify_noalloc(const float* a, const float* b, int H, int W, int T, int k, cpt_verify_result* res,
+                              void* stream);
+
 /* Fixed-point exponent k and bound eps' the compressor derives for a field
  * (device) and bound; synchronises `stream`. */
 cpt_status cpt_field_params(const float* field, int H, int W, int T, int eb_mode, double eb, int* k,

@@ -62,7 +62,8 @@ class VerifyResult(ctypes.Structure):
 EXPORTS = ["cpt_compress_bound", "cpt_compress", "cpt_compress_debug", "cpt_stream_info",
            "cpt_decompress", "cpt_extract_trajectories", "cpt_verify", "cpt_field_params",
            "cpt_selector_grad", "cpt_selector_train", "cpt_timing_enable", "cpt_timing_read",
-           "cpt_compress_batch", "cpt_autotune_batch", "cpt_decompress_batch", "cpt_last_error"]
+           "cpt_compress_batch", "cpt_autotune_batch", "cpt_decompress_batch", "cpt_verify_noalloc",
+           "cpt_last_error"]
 
 _lib = None
 
@@ -84,6 +85,7 @@ def lib():
         "cpt_decompress": [P, sz, P, sz, P],
         "cpt_extract_trajectories": [P, i32, i32, i32, i32, P, sz, P, P],
         "cpt_verify": [P, P, i32, i32, i32, i32, P, P],
+        "cpt_verify_noalloc": [P, P, i32, i32, i32, i32, P, P],
         "cpt_field_params": [P, i32, i32, i32, i32, dbl, P, P, P, P],
         "cpt_selector_grad": [P, P, P, i32, P, P, P],
         "cpt_selector_train": [P, P, i32, P, P, P, P, P],
@@ -319,6 +321,19 @@ def verify(a, b, k):
     _, T, H, W = fa.shape
     r = VerifyResult()
     _check(lib().cpt_verify(_ptr(fa), _ptr(fb), H, W, T, k, ctypes.byref(r), _stream()))
+    return dict(fc_t=r.fc_t, fc_s=r.fc_s, max_err=r.max_err, psnr=r.psnr)
+
+
+VERIFY_NOALLOC_MAX_VERTICES = 7866176
+
+
+def verify_noalloc(a, b, k):
+    """verify() through the allocation-free entry point (fields of at most
+    VERIFY_NOALLOC_MAX_VERTICES vertices)."""
+    fa, fb = _field(a), _field(b)
+    _, T, H, W = fa.shape
+    r = VerifyResult()
+    _check(lib().cpt_verify_noalloc(_ptr(fa), _ptr(fb), H, W, T, k, ctypes.byref(r), _stream()))
     return dict(fc_t=r.fc_t, fc_s=r.fc_s, max_err=r.max_err, psnr=r.psnr)
 
 

@@ -1158,6 +1158,75 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
 
 }  // namespace
 
+// ================================================ allocation-free check
+// cpt_verify_noalloc keeps every intermediate array of the check in one fixed
+// device array that the library's code object holds on each GPU from load
+// until the process ends.  The array's name is only a host-side stand-in:
+// host code uses the device address taken once per device with
+// hipGetSymbolAddress, never the name itself.
+static __device__ __align__(256) unsigned char scratch[CPT_VERIFY_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex g_na_mu;  // one call at a time per process: every call shares the array
+unsigned char* g_na_ptr[NA_MAX_DEVICES] = {nullptr};
+
+// Byte offsets of the check's arrays inside the scratch array for N vertices:
+// range records of both fields (2 x 16 B), the false-case counters and the
+// reduced error sums (4 x 8 B), fixed-point values, edge signs, both face
+// masks and the per-workgroup error partials.
+struct NaLayout {
+  size_t range, res, cur, edges, masks, masks2, part, end;
+};
+constexpr size_t na_up(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr NaLayout na_layout(size_t N) {
+  auto up = na_up;
+  NaLayout L{};
+  L.range = 0;
+  L.res = 256;
+  L.cur = 512;
+  L.edges = L.cur + up(8 * N);
+  L.masks = L.edges + up(N);
+  L.masks2 = L.masks + up(4 * N);
+  L.part = L.masks2 + up(4 * N);
+  L.end = L.part + up(16 * ((N + 255) / 256));  // compare_partials(N) workgroup partials
+  return L;
+}
+static_assert(na_layout(CPT_VERIFY_NOALLOC_MAX_VERTICES).end <= CPT_VERIFY_NOALLOC_SCRATCH_BYTES &&
+                  na_layout(CPT_VERIFY_NOALLOC_MAX_VERTICES + 1ull).end > CPT_VERIFY_NOALLOC_SCRATCH_BYTES,
+              "the vertex limit is the largest field whose arrays fit the scratch array");
+
+// the per-workgroup error partials of k_compare reduced in index order, as
+// the host does for cpt_verify: max |a - b| and the sum of squares
+__global__ void k_na_sum_partials(const double* __restrict__ part, size_t np, double* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double me = 0.0, se = 0.0;
+  for (size_t i = 0; i < np; i++) {
+    me = std::max(me, part[2 * i]);
+    se += part[2 * i + 1];
+  }
+  out[0] = me;
+  out[1] = se;
+}
+
+// the calling device's scratch address, looked up on its first call there
+cpt_status na_scratch(unsigned char** ptr) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(CPT_EHIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= NA_MAX_DEVICES) return fail(CPT_EUNSUPPORTED, "device index beyond the supported 64");
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(CPT_EHIP, std::string("hipGetSymbolAddress of the check's scratch array failed: ") +
+                                hipGetErrorString(e));
+    g_na_ptr[dev] = (unsigned char*)p;
+  }
+  *ptr = g_na_ptr[dev];
+  return CPT_OK;
+}
+}  // namespace
+
 // ================================================================ C ABI
 extern "C" {
 
@@ -1564,6 +1633,72 @@ cpt_status cpt_verify(const float* a, const float* bf, int H, int W, int T, int 
   double mse = se / (double)(2 * N);
   res->psnr = mse > 0 ? 20.0 * std::log10(ra.mx - ra.mn) - 10.0 * std::log10(mse) : INFINITY;
   return CPT_OK;
+}
+
+cpt_status cpt_verify_noalloc(const float* a, const float* bf, int H, int W, int T, int k,
+                              cpt_verify_result* res, void* stream) {
+  try {
+    if (!a || !bf || !res) return fail(CPT_EINVAL, "null pointer");
+    cpt_status st = check_dims(H, W, T);
+    if (st) return st;
+    if (k < -80 || k > 120) return fail(CPT_EINVAL, "k must be in -80..120");
+    const size_t N = (size_t)H * W * T;
+    const NaLayout L = na_layout(N);
+    if (L.end > CPT_VERIFY_NOALLOC_SCRATCH_BYTES)
+      return fail(CPT_EUNSUPPORTED, "the allocation-free check holds at most " +
+                                        std::to_string(CPT_VERIFY_NOALLOC_MAX_VERTICES) + " vertices; this field has " +
+                                        std::to_string(N));
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    unsigned char* base = nullptr;
+    st = na_scratch(&base);
+    if (st) return st;
+    int* ra = (int*)(base + L.range);
+    int* rb = ra + 4;
+    unsigned long long* fc = (unsigned long long*)(base + L.res);
+    double* sums = (double*)(base + L.res + 16);
+    int2* cur = (int2*)(base + L.cur);
+    uint8_t* edges = base + L.edges;
+    uint32_t* ma = (uint32_t*)(base + L.masks);
+    uint32_t* mb = (uint32_t*)(base + L.masks2);
+    double* part = (double*)(base + L.part);
+    // value ranges of both fields (each record is cleared by its own kernel)
+    launch_range(a, 2 * N, ra, s);
+    launch_range(bf, 2 * N, rb, s);
+    int hr[8];  // pageable host memory: no pinned staging is allocated
+    HIPCHK(hipMemcpyAsync(hr, ra, sizeof(hr), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hr[3] || hr[7]) return fail(CPT_EINVAL, "field contains NaN or Inf");
+    float fa, fb;
+    std::memcpy(&fa, &hr[2], 4);
+    std::memcpy(&fb, &hr[6], 4);
+    if (std::ldexp(std::max((double)fa, (double)fb), k) >= 16777216.0)
+      return fail(CPT_EINVAL, "max|x| 2^k must be below 2^24");
+    // crossed faces of both fields, then the comparison (counters cleared by
+    // a kernel inside launch_compare)
+    launch_convert(a, N, k, cur, s);
+    launch_masks(cur, H, W, T, edges, ma, s);
+    launch_convert(bf, N, k, cur, s);
+    launch_masks(cur, H, W, T, edges, mb, s);
+    launch_compare(ma, mb, a, bf, N, fc, part, s);
+    k_na_sum_partials<<<1, 64, 0, s>>>(part, compare_partials(N), sums);
+    uint64_t hres[4];
+    HIPCHK(hipMemcpyAsync(hres, fc, sizeof(hres), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    double me, se;
+    std::memcpy(&me, &hres[2], 8);
+    std::memcpy(&se, &hres[3], 8);
+    res->fc_t = hres[0];
+    res->fc_s = hres[1];
+    res->max_err = me;
+    const double mn = (double)key_to_float(hr[0]), mx = (double)key_to_float(hr[1]);
+    const double mse = se / (double)(2 * N);
+    res->psnr = mse > 0 ? 20.0 * std::log10(mx - mn) - 10.0 * std::log10(mse) : INFINITY;
+    return CPT_OK;
+  } catch (...) {
+    return fail(CPT_EHIP, "unexpected exception");
+  }
 }
 
 }  // extern "C"
