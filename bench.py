@@ -42,6 +42,128 @@ FP64_PEAK_TFLOPS = 78.6
 # In the timed loop every 16th launch of each kernel family is bracketed by
 # HIP events (each bracket costs a gap of ~10 us between kernels).
 TIMING_PERIOD = 16
+# MI355X HBM3E peak and the algorithmic bytes of a round trip per vertex:
+# compress reads 8 B and writes 8/CR B, decompress reads 8/CR B and writes 8 B.
+HBM_PEAK_GBPS = 8000.0
+# worker processes the CPU baseline's all-core leg may start (the GPU machine's
+# CPU share for one GPU)
+CPU_WORKERS_MAX = 16
+
+
+def path_roofline(nvert, cr, tc_ms, td_ms):
+    """Whole-path HBM fraction: (16 + 16/CR) bytes per vertex over the
+    compress + decompress time, against the 8 TB/s peak."""
+    algo = (16.0 + 16.0 / cr) * nvert
+    achieved = algo / ((tc_ms + td_ms) * 1e-3) / 1e9
+    return {"path_bound": "hbm", "path_algorithmic_bytes": int(algo), "path_achieved_GBps": round(achieved, 3),
+            "path_peak_GBps": HBM_PEAK_GBPS, "path_frac": round(achieved / HBM_PEAK_GBPS, 5)}
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def _oracle_job(arr, eb, kw):
+    """One oracle compress + decompress of a host array: (t_c, t_d, bytes)."""
+    import oracle
+    c0 = time.perf_counter()
+    b = oracle.compress(arr, eb, **kw)
+    c1 = time.perf_counter()
+    oracle.decompress(b)
+    c2 = time.perf_counter()
+    return c1 - c0, c2 - c1, arr.size * 4
+
+
+# a worker of the all-core leg: one crop from an .npy file, times on stdout
+_WORKER = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import oracle
+arr = np.load(sys.argv[2])
+kw = json.loads(sys.argv[4])
+c0 = time.perf_counter()
+b = oracle.compress(arr, float(sys.argv[3]), **kw)
+c1 = time.perf_counter()
+oracle.decompress(b)
+c2 = time.perf_counter()
+print(json.dumps([c1 - c0, c2 - c1, int(arr.size * 4)]))
+"""
+
+
+def cpu_baseline(f, eb, kw, crop=1024, frames=4, timeout=600):
+    """The oracle (plain single-threaded C) on bounded samples of the same
+    field: (1) one crop of `crop` x `crop` x `frames`, median of 3 runs on one
+    thread; (2) all usable cores (at most CPU_WORKERS_MAX) at once, each a
+    worker process compressing and decompressing a different crop, aggregate
+    bytes over the wall time."""
+    import statistics
+    import subprocess
+    import tempfile
+    import numpy as np
+    _, T, H, W = f.shape
+    S, ch, cw = min(frames, T), min(crop, H), min(crop, W)
+    sample = f[:, :S, :ch, :cw].cpu().numpy().copy()
+    runs = [_oracle_job(sample, eb, kw) for _ in range(3)]
+    med = statistics.median(r[0] + r[1] for r in runs)
+    one = [r for r in runs if r[0] + r[1] == med][0]
+    model, ncpu, usable = host_cpu()
+    workers = max(1, min(usable, CPU_WORKERS_MAX))
+    out = {
+        "value": round(sample.size * 4 / med / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
+        "sample": "%dx%dx%d crop (frames 0-%d) of the same field, %d bytes; one thread, median of 3 runs: "
+                  "compress %.2f s + decompress %.2f s" % (cw, ch, S, S - 1, sample.size * 4, one[0], one[1]),
+        "host_cpu": model, "nproc": ncpu, "usable_cpus": usable,
+    }
+    with tempfile.TemporaryDirectory() as tmp:
+        paths = []
+        for i in range(workers):
+            ty, tx = divmod(i, max(1, W // cw))
+            y0, x0 = (ty * ch) % max(1, H - ch + 1), (tx * cw) % max(1, W - cw + 1)
+            t0 = (i * S) % max(1, T - S + 1)
+            pth = os.path.join(tmp, "crop%d.npy" % i)
+            np.save(pth, f[:, t0:t0 + S, y0:y0 + ch, x0:x0 + cw].cpu().numpy())
+            paths.append(pth)
+        env = dict(os.environ, OMP_NUM_THREADS="1", HIP_VISIBLE_DEVICES="")
+        w0 = time.perf_counter()
+        procs = [subprocess.Popen([sys.executable, "-c", _WORKER, ROOT, pth, repr(eb), json.dumps(kw)],
+                                  stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+                 for pth in paths]
+        res, failed = [], None
+        for pr in procs:
+            try:
+                o, e = pr.communicate(timeout=max(1.0, timeout - (time.perf_counter() - w0)))
+            except subprocess.TimeoutExpired:
+                pr.kill()
+                pr.communicate()
+                failed = "a worker exceeded %d s" % timeout
+                continue
+            if pr.returncode != 0:
+                failed = "a worker failed: " + e.strip()[-300:]
+                continue
+            res.append(json.loads(o.strip().splitlines()[-1]))
+        wall = time.perf_counter() - w0
+    if failed:
+        out["all_cores"] = {"error": failed}
+    else:
+        allbytes = sum(r[2] for r in res)
+        out["all_cores"] = {"value": round(allbytes / wall / 1e9, 6), "unit": "GB/s", "cores": workers,
+                            "sample": "%d worker processes at once, each one oracle compress + decompress of a "
+                                      "different %dx%dx%d crop (%d bytes in all), wall %.2f s" %
+                                      (workers, cw, ch, S, allbytes, wall)}
+    return out
 
 
 def log(msg):
@@ -145,6 +267,7 @@ def bench_batch(args, cpt, torch, synthfields):
     cpt.timing_enable(False)
     kname = "k_phase_b<true>" if sched == "fused" else "k_phase_b<false>"
     roofline = phase_roofline(fam, kname)
+    roofline.update(path_roofline(nvert, raw / clen, tc, td))
     kernels = {name: {"avg_launch_us": round(m / c * 1e3, 3), "sampled_launches": c}
                for name, (m, c, _) in fam.items() if c}
 
@@ -268,13 +391,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="wind", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="turbulence", choices=sorted(WORKLOADS))
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--predictor", type=int, default=2)
     ap.add_argument("--mode-bt", type=int, default=1)
     ap.add_argument("--schedule", default="auto", choices=["auto", "launch", "fused"],
                     help="auto: the faster of the per-phase launch schedules, timed during warm-up")
     ap.add_argument("--cpu-frames", type=int, default=4, help="frames of the CPU-baseline sample")
+    ap.add_argument("--cpu-crop", type=int, default=1024, help="side of the CPU-baseline crop")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run one device copy of the field (profiler counter calibration)")
@@ -366,6 +490,7 @@ def main():
 
     kname = "k_phase_b<true>" if sched == "fused" else "k_phase_b<false>"
     roofline = phase_roofline(fam, kname, args.workload)
+    roofline.update(path_roofline(T * H * W, raw / clen, tc, td))
     kernels = {name: {"avg_launch_us": round(m / c * 1e3, 3), "sampled_launches": c}
                for name, (m, c, _) in fam.items() if c}
 
@@ -385,21 +510,10 @@ def main():
     }
 
     if not args.no_cpu_baseline:
-        import numpy as np
-        import oracle
-        S = min(args.cpu_frames, T)
-        sample = f[:, :S].cpu().numpy()
-        log("CPU baseline: oracle on %d of %d frames (%dx%d)" % (S, T, H, W))
-        c0 = time.perf_counter()
-        b = oracle.compress(sample, eb, predictor=args.predictor, mode_bt=args.mode_bt, dt_dx=dt, dt_dy=dt)
-        c1 = time.perf_counter()
-        oracle.decompress(b)
-        c2 = time.perf_counter()
-        sraw = sample.size * 4
-        result["cpu_baseline"] = {
-            "value": round(sraw / (c2 - c0) / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d frames of the same field at full %dx%d resolution (%d bytes); "
-                      "compress %.2f s + decompress %.2f s, single thread" % (S, T, H, W, sraw, c1 - c0, c2 - c1)}
+        log("CPU baseline: oracle on %dx%dx%d crops" % (args.cpu_crop, args.cpu_crop, args.cpu_frames))
+        result["cpu_baseline"] = cpu_baseline(f, eb, dict(predictor=args.predictor, mode_bt=args.mode_bt,
+                                                          dt_dx=dt, dt_dy=dt),
+                                              crop=args.cpu_crop, frames=args.cpu_frames)
     print(json.dumps(result), flush=True)
 
 
