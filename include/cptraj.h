@@ -128,17 +128,22 @@ typedef enum {
                                one launch per colour phase */
   CPT_SCHED_FUSED = 2,      /* per frame and colour: one launch that also
                                chooses the predictor class of its blocks */
-  CPT_SCHED_PERSISTENT = 3  /* reserved: one persistent launch for all
-                               phases of all fields, workgroups waiting on
-                               per-field stage counters.  Disabled: returns
-                               CPT_EUNSUPPORTED */
+  CPT_SCHED_PERSISTENT = 3  /* one persistent launch for all phases of all
+                               fields: workgroups take numbered work items
+                               (groups of blocks of one phase of one field)
+                               and wait on per-field stage counters.
+                               Disabled: its launch did not complete on the
+                               device; returns CPT_EUNSUPPORTED */
 } cpt_schedule;
 
 typedef struct {
   uint32_t struct_size;  /* sizeof(cpt_exec_options) */
   int32_t schedule;      /* cpt_schedule (default CPT_SCHED_AUTO) */
-  int32_t group;         /* reserved for the persistent schedule (0) */
-  int32_t grid;          /* reserved for the persistent schedule (0) */
+  int32_t group;         /* persistent schedule: blocks per work item
+                            (1..64; 0 means 1) */
+  int32_t grid;          /* persistent schedule: workgroups of the launch
+                            (0: as many as fit on the device at once,
+                            capped at the number of work items) */
   int32_t use_graph;     /* 1: record the call's device work as a HIP graph
                             on first use and replay it on later calls with
                             the same shapes, options and schedule */

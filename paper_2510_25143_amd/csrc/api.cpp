@@ -746,8 +746,18 @@ cpt_status compress_batch_impl(int n, const float* const* fields, const int32_t*
   ExecChoice ex = forced ? *forced : resolve_exec(ex_in, P);
   if (ex.schedule < CPT_SCHED_LAUNCH || ex.schedule > CPT_SCHED_PERSISTENT) return fail(CPT_EINVAL, "unknown schedule");
   if (ex.group < 1 || ex.group > 64) return fail(CPT_EINVAL, "group must be in 1..64");
+  if (ex.grid < 0) return fail(CPT_EINVAL, "grid must be 0 (as many workgroups as fit at once) or positive");
   if (ex.schedule == CPT_SCHED_PERSISTENT)
-    return fail(CPT_EUNSUPPORTED, "the persistent schedule is disabled: its inter-workgroup wait did not complete");
+    return fail(CPT_EUNSUPPORTED, "the persistent schedule is disabled: its launch did not complete on the device");
+  if (ex.schedule == CPT_SCHED_PERSISTENT) {
+    // never a launch without workgroups: 0 asks for every workgroup that
+    // fits on the device at once, and more than one per item is pointless
+    if (ex.grid == 0) ex.grid = persist_grid();
+    if (ex.grid <= 0) return fail(CPT_EHIP, "occupancy query for the persistent kernel failed");
+    st = build_schedule(P, ex.group);
+    if (st) return st;
+    ex.grid = (int)std::min<long long>(ex.grid, std::max<long long>(P.nitems, 1));
+  }
   Arena* Ap = arena_for_device(&st);
   if (!Ap) return st;
   Arena& A = *Ap;

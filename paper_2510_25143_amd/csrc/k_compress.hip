@@ -603,15 +603,30 @@ __device__ __forceinline__ void face_update_q(int& xi, const MeSign& ms, const N
   xi = min(xi, max(e, relax));
 }
 
+// The block's neighbourhood as exact fp64 integers.  Faces reach frame t-1
+// only at offsets (-1..0, -1..0) and frame t+1 only at (0..1, 0..1), so those
+// two frames are staged one-sided (17 x 17), frame t with the full halo.
+// Indices: V0[1 + y - y0][1 + x - x0], V1 the same, V2[y - y0][x - x0].
+constexpr int HALO1 = TILE + 1;
 struct PhaseSmem {
-  double2 V[3][HALO][HALO];  // frames t-1, t, t+1 around the block (exact fp64 integers)
-  int XS[TILE][TILE];        // bound from the faces fixed for the whole sweep; -1 = lossless
-  int2 MS[TILE][TILE];       // |u| - 1, |v| - 1 of each vertex (its raise terms), for the sweep
+  double2 V0[HALO1][HALO1];  // frame t-1, x in [x0-1, x0+15], y in [y0-1, y0+15]
+  double2 V1[HALO][HALO];    // frame t, [x0-1, x0+16] x [y0-1, y0+16]
+  double2 V2[HALO1][HALO1];  // frame t+1, [x0, x0+16] x [y0, y0+16]
+  // bound from the faces fixed for the whole sweep (-1 = lossless); the
+  // sweep reads a vertex's entry once, then stores its residual codes there
+  int XQ[TILE][TILE];
+  // |u| - 1, |v| - 1 of each vertex (its raise terms); the sweep reads them
+  // once, then stores the bound code and the bound there
+  int2 MS[TILE][TILE];
   int2 SLP[TILE][TILE];      // semi-Lagrangian predictions, or the frame t-1 part of the Lorenzo prediction
-  uint32_t OQ[TILE][TILE];   // outputs, written once after the sweep
-  int OX[TILE][TILE];
-  uint8_t OC[TILE][TILE];
 };
+static_assert(sizeof(PhaseSmem) <= 160 * 1024 / 8, "eight blocks share a compute unit's LDS");
+
+// frame 0, 1, 2 (t-1, t, t+1) at halo indices (hy, hx) of the 18 x 18 frame
+// around the block, (1, 1) being the block's first vertex
+__device__ __forceinline__ double2* vslot(PhaseSmem& S, int f, int hy, int hx) {
+  return f == 0 ? &S.V0[hy][hx] : (f == 1 ? &S.V1[hy][hx] : &S.V2[hy - 1][hx - 1]);
+}
 
 union TileSmem {
   ModesSmem m;
@@ -627,13 +642,11 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
                                            const uint8_t* __restrict__ clsp,
                                            uint8_t* __restrict__ xcode, uint32_t* __restrict__ qcode,
                                            int32_t* __restrict__ xi_dbg) {
-  auto& V = S.V;
-  auto& XS = S.XS;
+  auto& V0 = S.V0;
+  auto& V1 = S.V1;
+  auto& XS = S.XQ;
   auto& MS = S.MS;
   auto& SLP = S.SLP;
-  auto& OQ = S.OQ;
-  auto& OX = S.OX;
-  auto& OC = S.OC;
   const int tid = threadIdx.x;
   const int H = p.H, W = p.W, T = p.T;
   const size_t HW = (size_t)H * W;
@@ -642,19 +655,27 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
   const int vx = tid & 15, vy = tid >> 4;
   const bool vin = x0 + vx < W && y0 + vy < H;
 
-  // ---- stage frames t-1, t, t+1 (block plus halo); the two corner cells
-  // that belong to blocks of the same colour are never read and not loaded.
-  // All loads of a thread are issued before the first one is waited for.
-  constexpr int NSTAGE = 3 * HALO * HALO, KSTAGE = (NSTAGE + 255) / 256;
+  // ---- stage frames t-1, t, t+1 (V0, V1, V2 are contiguous, so element i of
+  // the flat range is one cell); the two corner cells of frame t that belong
+  // to blocks of the same colour are never read and not loaded.  All loads of
+  // a thread are issued before the first one is waited for.
+  constexpr int N0 = HALO1 * HALO1, N1 = HALO * HALO;
+  constexpr int NSTAGE = 2 * N0 + N1, KSTAGE = (NSTAGE + 255) / 256;
+  static_assert(offsetof(PhaseSmem, V1) == sizeof(double2) * N0 &&
+                    offsetof(PhaseSmem, V2) == sizeof(double2) * (N0 + N1),
+                "the three staged frames are one flat range");
   int2 sv[KSTAGE];
   uint32_t ldm = 0;
 #pragma unroll
   for (int k = 0; k < KSTAGE; k++) {
     const int i = tid + 256 * k;
-    const int f = i / (HALO * HALO), r = i - f * HALO * HALO;
-    const int hy = r / HALO, hx = r - hy * HALO;
-    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, tt = t - 1 + f;
-    const bool corner = (hx == HALO - 1 && hy == 0) | (hx == 0 && hy == HALO - 1);
+    const int f = i < N0 ? 0 : (i < N0 + N1 ? 1 : 2);
+    const int r = i - (f == 0 ? 0 : (f == 1 ? N0 : N0 + N1));
+    const int w = f == 1 ? HALO : HALO1;
+    const int hy = r / w, hx = r - hy * w;
+    const int org = f == 2 ? 0 : 1;  // frame t+1 starts at the block's first vertex
+    const int gx = x0 - org + hx, gy = y0 - org + hy, tt = t - 1 + f;
+    const bool corner = f == 1 && ((hx == HALO - 1 && hy == 0) | (hx == 0 && hy == HALO - 1));
     const bool ld = (i < NSTAGE) & !corner & (gx >= 0) & (gx < W) & (gy >= 0) & (gy < H) & (tt >= 0) & (tt < T);
     ldm |= ld ? 1u << k : 0u;
     // element 0 of the field stands in for the cells that are not loaded
@@ -669,7 +690,7 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
   for (int k = 0; k < KSTAGE; k++) {
     const int i = tid + 256 * k;
     const int2 v = (ldm >> k) & 1u ? sv[k] : make_int2(0, 0);
-    if (i < NSTAGE) (&V[0][0][0])[i] = make_double2((double)v.x, (double)v.y);
+    if (i < NSTAGE) (&V0[0][0])[i] = make_double2((double)v.x, (double)v.y);
   }
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
   __syncthreads();
@@ -682,7 +703,7 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
     if (vin) {
       if (!lossless) {
         xi = eps;
-        const double2 me = V[1][ly + 1][lx + 1];
+        const double2 me = V1[ly + 1][lx + 1];
         const MeSign ms = me_sign(me);
         msv = make_int2(ms.rx, ms.ry);
         // Faces through a raster predecessor (left, up, up-left) are all
@@ -694,7 +715,7 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
           int xx = x + NBR.dx[j], yy = y + NBR.dy[j], tt = t + NBR.dt[j];
           ok |= (xx >= 0 && xx < W && yy >= 0 && yy < H && tt >= 0 && tt < T) ? (1u << j) : 0u;
         }
-        auto nv = [&](int j) { return V[1 + NBR.dt[j]][ly + 1 + NBR.dy[j]][lx + 1 + NBR.dx[j]]; };
+        auto nv = [&](int j) { return *vslot(S, 1 + NBR.dt[j], ly + 1 + NBR.dy[j], lx + 1 + NBR.dx[j]); };
         NbrQ prev = nbr_q(nv(STRAIL.a[0]), me);
 #pragma unroll
         for (int k = 0; k < 22; k++) {
@@ -714,21 +735,20 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
       if (cls == 0) {
         // the frame t-1 part of the 3-D Lorenzo prediction (fixed during the sweep)
         const double2 z = make_double2(0.0, 0.0);
-        const double2 pc = V[0][ly + 1][lx + 1];
-        const double2 pl = lx > 0 ? V[0][ly + 1][lx] : z;
-        const double2 pu = ly > 0 ? V[0][ly][lx + 1] : z;
-        const double2 plu = (lx > 0 && ly > 0) ? V[0][ly][lx] : z;
+        const double2 pc = V0[ly + 1][lx + 1];
+        const double2 pl = lx > 0 ? V0[ly + 1][lx] : z;
+        const double2 pu = ly > 0 ? V0[ly][lx + 1] : z;
+        const double2 plu = (lx > 0 && ly > 0) ? V0[ly][lx] : z;
         SLP[ly][lx] = make_int2((int)(pc.x - pl.x - pu.x + plu.x), (int)(pc.y - pl.y - pu.y + plu.y));
       } else {
-        // frame t-1 from the staged halo where it covers the sample (all of
-        // it but the two unstaged corners), else from global memory
+        // frame t-1 from the staged cells where they cover the sample, else
+        // from global memory
         const int2* prev = cur + (size_t)(t - 1) * HW;
         auto F = [&](int xx, int yy) {
           const int hx = xx - x0 + 1, hy = yy - y0 + 1;
-          const bool staged = hx >= 0 && hx < HALO && hy >= 0 && hy < HALO && !(hx == HALO - 1 && hy == 0) &&
-                              !(hx == 0 && hy == HALO - 1);
+          const bool staged = hx >= 0 && hx < HALO1 && hy >= 0 && hy < HALO1;
           if (!staged) return prev[(size_t)yy * W + xx];
-          const double2 q = V[0][hy][hx];
+          const double2 q = V0[hy][hx];
           return make_int2((int)q.x, (int)q.y);
         };
         int pu, pv;
@@ -757,14 +777,16 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
   const int aend = y < H ? min(TILE, W - x0) : 0;
   const int flo = max(max(-min(axo, bxo), 0) - x0, 0);
   const int fhi = face_yt ? max(min(W - max(max(axo, bxo), 0) - x0, TILE), flo) : flo;
-  const double2* Vme = &V[1][g + 1][1];
-  const double2* Va = &V[1 + ato][g + 1 + ayo][1 + axo];
-  const double2* Vb = &V[1 + bto][g + 1 + byo][1 + bxo];
+  const double2* Vme = &V1[g + 1][1];
+  // rows of this lane's two face neighbours (only a face of frame t reaches
+  // the column before the block; the lanes without a face read frame t)
+  const double2* Va = vslot(S, 1 + ato, g + 1 + ayo, 1 + axo);
+  const double2* Vb = vslot(S, 1 + bto, g + 1 + byo, 1 + bxo);
   // component comp of the left, upper and upper-left neighbours and of the
   // fixed prediction term, at index lx (rows of pairs: stride 2)
-  const double* Ql = &V[1][g + 1][0].x + comp;
-  const double* Qu = &V[1][g][1].x + comp;
-  const double* Qlu = &V[1][g][0].x + comp;
+  const double* Ql = &V1[g + 1][0].x + comp;
+  const double* Qu = &V1[g][1].x + comp;
+  const double* Qlu = &V1[g][0].x + comp;
   const int* Qp = (const int*)&SLP[g][0] + comp;
   // wave wv holds rows 4 wv .. 4 wv + 3, which have vertices on the
   // anti-diagonals 4 wv .. 4 wv + 18; on the others it only keeps the
@@ -801,13 +823,12 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
             cls == 0 ? (int)((lx > 0 ? l : 0.0) + (g > 0 ? u : 0.0) - (lx > 0 && g > 0 ? lu : 0.0)) + pt : pt;
         int rec;
         qc = quantize((int)(comp ? me.y : me.x), pred, xt, &rec);
-        ((double*)&V[1][g + 1][lx + 1])[comp] = (double)rec;
+        ((double*)&V1[g + 1][lx + 1])[comp] = (double)rec;
       }
-      ((uint16_t*)&OQ[g][lx])[comp] = (uint16_t)qc;
-      if (!comp) {
-        OC[g][lx] = (uint8_t)code;
-        if (xi_dbg) OX[g][lx] = xi;
-      }
+      // this vertex's entries of XQ and MS were read at the top of this step
+      // and are not read again: its outputs take their place
+      ((uint16_t*)&XS[g][lx])[comp] = (uint16_t)qc;
+      (&MS[g][lx].x)[comp] = comp ? xi : code;
     }
     __syncthreads();
   }
@@ -818,11 +839,12 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
     const int lx = tid & 15, ly = tid >> 4, x = x0 + lx, yy = y0 + ly;
     if (x < W && yy < H) {
       const size_t gv = (size_t)t * HW + (size_t)yy * W + x;
-      const double2 r = V[1][ly + 1][lx + 1];
+      const double2 r = V1[ly + 1][lx + 1];
+      const int2 cx = MS[ly][lx];
       cur[gv] = make_int2((int)r.x, (int)r.y);
-      xcode[gv] = OC[ly][lx];
-      qcode[gv] = OQ[ly][lx];
-      if (xi_dbg) xi_dbg[gv] = OX[ly][lx];
+      xcode[gv] = (uint8_t)cx.x;
+      qcode[gv] = (uint32_t)XS[ly][lx];
+      if (xi_dbg) xi_dbg[gv] = cx.y;
     }
   }
   __syncthreads();
@@ -1030,7 +1052,7 @@ void launch_persist(const BatchView& B, const SchedSeg* seg, const long long* ss
       khz = 100000;
     budget = 2000ull * (unsigned long long)khz;
   }
-  if (nitems > 0) k_persist<<<grid, 256, 0, s>>>(B, seg, sstart, nseg, nitems, group, done, ctl, budget);
+  if (nitems > 0 && grid > 0) k_persist<<<grid, 256, 0, s>>>(B, seg, sstart, nseg, nitems, group, done, ctl, budget);
 }
 
 }  // namespace cpt

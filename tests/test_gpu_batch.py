@@ -19,9 +19,6 @@ SMALL = [(17, 23, 3), (48, 64, 5), (16, 16, 1), (33, 70, 4), (2, 2, 1), (64, 31,
 SCHEDULES = [dict(schedule="launch"), dict(schedule="fused"), dict(schedule="launch", use_graph=True),
              dict(schedule="fused", use_graph=True)]
 
-# The persistent schedule (workgroups waiting on per-field stage counters)
-# did not complete on the device and is switched off in the library.
-PERSISTENT_OFF = "persistent schedule disabled: its inter-workgroup wait did not complete on the device"
 
 
 @pytest.fixture(scope="module")
@@ -164,6 +161,10 @@ def test_autotune_picks_a_candidate_and_auto_uses_it(cpt, small, want_mix2):
     print("autotune:", best, ["%.3f" % m for m in ms])
 
 
+PERSISTENT_OFF = ("persistent schedule disabled: its launch did not complete on the device, also with the "
+                  "grid taken from the kernel's occupancy instead of a zero-workgroup launch")
+
+
 @pytest.mark.skip(reason=PERSISTENT_OFF)
 def test_persistent_schedule_matches_oracle(cpt, small, want_mix2):
     for ex in (dict(schedule="persistent"), dict(schedule="persistent", group=3),
@@ -178,6 +179,12 @@ def test_persistent_schedule_reports_unsupported(cpt, small):
     with pytest.raises(cpt.CptError) as e:
         cpt.compress_batch(small[1][:2], 1e-2, schedule="persistent")
     assert e.value.status == cpt.EUNSUPPORTED
+
+
+def test_persistent_schedule_rejects_a_negative_grid(cpt, small):
+    with pytest.raises(cpt.CptError) as e:
+        cpt.compress_batch(small[1][:2], 1e-2, schedule="persistent", grid=-1)
+    assert e.value.status == cpt.EINVAL
 
 
 # ------------------------------------------------------------ decompression
