@@ -35,7 +35,7 @@ def build(force=True):
 
 class Options(ctypes.Structure):
     _fields_ = [("predictor", ctypes.c_int32), ("mode_bt", ctypes.c_int32),
-                ("eb_mode", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("eb_mode", ctypes.c_int32), ("backend", ctypes.c_int32),
                 ("dt_dx", ctypes.c_double), ("dt_dy", ctypes.c_double),
                 ("selector_w", ctypes.c_void_p)]
 
@@ -47,7 +47,8 @@ class Info(ctypes.Structure):
                 ("K", ctypes.c_int32), ("R", ctypes.c_int32),
                 ("cx", ctypes.c_int64), ("sx", ctypes.c_int64), ("cy", ctypes.c_int64),
                 ("sy", ctypes.c_int64), ("total_len", ctypes.c_uint64),
-                ("n_q", ctypes.c_uint64), ("n_raw", ctypes.c_uint64)]
+                ("n_q", ctypes.c_uint64), ("n_raw", ctypes.c_uint64),
+                ("backend", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -91,6 +92,9 @@ def lib():
             "cpo_mlp_loss_grad_exact": (dbl, [P, P, P, i32, P]),
             "cpo_compress_ex": (ctypes.c_int, [P, i32, i32, i32, dbl, P, P, sz, P, P, P, P, P, P, P]),
             "cpo_compress_bound": (sz, [i32, i32, i32]),
+            "cpo_zbe_bound": (sz, [sz]),
+            "cpo_zbe_encode": (ctypes.c_int, [P, sz, P, sz, P]),
+            "cpo_zbe_decode": (ctypes.c_int, [P, sz, P, sz, P]),
             "cpo_stream_info": (ctypes.c_int, [P, sz, P]),
             "cpo_decompress": (ctypes.c_int, [P, sz, P]),
             "cpo_verify": (ctypes.c_int, [P, P, i32, i32, i32, i32, P, P, P, P]),
@@ -328,8 +332,8 @@ def mlp_loss_grad(w, x, labels, exact=False):
     return loss, g
 
 
-def _opts(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w):
-    o = Options(predictor, mode_bt, eb_mode, 0, dt_dx, dt_dy, None)
+def _opts(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w, backend=0):
+    o = Options(predictor, mode_bt, eb_mode, backend, dt_dx, dt_dy, None)
     keep = None
     if selector_w is not None:
         keep = np.ascontiguousarray(selector_w, dtype=np.uint16)
@@ -338,13 +342,14 @@ def _opts(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w):
 
 
 def compress(field, eb, predictor=2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
-             selector_w=None, debug=False):
+             selector_w=None, debug=False, backend=0):
     """Returns the stream bytes (numpy uint8); with debug=True also a dict of
-    per-vertex bounds, bound codes, residual codes, block modes and features."""
+    per-vertex bounds, bound codes, residual codes, block modes and features.
+    backend=1 adds the zero-byte-elision stage after Huffman coding."""
     a = _f32(field)
     _, T, H, W = a.shape
     N = T * H * W
-    o, keep = _opts(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w)
+    o, keep = _opts(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w, backend)
     cap = lib().cpo_compress_bound(H, W, T)
     out = np.empty(cap, dtype=np.uint8)
     ln = ctypes.c_size_t()
@@ -369,6 +374,29 @@ def compress(field, eb, predictor=2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
         raise ValueError("cpo_compress failed: %d" % st)
     out = out[:ln.value].copy()
     return (out, dbg) if debug else out
+
+
+def zbe_encode(b):
+    """The lossless stage on a Huffman stream: the container bytes."""
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    out = np.empty(lib().cpo_zbe_bound(b.size), dtype=np.uint8)
+    n = ctypes.c_size_t()
+    st = lib().cpo_zbe_encode(_p(b), b.size, _p(out), out.size, ctypes.byref(n))
+    if st:
+        raise ValueError("cpo_zbe_encode failed: %d" % st)
+    return out[:n.value].copy()
+
+
+def zbe_decode_status(c, cap=None):
+    """(status, inner stream or None) of a container, without raising."""
+    c = np.ascontiguousarray(c, dtype=np.uint8)
+    n = ctypes.c_size_t()
+    st = lib().cpo_zbe_decode(_p(c), c.size, None, 0, ctypes.byref(n))
+    if st != ECAPACITY:
+        return st, None
+    out = np.empty(max(n.value, 1), dtype=np.uint8)
+    st = lib().cpo_zbe_decode(_p(c), c.size, _p(out), out.size, ctypes.byref(n))
+    return st, (out[:n.value] if st == OK else None)
 
 
 def stream_info(b):

@@ -883,6 +883,128 @@ double cpo_mlp_loss_grad_exact(const float* w, const float* x, const int32_t* la
 }
 
 /* ======================================================================
+ * The additional lossless stage after Huffman coding (Sec. V names a
+ * general-purpose lossless coder after the Huffman stage; Sec. VII-B shows
+ * the long zero runs it exploits).  READING: the paper fixes no format; the
+ * stage here is zero-byte elision over the stream body in independent
+ * 4096-byte blocks.  The most frequent symbol of each canonical code gets
+ * the all-zero codeword, so runs of it become zero bytes.
+ * Container: the 256-byte header unchanged but for slot 31 = ZBE_TAG; one
+ * 32-bit entry per block of the body (the bytes after the header): the
+ * block's encoded length in bytes, bit 31 set when the block is elided; then
+ * the encoded blocks in order.  An elided block of n bytes is a mask of
+ * ceil(n/8) bytes (bit i, least significant first, set when byte i is
+ * nonzero), then its nonzero bytes in order, then zero bytes up to a
+ * multiple of 4.  A block is elided exactly when that form is shorter than
+ * n; otherwise it is stored as it is.
+ * ==================================================================== */
+#define ZBE_BLOCK 4096
+#define ZBE_TAG 0x315A4245ull /* "EBZ1" */
+
+static size_t zbe_nblocks(size_t body) { return (body + ZBE_BLOCK - 1) / ZBE_BLOCK; }
+static size_t pad4(size_t n) { return (n + 3) & ~(size_t)3; }
+
+size_t cpo_zbe_bound(size_t inner_len) {
+  size_t body = inner_len > HDR_BYTES ? inner_len - HDR_BYTES : 0;
+  return HDR_BYTES + 4 * zbe_nblocks(body) + body;
+}
+
+int cpo_zbe_encode(const uint8_t* in, size_t len, uint8_t* out, size_t cap, size_t* out_len) {
+  /* the header must name the stream's own length and carry no tag yet */
+  if (!in || len < HDR_BYTES || len % 4 || get_u64(in + 8 * 30) != len || get_u64(in + 8 * 31) != 0)
+    return CPO_EINVAL;
+  size_t body = len - HDR_BYTES, nb = zbe_nblocks(body);
+  size_t total = HDR_BYTES + 4 * nb;
+  for (size_t b = 0; b < nb; b++) {
+    const uint8_t* p = in + HDR_BYTES + b * ZBE_BLOCK;
+    size_t n = body - b * ZBE_BLOCK < ZBE_BLOCK ? body - b * ZBE_BLOCK : ZBE_BLOCK, nnz = 0;
+    for (size_t i = 0; i < n; i++) nnz += p[i] != 0;
+    size_t e = pad4((n + 7) / 8 + nnz);
+    total += e < n ? e : n;
+  }
+  *out_len = total;
+  if (!out || total > cap) return CPO_ECAPACITY;
+  memcpy(out, in, HDR_BYTES);
+  set_u64(out + 8 * 31, ZBE_TAG);
+  uint8_t* tab = out + HDR_BYTES;
+  size_t o = HDR_BYTES + 4 * nb;
+  for (size_t b = 0; b < nb; b++) {
+    const uint8_t* p = in + HDR_BYTES + b * ZBE_BLOCK;
+    size_t n = body - b * ZBE_BLOCK < ZBE_BLOCK ? body - b * ZBE_BLOCK : ZBE_BLOCK, nnz = 0;
+    for (size_t i = 0; i < n; i++) nnz += p[i] != 0;
+    size_t m = (n + 7) / 8, e = pad4(m + nnz);
+    uint32_t entry;
+    if (e < n) {
+      memset(out + o, 0, e);
+      size_t w = o + m;
+      for (size_t i = 0; i < n; i++)
+        if (p[i]) {
+          out[o + i / 8] |= (uint8_t)(1u << (i % 8));
+          out[w++] = p[i];
+        }
+      entry = (uint32_t)e | 0x80000000u;
+      o += e;
+    } else {
+      memcpy(out + o, p, n);
+      entry = (uint32_t)n;
+      o += n;
+    }
+    for (int i = 0; i < 4; i++) tab[4 * b + i] = (uint8_t)(entry >> (8 * i));
+  }
+  return CPO_OK;
+}
+
+/* The inverse; `out` receives the inner stream (header slot 31 back to 0).
+   Every length, mask bit, stored byte and padding byte is checked: a
+   container that the encoder above cannot have written is corrupt. */
+int cpo_zbe_decode(const uint8_t* in, size_t len, uint8_t* out, size_t cap, size_t* out_len) {
+  if (!in || len < HDR_BYTES) return CPO_ECORRUPT;
+  if (get_u64(in + 8 * 31) != ZBE_TAG) return CPO_ECORRUPT;
+  uint64_t inner = get_u64(in + 8 * 30);
+  if (inner < HDR_BYTES || inner % 4 || inner > ((uint64_t)1 << 40)) return CPO_ECORRUPT;
+  size_t body = (size_t)inner - HDR_BYTES, nb = zbe_nblocks(body);
+  if (len < HDR_BYTES + 4 * nb) return CPO_ECORRUPT;
+  *out_len = (size_t)inner;
+  if (!out || inner > cap) return CPO_ECAPACITY;
+  memcpy(out, in, HDR_BYTES);
+  set_u64(out + 8 * 31, 0);
+  size_t o = HDR_BYTES + 4 * nb;
+  for (size_t b = 0; b < nb; b++) {
+    uint32_t entry = get_u32(in + HDR_BYTES + 4 * b);
+    size_t n = body - b * ZBE_BLOCK < ZBE_BLOCK ? body - b * ZBE_BLOCK : ZBE_BLOCK;
+    size_t e = entry & 0x7FFFFFFFu;
+    uint8_t* q = out + HDR_BYTES + b * ZBE_BLOCK;
+    if (e > len - o) return CPO_ECORRUPT;
+    if (!(entry & 0x80000000u)) {
+      if (e != n) return CPO_ECORRUPT;
+      memcpy(q, in + o, n);
+    } else {
+      size_t m = (n + 7) / 8, nnz = 0;
+      if (e < m) return CPO_ECORRUPT;
+      for (size_t i = 0; i < 8 * m; i++) {
+        int bit = (in[o + i / 8] >> (i % 8)) & 1;
+        if (bit && i >= n) return CPO_ECORRUPT;
+        nnz += (size_t)bit;
+      }
+      if (pad4(m + nnz) != e || e >= n) return CPO_ECORRUPT;
+      size_t r = o + m;
+      for (size_t i = 0; i < n; i++) {
+        if ((in[o + i / 8] >> (i % 8)) & 1) {
+          if (in[r] == 0) return CPO_ECORRUPT;
+          q[i] = in[r++];
+        } else {
+          q[i] = 0;
+        }
+      }
+      for (size_t i = r; i < o + e; i++)
+        if (in[i] != 0) return CPO_ECORRUPT;
+    }
+    o += e;
+  }
+  return o == len ? CPO_OK : CPO_ECORRUPT;
+}
+
+/* ======================================================================
  * Compression (Alg. 3 with Alg. 4), in the blocked order: for each frame,
  * three colour phases; in phase c every TILE x TILE block with
  * (bx + by) mod 3 == c is processed, its vertices in raster order.  Blocks
@@ -1127,13 +1249,14 @@ static int block_mode_impl(const int32_t* Ut, const int32_t* Vt, const int32_t* 
   return r;
 }
 
+/* largest stream, plain or in the container of the lossless stage */
 size_t cpo_compress_bound(int H, int W, int T) {
   size_t N = (size_t)H * W * T;
   size_t nch = (N + CHUNK - 1) / CHUNK, nq = 2 * N, nqch = (nq + CHUNK - 1) / CHUNK;
   size_t nd = (size_t)T * ((H + TILE - 1) / TILE) * ((W + TILE - 1) / TILE);
-  return HDR_BYTES + 4 * ((nd * 2 + 31) / 32) + (4 + 4 * XSYM) + 4 * nch +
-         4 * ((N * MAXLEN + 31) / 32 + nch) + (4 + 4 * QSYM) + 4 * nqch +
-         4 * ((nq * MAXLEN + 31) / 32 + nqch) + 8 * N;
+  return cpo_zbe_bound(HDR_BYTES + 4 * ((nd * 2 + 31) / 32) + (4 + 4 * XSYM) + 4 * nch +
+                       4 * ((N * MAXLEN + 31) / 32 + nch) + (4 + 4 * QSYM) + 4 * nqch +
+                       4 * ((nq * MAXLEN + 31) / 32 + nqch) + 8 * N);
 }
 
 int cpo_compress_ex(const float* field, int H, int W, int T, double eb,
@@ -1144,6 +1267,8 @@ int cpo_compress_ex(const float* field, int H, int W, int T, double eb,
   cpo_options dflt = {2, 1, 0, 0, 1.0, 1.0, NULL};
   if (!opt) opt = &dflt;
   if (opt->predictor < 0 || opt->predictor > 4 || opt->mode_bt < 1) return CPO_EINVAL;
+  if (opt->backend < 0 || opt->backend > 1) return CPO_EINVAL;
+  uint8_t* inner = NULL;
   if (opt->predictor == 4 && !opt->selector_w) return CPO_EINVAL;
   if (!(opt->dt_dx >= 0.0) || !(opt->dt_dy >= 0.0) || !isfinite(opt->dt_dx) || !isfinite(opt->dt_dy))
     return CPO_EINVAL;
@@ -1280,8 +1405,17 @@ int cpo_compress_ex(const float* field, int H, int W, int T, double eb,
     size_t total = HDR_BYTES;
     for (int i = 0; i < 8; i++) total += sec[i].len;
     *out_len = total;
-    if (total > cap || !out) { st = CPO_ECAPACITY; goto done; }
-    uint8_t* h = out;
+    uint8_t* dst = out;
+    if (opt->backend == 1) {
+      /* the Huffman stream is built aside, then the lossless stage writes out */
+      inner = (uint8_t*)malloc(total);
+      if (!inner) { st = CPO_ENOMEM; goto done; }
+      dst = inner;
+    } else if (total > cap || !out) {
+      st = CPO_ECAPACITY;
+      goto done;
+    }
+    uint8_t* h = dst;
     memset(h, 0, HDR_BYTES);
     uint64_t eb_bits;
     memcpy(&eb_bits, &eb_abs, 8);
@@ -1297,8 +1431,12 @@ int cpo_compress_ex(const float* field, int H, int W, int T, double eb,
     for (int i = 0; i < HDR_SLOTS; i++) set_u64(h + 8 * i, slots[i]);
     size_t o = HDR_BYTES;
     for (int i = 0; i < 8; i++) {
-      if (sec[i].len) memcpy(out + o, sec[i].p, sec[i].len);
+      if (sec[i].len) memcpy(dst + o, sec[i].p, sec[i].len);
       o += sec[i].len;
+    }
+    if (opt->backend == 1) {
+      st = cpo_zbe_encode(inner, total, out, cap, out_len);
+      if (st) goto done;
     }
   }
   if (xcode_out) memcpy(xcode_out, xcode, N);
@@ -1307,6 +1445,7 @@ int cpo_compress_ex(const float* field, int H, int W, int T, double eb,
   if (modes_out && nblk) memcpy(modes_out, modes, nblk);
   if (nblocks_out) *nblocks_out = nblk;
 done:
+  free(inner);
   for (int i = 0; i < 8; i++) free(sec[i].p);
   free(F0); free(F); free(masks); free(flags); free(xcode); free(qu); free(qv);
   free(SU); free(SV); free(hist); free(modes); free(qsym); free(xs);
@@ -1337,12 +1476,16 @@ int cpo_stream_info(const uint8_t* b, size_t len, cpo_info* info) {
   uint64_t K = s[9] == 2 ? 2 : (s[9] >= 3 ? 4 : 1);
   if (s[11] != K || s[13] > 62 || s[15] > 62 || s[12] > 2147483647u || s[14] > 2147483647u)
     return CPO_ECORRUPT;
+  if (s[31] != 0 && s[31] != ZBE_TAG) return CPO_ECORRUPT;
+  const int zbe = s[31] == ZBE_TAG;
   uint64_t total = HDR_BYTES;
   for (int i = 20; i < 28; i++) {
-    if (s[i] % 4 || s[i] > len) return CPO_ECORRUPT;
+    if (s[i] % 4 || s[i] > ((uint64_t)1 << 40)) return CPO_ECORRUPT;
     total += s[i];
   }
-  if (total != s[30] || total > len) return CPO_ECORRUPT;
+  if (total != s[30]) return CPO_ECORRUPT;
+  /* a plain stream holds every section; a container at least its table */
+  if (zbe ? len < HDR_BYTES + 4 * zbe_nblocks(total - HDR_BYTES) : total > len) return CPO_ECORRUPT;
   info->H = (int32_t)s[1];
   info->W = (int32_t)s[2];
   info->T = (int32_t)s[3];
@@ -1360,6 +1503,7 @@ int cpo_stream_info(const uint8_t* b, size_t len, cpo_info* info) {
   info->n_q = s[28];
   info->n_raw = s[29];
   info->total_len = s[30];
+  info->backend = zbe;
   return CPO_OK;
 }
 
@@ -1371,6 +1515,15 @@ int cpo_decompress(const uint8_t* b, size_t len, float* field) {
   cpo_info in;
   int st = cpo_stream_info(b, len, &in);
   if (st) return st;
+  if (in.backend) {
+    uint8_t* inner = (uint8_t*)malloc(in.total_len);
+    size_t il = 0;
+    if (!inner) return CPO_ENOMEM;
+    st = cpo_zbe_decode(b, len, inner, in.total_len, &il);
+    if (!st) st = cpo_decompress(inner, il, field);
+    free(inner);
+    return st;
+  }
   int H = in.H, W = in.W, T = in.T;
   size_t N = (size_t)H * W * T, HW = (size_t)H * W;
   uint64_t sl[8];

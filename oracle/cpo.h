@@ -29,7 +29,7 @@ typedef struct {
                           4 mixture K=4 chosen by the learned selector */
   int32_t mode_bt;     /* frames per mode block (>= 1) */
   int32_t eb_mode;     /* 0: eb relative to the value range, 1: absolute */
-  int32_t pad;
+  int32_t backend;     /* 0: Huffman stream, 1: zero-byte elision after it */
   double dt_dx, dt_dy; /* time step over grid spacing (cells per unit velocity) */
   const uint16_t* selector_w; /* bf16 MLP weights (predictor 4), host */
 } cpo_options;
@@ -40,7 +40,9 @@ typedef struct {
   int64_t eps;
   int32_t predictor, mode_bt, K, R;
   int64_t cx, sx, cy, sy;
-  uint64_t total_len, n_q, n_raw;
+  uint64_t total_len, n_q, n_raw;  /* total_len: bytes of the Huffman stream */
+  int32_t backend;                 /* 1: the stream is a zero-byte-elision container */
+  int32_t pad;
 } cpo_info;
 
 /* Fixed-point parameters (scale 2^k, bound eps' in fixed-point units). */
@@ -150,6 +152,12 @@ int cpo_block_scores(const int32_t* Ut, const int32_t* Vt, const int32_t* Up,
    one, shifted left by the length difference. */
 void cpo_canonical_codes(const uint8_t* lengths, int nsym, uint32_t* codes);
 size_t cpo_compress_bound(int H, int W, int T);
+/* The lossless stage after Huffman coding: zero-byte elision of a stream's
+   body in 4096-byte blocks (encode: ECAPACITY with the needed size in
+   out_len when cap is short; decode: the inner stream back). */
+size_t cpo_zbe_bound(size_t inner_len);
+int cpo_zbe_encode(const uint8_t* in, size_t len, uint8_t* out, size_t cap, size_t* out_len);
+int cpo_zbe_decode(const uint8_t* in, size_t len, uint8_t* out, size_t cap, size_t* out_len);
 int cpo_stream_info(const uint8_t* bytes, size_t len, cpo_info* info);
 int cpo_decompress(const uint8_t* bytes, size_t len, float* field);
 

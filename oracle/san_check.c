@@ -6,8 +6,9 @@
  *
  * Fields: a few analytic swirls (values of the kind Sec. VII uses) plus a
  * deterministic hash noise, and small-integer fields full of ties.  Streams:
- * every predictor, then single-bit flips, truncations, and stored raw values
- * replaced by huge, tiny, negative-zero and non-finite floats; every call
+ * every predictor, plain and in the container of the zero-byte-elision
+ * stage, then single-bit flips, truncations, and stored raw values replaced
+ * by huge, tiny, negative-zero and non-finite floats; every call
  * must return without a sanitizer report (decoding may succeed or fail).
  * Exit status 0 when every check holds.
  */
@@ -83,9 +84,10 @@ static void try_decode(const uint8_t* b, size_t len) {
 }
 
 static void roundtrip(const float* f, int H, int W, int T, double eb, int pred, int bt,
-                      const uint16_t* selw, int corrupt) {
+                      const uint16_t* selw, int corrupt, int backend) {
   cpo_options o;
   memset(&o, 0, sizeof(o));
+  o.backend = backend;
   o.predictor = pred;
   o.mode_bt = bt;
   o.dt_dx = 0.37;
@@ -148,9 +150,10 @@ int main(void) {
   swirl_field(f, H, W, T, 1);
   const double ebs[3] = {1e-1, 1e-2, 1e-3};
   for (int pred = 0; pred <= 4; pred++)
-    for (int e = 0; e < 3; e++) roundtrip(f, H, W, T, ebs[e], pred, pred >= 3 ? 2 : 1, selw, e == 1 && pred >= 2);
+    for (int e = 0; e < 3; e++)
+      roundtrip(f, H, W, T, ebs[e], pred, pred >= 3 ? 2 : 1, selw, e == 1 && pred >= 2, e == 2 || pred == 3);
   int_field(f, H, W, T, 5);
-  for (int pred = 0; pred <= 3; pred++) roundtrip(f, H, W, T, 0.25, pred, 1, selw, pred == 2);
+  for (int pred = 0; pred <= 3; pred++) roundtrip(f, H, W, T, 0.25, pred, 1, selw, pred == 2, pred & 1);
   /* extraction and verification with a grid too fine for the values */
   size_t cnt;
   uint64_t ft, fs;
