@@ -395,6 +395,8 @@ def main():
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--predictor", type=int, default=2)
     ap.add_argument("--mode-bt", type=int, default=1)
+    ap.add_argument("--backend", type=int, default=1, choices=[0, 1],
+                    help="lossless stage after Huffman coding: 1 zero-byte elision (default), 0 none")
     ap.add_argument("--schedule", default="auto", choices=["auto", "launch", "fused"],
                     help="auto: the faster of the per-phase launch schedules, timed during warm-up")
     ap.add_argument("--cpu-frames", type=int, default=4, help="frames of the CPU-baseline sample")
@@ -431,7 +433,7 @@ def main():
     out = torch.empty(cpt.compress_bound(H, W, T), dtype=torch.uint8, device="cuda")
     dec = torch.empty_like(f)
 
-    opts = dict(predictor=args.predictor, mode_bt=args.mode_bt, dt_dx=dt, dt_dy=dt)
+    opts = dict(predictor=args.predictor, mode_bt=args.mode_bt, dt_dx=dt, dt_dy=dt, backend=args.backend)
     sched = args.schedule
     tune_ms = None
     if sched == "auto":
@@ -488,6 +490,24 @@ def main():
     cpt.timing_enable(False)
     value = args.steps * raw / elapsed / 1e9
 
+    # the other setting of the lossless stage, for comparison (same schedule)
+    other = dict(opts, backend=1 - args.backend)
+    (so,), _ = cpt.compress_batch([f], eb, schedule=sched, outs=[out], **other)
+    cpt.decompress(so, out=dec)
+    torch.cuda.synchronize()
+    olen = so.numel()
+    o0 = time.perf_counter()
+    for i in range(args.steps):
+        (so,), _ = cpt.compress_batch([f], eb, schedule=sched, outs=[out], **other)
+        cpt.decompress(so, out=dec)
+    torch.cuda.synchronize()
+    o_el = time.perf_counter() - o0
+    stage = {"CR_with_stage": round(raw / (clen if args.backend else olen), 4),
+             "CR_huffman_only": round(raw / (olen if args.backend else clen), 4),
+             "GBps_other_setting": round(args.steps * raw / o_el / 1e9, 4)}
+    log("lossless stage: CR %.3f with, %.3f Huffman only; %.2f GB/s with the other setting" %
+        (stage["CR_with_stage"], stage["CR_huffman_only"], stage["GBps_other_setting"]))
+
     kname = "k_phase_b<true>" if sched == "fused" else "k_phase_b<false>"
     roofline = phase_roofline(fam, kname, args.workload)
     roofline.update(path_roofline(T * H * W, raw / clen, tc, td))
@@ -505,14 +525,15 @@ def main():
                    "max_err": v["max_err"], "psnr": round(v["psnr"], 3),
                    "compress_ms": round(tc, 4), "decompress_ms": round(td, 4),
                    "compress_GBps": round(raw / tc / 1e6, 3), "decompress_GBps": round(raw / td / 1e6, 3),
-                   "kernels": kernels},
+                   "lossless_stage": "zero-byte elision after Huffman" if args.backend else "none (Huffman only)",
+                   "stage_comparison": stage, "kernels": kernels},
         "roofline": roofline,
     }
 
     if not args.no_cpu_baseline:
         log("CPU baseline: oracle on %dx%dx%d crops" % (args.cpu_crop, args.cpu_crop, args.cpu_frames))
         result["cpu_baseline"] = cpu_baseline(f, eb, dict(predictor=args.predictor, mode_bt=args.mode_bt,
-                                                          dt_dx=dt, dt_dy=dt),
+                                                          dt_dx=dt, dt_dy=dt, backend=args.backend),
                                               crop=args.cpu_crop, frames=args.cpu_frames)
     print(json.dumps(result), flush=True)
 

@@ -66,6 +66,11 @@ typedef struct {
   const uint16_t* selector_w; /* device, bf16 selector weights (5124 values,
                                  16-byte aligned, else CPT_EINVAL) when
                                  predictor == CPT_PRED_LEARNED */
+  int32_t backend;        /* lossless stage after Huffman coding (Sec. V):
+                             0 none (default), 1 zero-byte elision of the
+                             stream body in 4096-byte blocks.  A caller
+                             passing the size of the struct without this
+                             field gets 0. */
 } cpt_options;
 
 /* Parameters stored in a stream's header. */
@@ -75,7 +80,9 @@ typedef struct {
   double eb_abs;      /* absolute bound in field units */
   int64_t eps;        /* bound eps' in fixed-point units */
   int32_t predictor, mode_bt, K, R;
-  uint64_t total_len, n_q, n_raw;
+  uint64_t total_len, n_q, n_raw;  /* total_len: bytes of the Huffman stream */
+  int32_t backend;    /* 1: the stream is a container of the lossless stage */
+  int32_t pad;
 } cpt_info;
 
 /* Outcome of comparing two fields on the same fixed-point grid. */
@@ -86,7 +93,8 @@ typedef struct {
   double psnr;        /* 20 log10(range(a)) - 10 log10(MSE) */
 } cpt_verify_result;
 
-/* Largest stream cpt_compress can produce for these dimensions. */
+/* Largest stream cpt_compress can produce for these dimensions, with or
+ * without the lossless stage. */
 cpt_status cpt_compress_bound(int H, int W, int T, size_t* max_bytes);
 
 /*

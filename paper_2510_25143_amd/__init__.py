@@ -29,7 +29,7 @@ class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("eb_mode", ctypes.c_int32),
                 ("predictor", ctypes.c_int32), ("mode_bt", ctypes.c_int32),
                 ("dt_dx", ctypes.c_double), ("dt_dy", ctypes.c_double),
-                ("selector_w", ctypes.c_void_p)]
+                ("selector_w", ctypes.c_void_p), ("backend", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -37,7 +37,8 @@ class Info(ctypes.Structure):
                 ("k", ctypes.c_int32), ("eb_abs", ctypes.c_double), ("eps", ctypes.c_int64),
                 ("predictor", ctypes.c_int32), ("mode_bt", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("R", ctypes.c_int32), ("total_len", ctypes.c_uint64),
-                ("n_q", ctypes.c_uint64), ("n_raw", ctypes.c_uint64)]
+                ("n_q", ctypes.c_uint64), ("n_raw", ctypes.c_uint64), ("backend", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class TrainOptions(ctypes.Structure):
@@ -126,8 +127,8 @@ def _field(f):
     return f.contiguous()
 
 
-def _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w):
-    o = Options(ctypes.sizeof(Options), eb_mode, predictor, mode_bt, dt_dx, dt_dy, None)
+def _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w, backend=0):
+    o = Options(ctypes.sizeof(Options), eb_mode, predictor, mode_bt, dt_dx, dt_dy, None, backend)
     if selector_w is not None:
         if not (selector_w.is_cuda and selector_w.dtype in (torch.int16, torch.bfloat16, torch.uint16)):
             raise TypeError("selector_w must be a CUDA bf16/int16 tensor of %d values" % SELECTOR_PARAMS)
@@ -146,14 +147,15 @@ def compress_bound(H, W, T):
 
 
 def compress(field, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
-             selector_w=None, out=None):
+             selector_w=None, out=None, backend=0):
     """Compress ``field`` (2,T,H,W float32 CUDA) under bound ``eb``; returns the
-    stream as a uint8 CUDA tensor (a view of ``out`` when given)."""
+    stream as a uint8 CUDA tensor (a view of ``out`` when given).  backend=1
+    adds the zero-byte-elision stage after Huffman coding."""
     f = _field(field)
     _, T, H, W = f.shape
     if out is None:
         out = torch.empty(compress_bound(H, W, T), dtype=torch.uint8, device=f.device)
-    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w)
+    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w, backend)
     n = ctypes.c_size_t()
     _check(lib().cpt_compress(_ptr(f), H, W, T, eb, ctypes.byref(o), _ptr(out), out.numel(),
                               ctypes.byref(n), _stream()))
@@ -161,7 +163,7 @@ def compress(field, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt
 
 
 def compress_debug(field, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
-                   selector_w=None):
+                   selector_w=None, backend=0):
     """Compress and also return per-vertex bounds, bound codes, residual codes,
     per-block predictor classes and selector features."""
     f = _field(field)
@@ -175,7 +177,7 @@ def compress_debug(field, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1
     qcode = torch.empty(N, dtype=torch.int32, device=dev)
     modes = torch.zeros(max(nbmax, 1), dtype=torch.uint8, device=dev)
     feats = torch.zeros((max(nbmax, 1), 10), dtype=torch.float32, device=dev)
-    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w)
+    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w, backend)
     n, nb = ctypes.c_size_t(), ctypes.c_size_t()
     _check(lib().cpt_compress_debug(_ptr(f), H, W, T, eb, ctypes.byref(o), _ptr(out), out.numel(),
                                     ctypes.byref(n), _ptr(xi), _ptr(xcode), _ptr(qcode), _ptr(modes),
@@ -206,13 +208,13 @@ def _batch_args(fields, outs):
 
 def compress_batch(fields, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
                    selector_w=None, schedule="auto", group=0, grid=0, use_graph=False, outs=None,
-                   raise_on_error=True):
+                   raise_on_error=True, backend=0):
     """Compress a list of fields (each (2,T,H,W) float32 CUDA) in one device
     pipeline.  Returns (streams, status): streams[i] is a view of outs[i]
     trimmed to its length (None when field i failed), status[i] its
     cpt_status."""
     fs, n, hwt, outs, fp, op, caps = _batch_args(fields, outs)
-    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w)
+    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w, backend)
     ex = ExecOptions(ctypes.sizeof(ExecOptions), SCHEDULES[schedule], group, grid, int(bool(use_graph)))
     lens = (ctypes.c_size_t * n)()
     st = (ctypes.c_int32 * n)()
@@ -224,12 +226,12 @@ def compress_batch(fields, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=
 
 
 def autotune_batch(fields, eb, reps=2, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
-                   selector_w=None, outs=None):
+                   selector_w=None, outs=None, backend=0):
     """Time every candidate execution choice on this batch and remember the
     fastest for schedule="auto".  Returns (best, ms): best = (schedule,
     use_graph), ms the mean time per run of each of TUNE_CANDIDATES."""
     fs, n, hwt, outs, fp, op, caps = _batch_args(fields, outs)
-    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w)
+    o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w, backend)
     best = ExecOptions(ctypes.sizeof(ExecOptions), 0, 0, 0, 0)
     ms = (ctypes.c_double * len(TUNE_CANDIDATES))()
     _check(lib().cpt_autotune_batch(n, fp, hwt, eb, ctypes.byref(o), op, caps, reps, ctypes.byref(best), ms,

@@ -158,6 +158,16 @@ cpt_status reserve(Arena& A) {
   return CPT_OK;
 }
 
+// Largest Huffman stream of a field, and the most blocks of its body
+size_t huffman_bound(int H, int W, int T) {
+  const size_t N = (size_t)H * W * T;
+  const size_t nchx = (N + CHUNK - 1) / CHUNK, nq = 2 * N, nchq = (nq + CHUNK - 1) / CHUNK;
+  const size_t nd = (size_t)T * ((H + TILE - 1) / TILE) * ((W + TILE - 1) / TILE);
+  return HDR_BYTES + 4 * ((nd * 2 + 31) / 32) + (4 + 4 * XSYM) + 4 * nchx + 4 * ((N * MAXLEN + 31) / 32 + nchx) +
+         (4 + 4 * QSYM) + 4 * nchq + 4 * ((nq * MAXLEN + 31) / 32 + nchq) + 8 * N;
+}
+size_t zbe_blocks(size_t inner_len) { return (inner_len - HDR_BYTES + ZBE_BLOCK - 1) / ZBE_BLOCK; }
+
 bool group_decided(int g, int bt, int T) {
   int td = g * bt > 1 ? g * bt : 1;
   int end = (g + 1) * bt < T ? (g + 1) * bt : T;
@@ -303,6 +313,8 @@ struct Plan {
   std::vector<FieldDesc> D;
   std::vector<int> ord;
   std::vector<long long> rpre, gpre, hpre, cxpre, cqpre, fpre;  // natural order
+  std::vector<long long> zpre, ioff;  // lossless stage: most blocks per field, Huffman stream scratch offsets
+  long long ZB = 0, IB = 0;
   std::vector<long long> mpre, ppre;                      // launch order
   std::vector<int> m_at, mstate_at, gidx_at;              // per frame
   std::vector<uint64_t> hw_at, cv_at;                     // vertices per frame / per phase
@@ -316,11 +328,21 @@ struct Plan {
 };
 
 cpt_status check_options(const cpt_options* opt_in, double eb, cpt_options* opt) {
-  *opt = cpt_options{sizeof(cpt_options), 0, CPT_PRED_MIX2, 1, 1.0, 1.0, nullptr};
+  *opt = cpt_options{sizeof(cpt_options), 0, CPT_PRED_MIX2, 1, 1.0, 1.0, nullptr, 0};
   if (opt_in) {
-    if (opt_in->struct_size != sizeof(cpt_options)) return fail(CPT_EINVAL, "cpt_options.struct_size mismatch");
-    *opt = *opt_in;
+    // the struct as declared, or as it was before the backend field
+    constexpr size_t before_backend = offsetof(cpt_options, backend);
+    if (opt_in->struct_size == sizeof(cpt_options)) {
+      *opt = *opt_in;
+    } else if (opt_in->struct_size >= before_backend && opt_in->struct_size < sizeof(cpt_options)) {
+      std::memcpy(opt, opt_in, before_backend);
+      opt->backend = 0;
+    } else {
+      return fail(CPT_EINVAL, "cpt_options.struct_size mismatch");
+    }
+    opt->struct_size = sizeof(cpt_options);
   }
+  if (opt->backend < 0 || opt->backend > 1) return fail(CPT_EINVAL, "backend must be 0 or 1");
   if (opt->predictor < 0 || opt->predictor > 4) return fail(CPT_EINVAL, "unknown predictor");
   if (opt->mode_bt < 1 || opt->mode_bt > 1024) return fail(CPT_EINVAL, "mode_bt must be in 1..1024");
   if (opt->predictor == CPT_PRED_LEARNED && !opt->selector_w)
@@ -347,8 +369,10 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
   P.K = opt.predictor == 2 ? 2 : (opt.predictor >= 3 ? 4 : 1);
   const int K = P.K, bt = opt.mode_bt, mb = mode_bits(K);
   P.D.assign(n, FieldDesc{});
-  for (auto* v : {&P.rpre, &P.gpre, &P.hpre, &P.cxpre, &P.cqpre, &P.fpre, &P.mpre, &P.ppre}) v->assign(n + 1, 0);
-  P.key = std::to_string(n) + ":" + std::to_string(opt.predictor) + ":" + std::to_string(bt);
+  for (auto* v : {&P.rpre, &P.gpre, &P.hpre, &P.cxpre, &P.cqpre, &P.fpre, &P.mpre, &P.ppre, &P.zpre, &P.ioff})
+    v->assign(n + 1, 0);
+  P.key = std::to_string(n) + ":" + std::to_string(opt.predictor) + ":" + std::to_string(bt) + ":" +
+          std::to_string(opt.backend);
   for (int i = 0; i < n; i++) {
     const int H = HWT[3 * i], W = HWT[3 * i + 1], T = HWT[3 * i + 2];
     cpt_status st = check_dims(H, W, T);
@@ -390,11 +414,23 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
     P.cxpre[i + 1] = P.cxpre[i] + d.nchx;
     P.cqpre[i + 1] = P.cqpre[i] + ncq;
     P.fpre[i + 1] = P.fpre[i] + (long long)((W + FIELDPASS_TW - 1) / FIELDPASS_TW) * ((H + FIELDPASS_TH - 1) / FIELDPASS_TH);
+    if (opt.backend == 1) {
+      const size_t hb = huffman_bound(H, W, T);
+      d.zbase = P.zpre[i];
+      P.zpre[i + 1] = P.zpre[i] + (long long)zbe_blocks(hb);
+      P.ioff[i + 1] = P.ioff[i] + (long long)((hb + 255) & ~(size_t)255);
+    } else {
+      P.zpre[i + 1] = P.zpre[i];
+      P.ioff[i + 1] = P.ioff[i];
+    }
     P.maxT = std::max(P.maxT, T);
     P.key += ":" + std::to_string(H) + "x" + std::to_string(W) + "x" + std::to_string(T);
   }
-  for (auto v : {P.rpre.back(), P.gpre.back(), P.hpre.back(), P.cxpre.back(), P.cqpre.back(), P.fpre.back()})
+  for (auto v : {P.rpre.back(), P.gpre.back(), P.hpre.back(), P.cxpre.back(), P.cqpre.back(), P.fpre.back(),
+                 P.zpre.back()})
     if (v >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
+  P.ZB = P.zpre.back();
+  P.IB = P.ioff.back();
   P.ord.resize(n);
   for (int i = 0; i < n; i++) P.ord[i] = i;
   std::stable_sort(P.ord.begin(), P.ord.end(), [&](int a, int b) { return P.D[a].T > P.D[b].T; });
@@ -475,9 +511,12 @@ cpt_status build_schedule(Plan& P, int group) {
 struct BatchBufs {
   FieldDesc* D;
   int* ord;
-  long long *rpre, *gpre, *hpre, *cxpre, *cqpre, *fpre, *mpre, *ppre, *sstart;
+  long long *rpre, *gpre, *hpre, *cxpre, *cqpre, *fpre, *mpre, *ppre, *sstart, *zpre;
   SchedSeg* seg;
   size_t tables_bytes;
+  uint8_t* inner;           // Huffman streams ahead of the lossless stage
+  uint32_t *ztab, *zlen;    // per block: table entry, encoded length
+  long long* zoff;          // per block: offset in its container's payload
   unsigned *done, *ctl;
   int4* range;
   int2* cur;
@@ -506,7 +545,7 @@ cpt_status carve_batch(Arena& A, const Plan& P, BatchBufs& b) {
       {(void**)&b.cqpre, vec_bytes(P.cqpre)}, {(void**)&b.fpre, vec_bytes(P.fpre)},
       {(void**)&b.mpre, vec_bytes(P.mpre)},
       {(void**)&b.ppre, vec_bytes(P.ppre)},   {(void**)&b.sstart, 8 * (P.sstart.size() + 1)},
-      {(void**)&b.seg, sizeof(SchedSeg) * (P.seg.size() + 1)},
+      {(void**)&b.seg, sizeof(SchedSeg) * (P.seg.size() + 1)}, {(void**)&b.zpre, vec_bytes(P.zpre)},
   };
   std::vector<Item> rest = {
       {(void**)&b.done, 4 * (size_t)n + 64},   {(void**)&b.ctl, 64},
@@ -523,6 +562,8 @@ cpt_status carve_batch(Arena& A, const Plan& P, BatchBufs& b) {
       {(void**)&b.E.xcb, 128 * (size_t)n},      {(void**)&b.E.qcb, 4 * (size_t)(QSYM + 4) * n},
       {(void**)&b.E.used, 8 * (size_t)n},       {(void**)&b.E.xt, sizeof(HuffTables) * n},
       {(void**)&b.E.qt, sizeof(HuffTables) * n},
+      {(void**)&b.inner, (size_t)P.IB + 16},    {(void**)&b.ztab, 4 * (size_t)P.ZB + 16},
+      {(void**)&b.zlen, 4 * (size_t)P.ZB + 16}, {(void**)&b.zoff, 8 * (size_t)P.ZB + 16},
   };
   std::vector<size_t> offs;
   size_t t0 = 0;
@@ -573,6 +614,7 @@ void stage_tables(const Plan& P, const BatchBufs& b, char* stage) {
   put(b.ppre, P.ppre.data(), vec_bytes(P.ppre));
   put(b.sstart, P.sstart.data(), vec_bytes(P.sstart));
   put(b.seg, P.seg.data(), vec_bytes(P.seg));
+  put(b.zpre, P.zpre.data(), vec_bytes(P.zpre));
 }
 
 struct ExecChoice {
@@ -620,6 +662,8 @@ void enqueue_compress(const Plan& P, const BatchBufs& b, const ExecChoice& ex, c
     TimeScope ts(FAM_ENCODE, (uint64_t)P.Ntot, s);
     launch_assemble_b(b.D, n, B, b.E, b.cxpre, P.CX, b.cqpre, P.CQ, b.hpre, P.hpre.back(), s);
   }
+  // the additional lossless stage (Sec. V) into the caller's outputs
+  if (P.opt.backend == 1) launch_zbe_b(b.D, n, b.zpre, P.ZB, b.ztab, b.zlen, b.zoff, s);
 }
 
 cpt_status library_stream(Arena& A) {
@@ -765,6 +809,15 @@ cpt_status compress_batch_impl(int n, const float* const* fields, const int32_t*
   BatchBufs b;
   st = carve_batch(A, P, b);
   if (st) return st;
+  if (P.opt.backend == 1)
+    for (int i = 0; i < n; i++) {
+      // the Huffman stream goes to library scratch, the container to the caller
+      FieldDesc& d = P.D[i];
+      d.zout = d.out;
+      d.zcap = d.cap;
+      d.out = b.inner + P.ioff[i];
+      d.cap = P.ioff[i + 1] - P.ioff[i];
+    }
   const size_t rb_off = (b.tables_bytes + 255) & ~(size_t)255;
   const size_t rb_bytes = sizeof(FieldDesc) * n + 64;
   st = reserve_stage(A, rb_off + rb_bytes);
@@ -839,13 +892,18 @@ cpt_status parse_header(const uint8_t* h, size_t len, Parsed* P) {
   uint64_t K = s[9] == 2 ? 2 : (s[9] >= 3 ? 4 : 1);
   if (s[11] != K || s[13] > 62 || s[15] > 62 || s[12] > 2147483647u || s[14] > 2147483647u)
     return fail(CPT_ECORRUPT, "bad predictor parameters");
+  if (s[31] != 0 && s[31] != ZBE_TAG) return fail(CPT_ECORRUPT, "bad container tag");
+  const bool zbe = s[31] == ZBE_TAG;
   uint64_t total = HDR_BYTES;
   for (int i = 0; i < 8; i++) {
-    if (s[20 + i] % 4 || s[20 + i] > len) return fail(CPT_ECORRUPT, "bad section length");
+    if (s[20 + i] % 4 || s[20 + i] > ((uint64_t)1 << 40)) return fail(CPT_ECORRUPT, "bad section length");
     total += s[20 + i];
     P->sec[i] = s[20 + i];
   }
-  if (total != s[30] || total > len) return fail(CPT_ECORRUPT, "section lengths do not add up");
+  if (total != s[30]) return fail(CPT_ECORRUPT, "section lengths do not add up");
+  // a plain stream holds every section, a container at least its block table
+  if (zbe ? len < HDR_BYTES + 4 * zbe_blocks(total) : total > len)
+    return fail(CPT_ECORRUPT, "stream shorter than its sections");
   cpt_info& I = P->info;
   I.H = (int32_t)s[1];
   I.W = (int32_t)s[2];
@@ -860,6 +918,8 @@ cpt_status parse_header(const uint8_t* h, size_t len, Parsed* P) {
   I.n_q = s[28];
   I.n_raw = s[29];
   I.total_len = s[30];
+  I.backend = zbe ? 1 : 0;
+  I.pad = 0;
   P->cx = (int64_t)s[12];
   P->sx = (int64_t)s[13];
   P->cy = (int64_t)s[14];
@@ -880,15 +940,18 @@ struct DPlan {
   std::vector<DecDesc> D;
   std::vector<int> ord;
   std::vector<long long> mpre, cxpre, cqpre, dxpre, dqpre, spre, rpre, mtab;
+  std::vector<long long> upre, ioff;  // containers: blocks per stream, scratch offsets of their expansions
   std::vector<int> m_at;
-  long long Ntot = 0, CX = 0, CQ = 0, QS = 0, NB = 0, Stot = 0;
+  long long Ntot = 0, CX = 0, CQ = 0, QS = 0, NB = 0, Stot = 0, ZB = 0, IB = 0;
 };
 
 struct DBufs {
   DecDesc* D;
   int* ord;
-  long long *mpre, *cxpre, *cqpre, *dxpre, *dqpre, *spre, *rpre, *mtab;
+  long long *mpre, *cxpre, *cqpre, *dxpre, *dqpre, *spre, *rpre, *mtab, *upre;
   size_t tables_bytes;
+  uint8_t* inner;   // expansions of the containers
+  long long* uoff;  // per container block: its offset in the container's payload
   DecodeBufs B;
 };
 
@@ -906,6 +969,7 @@ cpt_status carve_dec(Arena& A, const DPlan& P, DBufs& b) {
       {(void**)&b.cqpre, vec_bytes(P.cqpre)}, {(void**)&b.dxpre, vec_bytes(P.dxpre)},
       {(void**)&b.dqpre, vec_bytes(P.dqpre)}, {(void**)&b.spre, vec_bytes(P.spre)},
       {(void**)&b.rpre, vec_bytes(P.rpre)}, {(void**)&b.mtab, vec_bytes(P.mtab)},
+      {(void**)&b.upre, vec_bytes(P.upre)},
   };
   std::vector<Item> rest = {
       {(void**)&b.B.lut, 8 * (size_t)n * (1u << MAXLEN)}, {(void**)&b.B.xw, 4 * CX + 16},
@@ -916,6 +980,8 @@ cpt_status carve_dec(Arena& A, const DPlan& P, DBufs& b) {
       {(void**)&b.B.sro, 4 * S + 16},                     {(void**)&b.B.modes, (size_t)P.NB + 16},
       {(void**)&b.B.cur, 8 * N},
       {(void**)&b.B.part, 4 * (scan_partials_size(std::max(S, std::max(CX, CQ))) + 16)},
+      {(void**)&b.inner, (size_t)P.IB + 16},
+      {(void**)&b.uoff, 8 * (size_t)P.ZB + 16},
   };
   std::vector<size_t> offs;
   size_t t0 = 0;
@@ -1059,6 +1125,18 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
       o += Q.sec[k];
     }
     d.out = fields[i];
+    if (I.backend) {
+      // sections are found in the container's expansion (pointers set once
+      // the scratch is carved); offsets relative to its start for now
+      d.zin = streams[i];
+      d.zlen = (long long)lens[i];
+      d.ilen = (long long)I.total_len;
+      d.nzb = (long long)zbe_blocks(I.total_len);
+      d.zbb = P.ZB;
+      P.ZB += d.nzb;
+    }
+    P.ioff.push_back(P.IB);
+    if (I.backend) P.IB += (long long)((I.total_len + 255) & ~(uint64_t)255);
     d.voff = P.Ntot;
     d.soff = P.Stot;
     d.nseg = (long long)T * H * tx;
@@ -1088,9 +1166,10 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
   const int m = (int)P.D.size();
   P.n = m;
   if (m > 0) {
-    for (auto* v : {&P.mpre, &P.cxpre, &P.cqpre, &P.dxpre, &P.dqpre, &P.spre, &P.rpre}) v->assign(m + 1, 0);
+    for (auto* v : {&P.mpre, &P.cxpre, &P.cqpre, &P.dxpre, &P.dqpre, &P.spre, &P.rpre, &P.upre}) v->assign(m + 1, 0);
     for (int j = 0; j < m; j++) {
       const DecDesc& d = P.D[j];
+      P.upre[j + 1] = P.upre[j] + d.nzb;
       P.mpre[j + 1] = P.mpre[j] + (d.nblk + 255) / 256;
       P.cxpre[j + 1] = P.cxpre[j] + d.nchx;
       P.cqpre[j + 1] = P.cqpre[j] + d.nchq;
@@ -1113,9 +1192,18 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
     }
     for (auto v : {P.mpre.back(), P.dxpre.back() + P.dqpre.back(), P.spre.back(), P.rpre.back()})
       if (v >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
+    if (P.upre.back() >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
     DBufs b;
     st = carve_dec(A, P, b);
     if (st) return st;
+    for (int j = 0; j < m; j++) {
+      DecDesc& d = P.D[j];
+      if (!d.nzb) continue;
+      // the container's sections are read from its expansion
+      d.inner = b.inner + P.ioff[j];
+      const uint8_t* base0 = (const uint8_t*)d.sec[0] - HDR_BYTES;
+      for (int k = 0; k < 8; k++) d.sec[k] = (const uint32_t*)(d.inner + ((const uint8_t*)d.sec[k] - base0));
+    }
     const size_t rb_off = (b.tables_bytes + 255) & ~(size_t)255;
     st = reserve_stage(A, rb_off + sizeof(DecDesc) * m + 64);
     if (st) return st;
@@ -1134,8 +1222,11 @@ cpt_status decompress_batch_impl(int n, const uint8_t* const* streams, const siz
       put(b.spre, P.spre.data(), vec_bytes(P.spre));
       put(b.rpre, P.rpre.data(), vec_bytes(P.rpre));
       put(b.mtab, P.mtab.data(), vec_bytes(P.mtab));
+      put(b.upre, P.upre.data(), vec_bytes(P.upre));
     }
     HIPCHK(hipMemcpyAsync(b.D, A.stage, b.tables_bytes, hipMemcpyHostToDevice, s));
+    // containers of the lossless stage are expanded first
+    if (P.ZB > 0) launch_unzbe_b(b.D, m, b.upre, P.ZB, b.uoff, s);
     launch_decode_front_b(b.D, m, b.B, b.mpre, P.mpre.back(), b.cxpre, P.CX, b.cqpre, P.CQ, s);
     {
       TimeScope ts(FAM_DECODE, (uint64_t)(P.Ntot + P.QS), s);
@@ -1377,12 +1468,9 @@ cpt_status cpt_compress_bound(int H, int W, int T, size_t* max_bytes) {
   if (!max_bytes) return fail(CPT_EINVAL, "null max_bytes");
   cpt_status st = check_dims(H, W, T);
   if (st) return st;
-  size_t N = (size_t)H * W * T;
-  size_t nchx = (N + CHUNK - 1) / CHUNK, nq = 2 * N, nchq = (nq + CHUNK - 1) / CHUNK;
-  size_t nd = (size_t)T * ((H + TILE - 1) / TILE) * ((W + TILE - 1) / TILE);
-  *max_bytes = HDR_BYTES + 4 * ((nd * 2 + 31) / 32) + (4 + 4 * XSYM) + 4 * nchx +
-               4 * ((N * MAXLEN + 31) / 32 + nchx) + (4 + 4 * QSYM) + 4 * nchq +
-               4 * ((nq * MAXLEN + 31) / 32 + nchq) + 8 * N;
+  // a container adds one table entry per block to a Huffman stream's bytes
+  const size_t hb = huffman_bound(H, W, T);
+  *max_bytes = hb + 4 * zbe_blocks(hb);
   return CPT_OK;
 }
 

@@ -24,6 +24,9 @@ constexpr size_t HDR_BYTES = 8 * HDR_SLOTS;
 constexpr uint64_t STREAM_MAGIC = 0x31545043ull;  // "CPT1"
 constexpr uint64_t STREAM_VERSION = 1;
 constexpr int SL_STRIDE = 2;  // stride of the rate-estimate subgrid
+// lossless stage after Huffman coding: zero-byte elision in blocks of the body
+constexpr int ZBE_BLOCK = 4096;
+constexpr uint64_t ZBE_TAG = 0x315A4245ull;  // header slot 31 of a container ("EBZ1")
 
 struct FieldDesc {
   // fixed by the dimensions and the call (host)
@@ -42,6 +45,12 @@ struct FieldDesc {
   long long cap;         // its capacity in bytes
   int32_t* xi_dbg;       // optional per-vertex bounds
   float* feats_dbg;      // optional per-block features
+  // with the lossless stage: out / cap above are the Huffman stream in
+  // library scratch, zout / zcap the caller's container output
+  uint8_t* zout;
+  long long zcap;
+  long long zbase;       // first block in the concatenated block tables
+  long long ilen;        // Huffman stream length once the container is laid out
   int eb_mode, predictor, K, bt;
   double eb, dt_dx, dt_dy;
   // derived on the device
@@ -147,6 +156,12 @@ struct DecDesc {
   const uint32_t* sec[8];   // the stream's sections (device)
   long long secw[8];        // their lengths in words
   float* out;               // decompressed field (2, T, H, W)
+  // a container of the lossless stage: its bytes, length and blocks, the
+  // first of them in the concatenated block offsets, and the scratch copy of
+  // the Huffman stream it expands to (ilen bytes); nzb = 0 for a plain stream
+  const uint8_t* zin;
+  long long zlen, nzb, zbb, ilen;
+  uint8_t* inner;
   uint32_t err;             // device error bits
   int status;               // 0 ok, else a cpt_status
 };
@@ -174,6 +189,13 @@ void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long lo
 void launch_decode_b(DecDesc* D, int n, const DecodeBufs& B, const long long* dxpre, long long dxblocks,
                      const long long* dqpre, long long dqblocks, const long long* spre, long long sblocks,
                      long long Stot, long long CX, long long CQ, hipStream_t s);
+// k_backend.hip: the lossless stage (zero-byte elision).  zpre: most blocks
+// per field (from the Huffman stream's bound); tables of zblocks entries
+void launch_zbe_b(FieldDesc* D, int n, const long long* zpre, long long zblocks, uint32_t* ztab, uint32_t* zlen,
+                  long long* zoff, hipStream_t s);
+// its inverse into each container's scratch copy (upre: blocks per stream)
+void launch_unzbe_b(DecDesc* D, int n, const long long* upre, long long ublocks, long long* uoff, hipStream_t s);
+
 // k_decompress.hip: reconstruction of frame t of the first m streams of the
 // launch order (pre: blocks per stream)
 // mtab[mtb + t]: offset of frame t's predictor classes in the stream's

@@ -104,3 +104,23 @@ def test_streams_shorter_than_a_header_touch_no_device(built):
     st, sb, s0, s1, *msg = r.stdout.split()
     assert (int(st), int(sb), int(s0), int(s1)) == (-3, -3, -3, -3)
     assert "shorter than its header" in " ".join(msg)
+
+
+def test_stream_info_reads_a_container_on_host(built):
+    """The header of a container of the lossless stage is readable as is."""
+    import numpy as np
+    import oracle
+    import synthfields
+    import paper_2510_25143_amd as cpt
+    import torch
+    f, _ = synthfields.workload(0)
+    b = oracle.compress(f.numpy(), 1e-2)
+    c = oracle.compress(f.numpy(), 1e-2, backend=1)
+    info = cpt.stream_info(torch.from_numpy(c))
+    assert info["backend"] == 1 and info["total_len"] == len(b)
+    assert cpt.stream_info(torch.from_numpy(b))["backend"] == 0
+    bad = c.copy()
+    bad[248] ^= 2   # container tag
+    with pytest.raises(cpt.CptError):
+        cpt.stream_info(torch.from_numpy(bad))
+    assert cpt.compress_bound(64, 64, 8) >= oracle.lib().cpo_compress_bound(64, 64, 8)
