@@ -305,3 +305,54 @@ def test_canonical_codes_by_hand(ora):
     # a longer example: lengths 2,2,3,3,3,4,4 -> 00 01 100 101 110 1110 1111
     assert list(ora.canonical_codes([4, 2, 3, 2, 3, 4, 3])) == [0b1110, 0b00, 0b100, 0b01, 0b101,
                                                                   0b1111, 0b110]
+
+
+# ---------------------------------------------------------- trajectories
+def _brute_tracks(a, H, W, T):
+    """(Lemma-1 violations, components) by brute force: the prism split's
+    tetrahedra, crossed faces from the generic SoS expansion, and a plain
+    union-find joining the two crossed faces of each tetrahedron."""
+    import itertools
+    from test_oracle_mesh import brute_tets
+    U, V = a[0].ravel().astype(int), a[1].ravel().astype(int)
+    crossed = {}
+    for tri in brute_faces(H, W, T):
+        c, _ = generic_crossed(U, V, tri)
+        if c:
+            crossed[tri] = tri
+    parent = {f: f for f in crossed}
+
+    def find(x):
+        while parent[x] != x:
+            x = parent[x]
+        return x
+
+    bad = 0
+    for tet in brute_tets(H, W, T):
+        faces = [f for f in itertools.combinations(sorted(tet), 3) if f in crossed]
+        if len(faces) not in (0, 2):
+            bad += 1
+        if len(faces) == 2:
+            ra, rb = find(faces[0]), find(faces[1])
+            if ra != rb:
+                parent[ra] = rb
+    return bad, len({find(f) for f in crossed})
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_tracks_equal_brute_force_components(ora, seed):
+    rng = np.random.default_rng(300 + seed)
+    H, W, T = 5, 6, 4
+    a = rng.integers(-2, 3, (2, T, H, W)).astype(np.float32)
+    assert ora.tracks(a, 0) == _brute_tracks(a, H, W, T)
+
+
+def test_tracks_of_two_separated_vortices(ora):
+    """Two translating swirls far apart: two trajectories, no violation."""
+    import synthfields
+    params = (np.array([[8.3, 9.1], [27.6, 21.2]]), np.array([[0.21, -0.13], [-0.17, 0.11]]),
+              np.array([1.3, -0.9]), np.array([3.5, 4.0]))
+    f, _ = synthfields.vortex_field(32, 36, 7, 2, seed=0, noise=0.0, params=params)
+    f = f.numpy()
+    k, _, _ = ora.params(f, 1e-2)
+    assert ora.tracks(f, k) == (0, 2)
