@@ -468,6 +468,12 @@ def main():
     clen = s.numel()
     log("stream %d bytes, CR %.3f, FC_t %d FC_s %d, max err %.3g <= %.3g" %
         (clen, raw / clen, v["fc_t"], v["fc_s"], v["max_err"], eb_abs))
+    # trajectories (Sec. IV-B) of the original and the decompressed field
+    bad0, traj0 = cpt.tracks(f, k)
+    bad1, traj1 = cpt.tracks(dec, k)
+    if (bad0, traj0) != (bad1, traj1):
+        raise SystemExit("trajectories differ: %d before, %d after" % (traj0, traj1))
+    log("trajectories: %d before and after compression, %d Lemma-1 violations" % (traj0, bad0))
 
     log("timed x%d" % args.steps)
     cpt.timing_enable(True, period=TIMING_PERIOD)
@@ -522,6 +528,7 @@ def main():
                    "eb_abs": eb_abs, "predictor": args.predictor, "mode_bt": args.mode_bt,
                    "schedule": sched, "tune_ms": tune_ms,
                    "CR": round(raw / clen, 4), "stream_bytes": clen, "fc_t": v["fc_t"], "fc_s": v["fc_s"],
+                   "n_traj_before": traj0, "n_traj_after": traj1, "lemma1_violations": bad0,
                    "max_err": v["max_err"], "psnr": round(v["psnr"], 3),
                    "compress_ms": round(tc, 4), "decompress_ms": round(td, 4),
                    "compress_GBps": round(raw / tc / 1e6, 3), "decompress_GBps": round(raw / td / 1e6, 3),

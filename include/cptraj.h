@@ -242,6 +242,17 @@ cpt_status cpt_decompress(const uint8_t* bytes, size_t len, float* field, size_t
 cpt_status cpt_extract_trajectories(const float* field, int H, int W, int T, int k, uint64_t* codes, size_t cap,
                                     size_t* count, void* stream);
 
+/* Critical-point trajectories of a field (device, (2,T,H,W) float32) on the
+ * grid 2^k (Sec. IV-B): the crossed faces of cpt_extract_trajectories
+ * joined through the tetrahedra of the prism split (two crossed faces of one
+ * tetrahedron belong to one trajectory) into connected components.
+ *   bad_tets  host, receives the tetrahedra with a crossed-face count other
+ *             than 0 or 2 (Lemma 1 makes it 0)
+ *   n_tracks  host, receives the number of components (#Traj of Sec. VII-A)
+ * Requires max|x| 2^k < 2^24.  Synchronises `stream`. */
+cpt_status cpt_tracks(const float* field, int H, int W, int T, int k, uint64_t* bad_tets, uint64_t* n_tracks,
+                      void* stream);
+
 /* The check of Sec. IV-A with the metrics of Sec. VII-A: both fields
  * (device, (2,T,H,W) float32) converted to the grid 2^k, their crossed faces
  * and signs extracted as cpt_extract_trajectories does, and every face whose

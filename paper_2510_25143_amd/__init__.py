@@ -64,7 +64,7 @@ EXPORTS = ["cpt_compress_bound", "cpt_compress", "cpt_compress_debug", "cpt_stre
            "cpt_decompress", "cpt_extract_trajectories", "cpt_verify", "cpt_field_params",
            "cpt_selector_grad", "cpt_selector_train", "cpt_timing_enable", "cpt_timing_read",
            "cpt_compress_batch", "cpt_autotune_batch", "cpt_decompress_batch", "cpt_verify_noalloc",
-           "cpt_last_error"]
+           "cpt_tracks", "cpt_last_error"]
 
 _lib = None
 
@@ -87,6 +87,7 @@ def lib():
         "cpt_extract_trajectories": [P, i32, i32, i32, i32, P, sz, P, P],
         "cpt_verify": [P, P, i32, i32, i32, i32, P, P],
         "cpt_verify_noalloc": [P, P, i32, i32, i32, i32, P, P],
+        "cpt_tracks": [P, i32, i32, i32, i32, P, P, P],
         "cpt_field_params": [P, i32, i32, i32, i32, dbl, P, P, P, P],
         "cpt_selector_grad": [P, P, P, i32, P, P, P],
         "cpt_selector_train": [P, P, i32, P, P, P, P, P],
@@ -324,6 +325,15 @@ def verify(a, b, k):
     r = VerifyResult()
     _check(lib().cpt_verify(_ptr(fa), _ptr(fb), H, W, T, k, ctypes.byref(r), _stream()))
     return dict(fc_t=r.fc_t, fc_s=r.fc_s, max_err=r.max_err, psnr=r.psnr)
+
+
+def tracks(field, k):
+    """(Lemma-1 violations, trajectories) of ``field`` on the grid 2^k."""
+    f = _field(field)
+    _, T, H, W = f.shape
+    bad, nt = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().cpt_tracks(_ptr(f), H, W, T, k, ctypes.byref(bad), ctypes.byref(nt), _stream()))
+    return bad.value, nt.value
 
 
 VERIFY_NOALLOC_MAX_VERTICES = 7866176

@@ -12,7 +12,7 @@ OBJDIR = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "libcptraj.so")
 
 SOURCES = ["k_field.hip", "k_compress.hip", "k_entropy.hip", "k_backend.hip", "k_decompress.hip", "k_selector.hip",
-           "api.cpp"]
+           "k_tracks.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("CPT_ARCH", "gfx950")

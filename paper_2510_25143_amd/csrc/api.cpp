@@ -1689,6 +1689,66 @@ cpt_status cpt_extract_trajectories(const float* field, int H, int W, int T, int
   return CPT_OK;
 }
 
+cpt_status cpt_tracks(const float* field, int H, int W, int T, int k, uint64_t* bad_tets, uint64_t* n_tracks,
+                      void* stream) {
+  try {
+    if (!field || !bad_tets || !n_tracks) return fail(CPT_EINVAL, "null pointer");
+    cpt_status st = check_dims(H, W, T);
+    if (st) return st;
+    if (k < -80 || k > 120) return fail(CPT_EINVAL, "k must be in -80..120");
+    hipStream_t s = (hipStream_t)stream;
+    Arena* Ap = arena_for_device(&st);
+    if (!Ap) return st;
+    Arena& A = *Ap;
+    std::lock_guard<std::mutex> lk(A.mu);
+    const size_t N = (size_t)H * W * T;
+    // pass 1: how many crossed faces
+    Bufs b;
+    st = carve(A, N, b);
+    if (st) return st;
+    Range r;
+    st = field_range(field, 2 * N, b, A, s, &r);
+    if (st) return st;
+    if (std::ldexp(r.ma, k) >= 16777216.0) return fail(CPT_EINVAL, "max|x| 2^k must be below 2^24");
+    launch_convert(field, N, k, b.cur, s);
+    launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
+    launch_count_faces(b.masks, N, b.nonll, s);
+    launch_scan(b.nonll, N, b.qofs, b.part, b.tot, s);
+    HIPCHK(hipMemcpyAsync(A.host, b.tot, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const size_t M = *(const uint32_t*)A.host;
+    if (M >= 2147483647u) return fail(CPT_EUNSUPPORTED, "2^31 or more crossed faces");
+    // pass 2: the same masks with room for the crossed faces and their union-find
+    st = carve(A, N, b);
+    if (st) return st;
+    const size_t oc = A.off(8 * M + 8), op = A.off(4 * M + 4), ot = A.off(16);
+    st = reserve(A);
+    if (st) return st;
+    st = carve(A, N, b);  // the arena may have moved: carve again, same offsets
+    if (st) return st;
+    (void)A.off(8 * M + 8);
+    (void)A.off(4 * M + 4);
+    (void)A.off(16);
+    uint64_t* codes = (uint64_t*)(A.base + oc);
+    int* parent = (int*)(A.base + op);
+    unsigned long long* ctr = (unsigned long long*)(A.base + ot);
+    launch_convert(field, N, k, b.cur, s);
+    launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
+    launch_count_faces(b.masks, N, b.nonll, s);
+    launch_scan(b.nonll, N, b.qofs, b.part, b.tot, s);
+    launch_write_codes(b.masks, b.qofs, N, codes, M, s);
+    launch_tracks(b.masks, H, W, T, codes, (long long)M, parent, ctr, s);
+    HIPCHK(hipMemcpyAsync(A.host, ctr, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    *bad_tets = A.host[0];
+    *n_tracks = A.host[1];
+    return CPT_OK;
+  } catch (...) {
+    return fail(CPT_EHIP, "unexpected exception");
+  }
+}
+
 cpt_status cpt_verify(const float* a, const float* bf, int H, int W, int T, int k, cpt_verify_result* res,
                       void* stream) {
   if (!a || !bf || !res) return fail(CPT_EINVAL, "null pointer");
