@@ -511,7 +511,7 @@ cpt_status build_schedule(Plan& P, int group) {
 struct BatchBufs {
   FieldDesc* D;
   int* ord;
-  long long *rpre, *gpre, *hpre, *cxpre, *cqpre, *fpre, *mpre, *ppre, *sstart, *zpre;
+  long long *rpre, *gpre, *hpre, *cxpre, *cqpre, *fpre, *mpre, *ppre, *sstart;
   SchedSeg* seg;
   size_t tables_bytes;
   uint8_t* inner;           // Huffman streams ahead of the lossless stage
@@ -545,7 +545,7 @@ cpt_status carve_batch(Arena& A, const Plan& P, BatchBufs& b) {
       {(void**)&b.cqpre, vec_bytes(P.cqpre)}, {(void**)&b.fpre, vec_bytes(P.fpre)},
       {(void**)&b.mpre, vec_bytes(P.mpre)},
       {(void**)&b.ppre, vec_bytes(P.ppre)},   {(void**)&b.sstart, 8 * (P.sstart.size() + 1)},
-      {(void**)&b.seg, sizeof(SchedSeg) * (P.seg.size() + 1)}, {(void**)&b.zpre, vec_bytes(P.zpre)},
+      {(void**)&b.seg, sizeof(SchedSeg) * (P.seg.size() + 1)},
   };
   std::vector<Item> rest = {
       {(void**)&b.done, 4 * (size_t)n + 64},   {(void**)&b.ctl, 64},
@@ -614,7 +614,6 @@ void stage_tables(const Plan& P, const BatchBufs& b, char* stage) {
   put(b.ppre, P.ppre.data(), vec_bytes(P.ppre));
   put(b.sstart, P.sstart.data(), vec_bytes(P.sstart));
   put(b.seg, P.seg.data(), vec_bytes(P.seg));
-  put(b.zpre, P.zpre.data(), vec_bytes(P.zpre));
 }
 
 struct ExecChoice {
@@ -663,7 +662,7 @@ void enqueue_compress(const Plan& P, const BatchBufs& b, const ExecChoice& ex, c
     launch_assemble_b(b.D, n, B, b.E, b.cxpre, P.CX, b.cqpre, P.CQ, b.hpre, P.hpre.back(), s);
   }
   // the additional lossless stage (Sec. V) into the caller's outputs
-  if (P.opt.backend == 1) launch_zbe_b(b.D, n, b.zpre, P.ZB, b.ztab, b.zlen, b.zoff, s);
+  if (P.opt.backend == 1) launch_zbe_b(b.D, n, P.ZB, b.ztab, b.zlen, b.zoff, s);
 }
 
 cpt_status library_stream(Arena& A) {
@@ -1718,26 +1717,23 @@ cpt_status cpt_tracks(const float* field, int H, int W, int T, int k, uint64_t* 
     HIPCHK(hipStreamSynchronize(s));
     const size_t M = *(const uint32_t*)A.host;
     if (M >= 2147483647u) return fail(CPT_EUNSUPPORTED, "2^31 or more crossed faces");
-    // pass 2: the same masks with room for the crossed faces and their union-find
+    // pass 2: the same masks and offsets with room for the union-find
     st = carve(A, N, b);
     if (st) return st;
-    const size_t oc = A.off(8 * M + 8), op = A.off(4 * M + 4), ot = A.off(16);
+    const size_t op = A.off(4 * M + 4), ot = A.off(16);
     st = reserve(A);
     if (st) return st;
     st = carve(A, N, b);  // the arena may have moved: carve again, same offsets
     if (st) return st;
-    (void)A.off(8 * M + 8);
     (void)A.off(4 * M + 4);
     (void)A.off(16);
-    uint64_t* codes = (uint64_t*)(A.base + oc);
     int* parent = (int*)(A.base + op);
     unsigned long long* ctr = (unsigned long long*)(A.base + ot);
     launch_convert(field, N, k, b.cur, s);
     launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
     launch_count_faces(b.masks, N, b.nonll, s);
     launch_scan(b.nonll, N, b.qofs, b.part, b.tot, s);
-    launch_write_codes(b.masks, b.qofs, N, codes, M, s);
-    launch_tracks(b.masks, H, W, T, codes, (long long)M, parent, ctr, s);
+    launch_tracks(b.masks, b.qofs, H, W, T, (long long)M, parent, ctr, s);
     HIPCHK(hipMemcpyAsync(A.host, ctr, 16, hipMemcpyDeviceToHost, s));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));

@@ -189,10 +189,11 @@ void launch_decode_front_b(DecDesc* D, int n, const DecodeBufs& B, const long lo
 void launch_decode_b(DecDesc* D, int n, const DecodeBufs& B, const long long* dxpre, long long dxblocks,
                      const long long* dqpre, long long dqblocks, const long long* spre, long long sblocks,
                      long long Stot, long long CX, long long CQ, hipStream_t s);
-// k_backend.hip: the lossless stage (zero-byte elision).  zpre: most blocks
-// per field (from the Huffman stream's bound); tables of zblocks entries
-void launch_zbe_b(FieldDesc* D, int n, const long long* zpre, long long zblocks, uint32_t* ztab, uint32_t* zlen,
-                  long long* zoff, hipStream_t s);
+// k_backend.hip: the lossless stage (zero-byte elision).  zblocks: the
+// fields' most blocks together (from their Huffman streams' bounds), the
+// size of the per-block tables; D[f].zbase: a field's first entry
+void launch_zbe_b(FieldDesc* D, int n, long long zblocks, uint32_t* ztab, uint32_t* zlen, long long* zoff,
+                  hipStream_t s);
 // its inverse into each container's scratch copy (upre: blocks per stream)
 void launch_unzbe_b(DecDesc* D, int n, const long long* upre, long long ublocks, long long* uoff, hipStream_t s);
 

@@ -11,11 +11,13 @@
 // byte i), the nonzero bytes in order, and zero bytes up to a multiple of 4;
 // a block is elided exactly when that is shorter than n.
 //
-// One workgroup of 256 threads per block, 16 bytes per thread: a pass that
-// counts nonzero bytes and decides, a per-field pass that lays the blocks
-// out, and a pass that builds each encoded block in LDS and stores it with
-// 32-bit writes.  Decoding mirrors it and checks every length, mask bit,
+// A workgroup of 256 threads works one block at a time, 16 bytes per
+// thread: a pass that counts nonzero bytes and decides, a per-field pass
+// that lays the blocks out, and a pass that builds each encoded block in
+// LDS and stores it with 32-bit writes.  Decoding mirrors it and checks every length, mask bit,
 // stored byte and padding byte, so that no read leaves the container.
+#include <algorithm>
+
 #include "batch.hpp"
 #include "cpt_device.hpp"
 
@@ -67,27 +69,28 @@ __device__ __forceinline__ T wg_exclusive(T v, T* sh, T* sum) {
 }  // namespace
 
 // ------------------------------------------------------------------ encode
-// zpre[f]: workgroups of the fields before f (each field's most blocks, from
-// its Huffman stream's bound); the field's actual blocks come from its length
-__global__ __launch_bounds__(256) void k_zbe_count_b(const FieldDesc* __restrict__ D,
-                                                     const long long* __restrict__ zpre, int n,
+// The grid is fixed (the number of blocks is known only on the device):
+// workgroup w takes blocks w, w + grid, ... of every field in turn.
+__global__ __launch_bounds__(256) void k_zbe_count_b(const FieldDesc* __restrict__ D, int n,
                                                      uint32_t* __restrict__ ztab, uint32_t* __restrict__ zlen) {
   __shared__ int sh[4];
-  const int f = find_field(zpre, n, blockIdx.x);
-  const FieldDesc& d = D[f];
-  const long long b = (long long)blockIdx.x - zpre[f];
-  const long long body = d.len - (long long)HDR_BYTES;
-  const long long nb = (body + ZBE_BLOCK - 1) / ZBE_BLOCK;
-  if (d.status || b >= nb) return;
-  const int nbytes = (int)min((long long)ZBE_BLOCK, body - b * ZBE_BLOCK);
-  const uint4 v = load16(d.out + HDR_BYTES + b * ZBE_BLOCK, threadIdx.x, nbytes);
-  int tot = 0;
-  (void)wg_exclusive<int>(__popc(mask16(v)), sh, &tot);
-  if (threadIdx.x == 0) {
-    const long long e = pad4((nbytes + 7) / 8 + tot);
-    const bool elide = e < nbytes;
-    ztab[d.zbase + b] = elide ? ((uint32_t)e | 0x80000000u) : (uint32_t)nbytes;
-    zlen[d.zbase + b] = elide ? (uint32_t)e : (uint32_t)nbytes;
+  for (int f = 0; f < n; f++) {
+    const FieldDesc& d = D[f];
+    if (d.status) continue;
+    const long long body = d.len - (long long)HDR_BYTES;
+    const long long nb = (body + ZBE_BLOCK - 1) / ZBE_BLOCK;
+    for (long long b = blockIdx.x; b < nb; b += gridDim.x) {
+      const int nbytes = (int)min((long long)ZBE_BLOCK, body - b * ZBE_BLOCK);
+      const uint4 v = load16(d.out + HDR_BYTES + b * ZBE_BLOCK, threadIdx.x, nbytes);
+      int tot = 0;
+      (void)wg_exclusive<int>(__popc(mask16(v)), sh, &tot);
+      if (threadIdx.x == 0) {
+        const long long e = pad4((nbytes + 7) / 8 + tot);
+        const bool elide = e < nbytes;
+        ztab[d.zbase + b] = elide ? ((uint32_t)e | 0x80000000u) : (uint32_t)nbytes;
+        zlen[d.zbase + b] = elide ? (uint32_t)e : (uint32_t)nbytes;
+      }
+    }
   }
 }
 
@@ -131,19 +134,9 @@ __global__ __launch_bounds__(256) void k_zbe_layout_b(FieldDesc* __restrict__ D,
   for (long long i = tid; i < nb; i += 256) o[HDR_BYTES / 4 + i] = ztab[d.zbase + i];
 }
 
-__global__ __launch_bounds__(256) void k_zbe_write_b(const FieldDesc* __restrict__ D,
-                                                     const long long* __restrict__ zpre, int n,
-                                                     const uint32_t* __restrict__ ztab,
-                                                     const long long* __restrict__ zoff) {
-  __shared__ int sh[4];
-  __shared__ __align__(16) uint8_t enc[ZBE_BLOCK];
-  const int f = find_field(zpre, n, blockIdx.x);
-  const FieldDesc& d = D[f];
-  if (d.status) return;
-  const long long b = (long long)blockIdx.x - zpre[f];
-  const long long body = d.ilen - (long long)HDR_BYTES;
-  const long long nb = (body + ZBE_BLOCK - 1) / ZBE_BLOCK;
-  if (b >= nb) return;
+__device__ __forceinline__ void zbe_write_block(const FieldDesc& d, long long b, long long nb, long long body,
+                                                const uint32_t* __restrict__ ztab, const long long* __restrict__ zoff,
+                                                int* sh, uint8_t* enc) {
   const int tid = threadIdx.x;
   const int nbytes = (int)min((long long)ZBE_BLOCK, body - b * ZBE_BLOCK);
   const uint32_t entry = ztab[d.zbase + b];
@@ -172,6 +165,21 @@ __global__ __launch_bounds__(256) void k_zbe_write_b(const FieldDesc* __restrict
   __syncthreads();
   const uint32_t* e32 = (const uint32_t*)enc;
   for (int i = tid; i < e / 4; i += 256) dst[i] = e32[i];
+  __syncthreads();  // enc is reused by the workgroup's next block
+}
+
+__global__ __launch_bounds__(256) void k_zbe_write_b(const FieldDesc* __restrict__ D, int n,
+                                                     const uint32_t* __restrict__ ztab,
+                                                     const long long* __restrict__ zoff) {
+  __shared__ int sh[4];
+  __shared__ __align__(16) uint8_t enc[ZBE_BLOCK];
+  for (int f = 0; f < n; f++) {
+    const FieldDesc& d = D[f];
+    if (d.status) continue;
+    const long long body = d.ilen - (long long)HDR_BYTES;
+    const long long nb = (body + ZBE_BLOCK - 1) / ZBE_BLOCK;
+    for (long long b = blockIdx.x; b < nb; b += gridDim.x) zbe_write_block(d, b, nb, body, ztab, zoff, sh, enc);
+  }
 }
 
 // ------------------------------------------------------------------ decode
@@ -268,11 +276,12 @@ __global__ __launch_bounds__(256) void k_unzbe_block_b(DecDesc* __restrict__ D, 
 }
 
 // ================================================================ launchers
-void launch_zbe_b(FieldDesc* D, int n, const long long* zpre, long long zblocks, uint32_t* ztab, uint32_t* zlen,
-                  long long* zoff, hipStream_t s) {
-  if (zblocks > 0) k_zbe_count_b<<<(unsigned)zblocks, 256, 0, s>>>(D, zpre, n, ztab, zlen);
+void launch_zbe_b(FieldDesc* D, int n, long long zblocks, uint32_t* ztab, uint32_t* zlen, long long* zoff,
+                  hipStream_t s) {
+  const unsigned grid = (unsigned)std::min<long long>(zblocks, 4096);
+  if (grid > 0) k_zbe_count_b<<<grid, 256, 0, s>>>(D, n, ztab, zlen);
   k_zbe_layout_b<<<n, 256, 0, s>>>(D, ztab, zlen, zoff);
-  if (zblocks > 0) k_zbe_write_b<<<(unsigned)zblocks, 256, 0, s>>>(D, zpre, n, ztab, zoff);
+  if (grid > 0) k_zbe_write_b<<<grid, 256, 0, s>>>(D, n, ztab, zoff);
 }
 
 void launch_unzbe_b(DecDesc* D, int n, const long long* upre, long long ublocks, long long* uoff, hipStream_t s) {

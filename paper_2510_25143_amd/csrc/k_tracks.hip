@@ -11,8 +11,10 @@
 // other vertices from the owner, as the extraction numbers them).  One
 // thread per cell counts the crossed faces of its six tetrahedra: a count
 // other than 0 or 2 is a Lemma-1 violation; for a count of 2 the two faces
-// are united in a lock-free union-find over the sorted list of crossed
-// faces.  Trajectories are the roots that remain.
+// are united in a lock-free union-find over the crossed faces, numbered in
+// (owner, type) order: a face's number is the exclusive prefix sum of the
+// crossed-face counts of the vertices before its owner plus its rank among
+// its owner's crossed faces.  Trajectories are the roots that remain.
 #include "cpt_device.hpp"
 #include "launch.hpp"
 
@@ -128,17 +130,6 @@ __device__ void uf_unite(int* p, int a, int b) {
   }
 }
 
-// position of crossed face `face` (owner * 12 + type) in the sorted codes
-__device__ __forceinline__ int face_index(const uint64_t* __restrict__ codes, long long M, uint64_t face) {
-  const uint64_t key = face << 1;
-  long long lo = 0, hi = M;
-  while (lo < hi) {
-    const long long mid = (lo + hi) >> 1;
-    if (codes[mid] < key) lo = mid + 1; else hi = mid;
-  }
-  return (int)lo;
-}
-
 }  // namespace
 
 __global__ __launch_bounds__(256) void k_uf_init(int* __restrict__ parent, long long M) {
@@ -147,8 +138,8 @@ __global__ __launch_bounds__(256) void k_uf_init(int* __restrict__ parent, long 
 }
 
 __global__ __launch_bounds__(256) void k_tet_pairs(const uint32_t* __restrict__ masks, int H, int W, int T,
-                                                   const uint64_t* __restrict__ codes, long long M,
-                                                   int* __restrict__ parent, unsigned long long* __restrict__ ctr) {
+                                                   const uint32_t* __restrict__ ofs, int* __restrict__ parent,
+                                                   unsigned long long* __restrict__ ctr) {
   const long long cells = (long long)(W - 1) * (H - 1) * (T - 1);
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned nbad = 0;
@@ -157,19 +148,20 @@ __global__ __launch_bounds__(256) void k_tet_pairs(const uint32_t* __restrict__ 
     const long long r = i / (W - 1);
     const int y = (int)(r % (H - 1)), t = (int)(r / (H - 1));
     for (int k = 0; k < 6; k++) {
-      uint64_t fa = 0, fb = 0;
+      int fa = 0, fb = 0;
       int cnt = 0;
       for (int s = 0; s < 4; s++) {
         const size_t g = ((size_t)(t + c_tet.dt[k][s]) * H + (y + c_tet.dy[k][s])) * W + (x + c_tet.dx[k][s]);
         const int type = c_tet.type[k][s];
-        if ((masks[g] >> type) & 1u) {
-          const uint64_t face = (uint64_t)g * 12 + (uint64_t)type;
+        const uint32_t m = masks[g];
+        if ((m >> type) & 1u) {
+          const int face = (int)(ofs[g] + (uint32_t)__popc(m & ((1u << type) - 1u)));
           if (cnt == 0) fa = face; else fb = face;
           cnt++;
         }
       }
       if (cnt != 0 && cnt != 2) nbad++;
-      if (cnt == 2) uf_unite(parent, face_index(codes, M, fa), face_index(codes, M, fb));
+      if (cnt == 2) uf_unite(parent, fa, fb);
     }
   }
   if (nbad) atomicAdd(&ctr[0], (unsigned long long)nbad);
@@ -186,13 +178,13 @@ __global__ void k_zero_ctr(unsigned long long* ctr) {
   if (threadIdx.x < 2) ctr[threadIdx.x] = 0;
 }
 
-void launch_tracks(const uint32_t* masks, int H, int W, int T, const uint64_t* codes, long long M, int* parent,
+void launch_tracks(const uint32_t* masks, const uint32_t* ofs, int H, int W, int T, long long M, int* parent,
                    unsigned long long* ctr, hipStream_t s) {
   k_zero_ctr<<<1, 64, 0, s>>>(ctr);
   const long long cells = (long long)(W - 1) * (H - 1) * (T - 1);
   if (M > 0) k_uf_init<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(parent, M);
   // without crossed faces no tetrahedron has two, so the union is never reached
-  if (cells > 0) k_tet_pairs<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(masks, H, W, T, codes, M, parent, ctr);
+  if (cells > 0) k_tet_pairs<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(masks, H, W, T, ofs, parent, ctr);
   if (M > 0) k_uf_roots<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(parent, M, ctr);
 }
 

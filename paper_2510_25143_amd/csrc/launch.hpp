@@ -33,8 +33,9 @@ void launch_compare(const uint32_t* ma, const uint32_t* mb, const float* a, cons
                     unsigned long long* fc, double* part, hipStream_t s);
 
 // k_tracks.hip: Lemma-1 violations (ctr[0]) and trajectories (ctr[1]) from
-// the face masks and the sorted crossed-face codes (M of them); parent: M ints
-void launch_tracks(const uint32_t* masks, int H, int W, int T, const uint64_t* codes, long long M, int* parent,
+// the face masks and the exclusive prefix sums of the per-vertex crossed-face
+// counts (M crossed faces in all); parent: M ints
+void launch_tracks(const uint32_t* masks, const uint32_t* ofs, int H, int W, int T, long long M, int* parent,
                    unsigned long long* ctr, hipStream_t s);
 
 // k_entropy.hip
