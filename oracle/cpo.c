@@ -33,11 +33,20 @@
 
 /* ---- format constants (READING: the paper prints none of these) ---- */
 #define TILE 16          /* spatial block edge for blocking and mode choice */
-#define QR 512           /* residual quantization radius R */
+/* R and the longest codeword are build-time constants so that the format
+   study in tests/format_cost_study.py can measure other values; the stream
+   records both and every build reads only its own. */
+#ifndef CPO_QR
+#define CPO_QR 512
+#endif
+#ifndef CPO_MAXLEN
+#define CPO_MAXLEN 12
+#endif
+#define QR CPO_QR        /* residual quantization radius R */
 #define QSYM (2 * QR)    /* residual-code alphabet; code 0 = unpredictable */
 #define XSYM 25          /* bound-code alphabet; 24 = lossless */
 #define XLOSSLESS 24
-#define MAXLEN 12        /* longest Huffman codeword */
+#define MAXLEN CPO_MAXLEN /* longest Huffman codeword */
 #define CHUNK 1024       /* symbols per independently decodable chunk */
 #define STRIDE 2         /* micro-encoding statistics subsample (Sec. VI-B) */
 #define NMAX 32          /* maximum substeps, Sec. VI-A */
