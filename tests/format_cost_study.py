@@ -2,11 +2,11 @@
 """Compression-ratio cost of the stream's format constants (a study, not a
 test): the residual quantization radius R and the longest Huffman codeword
 are 512 and 12 in this implementation (one workgroup builds a codebook, one
-4096-entry table decodes it); the alternative R = 32768 with 24-bit codes
-keeps more residuals out of the raw-float store at tight bounds.  Both are
-built from the CPU oracle with the constants overridden, and compress the
-same crops of the wind and turbulence workloads; CR is printed for each
-(Huffman stream, and with the zero-byte-elision stage).
+4096-entry table decodes it).  Longer codewords (16, 24) and the wider radius
+R = 32768 are built from the CPU oracle with the constants overridden, and
+compress the same crops of the wind and turbulence workloads; CR is printed
+for each (Huffman stream, and with the zero-byte-elision stage), with the
+change against R 512 / 12 bits.
 
 Usage: python tests/format_cost_study.py   (about a minute on one core)
 """
@@ -18,7 +18,7 @@ import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-VARIANTS = [("R512_L12", 512, 12), ("R32768_L24", 32768, 24)]
+VARIANTS = [("R512_L12", 512, 12), ("R512_L16", 512, 16), ("R512_L24", 512, 24), ("R32768_L24", 32768, 24)]
 CASES = [(1, (360, 720, 8), 1e-3), (1, (360, 720, 8), 1e-2), (2, (512, 512, 8), 1e-3), (2, (512, 512, 8), 1e-2)]
 
 WORKER = r"""
@@ -51,15 +51,14 @@ def main():
             out = subprocess.run([sys.executable, "-c", WORKER, ROOT, so, json.dumps(CASES)], capture_output=True,
                                  text=True, check=True).stdout
             res[name] = json.loads(out.strip().splitlines()[-1])
-    base = res[VARIANTS[0][0]]
-    for i, row in enumerate(base):
-        alt = res[VARIANTS[1][0]][i]
-        print("workload %d %s eb %g: CR %.3f (R 512, 12 bits) vs %.3f (R 32768, 24 bits), %+.2f%%; "
-              "with the stage %.3f vs %.3f; raw words %d vs %d" %
-              (row["workload"], "x".join(map(str, row["shape"])), row["eb"], row["CR"], alt["CR"],
-               100 * (alt["CR"] / row["CR"] - 1), row["CR_stage"], alt["CR_stage"], row["raw_words"],
-               alt["raw_words"]))
-
+    for i, row in enumerate(res[VARIANTS[0][0]]):
+        cells = []
+        for name, _, _ in VARIANTS:
+            alt = res[name][i]
+            cells.append("%s CR %.3f (%+.2f%%), with the stage %.3f, raw words %d" %
+                         (name, alt["CR"], 100 * (alt["CR"] / row["CR"] - 1), alt["CR_stage"], alt["raw_words"]))
+        print("workload %d %s eb %g: %s" % (row["workload"], "x".join(map(str, row["shape"])), row["eb"],
+                                            "; ".join(cells)))
 
 if __name__ == "__main__":
     main()
