@@ -534,23 +534,33 @@ static_assert(make_pairs().a[0] >= 0 && make_dyn_pairs().a[13] >= 0 && make_dyn_
 // for N = 0 the estimate ends at -1 and the final max gives the 0 of
 // Alg. 2.  The one-step correction of the fp64 reciprocal estimate is a
 // select, not a branch.
-__device__ __forceinline__ void lower_to(int& e, double N, double D) {
+__device__ __forceinline__ void lower_to(int& e, double& ed, double N, double D) {
+  if (N > ed * D) return;  // integers: N - 1 >= e D
   const double n1 = N - 1.0;
-  if (n1 >= (double)e * D) return;
   int q = (int)(n1 * __builtin_amdgcn_rcp(D));
   const double r = n1 - (double)q * D;
   q += (r >= D ? 1 : 0) - (r < 0.0 ? 1 : 0);
   e = max(q, 0);
+  ed = (double)e;
 }
 
 __device__ __forceinline__ double det2d(double2 a, double2 b) { return fma(a.x, b.y, -(a.y * b.x)); }
 
 // What the raise of Alg. 2 needs of the vertex itself besides its value:
 // |component| - 1.
+// The sign tests read the high words of the fp64 values: an integer-valued
+// double that is not -0 is positive, zero or negative exactly as its high
+// word is as an int32.  mx (my) is -1 when the vertex's u (v) is negative,
+// else 0; a neighbour component shares the vertex's strict sign when its
+// high word xor mx is positive (for a zero vertex component the raise term
+// is -1 and the test does not matter).
 struct MeSign {
-  int rx, ry;
+  int rx, ry, mx, my;
 };
-__device__ __forceinline__ MeSign me_sign(double2 me) { return MeSign{(int)fabs(me.x) - 1, (int)fabs(me.y) - 1}; }
+__device__ __forceinline__ int hiw(double v) { return __double2hiint(v); }
+__device__ __forceinline__ MeSign me_sign(double2 me) {
+  return MeSign{(int)fabs(me.x) - 1, (int)fabs(me.y) - 1, hiw(me.x) >> 31, hiw(me.y) >> 31};
+}
 
 // Running minimum with the Alg. 2 bound of the face (me, n0, n1).  A
 // component's raise applies when n0 and n1 share the strict sign of the
@@ -564,14 +574,15 @@ __device__ __forceinline__ void face_update(int& xi, double2 me, const MeSign& m
     xi = 0;
     return;
   }
-  const bool sx = fmin(n0.x * me.x, n1.x * me.x) > 0.0;
-  const bool sy = fmin(n0.y * me.y, n1.y * me.y) > 0.0;
+  const bool sx = min(hiw(n0.x) ^ ms.mx, hiw(n1.x) ^ ms.mx) > 0;
+  const bool sy = min(hiw(n0.y) ^ ms.my, hiw(n1.y) ^ ms.my) > 0;
   const int relax = max(sx ? ms.rx : -1, sy ? ms.ry : -1);
   if (relax >= xi) return;
   int e = xi;
-  lower_to(e, fabs(M), fabs(n1.x - n0.x) + fabs(n0.y - n1.y));
-  lower_to(e, fabs(d1), a1);
-  lower_to(e, fabs(d0), a0);
+  double ed = (double)xi;
+  lower_to(e, ed, fabs(M), fabs(n1.x - n0.x) + fabs(n0.y - n1.y));
+  lower_to(e, ed, fabs(d1), a1);
+  lower_to(e, ed, fabs(d0), a0);
   xi = min(xi, max(e, relax));
 }
 
@@ -583,8 +594,8 @@ struct NbrQ {
   double d, a;
   bool sx, sy;
 };
-__device__ __forceinline__ NbrQ nbr_q(double2 n, double2 me) {
-  return NbrQ{n, det2d(me, n), fabs(n.x) + fabs(n.y), n.x * me.x > 0.0, n.y * me.y > 0.0};
+__device__ __forceinline__ NbrQ nbr_q(double2 n, double2 me, const MeSign& ms) {
+  return NbrQ{n, det2d(me, n), fabs(n.x) + fabs(n.y), (hiw(n.x) ^ ms.mx) > 0, (hiw(n.y) ^ ms.my) > 0};
 }
 
 // face_update for neighbours given with their per-neighbour terms
@@ -597,9 +608,10 @@ __device__ __forceinline__ void face_update_q(int& xi, const MeSign& ms, const N
   const int relax = max(A.sx && B.sx ? ms.rx : -1, A.sy && B.sy ? ms.ry : -1);
   if (relax >= xi) return;
   int e = xi;
-  lower_to(e, fabs(M), fabs(B.n.x - A.n.x) + fabs(A.n.y - B.n.y));
-  lower_to(e, fabs(B.d), B.a);
-  lower_to(e, fabs(A.d), A.a);
+  double ed = (double)xi;
+  lower_to(e, ed, fabs(M), fabs(B.n.x - A.n.x) + fabs(A.n.y - B.n.y));
+  lower_to(e, ed, fabs(B.d), B.a);
+  lower_to(e, ed, fabs(A.d), A.a);
   xi = min(xi, max(e, relax));
 }
 
@@ -716,15 +728,15 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
           ok |= (xx >= 0 && xx < W && yy >= 0 && yy < H && tt >= 0 && tt < T) ? (1u << j) : 0u;
         }
         auto nv = [&](int j) { return *vslot(S, 1 + NBR.dt[j], ly + 1 + NBR.dy[j], lx + 1 + NBR.dx[j]); };
-        NbrQ prev = nbr_q(nv(STRAIL.a[0]), me);
+        NbrQ prev = nbr_q(nv(STRAIL.a[0]), me, ms);
 #pragma unroll
         for (int k = 0; k < 22; k++) {
           const int a = STRAIL.a[k], b = STRAIL.b[k];
           // the shared neighbour's value is read again from LDS (no VALU
           // work); its derived terms carry over in registers
-          NbrQ A = (k > 0 && a == STRAIL.b[k > 0 ? k - 1 : 0]) ? prev : nbr_q(nv(a), me);
+          NbrQ A = (k > 0 && a == STRAIL.b[k > 0 ? k - 1 : 0]) ? prev : nbr_q(nv(a), me, ms);
           A.n = nv(a);
-          const NbrQ B = nbr_q(nv(b), me);
+          const NbrQ B = nbr_q(nv(b), me, ms);
           prev = B;
           if (((ok >> a) & (ok >> b) & 1u) == 0) continue;
           face_update_q(xi, ms, A, B);
@@ -808,7 +820,7 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
     int e = eps;
     if (active) {
       e = xs >= 0 ? xs : eps;
-      if (xs >= 0 && (unsigned)(lx - flo) < (unsigned)(fhi - flo)) face_update(e, me, MeSign{msw.x, msw.y}, pa, pb);
+      if (xs >= 0 && (unsigned)(lx - flo) < (unsigned)(fhi - flo)) face_update(e, me, MeSign{msw.x, msw.y, hiw(me.x) >> 31, hiw(me.y) >> 31}, pa, pb);
     }
     e = row16_min(e);
     if (active && j < 2) {

@@ -27,6 +27,9 @@ workload 2  2048x2048x32 turbulence-like: streamfunction with E(k) ~ k^-5/3
 workload 3  256 fields: side round(exp U(ln 64, ln 1024)), T uniform in 8..64,
             4..32 vortices as workload 0.
 workload 4  1024x1024x128 as workload 2 with another seed.
+workload 5  1024x1024x64 as workload 2 (another seed, 16 vortices) with the
+            time step raised to CFL 6: the fastest point moves 6 cells per
+            step, so backtraces of 1, 2 and 4 cells per step differ.
 """
 import math
 
@@ -195,8 +198,9 @@ def wind_field(H=720, W=1440, T=64, seed=1000, device="cpu", dtype=torch.float64
 
 
 def turbulence_field(H=2048, W=2048, T=32, seed=2000, n_vortices=64, device="cpu",
-                     dtype=torch.float64):
-    """Workload 2/4 recipe (self-advected k^-5/3 turbulence plus vortices)."""
+                     dtype=torch.float64, cfl=0.5):
+    """Workload 2/4/5 recipe (self-advected k^-5/3 turbulence plus vortices);
+    the time step moves the fastest point cfl cells per step."""
     gen = torch.Generator().manual_seed(seed)
     kmax = min(512.0, min(H, W) / 2.0)
     ph = _spectral_psi(H, W, -7.0 / 3.0, 4.0, kmax, gen, device)
@@ -209,7 +213,7 @@ def turbulence_field(H=2048, W=2048, T=32, seed=2000, n_vortices=64, device="cpu
                            gamma_scale=1.0, dtype=dtype)
     umax = float(torch.max(torch.abs(u)).item()) + 1e-30
     vmax = float(torch.max(torch.abs(v)).item()) + 1e-30
-    dt = 0.5 / max(umax, vmax)
+    dt = cfl / max(umax, vmax)
     out = torch.empty((2, T, H, W), dtype=torch.float32, device=device)
     for t in range(T):
         out[0, t] = u.to(torch.float32) + vort[0, t]
@@ -217,7 +221,7 @@ def turbulence_field(H=2048, W=2048, T=32, seed=2000, n_vortices=64, device="cpu
         if t + 1 < T:
             u, v = _advect(u, v, u, v, dt, periodic_x=True)
             u, v = _project(u, v)
-    return out, dict(dt_dx=dt, seed=seed)
+    return out, dict(dt_dx=dt, seed=seed, cfl=cfl)
 
 
 WORKLOADS = {
@@ -225,6 +229,7 @@ WORKLOADS = {
     1: dict(shape=(720, 1440, 64), eb=1e-3, predictor=2, mode_bt=1),
     2: dict(shape=(2048, 2048, 32), eb=1e-3, predictor=2, mode_bt=1),
     4: dict(shape=(1024, 1024, 128), eb=1e-3, predictor=3, mode_bt=4),
+    5: dict(shape=(1024, 1024, 64), eb=1e-3, predictor=3, mode_bt=4),
 }
 
 
@@ -244,6 +249,9 @@ def workload(cfg, index=0, device="cpu", shape=None):
         H, W, T = shape or WORKLOADS[cfg]["shape"]
         nv = 64 if min(H, W) >= 256 else 8
         f, m = turbulence_field(H, W, T, seed, n_vortices=nv, device=device)
+    elif cfg == 5:
+        H, W, T = shape or WORKLOADS[cfg]["shape"]
+        f, m = turbulence_field(H, W, T, seed, n_vortices=16, device=device, cfl=6.0)
     else:
         raise ValueError("unknown workload %r" % cfg)
     m = dict(m)
