@@ -267,8 +267,8 @@ cpt_status cpt_verify(const float* a, const float* b, int H, int W, int T, int k
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the check
  * of cpt_verify, same arguments and results bit for bit, without any device
- * or pinned allocation.  Its intermediate arrays (fixed-point values, edge
- * signs, both face masks, error partials: about 17.1 bytes per vertex) live
+ * or pinned allocation.  Its intermediate arrays (both face masks and the
+ * error partials: about 8.06 bytes per vertex) live
  * in one fixed array of CPT_VERIFY_NOALLOC_SCRATCH_BYTES that the library
  * holds on every GPU it runs on from load until the process ends, so fields
  * of more than CPT_VERIFY_NOALLOC_MAX_VERTICES vertices (H W T) are refused
@@ -277,7 +277,7 @@ cpt_status cpt_verify(const float* a, const float* b, int H, int W, int T, int k
  * call at a time per process (a lock held until the call has synchronised
  * its stream).  Synchronises `stream` twice. */
 #define CPT_VERIFY_NOALLOC_SCRATCH_BYTES (128u << 20)
-#define CPT_VERIFY_NOALLOC_MAX_VERTICES 7866176u
+#define CPT_VERIFY_NOALLOC_MAX_VERTICES 16647040u
 cpt_status cpt_verify_noalloc(const float* a, const float* b, int H, int W, int T, int k, cpt_verify_result* res,
                               void* stream);
 

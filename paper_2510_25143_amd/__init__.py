@@ -336,7 +336,7 @@ def tracks(field, k):
     return bad.value, nt.value
 
 
-VERIFY_NOALLOC_MAX_VERTICES = 7866176
+VERIFY_NOALLOC_MAX_VERTICES = 16647040
 
 
 def verify_noalloc(a, b, k):

@@ -108,8 +108,6 @@ Arena* arena_for_device(cpt_status* st) {
 
 // Scratch layout for one field of N vertices.
 struct Bufs {  // scratch of the extraction, verification and parameter calls
-  int2* cur;
-  uint8_t* edges;
   uint32_t *masks, *masks2, *nonll, *qofs, *part, *tot;
   int* range;
   unsigned long long* fc;
@@ -125,7 +123,7 @@ cpt_status carve(Arena& A, size_t N, Bufs& b) {
     size_t bytes;
   };
   std::vector<Item> items = {
-      {(void**)&b.cur, 8 * N},        {(void**)&b.edges, N},          {(void**)&b.masks, 4 * N},
+      {(void**)&b.masks, 4 * N},
       {(void**)&b.masks2, 4 * N},     {(void**)&b.nonll, 4 * N},      {(void**)&b.qofs, 4 * N},
       {(void**)&b.part, 4 * (scan_partials_size(N) + 16)},            {(void**)&b.tot, 64},
       {(void**)&b.range, 64},         {(void**)&b.fc, 16},            {(void**)&b.cpart, 16 * (compare_partials(N) + 1)},
@@ -1276,7 +1274,7 @@ unsigned char* g_na_ptr[NA_MAX_DEVICES] = {nullptr};
 // reduced error sums (4 x 8 B), fixed-point values, edge signs, both face
 // masks and the per-workgroup error partials.
 struct NaLayout {
-  size_t range, res, cur, edges, masks, masks2, part, end;
+  size_t range, res, masks, masks2, part, end;
 };
 constexpr size_t na_up(size_t b) { return (b + 255) & ~(size_t)255; }
 constexpr NaLayout na_layout(size_t N) {
@@ -1284,9 +1282,7 @@ constexpr NaLayout na_layout(size_t N) {
   NaLayout L{};
   L.range = 0;
   L.res = 256;
-  L.cur = 512;
-  L.edges = L.cur + up(8 * N);
-  L.masks = L.edges + up(N);
+  L.masks = 512;
   L.masks2 = L.masks + up(4 * N);
   L.part = L.masks2 + up(4 * N);
   L.end = L.part + up(16 * ((N + 255) / 256));  // compare_partials(N) workgroup partials
@@ -1673,8 +1669,7 @@ cpt_status cpt_extract_trajectories(const float* field, int H, int W, int T, int
   st = field_range(field, 2 * N, b, A, s, &r);
   if (st) return st;
   if (std::ldexp(r.ma, k) >= 16777216.0) return fail(CPT_EINVAL, "max|x| 2^k must be below 2^24");
-  launch_convert(field, N, k, b.cur, s);
-  launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
+  launch_maskpass(field, H, W, T, k, b.masks, s);
   launch_count_faces(b.masks, N, b.nonll, s);
   launch_scan(b.nonll, N, b.qofs, b.part, b.tot, s);
   HIPCHK(hipMemcpyAsync(A.host, b.tot, 4, hipMemcpyDeviceToHost, s));
@@ -1709,8 +1704,7 @@ cpt_status cpt_tracks(const float* field, int H, int W, int T, int k, uint64_t* 
     st = field_range(field, 2 * N, b, A, s, &r);
     if (st) return st;
     if (std::ldexp(r.ma, k) >= 16777216.0) return fail(CPT_EINVAL, "max|x| 2^k must be below 2^24");
-    launch_convert(field, N, k, b.cur, s);
-    launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
+    launch_maskpass(field, H, W, T, k, b.masks, s);
     launch_count_faces(b.masks, N, b.nonll, s);
     launch_scan(b.nonll, N, b.qofs, b.part, b.tot, s);
     HIPCHK(hipMemcpyAsync(A.host, b.tot, 4, hipMemcpyDeviceToHost, s));
@@ -1729,8 +1723,7 @@ cpt_status cpt_tracks(const float* field, int H, int W, int T, int k, uint64_t* 
     (void)A.off(16);
     int* parent = (int*)(A.base + op);
     unsigned long long* ctr = (unsigned long long*)(A.base + ot);
-    launch_convert(field, N, k, b.cur, s);
-    launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
+    launch_maskpass(field, H, W, T, k, b.masks, s);
     launch_count_faces(b.masks, N, b.nonll, s);
     launch_scan(b.nonll, N, b.qofs, b.part, b.tot, s);
     launch_tracks(b.masks, b.qofs, H, W, T, (long long)M, parent, ctr, s);
@@ -1766,10 +1759,8 @@ cpt_status cpt_verify(const float* a, const float* bf, int H, int W, int T, int 
   st = field_range(bf, 2 * N, b, A, s, &rb);
   if (st) return st;
   if (std::ldexp(std::max(ra.ma, rb.ma), k) >= 16777216.0) return fail(CPT_EINVAL, "max|x| 2^k must be below 2^24");
-  launch_convert(a, N, k, b.cur, s);
-  launch_masks(b.cur, H, W, T, b.edges, b.masks, s);
-  launch_convert(bf, N, k, b.cur, s);
-  launch_masks(b.cur, H, W, T, b.edges, b.masks2, s);
+  launch_maskpass(a, H, W, T, k, b.masks, s);
+  launch_maskpass(bf, H, W, T, k, b.masks2, s);
   launch_compare(b.masks, b.masks2, a, bf, N, b.fc, b.cpart, s);
   size_t np = compare_partials(N);
   std::vector<double> part(2 * np);
@@ -1811,8 +1802,6 @@ cpt_status cpt_verify_noalloc(const float* a, const float* bf, int H, int W, int
     int* rb = ra + 4;
     unsigned long long* fc = (unsigned long long*)(base + L.res);
     double* sums = (double*)(base + L.res + 16);
-    int2* cur = (int2*)(base + L.cur);
-    uint8_t* edges = base + L.edges;
     uint32_t* ma = (uint32_t*)(base + L.masks);
     uint32_t* mb = (uint32_t*)(base + L.masks2);
     double* part = (double*)(base + L.part);
@@ -1830,10 +1819,8 @@ cpt_status cpt_verify_noalloc(const float* a, const float* bf, int H, int W, int
       return fail(CPT_EINVAL, "max|x| 2^k must be below 2^24");
     // crossed faces of both fields, then the comparison (counters cleared by
     // a kernel inside launch_compare)
-    launch_convert(a, N, k, cur, s);
-    launch_masks(cur, H, W, T, edges, ma, s);
-    launch_convert(bf, N, k, cur, s);
-    launch_masks(cur, H, W, T, edges, mb, s);
+    launch_maskpass(a, H, W, T, k, ma, s);
+    launch_maskpass(bf, H, W, T, k, mb, s);
     launch_compare(ma, mb, a, bf, N, fc, part, s);
     k_na_sum_partials<<<1, 64, 0, s>>>(part, compare_partials(N), sums);
     uint64_t hres[4];

@@ -72,98 +72,6 @@ __global__ __launch_bounds__(256) void k_range(const float* __restrict__ x, size
   }
 }
 
-// ------------------------------------------------------------- conversion
-__global__ __launch_bounds__(256) void k_convert(const float* __restrict__ f, size_t N, int k,
-                                                 int2* __restrict__ cur) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  cur[i] = make_int2(to_fixed(f[i], k), to_fixed(f[N + i], k));
-}
-
-// ------------------------------------------------------------- edge signs
-// bit 0..2: spatial edges to +x, +y, +x+y at t; bit 3: time edge; bits 4..6:
-// diagonals to the +x, +y, +x+y vertices at t+1.  Bit set = positive sign.
-__device__ __forceinline__ uint8_t edge_bits(const int2* __restrict__ cur, int H, int W, int T, size_t i) {
-  const size_t HW = (size_t)H * W;
-  int t = (int)(i / HW);
-  int r = (int)(i - (size_t)t * HW);
-  int y = r / W, x = r - y * W;
-  int2 a = cur[i];
-  bool px = x + 1 < W, py = y + 1 < H, pt = t + 1 < T;
-  uint32_t e = 0;
-  if (px) e |= (sos_sign(a.x, a.y, cur[i + 1].x, cur[i + 1].y) > 0) << 0;
-  if (py) e |= (sos_sign(a.x, a.y, cur[i + W].x, cur[i + W].y) > 0) << 1;
-  if (px && py) e |= (sos_sign(a.x, a.y, cur[i + W + 1].x, cur[i + W + 1].y) > 0) << 2;
-  if (pt) {
-    const int2* n = cur + i + HW;
-    e |= (sos_sign(a.x, a.y, n[0].x, n[0].y) > 0) << 3;
-    if (px) e |= (sos_sign(a.x, a.y, n[1].x, n[1].y) > 0) << 4;
-    if (py) e |= (sos_sign(a.x, a.y, n[W].x, n[W].y) > 0) << 5;
-    if (px && py) e |= (sos_sign(a.x, a.y, n[W + 1].x, n[W + 1].y) > 0) << 6;
-  }
-  return (uint8_t)e;
-}
-
-__global__ __launch_bounds__(256) void k_edges(const int2* __restrict__ cur, int H, int W, int T,
-                                               uint8_t* __restrict__ edges) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)H * W * T) return;
-  edges[i] = edge_bits(cur, H, W, T, i);
-}
-
-// crossed iff sigma(A,B) == sigma(B,C) == -sigma(A,C) for A < B < C
-__device__ __forceinline__ uint32_t face_bits(uint32_t sab, uint32_t sbc, uint32_t sac, int f) {
-  uint32_t crossed = (sab == sbc) && (sac != sbc);
-  return crossed ? ((1u << f) | (sab << (12 + f))) : 0u;
-}
-
-__device__ __forceinline__ uint32_t face_mask(const uint8_t* __restrict__ edges, int H, int W, int T, size_t i) {
-  const size_t HW = (size_t)H * W;
-  int t = (int)(i / HW);
-  int r = (int)(i - (size_t)t * HW);
-  int y = r / W, x = r - y * W;
-  bool px = x + 1 < W, py = y + 1 < H, pt = t + 1 < T;
-  uint32_t m = 0;
-  if (!(px || py)) return 0;
-  uint32_t ea = edges[i];
-  uint32_t eb = px ? edges[i + 1] : 0;
-  uint32_t ec = py ? edges[i + W] : 0;
-  uint32_t ed = (px && py) ? edges[i + W + 1] : 0;
-  uint32_t ea1 = pt ? edges[i + HW] : 0;
-  uint32_t eb1 = (pt && px) ? edges[i + HW + 1] : 0;
-  uint32_t ec1 = (pt && py) ? edges[i + HW + W] : 0;
-#define B(e, k) (((e) >> (k)) & 1u)
-  if (px && py) {
-    m |= face_bits(B(ea, 0), B(eb, 1), B(ea, 2), 0);
-    m |= face_bits(B(ea, 1), B(ec, 0), B(ea, 2), 1);
-    if (pt) {
-      m |= face_bits(B(ea, 0), B(eb, 5), B(ea, 6), 2);
-      m |= face_bits(B(ea, 4), B(eb1, 1), B(ea, 6), 3);
-      m |= face_bits(B(ea, 1), B(ec, 4), B(ea, 6), 4);
-      m |= face_bits(B(ea, 5), B(ec1, 0), B(ea, 6), 5);
-      m |= face_bits(B(ea, 2), B(ed, 3), B(ea, 6), 10);
-      m |= face_bits(B(ea, 3), B(ea1, 2), B(ea, 6), 11);
-    }
-  }
-  if (px && pt) {
-    m |= face_bits(B(ea, 0), B(eb, 3), B(ea, 4), 6);
-    m |= face_bits(B(ea, 3), B(ea1, 0), B(ea, 4), 7);
-  }
-  if (py && pt) {
-    m |= face_bits(B(ea, 1), B(ec, 3), B(ea, 5), 8);
-    m |= face_bits(B(ea, 3), B(ea1, 1), B(ea, 5), 9);
-  }
-#undef B
-  return m;
-}
-
-__global__ __launch_bounds__(256) void k_faces(const uint8_t* __restrict__ edges, int H, int W, int T,
-                                               uint32_t* __restrict__ masks) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)H * W * T) return;
-  masks[i] = face_mask(edges, H, W, T, i);
-}
-
 // --------------------------------------------------------- lossless flags
 // INC[o]: face types whose vertex set contains offset o = (ox,oy,ot) from the
 // owner; a vertex is lossless when any face through it is crossed.
@@ -183,30 +91,6 @@ constexpr IncTable make_inc() {
   return I;
 }
 __constant__ IncTable c_inc = make_inc();
-
-__device__ __forceinline__ uint8_t lossless_flag(const uint32_t* __restrict__ masks, int H, int W, size_t i,
-                                                 size_t HW) {
-  int t = (int)(i / HW);
-  int r = (int)(i - (size_t)t * HW);
-  int y = r / W, x = r - y * W;
-  uint32_t any = 0;
-#pragma unroll
-  for (int o = 0; o < 8; o++) {
-    int ox = o & 1, oy = (o >> 1) & 1, ot = (o >> 2) & 1;
-    if (x - ox < 0 || y - oy < 0 || t - ot < 0) continue;
-    any |= masks[i - ox - (size_t)oy * W - (size_t)ot * HW] & c_inc.m[o];
-  }
-  (void)H;
-  return any ? 1 : 0;
-}
-
-__global__ __launch_bounds__(256) void k_flags(const uint32_t* __restrict__ masks, int H, int W, int T,
-                                               uint8_t* __restrict__ flags) {
-  size_t HW = (size_t)H * W;
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= HW * T) return;
-  flags[i] = lossless_flag(masks, H, W, i, HW);
-}
 
 // ------------------------------------------------------- batched field pass
 // per-field range slots: min key, max key, max |x| bits, non-finite seen.
@@ -467,24 +351,18 @@ __device__ __forceinline__ uint32_t fp_mask(const uint8_t* E0, const uint8_t* E1
   return crossed | ((X & crossed) << 12);
 }
 
-// fpre[f]: tiles of the fields before f
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fieldpass_b(const FieldDesc* __restrict__ D,
-                                                     const long long* __restrict__ fpre, int n,
-                                                     int2* __restrict__ cur_all, uint8_t* __restrict__ flags_all) {
-  __shared__ FieldPassSmem S;
-  __shared__ uint32_t xz[128];  // the X and Z words of the face tests per edge byte of the owner
-  const int f = find_field(fpre, n, blockIdx.x);
-  const FieldDesc& d = D[f];
-  if (d.status) return;
-  const int H = d.H, W = d.W, T = d.T, k = d.p.k;
-  const int ntx = (W + FP_TW - 1) / FP_TW;
-  const int tile = (int)((long long)blockIdx.x - fpre[f]);
-  const int x0 = (tile % ntx) * FP_TW, y0 = (tile / ntx) * FP_TH;
-  const size_t HW = (size_t)H * W, N = (size_t)d.N;
-  const float* fu = d.field;
-  const float* fv = d.field + N;
-  int2* cur = cur_all + d.voff;
-  uint8_t* flags = flags_all + d.voff;
+// One 32x16 tile at (x0, y0) of a field marching through its frames.  With
+// MASKS false it writes the tile's fixed-point values (cur) and lossless
+// flags; with MASKS true only its face masks (twelve crossed-face bits and
+// their signs per vertex, as the extraction numbers them).
+template <bool MASKS>
+__device__ __forceinline__ void fieldpass_tile(FieldPassSmem& S, uint32_t* xz, const float* __restrict__ field,
+                                               int H, int W, int T, int k, int x0, int y0,
+                                               int2* __restrict__ cur, uint8_t* __restrict__ flags,
+                                               uint32_t* __restrict__ masks) {
+  const size_t HW = (size_t)H * W, N = HW * (size_t)T;
+  const float* fu = field;
+  const float* fv = field + N;
   const int tid = threadIdx.x;
 
   // Per-thread offsets of halo values j = tid + 256 q (flat [FP_CH][FP_CW]
@@ -527,7 +405,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   };
   auto store = [&](int t) {
     int2* sc = &S.cur[t & 1][0][0];
-    int2* pc = cur + (size_t)t * HW;
+    int2* pc = MASKS ? nullptr : cur + (size_t)t * HW;
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       const int j = tid + 256 * q;
@@ -535,7 +413,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
       const bool in = t < T && hoff[q] >= 0;
       const int2 v = in ? make_int2(to_fixed(ru[q], k), to_fixed(rv[q], k)) : make_int2(0, 0);
       sc[j] = v;
-      if (in && (tv >> q & 1u)) pc[hoff[q]] = v;
+      if (!MASKS && in && (tv >> q & 1u)) pc[hoff[q]] = v;
     }
   };
   auto edges_of = [&](int t) {  // edges of frame t (t + 1 < T uses frame t + 1)
@@ -584,21 +462,58 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
       }
     }
     __syncthreads();
-    // lossless flags of frame s: any crossed face through the vertex
-    uint8_t* pf = flags + (size_t)s * HW;
-    for (int j = tid; j < FP_TW * FP_TH; j += 256) {
-      const int iy = j / FP_TW, ix = j - iy * FP_TW;
-      const int x = x0 + ix, y = y0 + iy;
-      if (x >= W || y >= H) continue;
-      uint32_t any = 0;
-#pragma unroll
-      for (int o = 0; o < 8; o++) {
-        const int ox = o & 1, oy = (o >> 1) & 1, ot = (o >> 2) & 1;
-        any |= S.msk[(s - ot) & 1][iy + 1 - oy][ix + 1 - ox] & c_inc.m[o];
+    if constexpr (MASKS) {
+      // the face masks of the tile's vertices of frame s
+      uint32_t* pm = masks + (size_t)s * HW;
+      for (int j = tid; j < FP_TW * FP_TH; j += 256) {
+        const int iy = j / FP_TW, ix = j - iy * FP_TW;
+        const int x = x0 + ix, y = y0 + iy;
+        if (x < W && y < H) pm[(size_t)y * W + x] = S.msk[s & 1][iy + 1][ix + 1];
       }
-      pf[y * W + x] = any ? 1 : 0;
+    } else {
+      // lossless flags of frame s: any crossed face through the vertex
+      uint8_t* pf = flags + (size_t)s * HW;
+      for (int j = tid; j < FP_TW * FP_TH; j += 256) {
+        const int iy = j / FP_TW, ix = j - iy * FP_TW;
+        const int x = x0 + ix, y = y0 + iy;
+        if (x >= W || y >= H) continue;
+        uint32_t any = 0;
+#pragma unroll
+        for (int o = 0; o < 8; o++) {
+          const int ox = o & 1, oy = (o >> 1) & 1, ot = (o >> 2) & 1;
+          any |= S.msk[(s - ot) & 1][iy + 1 - oy][ix + 1 - ox] & c_inc.m[o];
+        }
+        pf[y * W + x] = any ? 1 : 0;
+      }
     }
   }
+}
+
+
+// fpre[f]: tiles of the fields before f
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fieldpass_b(const FieldDesc* __restrict__ D,
+                                                     const long long* __restrict__ fpre, int n,
+                                                     int2* __restrict__ cur_all, uint8_t* __restrict__ flags_all) {
+  __shared__ FieldPassSmem S;
+  __shared__ uint32_t xz[128];  // the X and Z words of the face tests per edge byte of the owner
+  const int f = find_field(fpre, n, blockIdx.x);
+  const FieldDesc& d = D[f];
+  if (d.status) return;
+  const int ntx = (d.W + FP_TW - 1) / FP_TW;
+  const int tile = (int)((long long)blockIdx.x - fpre[f]);
+  fieldpass_tile<false>(S, xz, d.field, d.H, d.W, d.T, d.p.k, (tile % ntx) * FP_TW, (tile / ntx) * FP_TH,
+                        cur_all + d.voff, flags_all + d.voff, nullptr);
+}
+
+// Face masks of one field on the grid 2^k, one workgroup per 32x16 tile.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_maskpass(
+    const float* __restrict__ field, int H, int W, int T, int k, uint32_t* __restrict__ masks) {
+  __shared__ FieldPassSmem S;
+  __shared__ uint32_t xz[128];
+  const int ntx = (W + FP_TW - 1) / FP_TW;
+  const int tile = blockIdx.x;
+  fieldpass_tile<true>(S, xz, field, H, W, T, k, (tile % ntx) * FP_TW, (tile / ntx) * FP_TH, nullptr, nullptr,
+                       masks);
 }
 
 // ------------------------------------------------------------- compaction
@@ -788,17 +703,9 @@ void launch_range(const float* x, size_t n, int* r, hipStream_t s) {
   if (g == 0) g = 1;
   k_range<<<g, 256, 0, s>>>(x, n, r);
 }
-void launch_convert(const float* f, size_t N, int k, int2* cur, hipStream_t s) {
-  k_convert<<<nblk(N), 256, 0, s>>>(f, N, k, cur);
-}
-void launch_masks(const int2* cur, int H, int W, int T, uint8_t* edges, uint32_t* masks, hipStream_t s) {
-  size_t N = (size_t)H * W * T;
-  k_edges<<<nblk(N), 256, 0, s>>>(cur, H, W, T, edges);
-  k_faces<<<nblk(N), 256, 0, s>>>(edges, H, W, T, masks);
-}
-void launch_flags(const uint32_t* masks, int H, int W, int T, uint8_t* flags, hipStream_t s) {
-  size_t N = (size_t)H * W * T;
-  k_flags<<<nblk(N), 256, 0, s>>>(masks, H, W, T, flags);
+void launch_maskpass(const float* f, int H, int W, int T, int k, uint32_t* masks, hipStream_t s) {
+  const long long tiles = (long long)((W + FP_TW - 1) / FP_TW) * ((H + FP_TH - 1) / FP_TH);
+  if (tiles > 0 && T > 0) k_maskpass<<<(unsigned)tiles, 256, 0, s>>>(f, H, W, T, k, masks);
 }
 size_t scan_partials_size(size_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 void launch_scan(const uint32_t* in, size_t n, uint32_t* out, uint32_t* part, uint32_t* total, hipStream_t s) {

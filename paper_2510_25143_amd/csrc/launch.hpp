@@ -20,9 +20,8 @@ struct FieldParams {
 
 // k_field.hip
 void launch_range(const float* x, size_t n, int* r, hipStream_t s);
-void launch_convert(const float* f, size_t N, int k, int2* cur, hipStream_t s);
-void launch_masks(const int2* cur, int H, int W, int T, uint8_t* edges, uint32_t* masks, hipStream_t s);
-void launch_flags(const uint32_t* masks, int H, int W, int T, uint8_t* flags, hipStream_t s);
+// the face masks of a float field on the grid 2^k in one time-marching pass
+void launch_maskpass(const float* f, int H, int W, int T, int k, uint32_t* masks, hipStream_t s);
 size_t scan_partials_size(size_t n);
 void launch_scan(const uint32_t* in, size_t n, uint32_t* out, uint32_t* part, uint32_t* total, hipStream_t s);
 void launch_count_faces(const uint32_t* masks, size_t N, uint32_t* cnt, hipStream_t s);
