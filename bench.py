@@ -226,11 +226,11 @@ def bench_batch(args, cpt, torch, synthfields):
     decs = [torch.empty_like(f) for f in fields]
     sched, tune_ms = args.schedule, None
     if sched == "auto":
-        (sched, graph), tune_ms = cpt.autotune_batch(fields, eb, reps=1, outs=outs)
+        (sched, graph), tune_ms = cpt.autotune_batch(fields, eb, reps=1, outs=outs, backend=args.backend)
         log("autotune: %s graph=%s (ms: %s)" % (sched, graph, ", ".join("%.2f" % m for m in tune_ms)))
 
     def comp():
-        st, status = cpt.compress_batch(fields, eb, schedule=sched, outs=outs)
+        st, status = cpt.compress_batch(fields, eb, schedule=sched, outs=outs, backend=args.backend)
         return st
 
     log("warmup x%d" % max(args.warmup, 1))
@@ -276,7 +276,7 @@ def bench_batch(args, cpt, torch, synthfields):
     log("one cpt_compress and one cpt_decompress call per field")
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     e0.record()
-    single = [cpt.compress(f, eb, out=o) for f, o in zip(fields, outs)]
+    single = [cpt.compress(f, eb, out=o, backend=args.backend) for f, o in zip(fields, outs)]
     e1.record()
     for st_, d in zip(single, decs):
         cpt.decompress(st_, out=d)
@@ -291,6 +291,7 @@ def bench_batch(args, cpt, torch, synthfields):
         "scaling": "weak", "vs_baseline": None, "dtype": "i32+f64(exact)", "data": "synthetic",
         "config": {"workload": WORKLOADS["batch"]["name"], "fields": len(fields), "vertices": nvert,
                    "raw_bytes": raw, "eb_rel": eb, "predictor": 2, "mode_bt": 1, "schedule": sched,
+                   "lossless_stage": "zero-byte elision after Huffman" if args.backend else "none",
                    "tune_ms": tune_ms, "CR": round(raw / clen, 4), "stream_bytes": clen,
                    "max_err_over_eb": round(worst, 6),
                    "compress_ms": round(tc, 3), "decompress_ms": round(td, 3),
@@ -343,7 +344,7 @@ def bench_selector(args, cpt, torch, synthfields):
         k, eb_abs, _ = cpt.field_params(f, eb)
         res = {}
         for name, kw in (("exhaustive", dict(predictor=3)), ("learned", dict(predictor=4, selector_w=wb))):
-            opts = dict(mode_bt=bt, dt_dx=dt, dt_dy=dt, schedule="launch", outs=[out], **kw)
+            opts = dict(mode_bt=bt, dt_dx=dt, dt_dy=dt, schedule="launch", outs=[out], backend=args.backend, **kw)
             for _ in range(max(args.warmup, 1)):
                 (st,), _ = cpt.compress_batch([f], eb, **opts)
                 cpt.decompress(st, out=dec)
@@ -392,6 +393,7 @@ def bench_selector(args, cpt, torch, synthfields):
         "vs_baseline": None, "dtype": "i32+f64(exact); selector bf16 weights, fp32 accumulation",
         "data": "synthetic",
         "config": {"workload": WORKLOADS["selector"]["name"], "eb_rel": eb, "mode_bt": bt, "schedule": "launch",
+                   "lossless_stage": "zero-byte elision after Huffman" if args.backend else "none",
                    "training": {"blocks": int(Y.numel()), "loss_before": round(l0, 4), "loss_after": round(loss, 4),
                                 "seconds": round(train_s, 3), "epochs": 30, "batch": 512, "lr": 2e-3},
                    "turbulence_1024x1024x128_cfl0.5": evals[4], "turbulence_1024x1024x64_cfl6": evals[5]},
