@@ -1528,6 +1528,11 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
                                                   {CPT_SCHED_LAUNCH, 1, 0, true},
                                                   {CPT_SCHED_FUSED, 1, 0, true}};
     std::vector<size_t> lens(n), ref;
+    std::vector<unsigned long long> dig(n), refdig;
+    // the digests of the candidates' streams (the tuner is not a hot path:
+    // one small allocation for its n digests)
+    unsigned long long* ddig = nullptr;
+    HIPCHK(hipMalloc((void**)&ddig, 8 * (size_t)n));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1540,6 +1545,18 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
       if (ref.empty()) ref = lens;
       if (lens != ref) {
         st = fail(CPT_EHIP, "internal: schedules disagree on stream lengths");
+        break;
+      }
+      // every candidate must write the same bytes, not only as many
+      launch_hash_streams(n, outs, lens.data(), ddig, s);
+      if (hipMemcpyAsync(dig.data(), ddig, 8 * (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        st = fail(CPT_EHIP, "stream digest readback failed");
+        break;
+      }
+      if (refdig.empty()) refdig = dig;
+      if (dig != refdig) {
+        st = fail(CPT_EHIP, "internal: schedules disagree on stream bytes");
         break;
       }
       float tot = 0.f;
@@ -1563,6 +1580,7 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    (void)hipFree(ddig);
     if (st) return st;
     ExecChoice b = cand[bi];
     {

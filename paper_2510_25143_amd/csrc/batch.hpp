@@ -196,6 +196,8 @@ void launch_zbe_b(FieldDesc* D, int n, long long zblocks, uint32_t* ztab, uint32
                   hipStream_t s);
 // its inverse into each container's scratch copy (upre: blocks per stream)
 void launch_unzbe_b(DecDesc* D, int n, const long long* upre, long long ublocks, long long* uoff, hipStream_t s);
+// digests of n device byte strings (host arrays of pointers and lengths) into h[n]
+void launch_hash_streams(int n, const uint8_t* const* p, const size_t* len, unsigned long long* h, hipStream_t s);
 
 // k_decompress.hip: reconstruction of frame t of the first m streams of the
 // launch order (pre: blocks per stream)

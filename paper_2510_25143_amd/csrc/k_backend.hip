@@ -275,7 +275,49 @@ __global__ __launch_bounds__(256) void k_unzbe_block_b(DecDesc* __restrict__ D, 
   if (tid == 0 && bad) atomicOr(&d.err, 512u);
 }
 
+// ============================================================ stream hash
+// A position-sensitive 64-bit digest of a byte string for comparing the
+// outputs of execution choices: the sum modulo 2^64 of splitmix64 (Steele,
+// Lea and Flood's generator finaliser, constants as published) of
+// (word index << 32 | word), over its little-endian 32-bit words (the last
+// one zero-padded).  Addition commutes, so the atomics give one result.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_hash_clear(unsigned long long* h, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) h[i] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_hash_bytes(const uint8_t* __restrict__ p, size_t len,
+                                                    unsigned long long* __restrict__ h) {
+  const size_t nw = (len + 3) / 4;
+  uint64_t acc = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (size_t)gridDim.x * blockDim.x) {
+    uint32_t w = 0;
+    for (int b = 0; b < 4; b++)
+      if (4 * i + b < len) w |= (uint32_t)p[4 * i + b] << (8 * b);
+    acc += splitmix64(((uint64_t)i << 32) | w);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(h, (unsigned long long)acc);
+}
+
 // ================================================================ launchers
+void launch_hash_streams(int n, const uint8_t* const* p, const size_t* len, unsigned long long* h, hipStream_t s) {
+  k_hash_clear<<<(n + 255) / 256, 256, 0, s>>>(h, n);
+  for (int i = 0; i < n; i++) {
+    const size_t nw = (len[i] + 3) / 4;
+    const unsigned grid = (unsigned)std::min<size_t>((nw + 255) / 256, 1024);
+    if (grid > 0) k_hash_bytes<<<grid, 256, 0, s>>>(p[i], len[i], h + i);
+  }
+}
+
+
 void launch_zbe_b(FieldDesc* D, int n, long long zblocks, uint32_t* ztab, uint32_t* zlen, long long* zoff,
                   hipStream_t s) {
   const unsigned grid = (unsigned)std::min<long long>(zblocks, 4096);

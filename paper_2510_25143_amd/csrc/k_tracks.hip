@@ -147,21 +147,35 @@ __global__ __launch_bounds__(256) void k_tet_pairs(const uint32_t* __restrict__ 
     const int x = (int)(i % (W - 1));
     const long long r = i / (W - 1);
     const int y = (int)(r % (H - 1)), t = (int)(r / (H - 1));
-    for (int k = 0; k < 6; k++) {
-      int fa = 0, fb = 0;
-      int cnt = 0;
-      for (int s = 0; s < 4; s++) {
-        const size_t g = ((size_t)(t + c_tet.dt[k][s]) * H + (y + c_tet.dy[k][s])) * W + (x + c_tet.dx[k][s]);
-        const int type = c_tet.type[k][s];
-        const uint32_t m = masks[g];
-        if ((m >> type) & 1u) {
-          const int face = (int)(ofs[g] + (uint32_t)__popc(m & ((1u << type) - 1u)));
-          if (cnt == 0) fa = face; else fb = face;
-          cnt++;
+    // every face of the cell's tetrahedra is owned by one of its eight
+    // corners: load their masks once, and leave when none has a crossed face
+    const size_t HW = (size_t)H * W, g0 = ((size_t)t * H + y) * W + x;
+    uint32_t m[8];
+    uint32_t any = 0;
+#pragma unroll
+    for (int o = 0; o < 8; o++) {
+      m[o] = masks[g0 + (size_t)(o >> 2) * HW + (size_t)((o >> 1) & 1) * W + (o & 1)];
+      any |= m[o];
+    }
+    if (any & 0xFFFu) {
+#pragma unroll
+      for (int k = 0; k < 6; k++) {
+        int fa = 0, fb = 0;
+        int cnt = 0;
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+          const int o = c_tet.dt[k][s] * 4 + c_tet.dy[k][s] * 2 + c_tet.dx[k][s];
+          const int type = c_tet.type[k][s];
+          if ((m[o] >> type) & 1u) {
+            const size_t g = g0 + (size_t)c_tet.dt[k][s] * HW + (size_t)c_tet.dy[k][s] * W + c_tet.dx[k][s];
+            const int face = (int)(ofs[g] + (uint32_t)__popc(m[o] & ((1u << type) - 1u)));
+            if (cnt == 0) fa = face; else fb = face;
+            cnt++;
+          }
         }
+        if (cnt != 0 && cnt != 2) nbad++;
+        if (cnt == 2) uf_unite(parent, fa, fb);
       }
-      if (cnt != 0 && cnt != 2) nbad++;
-      if (cnt == 2) uf_unite(parent, fa, fb);
     }
   }
   if (nbad) atomicAdd(&ctr[0], (unsigned long long)nbad);
