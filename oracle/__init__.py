@@ -305,7 +305,7 @@ def score(hist, n, L, K, bt):
     return lib().cpo_score(_p(h), h.size, n, L, K, bt)
 
 
-def huffman_lengths(counts, maxlen=12):
+def huffman_lengths(counts, maxlen=16):
     c = np.ascontiguousarray(counts, dtype=np.uint64)
     out = np.zeros(c.size, dtype=np.uint8)
     st = lib().cpo_huffman_lengths(_p(c), c.size, maxlen, _p(out))

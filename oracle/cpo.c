@@ -40,7 +40,7 @@
 #define CPO_QR 512
 #endif
 #ifndef CPO_MAXLEN
-#define CPO_MAXLEN 12
+#define CPO_MAXLEN 16
 #endif
 #define QR CPO_QR        /* residual quantization radius R */
 #define QSYM (2 * QR)    /* residual-code alphabet; code 0 = unpredictable */

@@ -969,7 +969,7 @@ cpt_status carve_dec(Arena& A, const DPlan& P, DBufs& b) {
       {(void**)&b.upre, vec_bytes(P.upre)},
   };
   std::vector<Item> rest = {
-      {(void**)&b.B.lut, 8 * (size_t)n * (1u << MAXLEN)}, {(void**)&b.B.xw, 4 * CX + 16},
+      {(void**)&b.B.lut, 8 * (size_t)n * LUT_WORDS}, {(void**)&b.B.xw, 4 * CX + 16},
       {(void**)&b.B.xwofs, 4 * CX + 16},                  {(void**)&b.B.qw, 4 * CQ + 16},
       {(void**)&b.B.qwofs, 4 * CQ + 16},                  {(void**)&b.B.xs, 2 * N},
       {(void**)&b.B.qs, 2 * (size_t)P.QS + 16},           {(void**)&b.B.sn, 4 * S + 16},

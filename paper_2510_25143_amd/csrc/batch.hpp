@@ -171,7 +171,7 @@ struct DecDesc {
 // the vertex order, so per-segment prefix sums of residual-coded vertices
 // and raw words locate every vertex's symbols and raw words.
 struct DecodeBufs {
-  uint32_t* lut;            // two 4096-entry tables per stream
+  uint32_t* lut;            // two decoding tables of LUT_WORDS words per stream
   uint32_t *xw, *xwofs, *qw, *qwofs;  // chunk words and their prefix sums
   uint16_t *xs, *qs;        // decoded symbols
   uint32_t *sn, *sq;        // per segment: residual-coded vertices, their exclusive prefix

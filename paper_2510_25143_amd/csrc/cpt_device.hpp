@@ -17,7 +17,18 @@ constexpr int QR = 512;          // residual quantization radius
 constexpr int QSYM = 2 * QR;     // residual code alphabet, code 0 = unpredictable
 constexpr int XSYM = 25;         // bound code alphabet, 24 = lossless
 constexpr int XLOSSLESS = 24;
-constexpr int MAXLEN = 12;       // longest Huffman codeword
+constexpr int MAXLEN = 16;       // longest Huffman codeword
+// Decoding table of one alphabet (32-bit words): the entry of every 12-bit
+// prefix (symbol | length << 16 for a code of at most 12 bits, LUT_LONG for
+// the prefix of longer codes, LUT_BAD where no code starts), then per length
+// 13..16 its first canonical code, its number of codes and the index of its
+// first symbol in the list of long codes, then that list as 16-bit symbols.
+constexpr int LUT_BITS = 12;
+constexpr int LUT_FIRST = 1 << LUT_BITS, LUT_COUNT = LUT_FIRST + 4, LUT_BASE = LUT_FIRST + 8;
+constexpr int LUT_SYMS = LUT_FIRST + 16;  // word index of the long-code symbol list
+constexpr int LUT_WORDS = LUT_SYMS + 512;
+constexpr uint32_t LUT_LONG = 0xFFFFFFFEu, LUT_BAD = 0xFFFFFFFFu;
+static_assert(MAXLEN - LUT_BITS == 4, "four long-code lengths");
 constexpr int CHUNK = 1024;      // symbols per independently decodable chunk
 constexpr int NMAX = 32;         // maximum semi-Lagrangian substeps
 constexpr int HALO = TILE + 2;   // block plus one-vertex halo

@@ -2,7 +2,7 @@
 // the framework overview in Sec. V of the paper) and its decoder.
 //
 // Two canonical codes, one for the bound codes (25 symbols) and one for the
-// residual codes (1024 symbols), lengths limited to 12 bits by package-merge
+// residual codes (1024 symbols), lengths limited to 16 bits by package-merge
 // (leaves ordered by (count, symbol); a leaf precedes a package of equal
 // weight).  Symbols are cut into chunks of 1024; every chunk is coded
 // MSB-first into its own run of 32-bit words, so encoding and decoding run
@@ -521,8 +521,7 @@ __global__ __launch_bounds__(256) void k_chunk_bits_b(const FieldDesc* __restric
 // One wave per chunk as above, CHUNK / 64 = 16 consecutive symbols per lane
 // (16-byte loads where the chunk is aligned); the chunk's words go to the
 // field's bitstream section.  Residual codes are looked up in a per-wave LDS
-// copy of the field's table, each entry code | length << 12 (a code of at
-// most MAXLEN = 12 bits).
+// copy of the field's table, each entry code | length << 16.
 template <bool RESID>
 __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ D, const long long* __restrict__ cpre,
                                                   int n, long long ctot, const uint8_t* __restrict__ xcode,
@@ -530,9 +529,9 @@ __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ 
                                                   const HuffTables* __restrict__ tabs,
                                                   const uint32_t* __restrict__ wofs) {
   constexpr int NW = CHUNK * MAXLEN / 32, PER = CHUNK / 64;
-  static_assert(MAXLEN <= 12 && QSYM == 64 * PER, "16-bit table entries, 16 per lane");
+  static_assert(MAXLEN <= 16 && QSYM == 64 * PER, "32-bit table entries, 16 per lane");
   __shared__ uint32_t wbuf[4][NW];
-  __shared__ __align__(16) uint16_t ctab[4][QSYM];
+  __shared__ __align__(16) uint32_t ctab[4][QSYM];
   const long long c = 4 * (long long)blockIdx.x + (threadIdx.x >> 6);
   if (c >= ctot) return;
   const int lane = threadIdx.x & 63;
@@ -543,7 +542,7 @@ __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ 
   const long long nsym = RESID ? d.nq : d.N;
   if (d.status || lc * CHUNK >= nsym) return;
   const HuffTables* t = tabs + f;
-  uint16_t* ct = ctab[threadIdx.x >> 6];
+  uint32_t* ct = ctab[threadIdx.x >> 6];
   if (RESID) {
     const uint4* cq = reinterpret_cast<const uint4*>(t->code) + 4 * lane;
     const uint4 c0 = cq[0], c1 = cq[1], c2 = cq[2], c3 = cq[3];
@@ -551,14 +550,12 @@ __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ 
     const uint32_t cv[16] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w,
                              c2.x, c2.y, c2.z, c2.w, c3.x, c3.y, c3.z, c3.w};
     const uint32_t lv[4] = {l4.x, l4.y, l4.z, l4.w};
-    uint32_t e[8];
+    uint32_t e[16];
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-      const uint32_t la = (lv[i >> 1] >> (16 * (i & 1))) & 0xFFu, lb = (lv[i >> 1] >> (16 * (i & 1) + 8)) & 0xFFu;
-      e[i] = (cv[2 * i] | (la << 12)) | ((cv[2 * i + 1] | (lb << 12)) << 16);
-    }
-    reinterpret_cast<uint4*>(ct)[2 * lane] = make_uint4(e[0], e[1], e[2], e[3]);
-    reinterpret_cast<uint4*>(ct)[2 * lane + 1] = make_uint4(e[4], e[5], e[6], e[7]);
+    for (int i = 0; i < 16; i++) e[i] = cv[i] | (((lv[i >> 2] >> (8 * (i & 3))) & 0xFFu) << 16);
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+      reinterpret_cast<uint4*>(ct)[4 * lane + i] = make_uint4(e[4 * i], e[4 * i + 1], e[4 * i + 2], e[4 * i + 3]);
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
@@ -598,8 +595,8 @@ __global__ __launch_bounds__(256) void k_encode_b(const FieldDesc* __restrict__ 
     const bool in = sym[i] != 0xFFFFFFFFu;
     if (RESID) {
       const uint32_t e = in ? ct[sym[i]] : 0u;
-      codes[i] = e & 0xFFFu;
-      lens[i] = (uint8_t)(e >> 12);
+      codes[i] = e & 0xFFFFu;
+      lens[i] = (uint8_t)(e >> 16);
     } else {
       codes[i] = in ? t->code[sym[i]] : 0u;
       lens[i] = in ? t->len[sym[i]] : (uint8_t)0;
@@ -795,13 +792,16 @@ __global__ __launch_bounds__(256) void k_raw_b(const FieldDesc* __restrict__ D, 
 }
 
 // ------------------------------------------------------------- decoding
-// LUT entry for every 12-bit prefix: symbol | length << 16; 0xFFFFFFFF when
-// no codeword matches.
+// The decoding table of one alphabet (layout: LUT_* in cpt_device.hpp).
 // Called by 1024 threads.  The codebook lists (symbol, length) in
 // increasing symbol order; a symbol's canonical code is first[l] plus its
-// rank among the symbols of length l.  Ranks come from wave ballots, the
-// codes are laid out in canonical order (their 12-bit left-aligned starts
-// then increase), and every table entry finds its code by binary search.
+// rank among the symbols of length l.  Ranks come from wave ballots; the
+// codes, left-aligned to MAXLEN bits, are laid out in canonical order (their
+// starts then increase), and every 12-bit prefix finds by binary search the
+// last code starting at or before the end of its 16-position window: a code
+// of at most 12 bits covers the whole window (its start is a multiple of
+// 16), a longer one makes the prefix LUT_LONG, and a window no code reaches
+// is LUT_BAD.  An invalid codebook leaves every entry LUT_BAD.
 __device__ void build_lut(const uint32_t* __restrict__ cb, size_t cb_words, int nsym, uint32_t* __restrict__ lut,
                           uint32_t* __restrict__ err) {
   __shared__ int lcount[MAXLEN + 2];
@@ -816,10 +816,12 @@ __device__ void build_lut(const uint32_t* __restrict__ cb, size_t cb_words, int 
     bad = 0;
     kraft = 0;
   }
+  // no long codes until the table says otherwise
+  if (tid < LUT_SYMS - LUT_FIRST) lut[LUT_FIRST + tid] = 0u;
   __syncthreads();
   const uint32_t used = cb_words >= 1 ? cb[0] : 0;
   if (cb_words < 1 || (size_t)used + 1 != cb_words || used > (uint32_t)nsym) {
-    for (int i = tid; i < (1 << MAXLEN); i += 1024) lut[i] = 0xFFFFFFFFu;
+    for (int i = tid; i < (1 << LUT_BITS); i += 1024) lut[i] = LUT_BAD;
     if (tid == 0) atomicOr(err, 1u);
     return;
   }
@@ -846,7 +848,7 @@ __device__ void build_lut(const uint32_t* __restrict__ cb, size_t cb_words, int 
   }
   __syncthreads();
   if (bad || kraft > (1u << MAXLEN)) {
-    for (int i = tid; i < (1 << MAXLEN); i += 1024) lut[i] = 0xFFFFFFFFu;
+    for (int i = tid; i < (1 << LUT_BITS); i += 1024) lut[i] = LUT_BAD;
     if (tid == 0) atomicOr(err, 1u);
     return;
   }
@@ -868,19 +870,35 @@ __device__ void build_lut(const uint32_t* __restrict__ cb, size_t cb_words, int 
     const uint32_t ci = lbase[l] + rank;
     sstart[ci] = (first[l] + rank) << (MAXLEN - l);
     sval[ci] = s | (l << 16);
+    // the long codes' symbols in canonical order, from index 0
+    if (l > (uint32_t)LUT_BITS)
+      reinterpret_cast<uint16_t*>(lut + LUT_SYMS)[ci - lbase[LUT_BITS + 1]] = (uint16_t)s;
+  }
+  if (tid < MAXLEN - LUT_BITS) {
+    const int L = LUT_BITS + 1 + tid;
+    lut[LUT_FIRST + tid] = first[L];
+    lut[LUT_COUNT + tid] = (uint32_t)lcount[L];
+    lut[LUT_BASE + tid] = lbase[L] - lbase[LUT_BITS + 1];
   }
   __syncthreads();
-  for (int i = tid; i < (1 << MAXLEN); i += 1024) {
-    uint32_t v = 0xFFFFFFFFu;
-    if (used > 0 && sstart[0] <= (uint32_t)i) {
-      int lo = 0, hi = (int)used - 1;  // the last code starting at or before i
+  constexpr uint32_t WIN = 1u << (MAXLEN - LUT_BITS);
+  for (int i = tid; i < (1 << LUT_BITS); i += 1024) {
+    uint32_t v = LUT_BAD;
+    const uint32_t ws = (uint32_t)i * WIN, we = ws + WIN - 1;
+    if (used > 0 && sstart[0] <= we) {
+      int lo = 0, hi = (int)used - 1;  // the last code starting at or before we
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (sstart[mid] <= (uint32_t)i) lo = mid;
+        if (sstart[mid] <= we) lo = mid;
         else hi = mid - 1;
       }
-      const uint32_t cl = sval[lo] >> 16;
-      if ((uint32_t)i < sstart[lo] + (1u << (MAXLEN - cl))) v = sval[lo];
+      const uint32_t cl = sval[lo] >> 16, st = sstart[lo];
+      if (st > ws || cl > (uint32_t)LUT_BITS) {
+        // a long code starts inside the window, or covers its start
+        if (st > ws || ws < st + (1u << (MAXLEN - cl))) v = LUT_LONG;
+      } else if (ws < st + (1u << (MAXLEN - cl))) {
+        v = sval[lo];
+      }
     }
     lut[i] = v;
   }
@@ -902,17 +920,21 @@ __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g
                               const uint32_t* __restrict__ wofs, uint32_t wbase, const uint32_t* __restrict__ bs,
                               size_t bs_words, size_t nsym_total, uint16_t* __restrict__ out,
                               uint32_t* __restrict__ err, size_t cfirst) {
-  __shared__ uint32_t lut[1 << MAXLEN];
+  __shared__ __align__(16) uint32_t lut[LUT_WORDS];
   __shared__ uint32_t stage[4][64][DEC_STEP / 2 + 1];  // per wave, per lane: DEC_STEP symbols
   __shared__ uint32_t win[4][64][DEC_WIN];             // per wave, per lane: the piece's words
   {
-    constexpr int NL = (1 << MAXLEN) / 4 / 256;
+    static_assert(LUT_WORDS % 4 == 0, "the table is copied in 16-byte pieces");
+    constexpr int NV = LUT_WORDS / 4, NL = (NV + 255) / 256;
     uint4 lv[NL];
 #pragma unroll
-    for (int k = 0; k < NL; k++) lv[k] = reinterpret_cast<const uint4*>(lut_g)[threadIdx.x + 256 * k];
+    for (int k = 0; k < NL; k++)
+      if (threadIdx.x + 256 * k < NV) lv[k] = reinterpret_cast<const uint4*>(lut_g)[threadIdx.x + 256 * k];
 #pragma unroll
-    for (int k = 0; k < NL; k++) reinterpret_cast<uint4*>(lut)[threadIdx.x + 256 * k] = lv[k];
+    for (int k = 0; k < NL; k++)
+      if (threadIdx.x + 256 * k < NV) reinterpret_cast<uint4*>(lut)[threadIdx.x + 256 * k] = lv[k];
   }
+  const uint16_t* lsym = reinterpret_cast<const uint16_t*>(lut + LUT_SYMS);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const size_t nch = (nsym_total + CHUNK - 1) / CHUNK;
@@ -963,9 +985,22 @@ __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g
           wi++;
           have += 32;
         }
-        const uint32_t e = lut[(uint32_t)(buf >> (64 - MAXLEN))];
+        uint32_t e = lut[(uint32_t)(buf >> (64 - LUT_BITS))];
+        if (e == LUT_LONG) {
+          // a code of 13..16 bits: the first length whose canonical range
+          // holds the window's prefix of that length
+          const uint32_t w16 = (uint32_t)(buf >> (64 - MAXLEN));
+          e = LUT_BAD;
+#pragma unroll
+          for (int L = LUT_BITS + 1; L <= MAXLEN; L++) {
+            const int i = L - LUT_BITS - 1;
+            const uint32_t dlt = (w16 >> (MAXLEN - L)) - lut[LUT_FIRST + i];
+            if (e == LUT_BAD && dlt < lut[LUT_COUNT + i])
+              e = (uint32_t)lsym[min(lut[LUT_BASE + i] + dlt, 1023u)] | ((uint32_t)L << 16);
+          }
+        }
         const uint32_t l = e >> 16;
-        if (e == 0xFFFFFFFFu || consumed + l > nbits) {
+        if (e == LUT_BAD || consumed + l > nbits) {
           atomicOr(err, 4u);
           bad = true;
         } else {
@@ -1031,7 +1066,7 @@ __global__ __launch_bounds__(256) void k_unpack_modes_b(DecDesc* __restrict__ D,
 __global__ __launch_bounds__(1024) void k_build_lut_b(DecDesc* __restrict__ D, uint32_t* __restrict__ luts) {
   const int f = blockIdx.x >> 1, a = blockIdx.x & 1;
   DecDesc& d = D[f];
-  build_lut(d.sec[a ? 4 : 1], (size_t)d.secw[a ? 4 : 1], a ? QSYM : XSYM, luts + (size_t)blockIdx.x * (1 << MAXLEN),
+  build_lut(d.sec[a ? 4 : 1], (size_t)d.secw[a ? 4 : 1], a ? QSYM : XSYM, luts + (size_t)blockIdx.x * LUT_WORDS,
             &d.err);
 }
 
@@ -1066,7 +1101,7 @@ __global__ __launch_bounds__(256) void k_decode_b(DecDesc* __restrict__ D, const
   const uint32_t* wofs = resid ? qwofs : xwofs;
   const size_t cb = (size_t)(resid ? d.cqb : d.cxb);
   const size_t cfirst = (size_t)(b - pre[f]) * 256;
-  decode_chunks(luts + (size_t)(2 * f + (resid ? 1 : 0)) * (1 << MAXLEN), d.sec[resid ? 5 : 2], wofs + cb, wofs[cb],
+  decode_chunks(luts + (size_t)(2 * f + (resid ? 1 : 0)) * LUT_WORDS, d.sec[resid ? 5 : 2], wofs + cb, wofs[cb],
                 d.sec[resid ? 6 : 3], (size_t)d.secw[resid ? 6 : 3], (size_t)(resid ? d.nq : d.N),
                 resid ? qs + (size_t)d.qsb : xs + (size_t)d.voff, &d.err, cfirst);
 }

@@ -1,8 +1,10 @@
 #!/usr/bin/env python3
 """Compression-ratio cost of the stream's format constants (a study, not a
 test): the residual quantization radius R and the longest Huffman codeword
-are 512 and 12 in this implementation (one workgroup builds a codebook, one
-4096-entry table decodes it).  Longer codewords (16, 24) and the wider radius
+were 512 and 12 when this study was written (one workgroup builds a
+codebook, one 4096-entry table decodes it; the format now allows 16-bit
+codewords, decoded through the same table plus a per-length search for the
+rare long ones).  Longer codewords (16, 24) and the wider radius
 R = 32768 are built from the CPU oracle with the constants overridden, and
 compress the same crops of the wind and turbulence workloads; CR is printed
 for each (Huffman stream, and with the zero-byte-elision stage), with the
