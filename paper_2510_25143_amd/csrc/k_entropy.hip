@@ -934,8 +934,17 @@ __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g
     for (int k = 0; k < NL; k++)
       if (threadIdx.x + 256 * k < NV) reinterpret_cast<uint4*>(lut)[threadIdx.x + 256 * k] = lv[k];
   }
-  const uint16_t* lsym = reinterpret_cast<const uint16_t*>(lut + LUT_SYMS);
   __syncthreads();
+  const uint16_t* lsym = reinterpret_cast<const uint16_t*>(lut + LUT_SYMS);
+  // the long-code ranges of the workgroup's alphabet, held in registers
+  // (read after the barrier that completes the copy)
+  uint32_t lfirst[MAXLEN - LUT_BITS], lcnt[MAXLEN - LUT_BITS], lbas[MAXLEN - LUT_BITS];
+#pragma unroll
+  for (int i = 0; i < MAXLEN - LUT_BITS; i++) {
+    lfirst[i] = lut[LUT_FIRST + i];
+    lcnt[i] = lut[LUT_COUNT + i];
+    lbas[i] = lut[LUT_BASE + i];
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const size_t nch = (nsym_total + CHUNK - 1) / CHUNK;
   const size_t c0 = cfirst + (size_t)wv * 64;  // first chunk of this wave
@@ -987,17 +996,20 @@ __device__ __forceinline__ void decode_chunks(const uint32_t* __restrict__ lut_g
         }
         uint32_t e = lut[(uint32_t)(buf >> (64 - LUT_BITS))];
         if (e == LUT_LONG) {
-          // a code of 13..16 bits: the first length whose canonical range
-          // holds the window's prefix of that length
+          // a code of 13..16 bits: the length whose canonical range holds
+          // the window's prefix of that length (codes are prefix-free, so
+          // at most one does; the shortest is kept)
           const uint32_t w16 = (uint32_t)(buf >> (64 - MAXLEN));
-          e = LUT_BAD;
+          uint32_t idx = 0, L = 0;
 #pragma unroll
-          for (int L = LUT_BITS + 1; L <= MAXLEN; L++) {
-            const int i = L - LUT_BITS - 1;
-            const uint32_t dlt = (w16 >> (MAXLEN - L)) - lut[LUT_FIRST + i];
-            if (e == LUT_BAD && dlt < lut[LUT_COUNT + i])
-              e = (uint32_t)lsym[min(lut[LUT_BASE + i] + dlt, 1023u)] | ((uint32_t)L << 16);
+          for (int i = MAXLEN - LUT_BITS - 1; i >= 0; i--) {
+            const uint32_t dlt = (w16 >> (MAXLEN - LUT_BITS - 1 - i)) - lfirst[i];
+            if (dlt < lcnt[i]) {
+              idx = lbas[i] + dlt;
+              L = (uint32_t)(LUT_BITS + 1 + i);
+            }
           }
+          e = L ? ((uint32_t)lsym[min(idx, 1023u)] | (L << 16)) : LUT_BAD;
         }
         const uint32_t l = e >> 16;
         if (e == LUT_BAD || consumed + l > nbits) {
