@@ -263,6 +263,19 @@ def workload(cfg, index=0, device="cpu", shape=None):
     return f, m
 
 
+def spiked_field(H=96, W=128, T=8, frac=0.01, amp=0.1, seed=11):
+    """A smooth (affine) field with a fraction `frac` of its components
+    displaced by U(-amp, amp): residual codes concentrate on a few symbols
+    with a long tail of rare ones, whose Huffman codewords exceed 12 bits."""
+    rng = np.random.default_rng(seed)
+    t, y, x = np.meshgrid(np.arange(T), np.arange(H), np.arange(W), indexing="ij")
+    f = np.stack([0.5 + 0.001 * x + 0.002 * y + 0.003 * t, -0.3 + 0.002 * x - 0.001 * y + 0.001 * t])
+    f = f.astype(np.float32)
+    m = rng.random(f.shape) < frac
+    f[m] += rng.uniform(-amp, amp, int(m.sum())).astype(np.float32)
+    return torch.from_numpy(f), dict(dt_dx=1.0, seed=seed)
+
+
 def batch_shapes(n=256, seed=3000):
     """(H, W, T) of the uneven batch: side log-uniform in [64, 1024], T in 8..64."""
     rng = np.random.default_rng(seed)

@@ -205,3 +205,20 @@ def test_hostile_stored_floats_rejected_by_both(cpt):
             with pytest.raises(cpt.CptError) as e:
                 cpt.decompress(dev(c))
             assert e.value.status == cpt.ECORRUPT
+
+
+@pytest.mark.parametrize("pred,backend", [(0, 0), (2, 0), (0, 1)])
+def test_long_codewords_match_oracle(cpt, pred, backend):
+    """Residual codewords of 13-16 bits, which the decoder finds through the
+    canonical ranges of the long lengths rather than its 12-bit table: bytes
+    and decoded values equal the oracle's."""
+    from test_oracle_entropy import stream_codebook_lengths
+    f, _ = synthfields.spiked_field()
+    want = oracle.compress(f.numpy(), 1e-3, predictor=pred, backend=backend)
+    plain = oracle.compress(f.numpy(), 1e-3, predictor=pred)
+    assert stream_codebook_lengths(plain, 4).max() > 12
+    got = cpt.compress(dev(f), 1e-3, predictor=pred, backend=backend)
+    assert_bytes_equal(got.cpu().numpy(), want)
+    g = cpt.decompress(dev(want)).cpu().numpy()
+    assert np.array_equal(g.view(np.uint32), oracle.decompress(plain).view(np.uint32))
+
