@@ -155,6 +155,11 @@ typedef struct {
   int32_t use_graph;     /* 1: record the call's device work as a HIP graph
                             on first use and replay it on later calls with
                             the same shapes, options and schedule */
+  int32_t field_tile;    /* tile of the fused field pass: 0 = 32x16,
+                            1 = 64x8, 2 = 16x32 vertices (the output does not
+                            depend on it; CPT_SCHED_AUTO takes the tuned
+                            one).  A struct_size that ends before this field
+                            (the earlier layout) means 0. */
 } cpt_exec_options;
 
 /*
@@ -178,11 +183,13 @@ cpt_status cpt_compress_batch(int n, const float* const* fields, const int32_t* 
                               const size_t* caps, size_t* lens, int32_t* status, void* stream);
 
 /* Number of execution choices cpt_autotune_batch times, in this order:
- * LAUNCH, FUSED, LAUNCH replayed as a graph, FUSED replayed as a graph. */
-#define CPT_TUNE_CANDIDATES 4
+ * LAUNCH, FUSED, LAUNCH replayed as a graph, FUSED replayed as a graph (all
+ * with field tile 0), then the fastest of those four with field tiles 1 and
+ * 2. */
+#define CPT_TUNE_CANDIDATES 6
 
 /*
- * Time every candidate schedule on this batch (arguments as for
+ * Time every candidate execution choice on this batch (arguments as for
  * cpt_compress_batch; the outputs are written), `reps` timed runs each after
  * one warm-up, and remember the fastest for CPT_SCHED_AUTO calls with the
  * same shapes and options (process-wide; graph replay is used when it won

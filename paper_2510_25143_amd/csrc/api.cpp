@@ -411,7 +411,6 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
     P.hpre[i + 1] = P.hpre[i] + (N + HIST_SPAN_VERTICES - 1) / HIST_SPAN_VERTICES;
     P.cxpre[i + 1] = P.cxpre[i] + d.nchx;
     P.cqpre[i + 1] = P.cqpre[i] + ncq;
-    P.fpre[i + 1] = P.fpre[i] + (long long)((W + FIELDPASS_TW - 1) / FIELDPASS_TW) * ((H + FIELDPASS_TH - 1) / FIELDPASS_TH);
     if (opt.backend == 1) {
       const size_t hb = huffman_bound(H, W, T);
       d.zbase = P.zpre[i];
@@ -424,8 +423,7 @@ cpt_status make_plan(int n, const int32_t* HWT, const cpt_options& opt, double e
     P.maxT = std::max(P.maxT, T);
     P.key += ":" + std::to_string(H) + "x" + std::to_string(W) + "x" + std::to_string(T);
   }
-  for (auto v : {P.rpre.back(), P.gpre.back(), P.hpre.back(), P.cxpre.back(), P.cqpre.back(), P.fpre.back(),
-                 P.zpre.back()})
+  for (auto v : {P.rpre.back(), P.gpre.back(), P.hpre.back(), P.cxpre.back(), P.cqpre.back(), P.zpre.back()})
     if (v >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
   P.ZB = P.zpre.back();
   P.IB = P.ioff.back();
@@ -617,7 +615,18 @@ void stage_tables(const Plan& P, const BatchBufs& b, char* stage) {
 struct ExecChoice {
   int schedule = CPT_SCHED_LAUNCH, group = 1, grid = 0;
   bool graph = false;
+  int ftile = 0;  // tile shape of the field pass (FP_SHAPE_TW / FP_SHAPE_TH)
 };
+
+// the field pass's workgroups per field for tile shape `shape`
+cpt_status set_fieldpass_shape(Plan& P, int shape) {
+  const long long tw = FP_SHAPE_TW[shape], th = FP_SHAPE_TH[shape];
+  P.fpre.assign(P.n + 1, 0);
+  for (int i = 0; i < P.n; i++)
+    P.fpre[i + 1] = P.fpre[i] + ((P.D[i].W + tw - 1) / tw) * ((P.D[i].H + th - 1) / th);
+  if (P.fpre.back() >= 2147483647LL) return fail(CPT_EINVAL, "batch too large for one launch");
+  return CPT_OK;
+}
 
 std::mutex g_tune_mu;
 std::map<std::string, ExecChoice> g_tuned;
@@ -630,7 +639,7 @@ void enqueue_compress(const Plan& P, const BatchBufs& b, const ExecChoice& ex, c
   // Alg. 3: fixed point, crossed faces of the original field, lossless flags
   {
     TimeScope ts(FAM_EXTRACT, (uint64_t)P.Ntot, s);
-    launch_fieldpass_b(b.D, n, b.rpre, P.rpre.back(), b.fpre, P.fpre.back(), b.range, b.cur, b.flags, s);
+    launch_fieldpass_b(b.D, n, b.rpre, P.rpre.back(), b.fpre, P.fpre.back(), b.range, b.cur, b.flags, ex.ftile, s);
   }
   if (ex.schedule == CPT_SCHED_PERSISTENT) {
     launch_zero_u32(b.done, (size_t)n, s);
@@ -677,8 +686,8 @@ cpt_status run_graph(const Plan& P, const BatchBufs& b, const ExecChoice& ex, Ar
   cpt_status st = library_stream(A);
   if (st) return st;
   char tag[160];
-  std::snprintf(tag, sizeof(tag), "|%d:%d:%d|%p:%zu|%p:%p", ex.schedule, ex.group, ex.grid, (void*)A.base, A.cap,
-                (const void*)P.opt.selector_w, (void*)A.tlog);
+  std::snprintf(tag, sizeof(tag), "|%d:%d:%d:%d|%p:%zu|%p:%p", ex.schedule, ex.group, ex.grid, ex.ftile,
+                (void*)A.base, A.cap, (const void*)P.opt.selector_w, (void*)A.tlog);
   const std::string key = P.key + tag;
   hipGraphExec_t exec = nullptr;
   for (size_t i = 0; i < A.graphs.size(); i++)
@@ -731,6 +740,8 @@ ExecChoice resolve_exec(const cpt_exec_options* ex, const Plan& P) {
     c.group = ex->group > 0 ? ex->group : 1;
     c.grid = ex->grid;
     c.graph = ex->use_graph != 0;
+    // a struct without the field (the earlier layout) means the default tile
+    if (ex->struct_size >= offsetof(cpt_exec_options, field_tile) + sizeof(int32_t)) c.ftile = ex->field_tile;
   }
   if (sched == CPT_SCHED_AUTO) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -740,6 +751,7 @@ ExecChoice resolve_exec(const cpt_exec_options* ex, const Plan& P) {
       c.group = it->second.group;
       c.grid = it->second.grid;
       c.graph = c.graph || it->second.graph;
+      c.ftile = it->second.ftile;
     } else {
       c.schedule = CPT_SCHED_LAUNCH;
     }
@@ -765,8 +777,10 @@ cpt_status compress_batch_impl(int n, const float* const* fields, const int32_t*
                                const size_t* caps, size_t* lens, int32_t* status, const Debug* dbg, hipStream_t s,
                                const ExecChoice* forced = nullptr) {
   if (!fields || !outs || !caps || !lens) return fail(CPT_EINVAL, "null argument");
-  if (ex_in && ex_in->struct_size != sizeof(cpt_exec_options))
+  if (ex_in && ex_in->struct_size != sizeof(cpt_exec_options) && ex_in->struct_size != offsetof(cpt_exec_options, field_tile))
     return fail(CPT_EINVAL, "cpt_exec_options.struct_size mismatch");
+  if (ex_in && ex_in->struct_size == sizeof(cpt_exec_options) && (ex_in->field_tile < 0 || ex_in->field_tile >= FP_SHAPES))
+    return fail(CPT_EINVAL, "field_tile must be 0, 1 or 2");
   cpt_options opt;
   cpt_status st = check_options(opt_in, eb, &opt);
   if (st) return st;
@@ -788,6 +802,9 @@ cpt_status compress_batch_impl(int n, const float* const* fields, const int32_t*
   if (ex.schedule < CPT_SCHED_LAUNCH || ex.schedule > CPT_SCHED_PERSISTENT) return fail(CPT_EINVAL, "unknown schedule");
   if (ex.group < 1 || ex.group > 64) return fail(CPT_EINVAL, "group must be in 1..64");
   if (ex.grid < 0) return fail(CPT_EINVAL, "grid must be 0 (as many workgroups as fit at once) or positive");
+  if (ex.ftile < 0 || ex.ftile >= FP_SHAPES) return fail(CPT_EINVAL, "field_tile must be 0, 1 or 2");
+  st = set_fieldpass_shape(P, ex.ftile);
+  if (st) return st;
   if (ex.schedule == CPT_SCHED_PERSISTENT)
     return fail(CPT_EUNSUPPORTED, "the persistent schedule is disabled: its launch did not complete on the device");
   if (ex.schedule == CPT_SCHED_PERSISTENT) {
@@ -1523,10 +1540,13 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
     Plan P;
     st = make_plan(n, HWT, opt, eb, P);
     if (st) return st;
-    const ExecChoice cand[CPT_TUNE_CANDIDATES] = {{CPT_SCHED_LAUNCH, 1, 0, false},
-                                                  {CPT_SCHED_FUSED, 1, 0, false},
-                                                  {CPT_SCHED_LAUNCH, 1, 0, true},
-                                                  {CPT_SCHED_FUSED, 1, 0, true}};
+    // four schedules with the default field tile, then the fastest of them
+    // with the other field tiles (filled in when the first four are timed)
+    ExecChoice cand[CPT_TUNE_CANDIDATES] = {{CPT_SCHED_LAUNCH, 1, 0, false, 0},
+                                            {CPT_SCHED_FUSED, 1, 0, false, 0},
+                                            {CPT_SCHED_LAUNCH, 1, 0, true, 0},
+                                            {CPT_SCHED_FUSED, 1, 0, true, 0}};
+    static_assert(CPT_TUNE_CANDIDATES == 4 + FP_SHAPES - 1, "schedules, then field tiles");
     std::vector<size_t> lens(n), ref;
     std::vector<unsigned long long> dig(n), refdig;
     // the digests of the candidates' streams (the tuner is not a hot path:
@@ -1539,6 +1559,10 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
     int bi = -1;
     double bms = 0;
     for (int c = 0; c < CPT_TUNE_CANDIDATES; c++) {
+      if (c >= 4) {
+        cand[c] = cand[bi];
+        cand[c].ftile = c - 3;
+      }
       st = compress_batch_impl(n, fields, HWT, eb, &opt, nullptr, outs, caps, lens.data(), nullptr, nullptr, s,
                                &cand[c]);
       if (st) break;
@@ -1587,7 +1611,7 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tuned[P.key] = b;
     }
-    *best = cpt_exec_options{sizeof(cpt_exec_options), b.schedule, b.group, b.grid, b.graph ? 1 : 0};
+    *best = cpt_exec_options{sizeof(cpt_exec_options), b.schedule, b.group, b.grid, b.graph ? 1 : 0, b.ftile};
     return CPT_OK;
   } catch (...) {
     return fail(CPT_EHIP, "unexpected exception");

@@ -111,8 +111,11 @@ constexpr int RANGE_SLOTS = 32, RANGE_SLOT_STRIDE = 8;
 // range and parameters only (k, eps', displacement factors into D[f].p)
 void launch_params_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, int4* range, hipStream_t s);
 void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* fpre,
-                        long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s);
-constexpr int FIELDPASS_TW = 32, FIELDPASS_TH = 16;
+                        long long fblocks, int4* range, int2* cur, uint8_t* flags, int shape, hipStream_t s);
+// tile shapes of the fused field pass (an execution choice: same output)
+constexpr int FP_SHAPES = 3;
+constexpr int FP_SHAPE_TW[FP_SHAPES] = {32, 64, 16};
+constexpr int FP_SHAPE_TH[FP_SHAPES] = {16, 8, 32};
 
 // launchers (k_entropy.hip); gpre: HIST_WG-vertex histogram workgroups per
 // field, hpre: HIST_SPAN-vertex workgroups, cxpre / cqpre: bound-code /

@@ -279,21 +279,29 @@ __global__ void k_params_b(FieldDesc* __restrict__ D, const int4* __restrict__ r
 // edges of s and s+1, the flags of frame s need the masks of s and s-1; two
 // frames of each are kept.  Halos: values [-1, 34) x [-1, 18), edges
 // [-1, 33) x [-1, 17), masks [-1, 32) x [-1, 16) relative to the tile.
-constexpr int FP_TW = 32, FP_TH = 16;
-constexpr int FP_CW = FP_TW + 3, FP_CH = FP_TH + 3;
-constexpr int FP_EW = FP_TW + 2, FP_EH = FP_TH + 2;
-constexpr int FP_MW = FP_TW + 1, FP_MH = FP_TH + 1;
-constexpr int FP_NC = FP_CW * FP_CH;  // 665 values per frame, 3 per thread
-static_assert(FP_NC <= 3 * 256, "three halo values per thread");
-
-struct FieldPassSmem {
-  int2 cur[2][FP_CH][FP_CW];
-  uint8_t edg[2][FP_EH][FP_EW];
-  uint32_t msk[2][FP_MH][FP_MW];
+// The tile is an execution parameter: every shape gives the same output.
+// Three shapes are built (FP_SHAPE_TW / FP_SHAPE_TH in batch.hpp), each with
+// at most 768 halo values, so that three per thread cover them.
+template <int TW, int TH>
+struct FpShape {
+  static constexpr int CW = TW + 3, CH = TH + 3;  // values
+  static constexpr int EW = TW + 2, EH = TH + 2;  // edge cells
+  static constexpr int MW = TW + 1, MH = TH + 1;  // mask cells
+  static constexpr int NC = CW * CH;
+  static_assert(NC <= 3 * 256, "three halo values per thread");
 };
 
-// A, B: values of frames t and t + 1 as flat [FP_CH][FP_CW] arrays; c: the
+template <int TW, int TH>
+struct FieldPassSmem {
+  using Sh = FpShape<TW, TH>;
+  int2 cur[2][Sh::CH][Sh::CW];
+  uint8_t edg[2][Sh::EH][Sh::EW];
+  uint32_t msk[2][Sh::MH][Sh::MW];
+};
+
+// A, B: values of frames t and t + 1 as flat [CH][CW] arrays; c: the
 // owner's flat index
+template <int FP_CW>
 __device__ __forceinline__ uint32_t fp_edges(const int2* A, const int2* B, int c, bool px, bool py, bool pt) {
   const int2 a = A[c];
   uint32_t e = 0;
@@ -334,8 +342,9 @@ __device__ __forceinline__ uint32_t fp_valid(bool px, bool py, bool pt) {
          (py && pt ? 0x300u : 0u);
 }
 
-// E0, E1: edge bytes of frames t and t + 1 as flat [FP_EH][FP_EW] arrays;
+// E0, E1: edge bytes of frames t and t + 1 as flat [EH][EW] arrays;
 // e: the owner's flat index; valid: fp_valid of the cell
+template <int FP_EW>
 __device__ __forceinline__ uint32_t fp_mask(const uint8_t* E0, const uint8_t* E1, const uint32_t* __restrict__ xz,
                                             int e, uint32_t valid) {
   if (!valid) return 0;
@@ -355,11 +364,13 @@ __device__ __forceinline__ uint32_t fp_mask(const uint8_t* E0, const uint8_t* E1
 // MASKS false it writes the tile's fixed-point values (cur) and lossless
 // flags; with MASKS true only its face masks (twelve crossed-face bits and
 // their signs per vertex, as the extraction numbers them).
-template <bool MASKS>
-__device__ __forceinline__ void fieldpass_tile(FieldPassSmem& S, uint32_t* xz, const float* __restrict__ field,
-                                               int H, int W, int T, int k, int x0, int y0,
-                                               int2* __restrict__ cur, uint8_t* __restrict__ flags,
+template <bool MASKS, int FP_TW, int FP_TH>
+__device__ __forceinline__ void fieldpass_tile(FieldPassSmem<FP_TW, FP_TH>& S, uint32_t* xz,
+                                               const float* __restrict__ field, int H, int W, int T, int k, int x0,
+                                               int y0, int2* __restrict__ cur, uint8_t* __restrict__ flags,
                                                uint32_t* __restrict__ masks) {
+  using Sh = FpShape<FP_TW, FP_TH>;
+  constexpr int FP_CW = Sh::CW, FP_EW = Sh::EW, FP_EH = Sh::EH, FP_MW = Sh::MW, FP_MH = Sh::MH, FP_NC = Sh::NC;
   const size_t HW = (size_t)H * W, N = HW * (size_t)T;
   const float* fu = field;
   const float* fv = field + N;
@@ -424,7 +435,7 @@ __device__ __forceinline__ void fieldpass_tile(FieldPassSmem& S, uint32_t* xz, c
     uint32_t c = ecell;
     for (int j = tid; j < FP_EW * FP_EH; j += 256, c >>= 3) {
       uint32_t e = 0;
-      if (c & 1u) e = fp_edges(A, B, j + j / FP_EW, c & 2u, c & 4u, pt);
+      if (c & 1u) e = fp_edges<FP_CW>(A, B, j + j / FP_EW, c & 2u, c & 4u, pt);
       E[j] = (uint8_t)e;
     }
   };
@@ -458,7 +469,7 @@ __device__ __forceinline__ void fieldpass_tile(FieldPassSmem& S, uint32_t* xz, c
       const bool pt = s + 1 < T;
       uint32_t c = mcell;
       for (int j = tid; j < FP_MW * FP_MH; j += 256, c >>= 3) {
-        M[j] = fp_mask(E0, E1, xz, j + j / FP_MW, (c & 1u) ? fp_valid(c & 2u, c & 4u, pt) : 0u);
+        M[j] = fp_mask<FP_EW>(E0, E1, xz, j + j / FP_MW, (c & 1u) ? fp_valid(c & 2u, c & 4u, pt) : 0u);
       }
     }
     __syncthreads();
@@ -491,29 +502,30 @@ __device__ __forceinline__ void fieldpass_tile(FieldPassSmem& S, uint32_t* xz, c
 
 
 // fpre[f]: tiles of the fields before f
+template <int TW, int TH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fieldpass_b(const FieldDesc* __restrict__ D,
                                                      const long long* __restrict__ fpre, int n,
                                                      int2* __restrict__ cur_all, uint8_t* __restrict__ flags_all) {
-  __shared__ FieldPassSmem S;
+  __shared__ FieldPassSmem<TW, TH> S;
   __shared__ uint32_t xz[128];  // the X and Z words of the face tests per edge byte of the owner
   const int f = find_field(fpre, n, blockIdx.x);
   const FieldDesc& d = D[f];
   if (d.status) return;
-  const int ntx = (d.W + FP_TW - 1) / FP_TW;
+  const int ntx = (d.W + TW - 1) / TW;
   const int tile = (int)((long long)blockIdx.x - fpre[f]);
-  fieldpass_tile<false>(S, xz, d.field, d.H, d.W, d.T, d.p.k, (tile % ntx) * FP_TW, (tile / ntx) * FP_TH,
-                        cur_all + d.voff, flags_all + d.voff, nullptr);
+  fieldpass_tile<false, TW, TH>(S, xz, d.field, d.H, d.W, d.T, d.p.k, (tile % ntx) * TW, (tile / ntx) * TH,
+                                cur_all + d.voff, flags_all + d.voff, nullptr);
 }
 
 // Face masks of one field on the grid 2^k, one workgroup per 32x16 tile.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_maskpass(
     const float* __restrict__ field, int H, int W, int T, int k, uint32_t* __restrict__ masks) {
-  __shared__ FieldPassSmem S;
+  __shared__ FieldPassSmem<32, 16> S;
   __shared__ uint32_t xz[128];
-  const int ntx = (W + FP_TW - 1) / FP_TW;
+  const int ntx = (W + 31) / 32;
   const int tile = blockIdx.x;
-  fieldpass_tile<true>(S, xz, field, H, W, T, k, (tile % ntx) * FP_TW, (tile / ntx) * FP_TH, nullptr, nullptr,
-                       masks);
+  fieldpass_tile<true, 32, 16>(S, xz, field, H, W, T, k, (tile % ntx) * 32, (tile / ntx) * 16, nullptr, nullptr,
+                               masks);
 }
 
 // ------------------------------------------------------------- compaction
@@ -704,7 +716,7 @@ void launch_range(const float* x, size_t n, int* r, hipStream_t s) {
   k_range<<<g, 256, 0, s>>>(x, n, r);
 }
 void launch_maskpass(const float* f, int H, int W, int T, int k, uint32_t* masks, hipStream_t s) {
-  const long long tiles = (long long)((W + FP_TW - 1) / FP_TW) * ((H + FP_TH - 1) / FP_TH);
+  const long long tiles = (long long)((W + 31) / 32) * ((H + 15) / 16);
   if (tiles > 0 && T > 0) k_maskpass<<<(unsigned)tiles, 256, 0, s>>>(f, H, W, T, k, masks);
 }
 size_t scan_partials_size(size_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
@@ -732,10 +744,16 @@ void launch_params_b(FieldDesc* D, int n, const long long* rpre, long long rbloc
   if (rblocks > 0) k_range_b<<<(unsigned)rblocks, 256, 0, s>>>(D, rpre, n, range);
   k_params_b<<<nblk(n, 64), 64, 0, s>>>(D, range, n);
 }
+static_assert(FP_SHAPES == 3 && FP_SHAPE_TW[0] == 32 && FP_SHAPE_TH[0] == 16 && FP_SHAPE_TW[1] == 64 &&
+                  FP_SHAPE_TH[1] == 8 && FP_SHAPE_TW[2] == 16 && FP_SHAPE_TH[2] == 32,
+              "the instantiated tile shapes");
 void launch_fieldpass_b(FieldDesc* D, int n, const long long* rpre, long long rblocks, const long long* fpre,
-                        long long fblocks, int4* range, int2* cur, uint8_t* flags, hipStream_t s) {
+                        long long fblocks, int4* range, int2* cur, uint8_t* flags, int shape, hipStream_t s) {
   launch_params_b(D, n, rpre, rblocks, range, s);
-  if (fblocks > 0) k_fieldpass_b<<<(unsigned)fblocks, 256, 0, s>>>(D, fpre, n, cur, flags);
+  if (fblocks <= 0) return;
+  if (shape == 1) k_fieldpass_b<64, 8><<<(unsigned)fblocks, 256, 0, s>>>(D, fpre, n, cur, flags);
+  else if (shape == 2) k_fieldpass_b<16, 32><<<(unsigned)fblocks, 256, 0, s>>>(D, fpre, n, cur, flags);
+  else k_fieldpass_b<32, 16><<<(unsigned)fblocks, 256, 0, s>>>(D, fpre, n, cur, flags);
 }
 void launch_compare(const uint32_t* ma, const uint32_t* mb, const float* a, const float* b, size_t N,
                     unsigned long long* fc, double* part, hipStream_t s) {

@@ -153,12 +153,28 @@ def test_capacity_reports_length(cpt, small, want_mix2):
 
 def test_autotune_picks_a_candidate_and_auto_uses_it(cpt, small, want_mix2):
     best, ms = cpt.autotune_batch(small[1], 1e-2, reps=1)
-    assert best in cpt.TUNE_CANDIDATES
+    sched, graph, tile = best
+    assert (sched, graph) in [c[:2] for c in cpt.TUNE_CANDIDATES[:4]] and tile in (0, 1, 2)
     assert len(ms) == len(cpt.TUNE_CANDIDATES) and all(m > 0 for m in ms)
     got, st = cpt.compress_batch(small[1], 1e-2, schedule="auto")
     for g, w in zip(got, want_mix2):
         assert np.array_equal(g.cpu().numpy(), w)
     print("autotune:", best, ["%.3f" % m for m in ms])
+
+
+def test_field_tiles_give_identical_streams(cpt, small, want_mix2):
+    """The field pass's tile shape is an execution choice: every shape, alone
+    or with a graph replay, writes the oracle's bytes (ragged fields whose
+    sides are not multiples of any tile)."""
+    for tile in range(len(cpt.FIELD_TILES)):
+        for ex in (dict(schedule="launch"), dict(schedule="fused", use_graph=True)):
+            got, st = cpt.compress_batch(small[1], 1e-2, field_tile=tile, **ex)
+            assert st == [0] * len(SMALL)
+            for i, (g, w) in enumerate(zip(got, want_mix2)):
+                assert np.array_equal(g.cpu().numpy(), w), "tile %d field %d %s" % (tile, i, SMALL[i])
+    for sched in ("launch", "auto"):
+        with pytest.raises(cpt.CptError, match="field_tile"):
+            cpt.compress_batch(small[1], 1e-2, schedule=sched, field_tile=3)
 
 
 PERSISTENT_OFF = ("persistent schedule disabled: its launch did not complete on the device, also with the "
