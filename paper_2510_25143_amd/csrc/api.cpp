@@ -1550,12 +1550,22 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
     std::vector<size_t> lens(n), ref;
     std::vector<unsigned long long> dig(n), refdig;
     // the digests of the candidates' streams (the tuner is not a hot path:
-    // one small allocation for its n digests)
-    unsigned long long* ddig = nullptr;
-    HIPCHK(hipMalloc((void**)&ddig, 8 * (size_t)n));
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    // one small allocation for its n digests) and the timing events,
+    // released on every way out
+    struct TuneRes {
+      unsigned long long* ddig = nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      ~TuneRes() {
+        if (ddig) (void)hipFree(ddig);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+      }
+    } R;
+    HIPCHK(hipMalloc((void**)&R.ddig, 8 * (size_t)n));
+    HIPCHK(hipEventCreate(&R.e0));
+    HIPCHK(hipEventCreate(&R.e1));
+    unsigned long long* ddig = R.ddig;
+    hipEvent_t e0 = R.e0, e1 = R.e1;
     int bi = -1;
     double bms = 0;
     for (int c = 0; c < CPT_TUNE_CANDIDATES; c++) {
@@ -1602,9 +1612,6 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
         bms = m;
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(ddig);
     if (st) return st;
     ExecChoice b = cand[bi];
     {
