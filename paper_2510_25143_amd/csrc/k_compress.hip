@@ -927,7 +927,7 @@ __device__ __forceinline__ void run_block(Smem& S, const BatchView& B, const Fie
 
 // predictor classes of frame t for every block of the first m fields of the
 // launch order; pre[j] = blocks of the fields before j
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_modes_b(BatchView B, const long long* __restrict__ pre, int m, int t,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_modes_b(BatchView B, const long long* __restrict__ pre, int m, int t,
                                                 int gidx) {
   __shared__ ModesSmem S;
   const int j = find_field(pre, m, blockIdx.x);
