@@ -519,6 +519,27 @@ __device__ __forceinline__ int c_nbr_dy(int j) { return c_nbr.dy[j]; }
 __device__ __forceinline__ int c_nbr_dt(int j) { return c_nbr.dt[j]; }
 static_assert(make_pairs().a[0] >= 0 && make_dyn_pairs().a[13] >= 0 && make_dyn_pairs().a[14] < 0,
               "face and neighbour tables are consistent");
+// Lane j's sweep face as one word: bit 0 set for the 14 lanes with a face,
+// then the offsets (dx, dy, dt) + 1 of its two neighbours, two bits each
+// (zero offsets for the two lanes without a face).
+struct DynLanes {
+  uint32_t e[16];
+};
+constexpr DynLanes make_dyn_lanes() {
+  DynLanes L{};
+  const DynPairs D = make_dyn_pairs();
+  for (int j = 0; j < 16; j++) {
+    const int fa = D.a[j], fb = D.b[j];
+    if (fa < 0) {
+      L.e[j] = 1u << 1 | 1u << 3 | 1u << 5 | 1u << 7 | 1u << 9 | 1u << 11;  // zero offsets, no face
+      continue;
+    }
+    L.e[j] = 1u | (uint32_t)(NBR.dx[fa] + 1) << 1 | (uint32_t)(NBR.dy[fa] + 1) << 3 | (uint32_t)(NBR.dt[fa] + 1) << 5 |
+             (uint32_t)(NBR.dx[fb] + 1) << 7 | (uint32_t)(NBR.dy[fb] + 1) << 9 | (uint32_t)(NBR.dt[fb] + 1) << 11;
+  }
+  return L;
+}
+__constant__ DynLanes c_dynlanes = make_dyn_lanes();
 
 // Running minimum of Alg. 2 bounds.  For the face (me, n0, n1) with
 // d0 = det(me, n0), d1 = det(me, n1):  Alg. 2 returns 0 when M = d0 - d1 +
@@ -620,6 +641,9 @@ __device__ __forceinline__ void face_update_q(int& xi, const MeSign& ms, const N
 // two frames are staged one-sided (17 x 17), frame t with the full halo.
 // Indices: V0[1 + y - y0][1 + x - x0], V1 the same, V2[y - y0][x - x0].
 constexpr int HALO1 = TILE + 1;
+struct TileInfo {
+  int x0, y0, H, W, T, eps, cls, valid;
+};
 struct PhaseSmem {
   double2 V0[HALO1][HALO1];  // frame t-1, x in [x0-1, x0+15], y in [y0-1, y0+15]
   double2 V1[HALO][HALO];    // frame t, [x0-1, x0+16] x [y0-1, y0+16]
@@ -630,9 +654,64 @@ struct PhaseSmem {
   // |u| - 1, |v| - 1 of each vertex (its raise terms); the sweep reads them
   // once, then stores the bound code and the bound there
   int2 MS[TILE][TILE];
-  int2 SLP[TILE][TILE];      // semi-Lagrangian predictions, or the frame t-1 part of the Lorenzo prediction
+  int2 SLP[TILE][TILE];      // semi-Lagrangian predictions, or the fixed part of the Lorenzo prediction
+  TileInfo info;             // what the sweep needs of the block when a workgroup holds several
 };
 static_assert(sizeof(PhaseSmem) <= 160 * 1024 / 8, "eight blocks share a compute unit's LDS");
+
+// The halo cells of the three staged frames, one entry each: index into the
+// contiguous V0, V1, V2 range (bits 0-9), x and y offset from the block's
+// first vertex plus one (bits 10-14 and 15-19), frame 0, 1, 2 for t-1, t,
+// t+1 (bits 20-21), and whether the cell is loaded (bit 22).  Frame t-1
+// needs the row above and the column left of the block, frame t+1 the row
+// below and the column right of it, frame t the whole ring; the two ring
+// corners of frame t that belong to blocks of the same colour are never
+// read and only cleared.
+constexpr int NHALO = 2 * (HALO1 + TILE) + (4 * HALO - 4);
+struct HaloTable {
+  uint32_t e[NHALO];
+};
+constexpr uint32_t halo_entry(int f, int hy, int hx, bool load) {
+  const int flat = f == 0 ? hy * HALO1 + hx : (f == 1 ? HALO1 * HALO1 + hy * HALO + hx : HALO1 * HALO1 + HALO * HALO + hy * HALO1 + hx);
+  const int ox = f == 2 ? hx + 1 : hx, oy = f == 2 ? hy + 1 : hy;
+  return (uint32_t)flat | (uint32_t)ox << 10 | (uint32_t)oy << 15 | (uint32_t)f << 20 | (load ? 1u : 0u) << 22;
+}
+constexpr HaloTable make_halo() {
+  HaloTable H{};
+  int n = 0;
+  for (int hx = 0; hx < HALO1; hx++) H.e[n++] = halo_entry(0, 0, hx, true);
+  for (int hy = 1; hy < HALO1; hy++) H.e[n++] = halo_entry(0, hy, 0, true);
+  for (int hx = 0; hx < HALO - 1; hx++) H.e[n++] = halo_entry(1, 0, hx, true);
+  for (int hx = 1; hx < HALO; hx++) H.e[n++] = halo_entry(1, HALO - 1, hx, true);
+  for (int hy = 1; hy < HALO - 1; hy++) H.e[n++] = halo_entry(1, hy, 0, true);
+  for (int hy = 1; hy < HALO - 1; hy++) H.e[n++] = halo_entry(1, hy, HALO - 1, true);
+  for (int hx = 0; hx < HALO1; hx++) H.e[n++] = halo_entry(2, TILE, hx, true);
+  for (int hy = 0; hy < TILE; hy++) H.e[n++] = halo_entry(2, hy, TILE, true);
+  H.e[n++] = halo_entry(1, 0, HALO - 1, false);
+  H.e[n++] = halo_entry(1, HALO - 1, 0, false);
+  return H;
+}
+constexpr bool halo_covers_ring() {
+  // every staged cell is either one thread's own cell or exactly one entry
+  bool seen[HALO1 * HALO1 * 2 + HALO * HALO] = {};
+  for (int v = 0; v < TILE * TILE; v++) {
+    const int vy = v / TILE, vx = v % TILE;
+    seen[(vy + 1) * HALO1 + vx + 1] = true;
+    seen[HALO1 * HALO1 + (vy + 1) * HALO + vx + 1] = true;
+    seen[HALO1 * HALO1 + HALO * HALO + vy * HALO1 + vx] = true;
+  }
+  const HaloTable H = make_halo();
+  for (int i = 0; i < NHALO; i++) {
+    const int flat = (int)(H.e[i] & 1023);
+    if (seen[flat]) return false;
+    seen[flat] = true;
+  }
+  for (bool b : seen)
+    if (!b) return false;
+  return true;
+}
+static_assert(NHALO == 134 && halo_covers_ring(), "the halo table and the threads' own cells cover the staged frames once");
+__constant__ HaloTable c_halo = make_halo();
 
 // frame 0, 1, 2 (t-1, t, t+1) at halo indices (hy, hx) of the 18 x 18 frame
 // around the block, (1, 1) being the block's first vertex
@@ -645,65 +724,70 @@ union TileSmem {
   PhaseSmem p;
 };
 
-// One block (bx, by) of frame t with predictor class *clsp, or cls0 when
-// clsp is null; cur, flags, xcode, qcode and xi_dbg point at the field's
-// own arrays.  Called by all 256 threads; ends with a barrier, so the shared
-// memory may be reused at once.
-__device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur, const uint8_t* __restrict__ flags,
-                                           const FieldParams& p, int t, int bx, int by, int cls0,
-                                           const uint8_t* __restrict__ clsp,
+// NB blocks of frame t, one per 256 threads: the thread's own block is
+// (bx, by) with predictor class *clsp, or cls0 when clsp is null; cur,
+// flags, xcode, qcode and xi_dbg point at that block's field's arrays, and
+// valid is false for a slot without a block (it only keeps the barriers).
+// Staging, the static faces and the results are per block; in the sweep a
+// wave holds 4 / NB rows of every block, so that with several blocks its
+// rows share their anti-diagonal steps.  Called by all 256 NB threads; ends
+// with a barrier, so the shared memory may be reused at once.
+template <int NB>
+__device__ __forceinline__ void phase_tile(PhaseSmem* SS, bool valid, int2* __restrict__ cur,
+                                           const uint8_t* __restrict__ flags, const FieldParams& p, int t, int bx,
+                                           int by, int cls0, const uint8_t* __restrict__ clsp,
                                            uint8_t* __restrict__ xcode, uint32_t* __restrict__ qcode,
                                            int32_t* __restrict__ xi_dbg) {
+  static_assert(NB == 1 || NB == 2 || NB == 4, "a wave holds 4 / NB rows of each block");
+  const int tid = threadIdx.x;
+  const int lt = NB == 1 ? tid : (tid & 255);  // thread within its own block
+  PhaseSmem& S = SS[NB == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 8)];
   auto& V0 = S.V0;
   auto& V1 = S.V1;
   auto& XS = S.XQ;
   auto& MS = S.MS;
   auto& SLP = S.SLP;
-  const int tid = threadIdx.x;
   const int H = p.H, W = p.W, T = p.T;
   const size_t HW = (size_t)H * W;
   const int x0 = bx * TILE, y0 = by * TILE;
   const int eps = p.eps;
-  const int vx = tid & 15, vy = tid >> 4;
-  const bool vin = x0 + vx < W && y0 + vy < H;
+  const int vx = lt & 15, vy = lt >> 4;
+  const bool vin = valid && x0 + vx < W && y0 + vy < H;
 
-  // ---- stage frames t-1, t, t+1 (V0, V1, V2 are contiguous, so element i of
-  // the flat range is one cell); the two corner cells of frame t that belong
-  // to blocks of the same colour are never read and not loaded.  All loads of
-  // a thread are issued before the first one is waited for.
-  constexpr int N0 = HALO1 * HALO1, N1 = HALO * HALO;
-  constexpr int NSTAGE = 2 * N0 + N1, KSTAGE = (NSTAGE + 255) / 256;
-  static_assert(offsetof(PhaseSmem, V1) == sizeof(double2) * N0 &&
-                    offsetof(PhaseSmem, V2) == sizeof(double2) * (N0 + N1),
-                "the three staged frames are one flat range");
-  int2 sv[KSTAGE];
-  uint32_t ldm = 0;
-#pragma unroll
-  for (int k = 0; k < KSTAGE; k++) {
-    const int i = tid + 256 * k;
-    const int f = i < N0 ? 0 : (i < N0 + N1 ? 1 : 2);
-    const int r = i - (f == 0 ? 0 : (f == 1 ? N0 : N0 + N1));
-    const int w = f == 1 ? HALO : HALO1;
-    const int hy = r / w, hx = r - hy * w;
-    const int org = f == 2 ? 0 : 1;  // frame t+1 starts at the block's first vertex
-    const int gx = x0 - org + hx, gy = y0 - org + hy, tt = t - 1 + f;
-    const bool corner = f == 1 && ((hx == HALO - 1 && hy == 0) | (hx == 0 && hy == HALO - 1));
-    const bool ld = (i < NSTAGE) & !corner & (gx >= 0) & (gx < W) & (gy >= 0) & (gy < H) & (tt >= 0) & (tt < T);
-    ldm |= ld ? 1u << k : 0u;
-    // element 0 of the field stands in for the cells that are not loaded
-    sv[k] = cur[ld ? (size_t)tt * HW + (size_t)gy * W + gx : 0];
+  // ---- stage frames t-1, t, t+1.  Every thread loads its own vertex's cell
+  // of the three frames, and threads 0 .. NHALO-1 one halo cell each (from
+  // a table); cells outside the domain or the frame range are staged as 0.
+  // All loads of a thread are issued before the first one is waited for.
+  // this lane's sweep face, read with the frame loads
+  const uint32_t dyn = c_dynlanes.e[tid & 15];
+  const size_t own = (size_t)(y0 + vy) * W + (x0 + vx);
+  const int2* f0 = cur + (size_t)(t > 0 ? t - 1 : 0) * HW;
+  const int2* f1 = cur + (size_t)t * HW;
+  const int2* f2 = cur + (size_t)(t + 1 < T ? t + 1 : t) * HW;
+  const bool ld0 = vin & (t > 0), ld2 = vin & (t + 1 < T);
+  const int2 c0 = f0[ld0 ? own : 0], c1 = f1[vin ? own : 0], c2 = f2[ld2 ? own : 0];
+  int2 ch = make_int2(0, 0);
+  int hslot = -1;
+  if (valid && lt < NHALO) {
+    const uint32_t e = c_halo.e[lt];
+    const int f = (int)(e >> 20) & 3;
+    const int gx = x0 + (int)((e >> 10) & 31) - 1, gy = y0 + (int)((e >> 15) & 31) - 1, tt = t - 1 + f;
+    const bool ld = ((e >> 22) & 1u) & (gx >= 0) & (gx < W) & (gy >= 0) & (gy < H) & (tt >= 0) & (tt < T);
+    ch = cur[ld ? (size_t)tt * HW + (size_t)gy * W + gx : 0];
+    if (!ld) ch = make_int2(0, 0);
+    hslot = (int)(e & 1023);
   }
   // this thread's lossless flag and the block's class (when read here), with
   // the frame loads in flight
-  const uint8_t fl = flags[vin ? (size_t)t * HW + (size_t)(y0 + vy) * W + x0 + vx : 0];
-  const int cls = clsp ? (int)*clsp : cls0;
+  const uint8_t fl = flags[vin ? (size_t)t * HW + own : 0];
+  const int cls = (valid && clsp) ? (int)*clsp : cls0;
   const bool lossless = !vin || fl != 0;
-#pragma unroll
-  for (int k = 0; k < KSTAGE; k++) {
-    const int i = tid + 256 * k;
-    const int2 v = (ldm >> k) & 1u ? sv[k] : make_int2(0, 0);
-    if (i < NSTAGE) (&V0[0][0])[i] = make_double2((double)v.x, (double)v.y);
-  }
+  auto dbl = [](int2 v) { return make_double2((double)v.x, (double)v.y); };
+  const double2 z2 = make_double2(0.0, 0.0);
+  V0[vy + 1][vx + 1] = ld0 ? dbl(c0) : z2;
+  V1[vy + 1][vx + 1] = vin ? dbl(c1) : z2;
+  S.V2[vy][vx] = ld2 ? dbl(c2) : z2;
+  if (hslot >= 0) (&V0[0][0])[hslot] = dbl(ch);
   const int dmax = p.predictor == 1 ? 2 : class_dmax(p.K, cls);
   __syncthreads();
 
@@ -721,12 +805,13 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
         // Faces through a raster predecessor (left, up, up-left) are all
         // evaluated in the sweep, also where that neighbour lies outside the
         // block; the other 22 are evaluated here for every vertex alike.
-        uint32_t ok = 0;
-#pragma unroll
-        for (int j = 3; j < 14; j++) {
-          int xx = x + NBR.dx[j], yy = y + NBR.dy[j], tt = t + NBR.dt[j];
-          ok |= (xx >= 0 && xx < W && yy >= 0 && yy < H && tt >= 0 && tt < T) ? (1u << j) : 0u;
-        }
+        // whether neighbour j lies in the domain, from six per-lane tests
+        const bool xl = x > 0, xr = x + 1 < W, yl = y > 0, yr = y + 1 < H, tl = t > 0, tr = t + 1 < T;
+        auto inside = [&](int j) {
+          const int dx = NBR.dx[j], dy = NBR.dy[j], dt = NBR.dt[j];
+          return (dx < 0 ? xl : (dx > 0 ? xr : true)) & (dy < 0 ? yl : (dy > 0 ? yr : true)) &
+                 (dt < 0 ? tl : (dt > 0 ? tr : true));
+        };
         auto nv = [&](int j) { return *vslot(S, 1 + NBR.dt[j], ly + 1 + NBR.dy[j], lx + 1 + NBR.dx[j]); };
         NbrQ prev = nbr_q(nv(STRAIL.a[0]), me, ms);
 #pragma unroll
@@ -738,73 +823,90 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
           A.n = nv(a);
           const NbrQ B = nbr_q(nv(b), me, ms);
           prev = B;
-          if (((ok >> a) & (ok >> b) & 1u) == 0) continue;
+          if (!(inside(a) & inside(b))) continue;
           face_update_q(xi, ms, A, B);
           // keep each face's loads with the face (fewer live registers)
           __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
       }
       if (cls == 0) {
-        // the frame t-1 part of the 3-D Lorenzo prediction (fixed during the sweep)
+        // the frame t-1 part of the 3-D Lorenzo prediction, less the halo
+        // cells of frame t that the sweep's sum left + up - upper-left reads
+        // at the block's left and top edges: the prediction counts them as
+        // 0, and they do not change during the sweep (all sums exact)
         const double2 z = make_double2(0.0, 0.0);
         const double2 pc = V0[ly + 1][lx + 1];
         const double2 pl = lx > 0 ? V0[ly + 1][lx] : z;
         const double2 pu = ly > 0 ? V0[ly][lx + 1] : z;
         const double2 plu = (lx > 0 && ly > 0) ? V0[ly][lx] : z;
-        SLP[ly][lx] = make_int2((int)(pc.x - pl.x - pu.x + plu.x), (int)(pc.y - pl.y - pu.y + plu.y));
+        const double2 hl = lx == 0 ? V1[ly + 1][lx] : z;
+        const double2 hu = ly == 0 ? V1[ly][lx + 1] : z;
+        const double2 hlu = (lx == 0 || ly == 0) ? V1[ly][lx] : z;
+        SLP[ly][lx] = make_int2((int)(((pc.x - pl.x) - (pu.x - plu.x)) - ((hl.x + hu.x) - hlu.x)),
+                                (int)(((pc.y - pl.y) - (pu.y - plu.y)) - ((hl.y + hu.y) - hlu.y)));
       } else {
-        // frame t-1 from the staged cells where they cover the sample, else
-        // from global memory
+        // the samples of frame t-1 from global memory (cache hits: the
+        // block's neighbourhood was just loaded), its value at the vertex
+        // from the staged copy
         const int2* prev = cur + (size_t)(t - 1) * HW;
-        auto F = [&](int xx, int yy) {
-          const int hx = xx - x0 + 1, hy = yy - y0 + 1;
-          const bool staged = hx >= 0 && hx < HALO1 && hy >= 0 && hy < HALO1;
-          if (!staged) return prev[(size_t)yy * W + xx];
-          const double2 q = V0[hy][hx];
-          return make_int2((int)q.x, (int)q.y);
-        };
+        auto F = [&](int xx, int yy) { return prev[(size_t)yy * W + xx]; };
+        const double2 gc = V0[ly + 1][lx + 1];
         int pu, pv;
-        sl_predict_f(F, H, W, x, y, SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pu, &pv);
+        sl_predict_g(F, H, W, x, y, make_int2((int)gc.x, (int)gc.y), SLConst{p.cx, p.sx, p.cy, p.sy}, dmax, &pu,
+                     &pv);
         SLP[ly][lx] = make_int2(pu, pv);
       }
     }
     XS[ly][lx] = xi;
     MS[ly][lx] = msv;
   }
+  if (NB > 1 && lt == 0) S.info = TileInfo{x0, y0, H, W, T, eps, cls, valid ? 1 : 0};
   __syncthreads();
 
   // ---- anti-diagonal sweep: row g of the block, lane j takes the j-th face
   // that meets a raster predecessor; lanes 0 and 1 then quantize u and v
-  const int g = tid >> 4, j = tid & 15;
-  const int y = y0 + g;
-  const int fa = c_dynp.a[j], fb = c_dynp.b[j];
-  const int axo = fa >= 0 ? c_nbr_dx(fa) : 0, ayo = fa >= 0 ? c_nbr_dy(fa) : 0, ato = fa >= 0 ? c_nbr_dt(fa) : 0;
-  const int bxo = fb >= 0 ? c_nbr_dx(fb) : 0, byo = fb >= 0 ? c_nbr_dy(fb) : 0, bto = fb >= 0 ? c_nbr_dt(fb) : 0;
+  const int j = tid & 15;
+  const int g = NB == 1 ? tid >> 4 : (tid >> 6) * (4 / NB) + ((tid >> 4) & 3) / NB;
+  PhaseSmem& Sw = SS[NB == 1 ? 0 : ((tid >> 4) & 3) % NB];
+  int bx0 = x0, by0 = y0, bH = H, bW = W, bT = T, beps = eps, bcls = cls;
+  bool bvalid = valid;
+  if constexpr (NB > 1) {
+    const TileInfo I = Sw.info;
+    bx0 = I.x0, by0 = I.y0, bH = I.H, bW = I.W, bT = I.T, beps = I.eps, bcls = I.cls, bvalid = I.valid != 0;
+  }
+  const int y = by0 + g;
+  const bool has_face = dyn & 1u;
+  const int axo = (int)((dyn >> 1) & 3) - 1, ayo = (int)((dyn >> 3) & 3) - 1, ato = (int)((dyn >> 5) & 3) - 1;
+  const int bxo = (int)((dyn >> 7) & 3) - 1, byo = (int)((dyn >> 9) & 3) - 1, bto = (int)((dyn >> 11) & 3) - 1;
   const int comp = j & 1;
   // y and t of this lane's face do not change during the sweep
-  const bool face_yt = fa >= 0 && y + ayo >= 0 && y + ayo < H && t + ato >= 0 && t + ato < T && y + byo >= 0 &&
-                       y + byo < H && t + bto >= 0 && t + bto < T;
+  const bool face_yt = has_face && y + ayo >= 0 && y + ayo < bH && t + ato >= 0 && t + ato < bT && y + byo >= 0 &&
+                       y + byo < bH && t + bto >= 0 && t + bto < bT;
   // columns of the block with a vertex [0, aend), and those where this
   // lane's face has both neighbours inside the domain [flo, fhi)
-  const int aend = y < H ? min(TILE, W - x0) : 0;
-  const int flo = max(max(-min(axo, bxo), 0) - x0, 0);
-  const int fhi = face_yt ? max(min(W - max(max(axo, bxo), 0) - x0, TILE), flo) : flo;
-  const double2* Vme = &V1[g + 1][1];
+  const int aend = bvalid && y < bH ? min(TILE, bW - bx0) : 0;
+  const int flo = max(max(-min(axo, bxo), 0) - bx0, 0);
+  const int fhi = face_yt ? max(min(bW - max(max(axo, bxo), 0) - bx0, TILE), flo) : flo;
+  auto& V1w = Sw.V1;
+  auto& XSw = Sw.XQ;
+  auto& MSw = Sw.MS;
+  const double2* Vme = &V1w[g + 1][1];
   // rows of this lane's two face neighbours (only a face of frame t reaches
   // the column before the block; the lanes without a face read frame t)
-  const double2* Va = vslot(S, 1 + ato, g + 1 + ayo, 1 + axo);
-  const double2* Vb = vslot(S, 1 + bto, g + 1 + byo, 1 + bxo);
+  const double2* Va = vslot(Sw, 1 + ato, g + 1 + ayo, 1 + axo);
+  const double2* Vb = vslot(Sw, 1 + bto, g + 1 + byo, 1 + bxo);
   // component comp of the left, upper and upper-left neighbours and of the
   // fixed prediction term, at index lx (rows of pairs: stride 2)
-  const double* Ql = &V1[g + 1][0].x + comp;
-  const double* Qu = &V1[g][1].x + comp;
-  const double* Qlu = &V1[g][0].x + comp;
-  const int* Qp = (const int*)&SLP[g][0] + comp;
-  // wave wv holds rows 4 wv .. 4 wv + 3, which have vertices on the
-  // anti-diagonals 4 wv .. 4 wv + 18; on the others it only keeps the
-  // workgroup's barrier count
+  const double* Ql = &V1w[g + 1][0].x + comp;
+  const double* Qu = &V1w[g][1].x + comp;
+  const double* Qlu = &V1w[g][0].x + comp;
+  const int* Qp = (const int*)&Sw.SLP[g][0] + comp;
+  // wave wv holds rows R wv .. R wv + R - 1 of each block (R = 4 / NB),
+  // which have vertices on the anti-diagonals R wv .. R wv + R + 14; on the
+  // others it only keeps the workgroup's barrier count
+  constexpr int R = 4 / NB;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int dlo = 4 * wv, dhi = 4 * wv + 19;
+  const int dlo = R * wv, dhi = R * wv + R - 1 + TILE;
   for (int d = 0; d < dlo; d++) __syncthreads();
   for (int d = dlo; d < dhi; d++) {
     const int lx = d - g;
@@ -812,35 +914,34 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
     // every value the step reads is final after the last barrier: read them
     // all at once (at a clamped column for the idle lanes)
     const int lc = min(max(lx, 0), TILE - 1);
-    const int xs = XS[g][lc];
-    const int2 msw = MS[g][lc];
+    const int xs = XSw[g][lc];
+    const int2 msw = MSw[g][lc];
     const double2 me = Vme[lc], pa = Va[lc], pb = Vb[lc];
     const double l = Ql[2 * lc], u = Qu[2 * lc], lu = Qlu[2 * lc];
     const int pt = Qp[2 * lc];
-    int e = eps;
+    int e = beps;
     if (active) {
-      e = xs >= 0 ? xs : eps;
+      e = xs >= 0 ? xs : beps;
       if (xs >= 0 && (unsigned)(lx - flo) < (unsigned)(fhi - flo)) face_update(e, me, MeSign{msw.x, msw.y, hiw(me.x) >> 31, hiw(me.y) >> 31}, pa, pb);
     }
     e = row16_min(e);
     if (active && j < 2) {
       const int xi = xs < 0 ? 0 : min(xs, e);
-      const int code = xi_code(eps, xi);
+      const int code = xi_code(beps, xi);
       int qc = 0;
       if (code != XLOSSLESS) {
-        const int xt = eps >> code;
-        // 3-D Lorenzo (the halo cells at the block's edges count as 0) or
-        // the semi-Lagrangian prediction
-        const int pred =
-            cls == 0 ? (int)((lx > 0 ? l : 0.0) + (g > 0 ? u : 0.0) - (lx > 0 && g > 0 ? lu : 0.0)) + pt : pt;
+        const int xt = beps >> code;
+        // 3-D Lorenzo (the fixed term already cancels the halo cells read
+        // at the block's edges) or the semi-Lagrangian prediction
+        const int pred = bcls == 0 ? (int)((l + u) - lu) + pt : pt;
         int rec;
         qc = quantize((int)(comp ? me.y : me.x), pred, xt, &rec);
-        ((double*)&V1[g + 1][lx + 1])[comp] = (double)rec;
+        ((double*)&V1w[g + 1][lx + 1])[comp] = (double)rec;
       }
       // this vertex's entries of XQ and MS were read at the top of this step
       // and are not read again: its outputs take their place
-      ((uint16_t*)&XS[g][lx])[comp] = (uint16_t)qc;
-      (&MS[g][lx].x)[comp] = comp ? xi : code;
+      ((uint16_t*)&XSw[g][lx])[comp] = (uint16_t)qc;
+      (&MSw[g][lx].x)[comp] = comp ? xi : code;
     }
     __syncthreads();
   }
@@ -848,8 +949,8 @@ __device__ __forceinline__ void phase_tile(PhaseSmem& S, int2* __restrict__ cur,
 
   // ---- results of the block, one coalesced write per array
   {
-    const int lx = tid & 15, ly = tid >> 4, x = x0 + lx, yy = y0 + ly;
-    if (x < W && yy < H) {
+    const int lx = lt & 15, ly = lt >> 4, x = x0 + lx, yy = y0 + ly;
+    if (valid && x < W && yy < H) {
       const size_t gv = (size_t)t * HW + (size_t)yy * W + x;
       const double2 r = V1[ly + 1][lx + 1];
       const int2 cx = MS[ly][lx];
@@ -886,10 +987,12 @@ __device__ __forceinline__ long long xcd_band(long long li, long long n) {
 }
 
 // Class of block (bx, by) of frame t, then its phase.  mstate says whether
-// frame t uses decided classes and whether this call decides them.
-template <bool DECIDE, typename Smem>
-__device__ __forceinline__ void run_block(Smem& S, const BatchView& B, const FieldDesc& d, const FieldParams& p,
-                                          int t, int bx, int by, int mstate, int gidx) {
+// frame t uses decided classes and whether this call decides them.  S is
+// the workgroup's TileSmem with DECIDE (one block per workgroup), else its
+// NB PhaseSmem; valid is false for a slot without a block.
+template <bool DECIDE, int NB, typename Smem>
+__device__ __forceinline__ void run_block(Smem* S, bool valid, const BatchView& B, const FieldDesc& d,
+                                          const FieldParams& p, int t, int bx, int by, int mstate, int gidx) {
   int2* cur = B.cur + d.voff;
   const uint8_t* flags = B.flags + d.voff;
   // the class is either known here or read from clsp inside the phase,
@@ -905,11 +1008,11 @@ __device__ __forceinline__ void run_block(Smem& S, const BatchView& B, const Fie
         if (mstate == MODES_DECIDE) {
           float* feats = d.feats_dbg ? d.feats_dbg + (size_t)gidx * p.tx * p.ty * 10 : nullptr;
           if (threadIdx.x < 64) {
-            const int c = block_mode(S.m, cur, flags, p, t, bx, by, B.tlog, B.selw, mrow, feats);
-            if (threadIdx.x == 0) S.m.cls = c;
+            const int c = block_mode(S->m, cur, flags, p, t, bx, by, B.tlog, B.selw, mrow, feats);
+            if (threadIdx.x == 0) S->m.cls = c;
           }
           __syncthreads();
-          cls = S.m.cls;
+          cls = S->m.cls;
           __syncthreads();
         } else {
           clsp = mrow + (size_t)by * p.tx + bx;
@@ -920,9 +1023,9 @@ __device__ __forceinline__ void run_block(Smem& S, const BatchView& B, const Fie
     }
   }
   if constexpr (DECIDE)
-    phase_tile(S.p, cur, flags, p, t, bx, by, cls, clsp, B.xcode + d.voff, B.qcode + d.voff, d.xi_dbg);
+    phase_tile<1>(&S->p, valid, cur, flags, p, t, bx, by, cls, clsp, B.xcode + d.voff, B.qcode + d.voff, d.xi_dbg);
   else
-    phase_tile(S, cur, flags, p, t, bx, by, cls, clsp, B.xcode + d.voff, B.qcode + d.voff, d.xi_dbg);
+    phase_tile<NB>(S, valid, cur, flags, p, t, bx, by, cls, clsp, B.xcode + d.voff, B.qcode + d.voff, d.xi_dbg);
 }
 
 // predictor classes of frame t for every block of the first m fields of the
@@ -941,20 +1044,39 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
   block_mode(S, B.cur + d.voff, B.flags + d.voff, p, t, bx, by, B.tlog, B.selw, mrow, feats);
 }
 
-// colour phase c of frame t over the first m fields of the launch order;
-// with DECIDE the classes of a decision frame are chosen in the same launch
-template <bool DECIDE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_phase_b(
-    BatchView B, const long long* __restrict__ pre, int m, int t, int c, int mstate, int gidx) {
-  using Smem = typename std::conditional<DECIDE, TileSmem, PhaseSmem>::type;
-  __shared__ Smem S;
-  const int j = find_field(pre, m, blockIdx.x);
-  const FieldDesc& d = B.D[j == 0 ? B.ord0 : B.ord[j]];
-  if (d.status) return;
-  const FieldParams p = d.p;
-  int bx, by;
-  if (!phase_block(xcd_band((long long)blockIdx.x - pre[j], pre[j + 1] - pre[j]), p.tx, c, &bx, &by)) return;
-  run_block<DECIDE>(S, B, d, p, t, bx, by, mstate, gidx);
+// colour phase c of frame t over the first m fields of the launch order
+// (nblocks blocks of column-padded phase grids); with DECIDE the classes of
+// a decision frame are chosen in the same launch.  A workgroup of 256 NB
+// threads takes NB consecutive blocks of the launch (NB > 1 only without
+// DECIDE); the workgroups are banded over the XCDs.
+template <bool DECIDE, int NB>
+__global__ __launch_bounds__(256 * NB) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_phase_b(
+    BatchView B, const long long* __restrict__ pre, int m, int t, int c, int mstate, int gidx, long long nblocks) {
+  static_assert(NB == 1 || !DECIDE, "the fused predictor choice takes one block per workgroup");
+  if constexpr (NB == 1) {
+    using Smem = typename std::conditional<DECIDE, TileSmem, PhaseSmem>::type;
+    __shared__ Smem S;
+    const int j = find_field(pre, m, blockIdx.x);
+    const FieldDesc& d = B.D[j == 0 ? B.ord0 : B.ord[j]];
+    if (d.status) return;
+    const FieldParams p = d.p;
+    int bx, by;
+    if (!phase_block(xcd_band((long long)blockIdx.x - pre[j], pre[j + 1] - pre[j]), p.tx, c, &bx, &by)) return;
+    run_block<DECIDE, 1>(&S, true, B, d, p, t, bx, by, mstate, gidx);
+  } else {
+    // every slot keeps the barriers, with or without a block
+    __shared__ PhaseSmem S[NB];
+    // the slot of the wave's own block (uniform over the wave)
+    const int bs = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 8));
+    const long long li = xcd_band(blockIdx.x, (nblocks + NB - 1) / NB) * NB + bs;
+    bool valid = li < nblocks;
+    const int j = find_field(pre, m, valid ? li : nblocks - 1);
+    const FieldDesc& d = B.D[j == 0 ? B.ord0 : B.ord[j]];
+    const FieldParams p = d.p;
+    int bx = 0, by = 0;
+    valid = valid && !d.status && phase_block(li - pre[j], p.tx, c, &bx, &by);
+    run_block<false, NB>(S, valid, B, d, p, t, bx, by, mstate, gidx);
+  }
 }
 
 // ------------------------------------------------------ persistent schedule
@@ -1023,7 +1145,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
         const long long li = li0 + g;
         if (li >= sg.nb) break;
         int bx, by;
-        if (phase_block(li, p.tx, sg.c, &bx, &by)) run_block<true>(S, B, d, p, sg.t, bx, by, sg.mstate, sg.gidx);
+        if (phase_block(li, p.tx, sg.c, &bx, &by)) run_block<true, 1>(&S, true, B, d, p, sg.t, bx, by, sg.mstate, sg.gidx);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1038,11 +1160,15 @@ void launch_modes_b(const BatchView& B, const long long* pre, int m, long long n
   if (nblocks > 0) k_modes_b<<<(unsigned)nblocks, 64, 0, s>>>(B, pre, m, t, gidx);
 }
 
+#ifndef CPT_PHASE_NB
+#define CPT_PHASE_NB 2
+#endif
 void launch_phase_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int c,
                     int mstate, int gidx, bool fused, hipStream_t s) {
   if (nblocks <= 0) return;
-  if (fused) k_phase_b<true><<<(unsigned)nblocks, 256, 0, s>>>(B, pre, m, t, c, mstate, gidx);
-  else k_phase_b<false><<<(unsigned)nblocks, 256, 0, s>>>(B, pre, m, t, c, mstate, gidx);
+  constexpr int NB = CPT_PHASE_NB;
+  if (fused) k_phase_b<true, 1><<<(unsigned)nblocks, 256, 0, s>>>(B, pre, m, t, c, mstate, gidx, nblocks);
+  else k_phase_b<false, NB><<<(unsigned)((nblocks + NB - 1) / NB), 256 * NB, 0, s>>>(B, pre, m, t, c, mstate, gidx, nblocks);
 }
 
 int persist_grid() {

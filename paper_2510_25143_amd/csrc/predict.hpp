@@ -41,12 +41,12 @@ __device__ __forceinline__ void bilinear2f(const Fetch& F, int H, int W, int64_t
   *ov = (r0v * gy + r1v * fy + (1LL << 31)) >> 32;
 }
 
+// g is the previous frame's value at the grid point (x, y) itself
 template <typename Fetch>
-__device__ __forceinline__ void sl_predict_f(const Fetch& F, int H, int W, int x, int y, const SLConst& k, int dmax,
-                                             int* pu, int* pv) {
+__device__ __forceinline__ void sl_predict_g(const Fetch& F, int H, int W, int x, int y, int2 g, const SLConst& k,
+                                             int dmax, int* pu, int* pv) {
   const int64_t XM = (int64_t)(W - 1) << 16, YM = (int64_t)(H - 1) << 16;
   const int64_t px = (int64_t)x << 16, py = (int64_t)y << 16;
-  int2 g = F(x, y);
   int64_t dx = sl_disp(g.x, k.cx, k.sx), dy = sl_disp(g.y, k.cy, k.sy);
   int64_t ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy;
   int64_t dinf = ax > ay ? ax : ay;
@@ -76,6 +76,12 @@ __device__ __forceinline__ void sl_predict_f(const Fetch& F, int H, int W, int x
   bilinear2f(F, H, W, qx, qy, &ru, &rv);
   *pu = (int)ru;
   *pv = (int)rv;
+}
+
+template <typename Fetch>
+__device__ __forceinline__ void sl_predict_f(const Fetch& F, int H, int W, int x, int y, const SLConst& k, int dmax,
+                                             int* pu, int* pv) {
+  sl_predict_g(F, H, W, x, y, F(x, y), k, dmax, pu, pv);
 }
 
 // the same reading every sample from the previous frame in global memory
