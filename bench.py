@@ -271,7 +271,7 @@ def bench_batch(args, cpt, torch, synthfields):
     td = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
     fam = {name: cpt.timing_read(name) for name in cpt.TIMING_FAMILIES}
     cpt.timing_enable(False)
-    kname = "k_phase_b<true>" if sched == "fused" else "k_phase_b<false>"
+    kname = "k_phase_b<true, 1>" if sched == "fused" else "k_phase_b<false, 2>"
     roofline = phase_roofline(fam, kname)
     roofline.update(path_roofline(nvert, raw / clen, tc, td))
     kernels = {name: {"avg_launch_us": round(m / c * 1e3, 3), "sampled_launches": c}
@@ -380,7 +380,7 @@ def bench_selector(args, cpt, torch, synthfields):
                          "decompress_ms": round(sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps, 3),
                          "choice_us_per_launch": round(fam["modes"][0] / max(fam["modes"][1], 1) * 1e3, 3),
                          "blocks_per_class": classes, "max_err": v["max_err"], "fc_t": v["fc_t"],
-                         "fc_s": v["fc_s"], "roofline": phase_roofline(fam, "k_phase_b<false>")}
+                         "fc_s": v["fc_s"], "roofline": phase_roofline(fam, "k_phase_b<false, 2>")}
             res[name + "_modes"] = dbg["modes"]
             log("workload %d %s: %s" % (cfg, name, {kk: vv for kk, vv in res[name].items() if kk != "roofline"}))
         agree = float((res.pop("exhaustive_modes") == res.pop("learned_modes")).float().mean())
@@ -610,7 +610,7 @@ def main():
     log("lossless stage: CR %.3f with, %.3f Huffman only; %.2f GB/s with the other setting" %
         (stage["CR_with_stage"], stage["CR_huffman_only"], stage["GBps_other_setting"]))
 
-    kname = "k_phase_b<true>" if sched == "fused" else "k_phase_b<false>"
+    kname = "k_phase_b<true, 1>" if sched == "fused" else "k_phase_b<false, 2>"
     roofline = phase_roofline(fam, kname, args.workload)
     roofline.update(path_roofline(T * H * W, raw / clen, tc, td))
     kernels = {name: {"avg_launch_us": round(m / c * 1e3, 3), "sampled_launches": c}
