@@ -26,26 +26,7 @@
 
 namespace cpt {
 
-__constant__ FaceTable c_ft = make_face_table();
-
-struct DynList {
-  uint8_t idx[14];
-  int n;
-};
-constexpr DynList make_dyn() {
-  DynList D{};
-  D.n = 0;
-  FaceTable T = make_face_table();
-  const uint8_t p1 = pack_off(-1, 0, 0), p2 = pack_off(0, -1, 0), p3 = pack_off(-1, -1, 0);
-  for (int f = 0; f < T.n; f++) {
-    uint8_t a = T.a[f], b = T.b[f];
-    if (a == p1 || a == p2 || a == p3 || b == p1 || b == p2 || b == p3) D.idx[D.n++] = (uint8_t)f;
-  }
-  return D;
-}
-__constant__ DynList c_dyn = make_dyn();
 static_assert(make_face_table().n == 36, "36 incident faces per interior vertex");
-static_assert(make_dyn().n == 14, "14 faces meet a raster predecessor in the block");
 
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ int lorenzo_local(const int2 (*C)[TILE], const int2 (*P)[TILE], int lx, int ly,
@@ -471,7 +452,6 @@ constexpr DynPairs make_dyn_pairs() {
   }
   return D;
 }
-__constant__ DynPairs c_dynp = make_dyn_pairs();
 struct StaticPairs {
   int8_t a[22], b[22];
 };
@@ -513,10 +493,6 @@ constexpr bool trail_covers_static() {
   return true;
 }
 static_assert(trail_covers_static(), "the trails hold every static face once");
-__constant__ NbrTable c_nbr = NBR;
-__device__ __forceinline__ int c_nbr_dx(int j) { return c_nbr.dx[j]; }
-__device__ __forceinline__ int c_nbr_dy(int j) { return c_nbr.dy[j]; }
-__device__ __forceinline__ int c_nbr_dt(int j) { return c_nbr.dt[j]; }
 static_assert(make_pairs().a[0] >= 0 && make_dyn_pairs().a[13] >= 0 && make_dyn_pairs().a[14] < 0,
               "face and neighbour tables are consistent");
 // Lane j's sweep face as one word: bit 0 set for the 14 lanes with a face,
