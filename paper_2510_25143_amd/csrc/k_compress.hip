@@ -687,6 +687,9 @@ constexpr bool halo_covers_ring() {
   return true;
 }
 static_assert(NHALO == 134 && halo_covers_ring(), "the halo table and the threads' own cells cover the staged frames once");
+static_assert(offsetof(PhaseSmem, V1) == sizeof(double2) * HALO1 * HALO1 &&
+                  offsetof(PhaseSmem, V2) == sizeof(double2) * (HALO1 * HALO1 + HALO * HALO),
+              "a halo entry's index runs over V0, V1, V2 as one range");
 __constant__ HaloTable c_halo = make_halo();
 
 // frame 0, 1, 2 (t-1, t, t+1) at halo indices (hy, hx) of the 18 x 18 frame
@@ -730,12 +733,13 @@ __device__ __forceinline__ void phase_tile(PhaseSmem* SS, bool valid, int2* __re
   const int vx = lt & 15, vy = lt >> 4;
   const bool vin = valid && x0 + vx < W && y0 + vy < H;
 
+  // this lane's sweep face, read with the frame loads
+  const uint32_t dyn = c_dynlanes.e[tid & 15];
+
   // ---- stage frames t-1, t, t+1.  Every thread loads its own vertex's cell
   // of the three frames, and threads 0 .. NHALO-1 one halo cell each (from
   // a table); cells outside the domain or the frame range are staged as 0.
   // All loads of a thread are issued before the first one is waited for.
-  // this lane's sweep face, read with the frame loads
-  const uint32_t dyn = c_dynlanes.e[tid & 15];
   const size_t own = (size_t)(y0 + vy) * W + (x0 + vx);
   const int2* f0 = cur + (size_t)(t > 0 ? t - 1 : 0) * HW;
   const int2* f1 = cur + (size_t)t * HW;
