@@ -186,11 +186,9 @@ __device__ int block_mode(ModesSmem& S, const int2* __restrict__ cur, const uint
     if (lane + 64 * k <= 128) S.T[lane + 64 * k] = (int)tv[k];
   for (int i = lane; i < p.K * 128; i += 64) (&SAMP[0][0])[i] = -1;
   wave_sync();
-  // frame t-1 at a domain vertex: from the staged block where it covers it
-  auto Fprev = [&](int xx, int yy) {
-    const int tx_ = xx - x0, ty_ = yy - y0;
-    return (tx_ >= 0 && tx_ < TILE && ty_ >= 0 && ty_ < TILE) ? P[ty_][tx_] : pf[(size_t)yy * W + xx];
-  };
+  // frame t-1 at a domain vertex, from global memory (cache hits: the
+  // block was just loaded)
+  auto Fprev = [&](int xx, int yy) { return pf[(size_t)yy * W + xx]; };
 
   // ---------------- block features (also the selector's input)
   int cls_learned = -1;
