@@ -226,15 +226,16 @@ def bench_batch(args, cpt, torch, synthfields):
     decs = [torch.empty_like(f) for f in fields]
     sched, tune_ms = args.schedule, None
     if sched == "auto":
-        (sched, graph, ftile), tune_ms = cpt.autotune_batch(fields, eb, reps=1, outs=outs, backend=args.backend)
-        log("autotune: %s graph=%s field tile %s (ms: %s)" %
-            (sched, graph, cpt.FIELD_TILES[ftile], ", ".join("%.2f" % m for m in tune_ms)))
+        (sched, graph, ftile, pblocks), tune_ms = cpt.autotune_batch(fields, eb, reps=1, outs=outs,
+                                                                     backend=args.backend)
+        log("autotune: %s graph=%s field tile %s, %d block(s) per phase workgroup (ms: %s)" %
+            (sched, graph, cpt.FIELD_TILES[ftile], pblocks, ", ".join("%.2f" % m for m in tune_ms)))
     else:
-        ftile = 0
+        ftile, pblocks = 0, 2
 
     def comp():
         st, status = cpt.compress_batch(fields, eb, schedule=sched, outs=outs, backend=args.backend,
-                                        field_tile=ftile)
+                                        field_tile=ftile, phase_blocks=pblocks)
         return st
 
     log("warmup x%d" % max(args.warmup, 1))
@@ -271,7 +272,7 @@ def bench_batch(args, cpt, torch, synthfields):
     td = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
     fam = {name: cpt.timing_read(name) for name in cpt.TIMING_FAMILIES}
     cpt.timing_enable(False)
-    kname = "k_phase_b<true, 1>" if sched == "fused" else "k_phase_b<false, 2>"
+    kname = "k_phase_b<true, 1>" if sched == "fused" else "k_phase_b<false, %d>" % pblocks
     roofline = phase_roofline(fam, kname)
     roofline.update(path_roofline(nvert, raw / clen, tc, td))
     kernels = {name: {"avg_launch_us": round(m / c * 1e3, 3), "sampled_launches": c}
@@ -295,7 +296,7 @@ def bench_batch(args, cpt, torch, synthfields):
         "scaling": "weak", "vs_baseline": None, "dtype": "i32+f64(exact)", "data": "synthetic",
         "config": {"workload": WORKLOADS["batch"]["name"], "fields": len(fields), "vertices": nvert,
                    "raw_bytes": raw, "eb_rel": eb, "predictor": 2, "mode_bt": 1, "schedule": sched,
-                   "field_tile": cpt.FIELD_TILES[ftile],
+                   "field_tile": cpt.FIELD_TILES[ftile], "phase_blocks": pblocks,
                    "lossless_stage": "zero-byte elision after Huffman" if args.backend else "none",
                    "tune_ms": tune_ms, "CR": round(raw / clen, 4), "stream_bytes": clen,
                    "max_err_over_eb": round(worst, 6),
@@ -529,19 +530,20 @@ def main():
     opts = dict(predictor=args.predictor, mode_bt=args.mode_bt, dt_dx=dt, dt_dy=dt, backend=args.backend)
     sched = args.schedule
     tune_ms = None
-    ftile = 0
+    ftile, pblocks = 0, 2
     if sched == "auto":
         # execution choice only (identical streams): per-phase launches with
         # or without the predictor choice fused into the phases, each eager
-        # and as a graph replay, then the field pass's tile shape; the timed
-        # loop runs the winner eagerly so that its kernels can be timed one
-        # by one
-        (sched, _, ftile), tune_ms = cpt.autotune_batch([f], eb, reps=2, outs=[out], **opts)
-        log("autotune: %s, field tile %s (ms: %s)" %
-            (sched, cpt.FIELD_TILES[ftile], ", ".join("%.3f" % m for m in tune_ms)))
+        # and as a graph replay, then the field pass's tile shape, then the
+        # blocks per phase workgroup; the timed loop runs the winner eagerly
+        # so that its kernels can be timed one by one
+        (sched, _, ftile, pblocks), tune_ms = cpt.autotune_batch([f], eb, reps=2, outs=[out], **opts)
+        log("autotune: %s, field tile %s, %d block(s) per phase workgroup (ms: %s)" %
+            (sched, cpt.FIELD_TILES[ftile], pblocks, ", ".join("%.3f" % m for m in tune_ms)))
 
     def comp():
-        (st,), _ = cpt.compress_batch([f], eb, schedule=sched, outs=[out], field_tile=ftile, **opts)
+        (st,), _ = cpt.compress_batch([f], eb, schedule=sched, outs=[out], field_tile=ftile, phase_blocks=pblocks,
+                                      **opts)
         return st
 
     if args.calibration_copy:
@@ -610,7 +612,7 @@ def main():
     log("lossless stage: CR %.3f with, %.3f Huffman only; %.2f GB/s with the other setting" %
         (stage["CR_with_stage"], stage["CR_huffman_only"], stage["GBps_other_setting"]))
 
-    kname = "k_phase_b<true, 1>" if sched == "fused" else "k_phase_b<false, 2>"
+    kname = "k_phase_b<true, 1>" if sched == "fused" else "k_phase_b<false, %d>" % pblocks
     roofline = phase_roofline(fam, kname, args.workload)
     roofline.update(path_roofline(T * H * W, raw / clen, tc, td))
     kernels = {name: {"avg_launch_us": round(m / c * 1e3, 3), "sampled_launches": c}
@@ -622,7 +624,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "i32+f64(exact)", "data": "synthetic",
         "config": {"workload": wl["name"], "shape_T_H_W": [T, H, W], "raw_bytes": raw, "eb_rel": eb,
                    "eb_abs": eb_abs, "predictor": args.predictor, "mode_bt": args.mode_bt,
-                   "schedule": sched, "field_tile": cpt.FIELD_TILES[ftile], "tune_ms": tune_ms,
+                   "schedule": sched, "field_tile": cpt.FIELD_TILES[ftile], "phase_blocks": pblocks,
+                   "tune_ms": tune_ms,
                    "CR": round(raw / clen, 4), "stream_bytes": clen, "fc_t": v["fc_t"], "fc_s": v["fc_s"],
                    "n_traj_before": traj0, "n_traj_after": traj1, "lemma1_violations": bad0,
                    "max_err": v["max_err"], "psnr": round(v["psnr"], 3),

@@ -160,6 +160,12 @@ typedef struct {
                             depend on it; CPT_SCHED_AUTO takes the tuned
                             one).  A struct_size that ends before this field
                             (the earlier layout) means 0. */
+  int32_t phase_blocks;  /* 16x16 blocks per workgroup of the per-phase
+                            launches (CPT_SCHED_LAUNCH): 1 or 2, 0 meaning
+                            2; the fused schedule always takes one.  The
+                            output does not depend on it; CPT_SCHED_AUTO
+                            takes the tuned one.  A struct_size that ends
+                            before this field means 0. */
 } cpt_exec_options;
 
 /*
@@ -184,9 +190,10 @@ cpt_status cpt_compress_batch(int n, const float* const* fields, const int32_t* 
 
 /* Number of execution choices cpt_autotune_batch times, in this order:
  * LAUNCH, FUSED, LAUNCH replayed as a graph, FUSED replayed as a graph (all
- * with field tile 0), then the fastest of those four with field tiles 1 and
- * 2. */
-#define CPT_TUNE_CANDIDATES 6
+ * with field tile 0 and two blocks per phase workgroup), then the fastest of
+ * those four with field tiles 1 and 2, then the fastest so far with one
+ * block per phase workgroup. */
+#define CPT_TUNE_CANDIDATES 7
 
 /*
  * Time every candidate execution choice on this batch (arguments as for

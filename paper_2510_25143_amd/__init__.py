@@ -48,14 +48,15 @@ class TrainOptions(ctypes.Structure):
 
 class ExecOptions(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("schedule", ctypes.c_int32), ("group", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("field_tile", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("field_tile", ctypes.c_int32),
+                ("phase_blocks", ctypes.c_int32)]
 
 
 SCHEDULES = {"auto": 0, "launch": 1, "fused": 2, "persistent": 3}
 # (schedule, graph replay, field tile); the last two take the schedule and
 # graph setting of the fastest of the first four
-TUNE_CANDIDATES = [("launch", False, 0), ("fused", False, 0), ("launch", True, 0), ("fused", True, 0),
-                   ("best", None, 1), ("best", None, 2)]
+TUNE_CANDIDATES = [("launch", False, 0, 2), ("fused", False, 0, 2), ("launch", True, 0, 2), ("fused", True, 0, 2),
+                   ("best", None, 1, 2), ("best", None, 2, 2), ("best", None, None, 1)]
 FIELD_TILES = [(32, 16), (64, 8), (16, 32)]
 
 
@@ -213,14 +214,15 @@ def _batch_args(fields, outs):
 
 def compress_batch(fields, eb, predictor=PRED_MIX2, mode_bt=1, eb_mode=0, dt_dx=1.0, dt_dy=1.0,
                    selector_w=None, schedule="auto", group=0, grid=0, use_graph=False, outs=None,
-                   raise_on_error=True, backend=0, field_tile=0):
+                   raise_on_error=True, backend=0, field_tile=0, phase_blocks=0):
     """Compress a list of fields (each (2,T,H,W) float32 CUDA) in one device
     pipeline.  Returns (streams, status): streams[i] is a view of outs[i]
     trimmed to its length (None when field i failed), status[i] its
     cpt_status."""
     fs, n, hwt, outs, fp, op, caps = _batch_args(fields, outs)
     o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w, backend)
-    ex = ExecOptions(ctypes.sizeof(ExecOptions), SCHEDULES[schedule], group, grid, int(bool(use_graph)), field_tile)
+    ex = ExecOptions(ctypes.sizeof(ExecOptions), SCHEDULES[schedule], group, grid, int(bool(use_graph)), field_tile,
+                     phase_blocks)
     lens = (ctypes.c_size_t * n)()
     st = (ctypes.c_int32 * n)()
     r = lib().cpt_compress_batch(n, fp, hwt, eb, ctypes.byref(o), ctypes.byref(ex), op, caps, lens, st, _stream())
@@ -234,16 +236,16 @@ def autotune_batch(fields, eb, reps=2, predictor=PRED_MIX2, mode_bt=1, eb_mode=0
                    selector_w=None, outs=None, backend=0):
     """Time every candidate execution choice on this batch and remember the
     fastest for schedule="auto".  Returns (best, ms): best = (schedule,
-    use_graph, field_tile), ms the mean time per run of each of
-    TUNE_CANDIDATES."""
+    use_graph, field_tile, phase_blocks), ms the mean time per run of each
+    of TUNE_CANDIDATES."""
     fs, n, hwt, outs, fp, op, caps = _batch_args(fields, outs)
     o = _options(predictor, mode_bt, eb_mode, dt_dx, dt_dy, selector_w, backend)
-    best = ExecOptions(ctypes.sizeof(ExecOptions), 0, 0, 0, 0, 0)
+    best = ExecOptions(ctypes.sizeof(ExecOptions), 0, 0, 0, 0, 0, 0)
     ms = (ctypes.c_double * len(TUNE_CANDIDATES))()
     _check(lib().cpt_autotune_batch(n, fp, hwt, eb, ctypes.byref(o), op, caps, reps, ctypes.byref(best), ms,
                                     _stream()))
     name = {v: k for k, v in SCHEDULES.items()}[best.schedule]
-    return (name, bool(best.use_graph), best.field_tile), list(ms)
+    return (name, bool(best.use_graph), best.field_tile, best.phase_blocks), list(ms)
 
 
 def _out_field(out):

@@ -616,6 +616,7 @@ struct ExecChoice {
   int schedule = CPT_SCHED_LAUNCH, group = 1, grid = 0;
   bool graph = false;
   int ftile = 0;  // tile shape of the field pass (FP_SHAPE_TW / FP_SHAPE_TH)
+  int pblocks = 2;  // blocks per workgroup of the per-phase launches (1 or 2)
 };
 
 // the field pass's workgroups per field for tile shape `shape`
@@ -657,7 +658,7 @@ void enqueue_compress(const Plan& P, const BatchBufs& b, const ExecChoice& ex, c
       }
       for (int c = 0; c < 3; c++) {
         TimeScope ts(FAM_PHASE, P.cv_at[3 * t + c], s);
-        launch_phase_b(B, b.ppre, m, P.ppre[m], t, c, ms, gi, ex.schedule == CPT_SCHED_FUSED, s);
+        launch_phase_b(B, b.ppre, m, P.ppre[m], t, c, ms, gi, ex.schedule == CPT_SCHED_FUSED, ex.pblocks, s);
       }
     }
   }
@@ -686,7 +687,7 @@ cpt_status run_graph(const Plan& P, const BatchBufs& b, const ExecChoice& ex, Ar
   cpt_status st = library_stream(A);
   if (st) return st;
   char tag[160];
-  std::snprintf(tag, sizeof(tag), "|%d:%d:%d:%d|%p:%zu|%p:%p", ex.schedule, ex.group, ex.grid, ex.ftile,
+  std::snprintf(tag, sizeof(tag), "|%d:%d:%d:%d:%d|%p:%zu|%p:%p", ex.schedule, ex.group, ex.grid, ex.ftile, ex.pblocks,
                 (void*)A.base, A.cap, (const void*)P.opt.selector_w, (void*)A.tlog);
   const std::string key = P.key + tag;
   hipGraphExec_t exec = nullptr;
@@ -740,8 +741,10 @@ ExecChoice resolve_exec(const cpt_exec_options* ex, const Plan& P) {
     c.group = ex->group > 0 ? ex->group : 1;
     c.grid = ex->grid;
     c.graph = ex->use_graph != 0;
-    // a struct without the field (the earlier layout) means the default tile
+    // a struct without a field (an earlier layout) means its default
     if (ex->struct_size >= offsetof(cpt_exec_options, field_tile) + sizeof(int32_t)) c.ftile = ex->field_tile;
+    if (ex->struct_size >= offsetof(cpt_exec_options, phase_blocks) + sizeof(int32_t) && ex->phase_blocks != 0)
+      c.pblocks = ex->phase_blocks;
   }
   if (sched == CPT_SCHED_AUTO) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -752,6 +755,7 @@ ExecChoice resolve_exec(const cpt_exec_options* ex, const Plan& P) {
       c.grid = it->second.grid;
       c.graph = c.graph || it->second.graph;
       c.ftile = it->second.ftile;
+      c.pblocks = it->second.pblocks;
     } else {
       c.schedule = CPT_SCHED_LAUNCH;
     }
@@ -777,10 +781,15 @@ cpt_status compress_batch_impl(int n, const float* const* fields, const int32_t*
                                const size_t* caps, size_t* lens, int32_t* status, const Debug* dbg, hipStream_t s,
                                const ExecChoice* forced = nullptr) {
   if (!fields || !outs || !caps || !lens) return fail(CPT_EINVAL, "null argument");
-  if (ex_in && ex_in->struct_size != sizeof(cpt_exec_options) && ex_in->struct_size != offsetof(cpt_exec_options, field_tile))
+  if (ex_in && ex_in->struct_size != sizeof(cpt_exec_options) &&
+      ex_in->struct_size != offsetof(cpt_exec_options, phase_blocks) &&
+      ex_in->struct_size != offsetof(cpt_exec_options, field_tile))
     return fail(CPT_EINVAL, "cpt_exec_options.struct_size mismatch");
-  if (ex_in && ex_in->struct_size == sizeof(cpt_exec_options) && (ex_in->field_tile < 0 || ex_in->field_tile >= FP_SHAPES))
+  if (ex_in && ex_in->struct_size >= offsetof(cpt_exec_options, phase_blocks) &&
+      (ex_in->field_tile < 0 || ex_in->field_tile >= FP_SHAPES))
     return fail(CPT_EINVAL, "field_tile must be 0, 1 or 2");
+  if (ex_in && ex_in->struct_size == sizeof(cpt_exec_options) && (ex_in->phase_blocks < 0 || ex_in->phase_blocks > 2))
+    return fail(CPT_EINVAL, "phase_blocks must be 0, 1 or 2");
   cpt_options opt;
   cpt_status st = check_options(opt_in, eb, &opt);
   if (st) return st;
@@ -803,6 +812,7 @@ cpt_status compress_batch_impl(int n, const float* const* fields, const int32_t*
   if (ex.group < 1 || ex.group > 64) return fail(CPT_EINVAL, "group must be in 1..64");
   if (ex.grid < 0) return fail(CPT_EINVAL, "grid must be 0 (as many workgroups as fit at once) or positive");
   if (ex.ftile < 0 || ex.ftile >= FP_SHAPES) return fail(CPT_EINVAL, "field_tile must be 0, 1 or 2");
+  if (ex.pblocks < 1 || ex.pblocks > 2) return fail(CPT_EINVAL, "phase_blocks must be 0, 1 or 2");
   st = set_fieldpass_shape(P, ex.ftile);
   if (st) return st;
   if (ex.schedule == CPT_SCHED_PERSISTENT)
@@ -1540,13 +1550,14 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
     Plan P;
     st = make_plan(n, HWT, opt, eb, P);
     if (st) return st;
-    // four schedules with the default field tile, then the fastest of them
-    // with the other field tiles (filled in when the first four are timed)
-    ExecChoice cand[CPT_TUNE_CANDIDATES] = {{CPT_SCHED_LAUNCH, 1, 0, false, 0},
-                                            {CPT_SCHED_FUSED, 1, 0, false, 0},
-                                            {CPT_SCHED_LAUNCH, 1, 0, true, 0},
-                                            {CPT_SCHED_FUSED, 1, 0, true, 0}};
-    static_assert(CPT_TUNE_CANDIDATES == 4 + FP_SHAPES - 1, "schedules, then field tiles");
+    // four schedules with the default field tile and phase workgroup, then
+    // the fastest of them with the other field tiles, then the fastest so
+    // far with one block per phase workgroup (filled in as they are timed)
+    ExecChoice cand[CPT_TUNE_CANDIDATES] = {{CPT_SCHED_LAUNCH, 1, 0, false, 0, 2},
+                                            {CPT_SCHED_FUSED, 1, 0, false, 0, 2},
+                                            {CPT_SCHED_LAUNCH, 1, 0, true, 0, 2},
+                                            {CPT_SCHED_FUSED, 1, 0, true, 0, 2}};
+    static_assert(CPT_TUNE_CANDIDATES == 4 + FP_SHAPES - 1 + 1, "schedules, field tiles, phase workgroup");
     std::vector<size_t> lens(n), ref;
     std::vector<unsigned long long> dig(n), refdig;
     // the digests of the candidates' streams (the tuner is not a hot path:
@@ -1569,9 +1580,12 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
     int bi = -1;
     double bms = 0;
     for (int c = 0; c < CPT_TUNE_CANDIDATES; c++) {
-      if (c >= 4) {
+      if (c >= 4 && c < 4 + FP_SHAPES - 1) {
         cand[c] = cand[bi];
         cand[c].ftile = c - 3;
+      } else if (c == 4 + FP_SHAPES - 1) {
+        cand[c] = cand[bi];
+        cand[c].pblocks = 1;
       }
       st = compress_batch_impl(n, fields, HWT, eb, &opt, nullptr, outs, caps, lens.data(), nullptr, nullptr, s,
                                &cand[c]);
@@ -1618,7 +1632,7 @@ cpt_status cpt_autotune_batch(int n, const float* const* fields, const int32_t* 
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tuned[P.key] = b;
     }
-    *best = cpt_exec_options{sizeof(cpt_exec_options), b.schedule, b.group, b.grid, b.graph ? 1 : 0, b.ftile};
+    *best = cpt_exec_options{sizeof(cpt_exec_options), b.schedule, b.group, b.grid, b.graph ? 1 : 0, b.ftile, b.pblocks};
     return CPT_OK;
   } catch (...) {
     return fail(CPT_EHIP, "unexpected exception");

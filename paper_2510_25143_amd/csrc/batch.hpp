@@ -212,8 +212,9 @@ void launch_reconstruct_b(DecDesc* D, const int* ord, int ord0, const long long*
 // launchers (k_compress.hip)
 void launch_modes_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int gidx,
                     hipStream_t s);
+// nb: blocks per workgroup without the fused predictor choice (1 or 2)
 void launch_phase_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int c,
-                    int mstate, int gidx, bool fused, hipStream_t s);
+                    int mstate, int gidx, bool fused, int nb, hipStream_t s);
 // workgroups of the persistent kernel that fit on the current device at once
 int persist_grid();
 void launch_persist(const BatchView& B, const SchedSeg* seg, const long long* sstart, int nseg, long long nitems,

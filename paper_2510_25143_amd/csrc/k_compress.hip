@@ -1138,15 +1138,12 @@ void launch_modes_b(const BatchView& B, const long long* pre, int m, long long n
   if (nblocks > 0) k_modes_b<<<(unsigned)nblocks, 64, 0, s>>>(B, pre, m, t, gidx);
 }
 
-#ifndef CPT_PHASE_NB
-#define CPT_PHASE_NB 2
-#endif
 void launch_phase_b(const BatchView& B, const long long* pre, int m, long long nblocks, int t, int c,
-                    int mstate, int gidx, bool fused, hipStream_t s) {
+                    int mstate, int gidx, bool fused, int nb, hipStream_t s) {
   if (nblocks <= 0) return;
-  constexpr int NB = CPT_PHASE_NB;
   if (fused) k_phase_b<true, 1><<<(unsigned)nblocks, 256, 0, s>>>(B, pre, m, t, c, mstate, gidx, nblocks);
-  else k_phase_b<false, NB><<<(unsigned)((nblocks + NB - 1) / NB), 256 * NB, 0, s>>>(B, pre, m, t, c, mstate, gidx, nblocks);
+  else if (nb == 1) k_phase_b<false, 1><<<(unsigned)nblocks, 256, 0, s>>>(B, pre, m, t, c, mstate, gidx, nblocks);
+  else k_phase_b<false, 2><<<(unsigned)((nblocks + 1) / 2), 512, 0, s>>>(B, pre, m, t, c, mstate, gidx, nblocks);
 }
 
 int persist_grid() {

@@ -153,8 +153,8 @@ def test_capacity_reports_length(cpt, small, want_mix2):
 
 def test_autotune_picks_a_candidate_and_auto_uses_it(cpt, small, want_mix2):
     best, ms = cpt.autotune_batch(small[1], 1e-2, reps=1)
-    sched, graph, tile = best
-    assert (sched, graph) in [c[:2] for c in cpt.TUNE_CANDIDATES[:4]] and tile in (0, 1, 2)
+    sched, graph, tile, pblocks = best
+    assert (sched, graph) in [c[:2] for c in cpt.TUNE_CANDIDATES[:4]] and tile in (0, 1, 2) and pblocks in (1, 2)
     assert len(ms) == len(cpt.TUNE_CANDIDATES) and all(m > 0 for m in ms)
     got, st = cpt.compress_batch(small[1], 1e-2, schedule="auto")
     for g, w in zip(got, want_mix2):
@@ -175,6 +175,22 @@ def test_field_tiles_give_identical_streams(cpt, small, want_mix2):
     for sched in ("launch", "auto"):
         with pytest.raises(cpt.CptError, match="field_tile"):
             cpt.compress_batch(small[1], 1e-2, schedule=sched, field_tile=3)
+
+
+def test_phase_blocks_give_identical_streams(cpt, small, want_mix2):
+    """One or two 16x16 blocks per workgroup of the per-phase launches is an
+    execution choice: both write the oracle's bytes, eager and as a graph
+    replay, on ragged fields in one batch (workgroups that pair blocks of two
+    fields, and a last workgroup with one block and one empty slot)."""
+    for pb in (1, 2):
+        for ex in (dict(schedule="launch"), dict(schedule="launch", use_graph=True)):
+            got, st = cpt.compress_batch(small[1], 1e-2, phase_blocks=pb, **ex)
+            assert st == [0] * len(SMALL)
+            for i, (g, w) in enumerate(zip(got, want_mix2)):
+                assert np.array_equal(g.cpu().numpy(), w), "phase_blocks %d field %d %s" % (pb, i, SMALL[i])
+    for sched in ("launch", "auto"):
+        with pytest.raises(cpt.CptError, match="phase_blocks"):
+            cpt.compress_batch(small[1], 1e-2, schedule=sched, phase_blocks=3)
 
 
 PERSISTENT_OFF = ("persistent schedule disabled: its launch did not complete on the device, also with the "
