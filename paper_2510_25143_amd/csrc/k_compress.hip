@@ -3,11 +3,12 @@
 //
 // Order (reproducible by construction): for every frame t, three colour
 // phases; phase c processes every 16x16 block with (bx + by) mod 3 == c.
-// Blocks of one colour share no face, so they run as independent
-// workgroups.  Inside a block the vertices are taken in raster order; with
-// the main-diagonal triangulation the raster predecessors of a vertex are
-// exactly its neighbours on earlier anti-diagonals, so the workgroup sweeps
-// the 31 anti-diagonals and processes each one in parallel.
+// Blocks of one colour share no face, so they are processed independently
+// (one or two per workgroup).  Inside a block the vertices are taken in
+// raster order; with the main-diagonal triangulation the raster
+// predecessors of a vertex are exactly its neighbours on earlier
+// anti-diagonals, so the block is swept along its 31 anti-diagonals, each
+// one processed in parallel.
 //
 // Per vertex (Alg. 3 and Alg. 4 of the paper): a vertex on a crossed face of
 // the original field is stored losslessly; otherwise its bound is the
