@@ -124,3 +124,41 @@ def test_stream_info_reads_a_container_on_host(built):
     with pytest.raises(cpt.CptError):
         cpt.stream_info(torch.from_numpy(bad))
     assert cpt.compress_bound(64, 64, 8) >= oracle.lib().cpo_compress_bound(64, 64, 8)
+
+
+EXEC_OPTIONS = r'''
+import ctypes, sys
+L = ctypes.CDLL(sys.argv[1])
+L.cpt_last_error.restype = ctypes.c_char_p
+P = ctypes.c_void_p
+class Ex(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("schedule", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("field_tile", ctypes.c_int32),
+                ("phase_blocks", ctypes.c_int32)]
+buf = (ctypes.c_uint32 * 64)()          # host memory: never read, every call is refused first
+fields = (P * 1)(ctypes.addressof(buf))
+outs = (P * 1)(ctypes.addressof(buf))
+hwt = (ctypes.c_int32 * 3)(16, 16, 2)
+caps = (ctypes.c_size_t * 1)(256)
+lens = (ctypes.c_size_t * 1)()
+status = (ctypes.c_int32 * 1)()
+L.cpt_compress_batch.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P, P, P, P, P, P, P]
+for size, tile, pb in ((28, 0, 3), (28, 0, -1), (28, 3, 0), (24, 5, 0), (26, 0, 0)):
+    ex = Ex(size, 0, 0, 0, 0, tile, pb)
+    st = L.cpt_compress_batch(1, fields, hwt, 1e-2, None, ctypes.byref(ex), outs, caps, lens, status, None)
+    print(size, tile, pb, st, L.cpt_last_error().decode().replace(" ", "_"))
+'''
+
+
+def test_exec_options_are_checked_on_host(built):
+    """Execution options out of range (blocks per phase workgroup, field
+    tile) and a struct_size of no known layout are refused before any device
+    work, in every layout that holds the field."""
+    r = subprocess.run([sys.executable, "-c", EXEC_OPTIONS, built], capture_output=True, text=True,
+                       env=dict(os.environ, HIP_VISIBLE_DEVICES=""), timeout=120)
+    assert r.returncode == 0, r.stderr
+    rows = [line.split() for line in r.stdout.strip().splitlines()]
+    assert len(rows) == 5
+    want = ["phase_blocks", "phase_blocks", "field_tile", "field_tile", "struct_size"]
+    for (size, tile, pb, st, msg), w in zip(rows, want):
+        assert int(st) == -1 and w in msg, (size, tile, pb, st, msg)
